@@ -1,0 +1,215 @@
+"""ctypes front end of the FP64 CPU oracle (``pd_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library.  It marshals numpy
+arrays; every computation happens in the C file, which is a literal, slow
+transcription of the paper's definitions (Algorithm 1, the velocity-Verlet
+equations, the tangent equation and the implicit flow chart).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pd_oracle.c")
+LIB = os.path.join(HERE, "libpd_oracle.so")
+
+BC_FREE, BC_CLAMPED, BC_VELOCITY = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP contraction off, OpenMP over nodes)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        i64, i32, dbl, ptr = C.c_int64, C.c_int, C.c_double, C.c_void_p
+        L.or_threshold.restype = dbl
+        L.or_threshold.argtypes = [dbl]
+        L.or_micromodulus.restype = dbl
+        L.or_micromodulus.argtypes = [i32, dbl, dbl]
+        for name in ("or_nbr_brute", "or_nbr_binned"):
+            fn = getattr(L, name)
+            fn.restype = i64
+            fn.argtypes = [i32, i64, ptr, dbl, ptr, ptr]
+        L.or_force.restype = None
+        L.or_force.argtypes = [i32, i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, ptr, ptr, ptr]
+        L.or_kinetic.restype = dbl
+        L.or_kinetic.argtypes = [i32, i64, ptr, dbl, ptr]
+        L.or_potential.restype = dbl
+        L.or_potential.argtypes = [i64, ptr, ptr]
+        L.or_notch_cut.restype = None
+        L.or_notch_cut.argtypes = [i32, i64, ptr, ptr, ptr, i32, ptr, ptr]
+        L.or_verlet.restype = None
+        L.or_verlet.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, ptr, ptr, ptr,
+                                i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
+        L.or_apply_tangent.restype = None
+        L.or_apply_tangent.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, ptr, ptr, ptr, ptr]
+        L.or_cg.restype = i32
+        L.or_cg.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, ptr, ptr, ptr, ptr, dbl, i32,
+                            ptr, ptr]
+        L.or_residual.restype = dbl
+        L.or_residual.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, ptr, ptr, ptr, ptr, ptr]
+        L.or_solve_implicit.restype = i32
+        L.or_solve_implicit.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, ptr, ptr, ptr, ptr,
+                                        dbl, dbl, i32, i32, ptr, ptr, ptr]
+        L.or_num_threads.restype = i32
+        L.or_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threshold(delta):
+    return lib().or_threshold(float(delta))
+
+
+def micromodulus(dim, E, delta):
+    return lib().or_micromodulus(int(dim), float(E), float(delta))
+
+
+def neighbors(X, delta, method="binned"):
+    """CSR (row_ptr int64[n+1], col int32[nnz]) of B_delta, rows ascending."""
+    X = _f64(X)
+    n, dim = X.shape
+    thr = threshold(delta)
+    fn = lib().or_nbr_brute if method == "brute" else lib().or_nbr_binned
+    row_ptr = np.zeros(n + 1, np.int64)
+    nnz = fn(dim, n, _p(X), thr, _p(row_ptr), None)
+    if nnz < 0:
+        raise ValueError("coincident nodes")
+    col = np.zeros(max(int(nnz), 1), np.int32)
+    fn(dim, n, _p(X), thr, _p(row_ptr), _p(col))
+    return row_ptr, col[:nnz]
+
+
+class Mesh:
+    """Reference configuration + neighbour list, as the oracle sees it."""
+
+    def __init__(self, X, V, delta, method="binned", row_ptr=None, col=None):
+        self.X = _f64(X)
+        self.V = _f64(V)
+        self.n, self.dim = self.X.shape
+        self.delta = float(delta)
+        if row_ptr is None:
+            row_ptr, col = neighbors(self.X, delta, method)
+        self.row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+        self.col = np.ascontiguousarray(col, np.int32)
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+    def all_alive(self):
+        return np.ones(max(self.nnz, 1), np.uint8)[: self.nnz]
+
+    def force(self, u, c, s_c=0.0, alive=None, energy=False):
+        u = _f64(u)
+        f = np.zeros_like(self.X)
+        U = np.zeros(self.n) if energy else None
+        lib().or_force(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V),
+                       _p(u), float(c), float(s_c), _p(alive), _p(f), _p(U))
+        return (f, U) if energy else f
+
+    def potential(self, u, c, alive=None):
+        _, U = self.force(u, c, 0.0, alive, energy=True)
+        return lib().or_potential(self.n, _p(self.V), _p(U))
+
+    def kinetic(self, v, rho):
+        v = _f64(v)
+        return lib().or_kinetic(self.dim, self.n, _p(self.V), float(rho), _p(v))
+
+    def notch_cut(self, notch, alive):
+        seg = _f64(np.asarray(notch).reshape(-1, 4))
+        lib().or_notch_cut(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                           int(seg.shape[0]), _p(seg), _p(alive))
+        return alive
+
+    def verlet(self, state, c, rho, s_c, dt, nsteps, bc_kind=None, bc_vel=None, b=None,
+               ramp=0):
+        """Advance ``state`` (dict u, v, f, alive, step) by nsteps in place."""
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        lib().or_verlet(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                        _p(self.V), float(rho), float(c), float(s_c), _p(bc_kind), _p(bc_vel),
+                        _p(b), int(ramp), float(dt), int(state["step"]), int(nsteps),
+                        _p(state["u"]), _p(state["v"]), _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
+
+    def start(self, u0, v0, c, s_c=0.0, alive=None):
+        """Initial state: f^0 = force(u^0), with the damage test at u^0."""
+        alive = self.all_alive() if alive is None else np.ascontiguousarray(alive, np.uint8).copy()
+        u = _f64(u0).copy()
+        v = _f64(v0).copy()
+        f = self.force(u, c, s_c, alive)
+        return {"u": u, "v": v, "f": f, "alive": alive, "step": 0}
+
+    def apply_tangent(self, w, c, fixed=None, alive=None):
+        w = _f64(w)
+        y = np.zeros_like(w)
+        fixed = None if fixed is None else np.ascontiguousarray(fixed, np.uint8)
+        lib().or_apply_tangent(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                               _p(self.V), float(c), _p(alive), _p(fixed), _p(w), _p(y))
+        return y
+
+    def cg(self, rhs, c, fixed=None, alive=None, x0=None, rtol=1e-13, maxit=100000):
+        rhs = _f64(rhs)
+        x = np.zeros_like(rhs) if x0 is None else _f64(x0).copy()
+        fixed = None if fixed is None else np.ascontiguousarray(fixed, np.uint8)
+        it = C.c_int(0)
+        rel = C.c_double(0)
+        st = lib().or_cg(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                         _p(self.V), float(c), _p(alive), _p(fixed), _p(rhs), _p(x),
+                         float(rtol), int(maxit), C.byref(it), C.byref(rel))
+        return x, {"status": st, "iters": it.value, "relres": rel.value}
+
+    def residual(self, u, c, b, fixed=None, alive=None):
+        u = _f64(u)
+        r = np.zeros_like(u)
+        fixed = None if fixed is None else np.ascontiguousarray(fixed, np.uint8)
+        b = None if b is None else _f64(b)
+        nrm = lib().or_residual(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                                _p(self.V), float(c), _p(alive), _p(fixed), _p(b), _p(u), _p(r))
+        return r, nrm
+
+    def solve_implicit(self, u0, c, b, fixed, alive=None, rtol=1e-10, inner_rtol=1e-13,
+                       maxit=200000, max_outer=5):
+        u = _f64(u0).copy()
+        fixed = np.ascontiguousarray(fixed, np.uint8)
+        b = _f64(b)
+        o, i, rel = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = lib().or_solve_implicit(self.dim, self.n, _p(self.row_ptr), _p(self.col),
+                                     _p(self.X), _p(self.V), float(c), _p(alive), _p(fixed),
+                                     _p(b), _p(u), float(rtol), float(inner_rtol), int(maxit),
+                                     int(max_outer), C.byref(o), C.byref(i), C.byref(rel))
+        return u, {"status": st, "outer": o.value, "inner": i.value, "relres": rel.value}
+
+
+def num_threads():
+    return lib().or_num_threads()

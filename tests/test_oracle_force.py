@@ -1,0 +1,172 @@
+"""Pins of the oracle's bond force (Algorithm 1, linearised law, J = 1) and
+strain energy: hand-computed two-node values, the continuum energy density
+of classical elasticity, exact invariants, and the force/energy identity."""
+import numpy as np
+import pytest
+
+from paper_1806_06917_amd import inputs
+
+
+def two_node_mesh(orc, X, V, delta):
+    return orc.Mesh(np.array(X, float), np.array(V, float), delta, method="brute")
+
+
+def test_two_nodes_by_hand(orc):
+    # xi = (0.3, 0.4), |xi| = 0.5; eta = (0.003, 0.004); S = 0.0025/0.25 = 0.01
+    # e = (0.6, 0.8); c = 2, V1 = 0.25, V2 = 0.5
+    m = two_node_mesh(orc, [[0, 0], [0.3, 0.4]], [0.25, 0.5], 0.6)
+    u = np.array([[0.001, -0.002], [0.004, 0.002]])
+    f, U = m.force(u, 2.0, energy=True)
+    np.testing.assert_allclose(f[0], [0.006, 0.008], rtol=1e-13)     # c S V2 e
+    np.testing.assert_allclose(f[1], [-0.003, -0.004], rtol=1e-13)   # -c S V1 e
+    np.testing.assert_allclose(U, [0.25 * 2 * 1e-4 * 0.5 * 0.5,      # (c/4) S^2 |xi| V_j
+                                   0.25 * 2 * 1e-4 * 0.5 * 0.25], rtol=1e-13)
+
+
+def test_two_nodes_3d_compression(orc):
+    # xi = (0, 0, 2), eta = (0, 0, -0.02): S = -0.01, e = (0, 0, 1)
+    m = two_node_mesh(orc, [[1, 1, 1], [1, 1, 3]], [1.0, 3.0], 2.5)
+    u = np.array([[0.0, 0.0, 0.01], [0.0, 0.0, -0.01]])
+    f = m.force(u, 5.0)
+    np.testing.assert_allclose(f, [[0, 0, 5 * -0.01 * 3.0], [0, 0, 5 * 0.01 * 1.0]],
+                               rtol=1e-13, atol=0)
+    # transverse motion produces no linearised strain and no force
+    u2 = np.array([[0.0, 0.0, 0.0], [0.01, -0.02, 0.0]])
+    assert np.all(m.force(u2, 5.0) == 0.0)
+
+
+def lattice_patch(orc, dim, m, N=None):
+    N = N or (2 * m + 3)
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * dim, h)
+    mesh = orc.Mesh(X, np.full(X.shape[0], h ** dim), m * h)
+    centre = int(np.argmin(np.sum((X - X.mean(0)) ** 2, axis=1)))
+    return mesh, centre
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_density_approaches_classical(orc, dim):
+    """Isotropic strain eps: the PD energy density at an interior node tends
+    to the classical value (2-d plane stress nu = 1/3: E eps^2/(1-nu);
+    3-d nu = 1/4: 9/2 K eps^2 with K = E/(3(1-2 nu))) as m grows, with the
+    micromodulus calibration of the linearised law."""
+    E, eps = 2.5, 1e-3
+    target = E * eps ** 2 / (1 - 1 / 3) if dim == 2 else 4.5 * (E / (3 * 0.5)) * eps ** 2
+    errs = []
+    for m in ([4, 8, 16] if dim == 2 else [3, 5, 8]):
+        mesh, ci = lattice_patch(orc, dim, m)
+        c = orc.micromodulus(dim, E, mesh.delta)
+        _, U = mesh.force(eps * mesh.X, c, energy=True)
+        errs.append(abs(U[ci] / target - 1))
+    assert errs[-1] < 0.06 and errs[-1] < errs[0]
+
+
+def test_uniaxial_energy_2d(orc):
+    """Uniaxial strain along x in 2-d: W = C11 eps^2 / 2, C11 = E/(1-nu^2)."""
+    E, eps, m = 1.0, 1e-3, 16
+    mesh, ci = lattice_patch(orc, 2, m)
+    c = orc.micromodulus(2, E, mesh.delta)
+    u = np.zeros_like(mesh.X)
+    u[:, 0] = eps * mesh.X[:, 0]
+    _, U = mesh.force(u, c, energy=True)
+    target = 0.5 * E / (1 - 1 / 9) * eps ** 2
+    assert abs(U[ci] / target - 1) < 0.06
+
+
+def jittered(orc, dim, N, seed, m=3):
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * dim, h, jitter=0.05, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    V = h ** dim * rng.uniform(0.8, 1.2, X.shape[0])
+    return orc.Mesh(X, V, m * h)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_net_force(orc, dim):
+    mesh = jittered(orc, dim, 24 if dim == 2 else 10, seed=11)
+    u = inputs.random_field(mesh.n, dim, 12)
+    f = mesh.force(u, 1.0)
+    net = np.abs((mesh.V[:, None] * f).sum(0))
+    assert np.all(net <= 1e-13 * np.sum(mesh.V[:, None] * np.abs(f), axis=0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rigid_translation_exactly_zero(orc, dim):
+    mesh = jittered(orc, dim, 20 if dim == 2 else 9, seed=13)
+    u = np.tile(np.array([0.3, -0.7, 0.11][:dim]), (mesh.n, 1))
+    assert np.all(mesh.force(u, 3.0) == 0.0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_patch_affine_and_rotation(orc, dim):
+    N, m = (30, 3) if dim == 2 else (12, 3)
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * dim, h)
+    mesh = orc.Mesh(X, np.full(X.shape[0], h ** dim), m * h)
+    rng = np.random.Generator(np.random.PCG64(5))
+    A = 1e-3 * rng.standard_normal((dim, dim))
+    u = X @ A.T + 0.1
+    f = mesh.force(u, 1.0)
+    ij = inputs.lattice_index((N,) * dim)
+    inner = np.all((ij >= m) & (ij < N - m), axis=1)
+    # size of one node's bond terms: c |S| sum_j V_j with |S| ~ max|A|
+    scale = 1.0 * np.abs(A).max() * np.diff(mesh.row_ptr).max() * h ** dim
+    assert np.abs(f[inner]).max() < 1e-12 * scale
+    assert np.abs(f[~inner]).max() > 1e-3 * scale        # surface effect is real
+    W = 1e-3 * (rng.standard_normal((dim, dim)))
+    R = W - W.T                                           # infinitesimal rotation
+    fr = mesh.force(X @ R.T, 1.0)
+    assert np.abs(fr).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_force_is_minus_energy_gradient(orc, dim):
+    """-dPi/du_i = V_i f_i with Pi = sum V_i U_i; Pi is quadratic for the
+    linearised law, so the central difference is exact up to rounding."""
+    mesh = jittered(orc, dim, 16 if dim == 2 else 8, seed=21)
+    u = inputs.random_field(mesh.n, dim, 22)
+    w = inputs.random_field(mesh.n, dim, 23, scale=1.0)
+    c = 1.7
+    eps = 1e-4
+    dpi = (mesh.potential(u + eps * w, c) - mesh.potential(u - eps * w, c)) / (2 * eps)
+    f = mesh.force(u, c)
+    rhs = -np.sum(mesh.V[:, None] * f * w)
+    assert abs(dpi - rhs) <= 1e-7 * abs(rhs)
+
+
+def test_damage_breaks_only_in_tension_and_symmetrically(orc):
+    mesh = jittered(orc, 2, 20, seed=31)
+    u = inputs.random_field(mesh.n, 2, 32, scale=3e-3)
+    alive = mesh.all_alive()
+    s_c = 0.05
+    f = mesh.force(u, 1.0, s_c, alive)
+    # recompute S per bond with numpy: broken <=> S > s_c
+    i = np.repeat(np.arange(mesh.n), np.diff(mesh.row_ptr))
+    j = mesh.col
+    xi = mesh.X[j] - mesh.X[i]
+    eta = u[j] - u[i]
+    S = np.sum(eta * xi, 1) / np.sum(xi * xi, 1)
+    far = np.abs(S / s_c - 1) > 1e-9
+    assert np.array_equal((alive == 0)[far], (S > s_c)[far])
+    assert 0 < np.count_nonzero(alive == 0) < alive.size
+    # symmetric flags
+    key = dict(zip(zip(i.tolist(), j.tolist()), alive.tolist()))
+    assert all(key[(b, a)] == v for (a, b), v in key.items())
+    # broken bonds carry no force: same result as a force evaluation with
+    # those bonds already dead and no damage test
+    f2 = mesh.force(u, 1.0, 0.0, alive.copy())
+    assert np.array_equal(f, f2)
+    # irreversible: returning to u = 0 does not heal
+    before = alive.copy()
+    mesh.force(np.zeros_like(u), 1.0, s_c, alive)
+    assert np.array_equal(alive, before)
+
+
+def test_micromodulus_in_paper_form(orc):
+    """c = 4 psi'(0)/(delta |B_delta(0)|) (Algorithm 1) with psi'(0) = 9E/4 in
+    2-d (|B| = pi delta^2) and psi'(0) = 4E in 3-d (|B| = 4/3 pi delta^3); the
+    values of psi'(0) come from the energy calibration pinned above."""
+    d, E = 0.1, 1.3
+    assert np.isclose(orc.micromodulus(2, E, d), 4 * (9 * E / 4) / (d * np.pi * d ** 2), rtol=1e-14)
+    assert np.isclose(orc.micromodulus(3, E, d), 4 * (4 * E) / (d * 4 / 3 * np.pi * d ** 3),
+                      rtol=1e-14)
