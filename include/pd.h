@@ -1,0 +1,272 @@
+/*
+ * pd.h -- C ABI of the MI355X (gfx950) peridynamics hot-path library.
+ *
+ * The library computes the bond-based peridynamic model of Diehl, Jha,
+ * Kaiser, Lipton and Levesque (arXiv:1806.06917):
+ *   - discrete horizon B_delta(X_i) = {X_j : |X_j - X_i| <= delta}
+ *     (Section "Discretization of peridynamics equations");
+ *   - internal force density of the linearised bond law (Algorithm 1 with
+ *     influence function J = 1 and psi' = psi'(0), the "LP" model of the
+ *     2-d explicit validation): f_i = sum_j mu_ij c S_ij (xi/|xi|) V_j,
+ *     S_ij = (u_j - u_i).xi/|xi|^2, xi = X_j - X_i,
+ *     c = 4 psi'(0)/(delta |B_delta(0)|);
+ *   - critical-stretch bond damage (the PMB model named with Algorithm 1):
+ *     mu_ij drops to 0, irreversibly, at the first force evaluation with
+ *     S_ij > s_c;
+ *   - velocity-Verlet time stepping (Section "Explicit time integration");
+ *   - the tangent operator of the quasi-static problem applied matrix-free,
+ *     and its solution by conjugate gradients (Section "Implicit time
+ *     integration").
+ *
+ * Conventions for every entry point:
+ *   - Return value: PD_OK (0) or a negative PD_E* status.  Nothing throws
+ *     across the ABI.  A message for the last failure on a context is
+ *     available from pd_last_error(ctx) (per context; not thread-safe for
+ *     concurrent callers on one context).
+ *   - Arguments are validated before any launch; on a validation error no
+ *     output is touched.
+ *   - "device" pointers are GPU memory of the context's device (for example
+ *     the data_ptr() of torch tensors), "host" pointers are CPU memory.
+ *     The caller owns every pointer it passes; the library owns its handles
+ *     and everything inside them and frees them in the *_destroy calls.
+ *   - Nodal arrays are dense row-major [n][dim] float64 (x, y[, z]) in the
+ *     caller's node numbering ("original order").  Bond arrays (alive flags)
+ *     are in the "exported bond order": rows by ascending node id, within a
+ *     row by ascending neighbour id, exactly the CSR that pd_nbr_export
+ *     returns.  The library's internal space-filling-curve order is never
+ *     exposed.
+ *   - All work is enqueued on the context's stream in order.  Calls return
+ *     before the GPU finishes except pd_build_neighbors, pd_nbr_info,
+ *     pd_nbr_export, pd_sim_get and pd_solve_implicit, which synchronise the
+ *     stream.  Handles built on one context must only be used with it.
+ *   - A pd_nbr must outlive every pd_sim created from it.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PD_OK = 0,
+    PD_EINVAL = -1,      /* invalid argument (shape, value, null pointer, coincident nodes) */
+    PD_ENOMEM = -2,      /* device allocation failed */
+    PD_EDEVICE = -3,     /* HIP runtime or kernel error; the context stays failed */
+    PD_ENOCONV = -4,     /* iterative solve reached its limit; info and u hold the last iterate */
+    PD_ENONFINITE = -5,  /* a non-finite displacement or velocity was produced */
+    PD_ECAPACITY = -6    /* problem exceeds a documented size limit */
+};
+
+enum { PD_FP64 = 0, PD_MIXED = 1 };
+
+enum { PD_BC_FREE = 0, PD_BC_CLAMPED = 1, PD_BC_VELOCITY = 2 };
+
+typedef struct pd_ctx_s *pd_ctx;
+typedef struct pd_nbr_s *pd_nbr;
+typedef struct pd_sim_s *pd_sim;
+
+/*
+ * Material and arithmetic of one model.
+ *   dim        2 or 3
+ *   precision  PD_FP64: every bond computed in float64.
+ *              PD_MIXED: bond vectors xi = X_j - X_i and eta = u_j - u_i are
+ *              formed in float64, then the bond strain, the damage test and
+ *              the bond force are computed in float32 and each node's sum is
+ *              accumulated with compensated (two-sum) float32 arithmetic.
+ *              Positions, velocities and the time integration stay float64.
+ *   c          micromodulus c = 4 psi'(0)/(delta |B_delta(0)|) (Algorithm 1);
+ *              see pd_micromodulus.
+ *   rho        mass density (velocity-Verlet equations), > 0
+ *   s_c        critical stretch; <= 0 disables damage
+ */
+typedef struct {
+    int dim;
+    int precision;
+    double c;
+    double rho;
+    double s_c;
+} pd_material;
+
+typedef struct {
+    int outer_iters;      /* Newton / iterative-refinement steps taken */
+    int inner_iters;      /* total conjugate-gradient iterations */
+    double rel_residual;  /* ||V (f(u) + b)||_2 / ||V b||_2 over free nodes, in float64 */
+} pd_solve_info;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int pd_version(void);
+
+/* Static text for a status code. */
+const char *pd_status_string(int status);
+
+/*
+ * Micromodulus of the linearised bond law, c = 4 psi'(0)/(delta |B_delta|)
+ * (Algorithm 1), calibrated so that under a uniform isotropic strain the
+ * peridynamic strain-energy density equals the classical one with the
+ * Poisson ratio fixed by the bond-based model (Section "Peridynamics
+ * theory"): 2-d plane stress nu = 1/3 gives c = 9E/(pi delta^3); 3-d
+ * nu = 1/4 gives c = 12E/(pi delta^4).  Host only; returns NaN for
+ * dim not in {2, 3}.
+ */
+double pd_micromodulus(int dim, double E, double delta);
+
+/*
+ * Create a context on HIP device `device`.  `hip_stream` is a borrowed
+ * hipStream_t (NULL = the null stream); it must outlive the context.
+ * Returns PD_EDEVICE when no such device exists.
+ */
+int pd_ctx_create(int device, void *hip_stream, pd_ctx *out);
+int pd_ctx_destroy(pd_ctx ctx);
+const char *pd_last_error(pd_ctx ctx);
+
+/*
+ * Tuning: lanes of a wavefront that share one node's bond sum (1, 2, 4, 8,
+ * 16, 32 or 64); 0 restores the automatic choice from the mean row length.
+ * The per-node summation order, and hence the float rounding, depends on
+ * this value only.
+ */
+int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
+
+/*
+ * Build the neighbour lists B_delta(X_i) (Section "Discretization of
+ * peridynamics equations") in the reference configuration, once.
+ *   X      device, [n][dim] float64 reference coordinates
+ *   delta  horizon, finite and > 0
+ * Membership: j != i and d2 <= (delta*delta)*(1 + 1e-10), where
+ * d2 = (dx*dx + dy*dy) + dz*dz with dx = X_j.x - X_i.x etc., each operation
+ * separately rounded (no fused multiply-add), so the closed ball keeps the
+ * lattice neighbours that sit exactly at distance delta.
+ * Errors: PD_EINVAL for dim not in {2,3}, n <= 0, bad delta, non-finite X or
+ * two coincident nodes; PD_ECAPACITY for more than 2^32 - 1 bonds, n >= 2^31
+ * or a bounding box needing more than 2^27 bins of edge delta.
+ * Synchronises the stream.
+ */
+int pd_build_neighbors(pd_ctx ctx, int dim, int64_t n, const double *X, double delta,
+                       pd_nbr *out);
+
+/* nnz = number of directed bonds; max_row = longest row.  Either may be NULL. */
+int pd_nbr_info(pd_nbr nbr, int64_t *nnz, int32_t *max_row);
+
+/*
+ * Copy the neighbour lists to the host in original numbering: row_ptr
+ * (host, int64[n+1]) and col (host, int32[nnz]), rows ascending by node id,
+ * neighbours ascending by id.  Either pointer may be NULL.
+ */
+int pd_nbr_export(pd_nbr nbr, int64_t *row_ptr, int32_t *col);
+
+/* Host int32[n]: perm[k] = original id of the k-th node in the library's
+ * internal space-filling-curve order (for diagnostics). */
+int pd_nbr_permutation(pd_nbr nbr, int32_t *perm);
+
+int pd_nbr_destroy(pd_nbr nbr);
+
+/*
+ * One evaluation of the internal force density (Algorithm 1, linearised law)
+ * at displacement u:
+ *   X, V, u  device float64, [n][dim], [n], [n][dim]; X must be the array the
+ *            neighbour lists were built from.
+ *   alive    device uint8[nnz] in exported bond order, in/out, or NULL.
+ *            NULL: every bond intact and no damage test.  Otherwise dead
+ *            bonds (0) are skipped and, if mat->s_c > 0, every live bond with
+ *            S > s_c is set to 0 before it contributes.
+ *   f        device float64 [n][dim] output
+ *   U        device float64 [n] output strain-energy density
+ *            U_i = sum_j mu_ij (c/4) S_ij^2 |xi| V_j (Algorithm 1 with the
+ *            linearised potential), or NULL.
+ * Asynchronous.
+ */
+int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                      const double *V, const double *u, uint8_t *alive, double *f, double *U);
+
+/*
+ * Create a resident explicit simulation (state kept on the GPU in internal
+ * order).  Arrays are copied; the caller may free them afterwards.
+ *   X, V        device reference coordinates and volumes (as for the nbr)
+ *   u0, v0      device [n][dim] initial displacement and velocity (NULL = 0)
+ *   bc_kind     device uint8[n]: PD_BC_FREE, PD_BC_CLAMPED (u = v = 0) or
+ *               PD_BC_VELOCITY (prescribed velocity), NULL = all free
+ *   bc_vel      device [n][dim] prescribed velocity of PD_BC_VELOCITY nodes
+ *               (required when any such node exists)
+ *   b           device [n][dim] body force density (constant in time), NULL = 0
+ *   notch       host float64 [nseg][4] segments (ax, ay, bx, by), dim 2 only:
+ *               a bond whose closed segment [X_i, X_j] meets a notch segment
+ *               starts broken (orientation tests in float64 without fused
+ *               multiply-add, end points taken in lexicographic order).
+ *   ramp_steps  prescribed velocities are scaled by min(1, t/(ramp_steps dt));
+ *               0 = no ramp.
+ * The first force evaluation (and damage test) happens at the first step.
+ */
+int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                  const double *V, const double *u0, const double *v0, const uint8_t *bc_kind,
+                  const double *bc_vel, const double *b, const double *notch, int nseg,
+                  int64_t ramp_steps, pd_sim *out);
+
+/*
+ * Advance a simulation by nsteps velocity-Verlet steps of size dt (velocity
+ * Verlet equations, boundary data at t^{k+1}):
+ *   v^{k+1/2} = v^k + (dt/2) (f^k + b)/rho,  u^{k+1} = u^k + dt v^{k+1/2},
+ *   v^{k+1} = v^{k+1/2} + (dt/2) (f^{k+1} + b)/rho,
+ * with the damage test at every force evaluation.  Clamped nodes keep
+ * u = v = 0; prescribed-velocity nodes take v^{k+1/2} = r(k+1/2) vbar,
+ * u^{k+1} = u^k + dt v^{k+1/2}, v^{k+1} = r(k+1) vbar, r(s) =
+ * min(1, s/ramp_steps).  One fused kernel per step (force + damage +
+ * half-kicks + drift + boundary data); the force at the final state is
+ * evaluated lazily by pd_sim_get.  Asynchronous.
+ */
+int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt);
+
+/*
+ * Read the state back (each output may be NULL): u, v device [n][dim],
+ * alive device uint8[nnz] (exported order), ke_pe host double[2] =
+ * {sum_i rho V_i |v_i|^2 / 2, sum_i V_i U_i}, step host int64.
+ * Returns PD_ENONFINITE (outputs still written) if u or v is not finite.
+ * Synchronises the stream.
+ */
+int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, double *ke_pe, int64_t *step);
+
+/* Overwrite the state (checkpoint restore); NULL leaves that part as is. */
+int pd_sim_set(pd_sim sim, const double *u, const double *v, const uint8_t *alive, int64_t step);
+
+int pd_sim_destroy(pd_sim sim);
+
+/*
+ * Matrix-free tangent operator of the quasi-static problem, y = H w with
+ * H = -V (x) df/du (the paper's tangent equation; exact for the linearised
+ * law):
+ *   y_i = -V_i sum_j mu_ij c ((w_j - w_i).xi/|xi|^2) (xi/|xi|) V_j  (free i)
+ *   y_i = w_i                                                       (fixed i)
+ * with w_j read as 0 at fixed nodes.  fixed: device uint8[n] (NULL = none),
+ * alive: device uint8[nnz] exported order (NULL = all intact).  w, y device
+ * [n][dim] float64.  mat->precision selects float64 or float32 bond
+ * arithmetic (float64 differences, float64 sums).  Asynchronous.
+ */
+int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                     const double *V, const uint8_t *alive, const uint8_t *fixed,
+                     const double *w, double *y);
+
+/*
+ * Quasi-static solve (implicit scheme of the paper, one load step): find u
+ * with u = given values on fixed nodes and f(u) + b = 0 on free nodes, by
+ * Newton steps H du = V (f(u) + b) solved with conjugate gradients.
+ *   precision PD_FP64: float64 CG.  PD_MIXED: float32 inner CG (float32
+ *   tangent, float64 dot products) inside float64 iterative refinement.
+ *   u      device [n][dim], in: initial guess holding the fixed values,
+ *          out: solution (or last iterate)
+ *   b      device [n][dim] body force density
+ *   rtol   target ||V (f(u)+b)|| / ||V b|| over free nodes (e.g. 1e-10)
+ *   maxit  limit on the total number of CG iterations
+ * Returns PD_ENOCONV with info filled when the target is not reached.
+ * Synchronises the stream.
+ */
+int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                      const double *V, const uint8_t *alive, const uint8_t *fixed,
+                      const double *b, double *u, double rtol, int maxit, pd_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PD_H */

@@ -1,0 +1,679 @@
+// Bond-force gather (Algorithm 1, linearised law, J = 1) with the fused
+// critical-stretch damage test, and the velocity-Verlet step built on it
+// (Section "Explicit time integration").
+//
+// One group of L lanes (L | 64, so a group never straddles a wavefront)
+// owns one node i in sfc order.  Lane l walks bonds row_ptr[i] + l,
+// + l + L, ... : the column and flag streams are read contiguously by the
+// group, the neighbour records XV[j], u[j] are gathered (neighbours of
+// consecutive sfc nodes overlap, so these mostly hit L2).  The L partial sums
+// are combined by an xor butterfly, so the order of the per-node sum depends
+// only on L and on the row, never on the rest of the mesh.  Lane 0 then
+// applies the node update selected by `mode`; the kernel boundary is the
+// global synchronisation between the drift of one step and the gather of the
+// next (the displacement is double-buffered).
+//
+// FP64 mode: every bond operation in float64.  Mixed mode: xi and eta are
+// formed in float64 (differences of nearby float64 values keep their
+// accuracy), rounded to float32; strain, damage test and bond force run in
+// float32 and each lane accumulates with Knuth's two-sum, carrying the
+// rounding error in a second float32, through the butterfly as well.
+#include <cmath>
+
+#include "pd_internal.hpp"
+
+namespace {
+
+enum Mode { M_FORCE = 0, M_STEP_FIRST = 1, M_STEP_CONT = 2, M_CLOSE = 3, M_ENERGY = 4, M_TANGENT = 5 };
+
+struct NodeArgs {
+    const double *__restrict__ xv;     // [n][4]
+    const double *__restrict__ u;      // [n][US]
+    double *__restrict__ u_out;        // [n][US]
+    double *__restrict__ v;            // [n][US]
+    const uint32_t *__restrict__ row_ptr;
+    const int32_t *__restrict__ col;
+    uint8_t *__restrict__ alive;       // NULL: all intact, no damage
+    const uint8_t *__restrict__ bc;    // NULL: all free (tangent mode: fixed flags)
+    const double *__restrict__ bc_vel; // [n][US]
+    const double *__restrict__ b;      // [n][US] or NULL
+    double *__restrict__ f_out;        // [n][US] force (M_FORCE) or y (M_TANGENT)
+    double *__restrict__ e_out;        // M_FORCE: U_i; M_ENERGY: {V_i U_i, KE_i} pairs
+    int *__restrict__ flag;            // non-finite report
+    const int *__restrict__ done;      // if set and *done != 0 the launch is a no-op
+    uint32_t n;
+    int mode;
+    int damage;
+    double c, s_c, rho, dt, r_half, r_full;
+    float c32, s_c32;
+};
+
+template <int DIM>
+struct US_ {
+    static constexpr int value = DIM == 3 ? 4 : 2;
+};
+
+struct Acc64 {
+    double x = 0, y = 0, z = 0, e = 0;
+};
+
+struct Acc32 {
+    float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0, e = 0;
+};
+
+// s + a = s' + err exactly (Knuth two-sum); err accumulates into c
+__device__ __forceinline__ void two_sum_acc(float &s, float &c, float a) {
+#pragma clang fp contract(off)
+    const float t = s + a;
+    const float z = t - s;
+    const float err = (s - (t - z)) + (a - z);
+    s = t;
+    c = c + err;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m, int w) { return __shfl_xor(v, m, w); }
+__device__ __forceinline__ float shfl_xor_f(float v, int m, int w) { return __shfl_xor(v, m, w); }
+
+template <int DIM>
+__device__ __forceinline__ void load_vec(const double *p, uint32_t i, double &x, double &y,
+                                         double &z) {
+    if (DIM == 3) {
+        const double4 q = reinterpret_cast<const double4 *>(p)[i];
+        x = q.x; y = q.y; z = q.z;
+    } else {
+        const double2 q = reinterpret_cast<const double2 *>(p)[i];
+        x = q.x; y = q.y; z = 0.0;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void store_vec(double *p, uint32_t i, double x, double y, double z) {
+    if (DIM == 3) reinterpret_cast<double4 *>(p)[i] = make_double4(x, y, z, 0.0);
+    else reinterpret_cast<double2 *>(p)[i] = make_double2(x, y);
+}
+
+template <int DIM, int L, bool MIXED>
+__global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
+    if (a.done && *a.done) return;
+    const uint32_t tile = pd_xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t gid = tile * PD_BLOCK + threadIdx.x;
+    const uint32_t i = gid / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool valid = i < a.n;
+    const bool tangent = a.mode == M_TANGENT;
+    const bool want_e = a.mode == M_ENERGY || (a.mode == M_FORCE && a.e_out);
+
+    double xix = 0, xiy = 0, xiz = 0, Vi = 0, uix = 0, uiy = 0, uiz = 0;
+    Acc64 s64;
+    Acc32 s32;
+    bool fixed_i = false;
+    if (valid) {
+        const double4 q = reinterpret_cast<const double4 *>(a.xv)[i];
+        xix = q.x; xiy = q.y;
+        if (DIM == 3) { xiz = q.z; Vi = q.w; } else { Vi = q.z; }
+        load_vec<DIM>(a.u, i, uix, uiy, uiz);
+        if (tangent && a.bc) fixed_i = a.bc[i] != 0;
+        if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
+        const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+        for (uint32_t p = rs + lane; p < re; p += L) {
+            if (a.alive && !a.alive[p]) continue;
+            const uint32_t j = (uint32_t)a.col[p];
+            const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+            double ujx, ujy, ujz;
+            load_vec<DIM>(a.u, j, ujx, ujy, ujz);
+            if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
+            const double Vj = DIM == 3 ? xj.w : xj.z;
+            const double dxx = xj.x - xix, dxy = xj.y - xiy, dxz = DIM == 3 ? xj.z - xiz : 0.0;
+            const double dux = ujx - uix, duy = ujy - uiy, duz = DIM == 3 ? ujz - uiz : 0.0;
+            if (!MIXED) {
+                const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
+                const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+                const double inv = rsqrt(r2);
+                const double S = ex * (inv * inv);
+                if (a.damage && S > a.s_c) {
+                    a.alive[p] = 0;
+                    continue;
+                }
+                const double g = a.c * S * Vj * inv;
+                s64.x += g * dxx;
+                s64.y += g * dxy;
+                if (DIM == 3) s64.z += g * dxz;
+                if (want_e) s64.e += 0.25 * a.c * S * S * (r2 * inv) * Vj;
+            } else {
+                const float fx = (float)dxx, fy = (float)dxy, fz = (float)dxz;
+                const float ux = (float)dux, uy = (float)duy, uz = (float)duz;
+                const float r2 = DIM == 3 ? fx * fx + fy * fy + fz * fz : fx * fx + fy * fy;
+                const float ex = DIM == 3 ? ux * fx + uy * fy + uz * fz : ux * fx + uy * fy;
+                const float inv = rsqrtf(r2);
+                const float S = ex * (inv * inv);
+                if (a.damage && S > a.s_c32) {
+                    a.alive[p] = 0;
+                    continue;
+                }
+                const float g = a.c32 * S * (float)Vj * inv;
+                two_sum_acc(s32.x, s32.cx, g * fx);
+                two_sum_acc(s32.y, s32.cy, g * fy);
+                if (DIM == 3) two_sum_acc(s32.z, s32.cz, g * fz);
+                if (want_e) s32.e += 0.25f * a.c32 * S * S * (r2 * inv) * (float)Vj;
+            }
+        }
+    }
+
+    double fx, fy, fz, Ue;
+    if (!MIXED) {
+#pragma unroll
+        for (int m = L / 2; m > 0; m >>= 1) {
+            s64.x += shfl_xor_d(s64.x, m, L);
+            s64.y += shfl_xor_d(s64.y, m, L);
+            if (DIM == 3) s64.z += shfl_xor_d(s64.z, m, L);
+            if (want_e) s64.e += shfl_xor_d(s64.e, m, L);
+        }
+        fx = s64.x; fy = s64.y; fz = s64.z; Ue = s64.e;
+    } else {
+#pragma unroll
+        for (int m = L / 2; m > 0; m >>= 1) {
+            const float ox = shfl_xor_f(s32.x, m, L), ocx = shfl_xor_f(s32.cx, m, L);
+            const float oy = shfl_xor_f(s32.y, m, L), ocy = shfl_xor_f(s32.cy, m, L);
+            two_sum_acc(s32.x, s32.cx, ox);
+            s32.cx += ocx;
+            two_sum_acc(s32.y, s32.cy, oy);
+            s32.cy += ocy;
+            if (DIM == 3) {
+                const float oz = shfl_xor_f(s32.z, m, L), ocz = shfl_xor_f(s32.cz, m, L);
+                two_sum_acc(s32.z, s32.cz, oz);
+                s32.cz += ocz;
+            }
+            if (want_e) s32.e += shfl_xor_f(s32.e, m, L);
+        }
+        fx = (double)s32.x + (double)s32.cx;
+        fy = (double)s32.y + (double)s32.cy;
+        fz = (double)s32.z + (double)s32.cz;
+        Ue = (double)s32.e;
+    }
+    if (!valid || lane != 0) return;
+
+    switch (a.mode) {
+    case M_FORCE:
+        store_vec<DIM>(a.f_out, i, fx, fy, fz);
+        if (a.e_out) a.e_out[i] = Ue;
+        return;
+    case M_TANGENT: {
+        if (fixed_i) {
+            double wx, wy, wz;
+            load_vec<DIM>(a.u, i, wx, wy, wz);
+            store_vec<DIM>(a.f_out, i, wx, wy, wz);
+        } else {
+            store_vec<DIM>(a.f_out, i, -Vi * fx, -Vi * fy, -Vi * fz);
+        }
+        return;
+    }
+    case M_ENERGY: {
+        double vx, vy, vz;
+        load_vec<DIM>(a.v, i, vx, vy, vz);
+        const double vv = DIM == 3 ? vx * vx + vy * vy + vz * vz : vx * vx + vy * vy;
+        a.e_out[2 * (size_t)i] = 0.5 * a.rho * Vi * vv;
+        a.e_out[2 * (size_t)i + 1] = Vi * Ue;
+        return;
+    }
+    default: break;
+    }
+
+    // time integration (lane 0 of the group)
+    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
+    double vx, vy, vz;
+    load_vec<DIM>(a.v, i, vx, vy, vz);
+    const double hdt = 0.5 * a.dt;
+    if (a.mode == M_CLOSE) {
+        if (kind == PD_BC_FREE) {
+            double bx = 0, by = 0, bz = 0;
+            if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
+            vx = vx + hdt * (fx + bx) / a.rho;
+            vy = vy + hdt * (fy + by) / a.rho;
+            vz = vz + hdt * (fz + bz) / a.rho;
+        } else if (kind == PD_BC_CLAMPED) {
+            vx = vy = vz = 0.0;
+        } else {
+            double wx, wy, wz;
+            load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
+            vx = a.r_full * wx; vy = a.r_full * wy; vz = a.r_full * wz;
+        }
+        store_vec<DIM>(a.v, i, vx, vy, vz);
+        const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(uix) &&
+                         isfinite(uiy) && isfinite(uiz);
+        if (!fin) atomicOr(a.flag, 1);
+        return;
+    }
+    double nx, ny, nz;
+    if (kind == PD_BC_FREE) {
+        double bx = 0, by = 0, bz = 0;
+        if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
+        if (a.mode == M_STEP_CONT) {   // second half-kick of the previous step
+            vx = vx + hdt * (fx + bx) / a.rho;
+            vy = vy + hdt * (fy + by) / a.rho;
+            vz = vz + hdt * (fz + bz) / a.rho;
+        }
+        vx = vx + hdt * (fx + bx) / a.rho;   // first half-kick of this step
+        vy = vy + hdt * (fy + by) / a.rho;
+        vz = vz + hdt * (fz + bz) / a.rho;
+        nx = uix + a.dt * vx;
+        ny = uiy + a.dt * vy;
+        nz = uiz + a.dt * vz;
+    } else if (kind == PD_BC_CLAMPED) {
+        vx = vy = vz = 0.0;
+        nx = ny = nz = 0.0;
+    } else {
+        double wx, wy, wz;
+        load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
+        vx = a.r_half * wx; vy = a.r_half * wy; vz = a.r_half * wz;
+        nx = uix + a.dt * vx;
+        ny = uiy + a.dt * vy;
+        nz = uiz + a.dt * vz;
+    }
+    store_vec<DIM>(a.v, i, vx, vy, vz);
+    store_vec<DIM>(a.u_out, i, nx, ny, nz);
+}
+
+// notch pre-crack: orientation tests in float64 without contraction, end
+// points of the bond in lexicographic order so (i,j) and (j,i) agree
+__device__ __forceinline__ double orient(double ax, double ay, double bx, double by, double cx,
+                                         double cy) {
+#pragma clang fp contract(off)
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+__device__ __forceinline__ int sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+__device__ bool segments_meet(double px, double py, double qx, double qy, double ax, double ay,
+                              double bx, double by) {
+    if (qx < px || (qx == px && qy < py)) {
+        double t = px; px = qx; qx = t;
+        t = py; py = qy; qy = t;
+    }
+    const int o1 = sgn(orient(ax, ay, bx, by, px, py));
+    const int o2 = sgn(orient(ax, ay, bx, by, qx, qy));
+    const int o3 = sgn(orient(px, py, qx, qy, ax, ay));
+    const int o4 = sgn(orient(px, py, qx, qy, bx, by));
+    if (o1 == 0 && o2 == 0 && o3 == 0 && o4 == 0)
+        return fmax(fmin(px, qx), fmin(ax, bx)) <= fmin(fmax(px, qx), fmax(ax, bx)) &&
+               fmax(fmin(py, qy), fmin(ay, by)) <= fmin(fmax(py, qy), fmax(ay, by));
+    return o1 * o2 <= 0 && o3 * o4 <= 0;
+}
+
+struct NotchSegs {
+    double s[8][4];
+};
+
+__global__ void notch_k(uint32_t n, const double *xv, const uint32_t *row_ptr, const int32_t *col,
+                        int nseg, NotchSegs segs, uint8_t *alive) {
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const uint32_t lane = threadIdx.x % 64;
+    if (i >= n) return;
+    const double4 P = reinterpret_cast<const double4 *>(xv)[i];
+    for (uint32_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += 64) {
+        const double4 Q = reinterpret_cast<const double4 *>(xv)[col[p]];
+        for (int s = 0; s < nseg; ++s)
+            if (segments_meet(P.x, P.y, Q.x, Q.y, segs.s[s][0], segs.s[s][1], segs.s[s][2],
+                              segs.s[s][3]))
+                alive[p] = 0;
+    }
+}
+
+template <int DIM, int L>
+int launch_t(pd_ctx ctx, const NodeArgs &a, bool mixed) {
+    const unsigned grid = pd_blocks((uint64_t)a.n * L);
+    if (grid == 0) return PD_OK;
+    if (mixed) node_kernel<DIM, L, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    else node_kernel<DIM, L, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+template <int DIM>
+int launch_d(pd_ctx ctx, const NodeArgs &a, int lanes, bool mixed) {
+    switch (lanes) {
+    case 1: return launch_t<DIM, 1>(ctx, a, mixed);
+    case 2: return launch_t<DIM, 2>(ctx, a, mixed);
+    case 4: return launch_t<DIM, 4>(ctx, a, mixed);
+    case 8: return launch_t<DIM, 8>(ctx, a, mixed);
+    case 16: return launch_t<DIM, 16>(ctx, a, mixed);
+    case 32: return launch_t<DIM, 32>(ctx, a, mixed);
+    case 64: return launch_t<DIM, 64>(ctx, a, mixed);
+    default: return pd_set_error(ctx, PD_EINVAL, "unsupported lane count %d", lanes);
+    }
+}
+
+int launch_node(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mixed) {
+    return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed) : launch_d<2>(ctx, a, lanes, mixed);
+}
+
+int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
+    if (!mat) return pd_set_error(ctx, PD_EINVAL, "material must not be NULL");
+    if (mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "material dim != neighbour dim");
+    if (mat->precision != PD_FP64 && mat->precision != PD_MIXED)
+        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
+    if (!std::isfinite(mat->c) || !std::isfinite(mat->s_c))
+        return pd_set_error(ctx, PD_EINVAL, "c and s_c must be finite");
+    return PD_OK;
+}
+
+NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
+    NodeArgs a{};
+    a.row_ptr = nbr->row_ptr;
+    a.col = nbr->col;
+    a.n = nbr->n;
+    a.c = mat->c;
+    a.c32 = (float)mat->c;
+    a.s_c = mat->s_c;
+    a.s_c32 = (float)mat->s_c;
+    a.rho = mat->rho;
+    return a;
+}
+
+int ensure_scratch(pd_ctx ctx, pd_nbr nbr) {
+    const int us = nbr->dim == 3 ? 4 : 2;
+    if (!nbr->s_xv) PD_TRY(pd_alloc(ctx, &nbr->s_xv, (size_t)nbr->n * 4));
+    if (!nbr->s_u) PD_TRY(pd_alloc(ctx, &nbr->s_u, (size_t)nbr->n * us));
+    if (!nbr->s_f) PD_TRY(pd_alloc(ctx, &nbr->s_f, (size_t)nbr->n * us));
+    if (!nbr->s_U) PD_TRY(pd_alloc(ctx, &nbr->s_U, (size_t)nbr->n));
+    if (!nbr->s_alive) PD_TRY(pd_alloc(ctx, &nbr->s_alive, nbr->nnz));
+    if (!nbr->s_fixed) PD_TRY(pd_alloc(ctx, &nbr->s_fixed, (size_t)nbr->n));
+    return PD_OK;
+}
+
+double ramp_factor(double s, int64_t ramp) {
+    if (ramp <= 0) return 1.0;
+    const double r = s / (double)ramp;
+    return r < 1.0 ? r : 1.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// stateless force evaluation
+// ---------------------------------------------------------------------------
+extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                                 const double *V, const double *u, uint8_t *alive, double *f,
+                                 double *U) {
+    if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    PD_TRY(pd_check_ctx(ctx));
+    if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
+    PD_TRY(check_material(ctx, nbr, mat));
+    PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
+    PD_TRY(pd_check_dev_ptr(ctx, V, "V"));
+    PD_TRY(pd_check_dev_ptr(ctx, u, "u"));
+    PD_TRY(pd_check_dev_ptr(ctx, f, "f"));
+    if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
+    if (U) PD_TRY(pd_check_dev_ptr(ctx, U, "U"));
+    PD_TRY(ensure_scratch(ctx, nbr));
+    PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
+    PD_TRY(pd_gather_vec(ctx, nbr, u, nbr->s_u, false));
+    if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
+    NodeArgs a = base_args(nbr, mat);
+    a.xv = nbr->s_xv;
+    a.u = nbr->s_u;
+    a.alive = alive ? nbr->s_alive : nullptr;
+    a.damage = alive && mat->s_c > 0.0;
+    a.f_out = nbr->s_f;
+    a.e_out = U ? nbr->s_U : nullptr;
+    a.mode = M_FORCE;
+    PD_TRY(launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
+                       mat->precision == PD_MIXED));
+    PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, f));
+    if (U) PD_TRY(pd_scatter_scalar(ctx, nbr, nbr->s_U, U));
+    if (alive && a.damage) PD_TRY(pd_alive_out(ctx, nbr, nbr->s_alive, alive));
+    return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tangent operator (used by the implicit solver as well)
+// ---------------------------------------------------------------------------
+int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
+                   const uint8_t *alive_sfc, const uint8_t *fixed_sfc, const double *w,
+                   double *y, const int *done) {
+    NodeArgs a = base_args(nbr, mat);
+    a.done = done;
+    a.xv = xv;
+    a.u = w;
+    a.alive = const_cast<uint8_t *>(alive_sfc);
+    a.damage = 0;
+    a.bc = fixed_sfc;
+    a.f_out = y;
+    a.mode = M_TANGENT;
+    return launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
+                       mat->precision == PD_MIXED);
+}
+
+// internal force in sfc order, no damage: f = force(u) (implicit residuals)
+int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
+                 const uint8_t *alive_sfc, const double *u, double *f) {
+    NodeArgs a = base_args(nbr, mat);
+    a.xv = xv;
+    a.u = u;
+    a.alive = const_cast<uint8_t *>(alive_sfc);
+    a.damage = 0;
+    a.f_out = f;
+    a.mode = M_FORCE;
+    return launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false);
+}
+
+extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                                const double *V, const uint8_t *alive, const uint8_t *fixed,
+                                const double *w, double *y) {
+    if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    PD_TRY(pd_check_ctx(ctx));
+    if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
+    PD_TRY(check_material(ctx, nbr, mat));
+    PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
+    PD_TRY(pd_check_dev_ptr(ctx, V, "V"));
+    PD_TRY(pd_check_dev_ptr(ctx, w, "w"));
+    PD_TRY(pd_check_dev_ptr(ctx, y, "y"));
+    if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
+    if (fixed) PD_TRY(pd_check_dev_ptr(ctx, fixed, "fixed"));
+    PD_TRY(ensure_scratch(ctx, nbr));
+    PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
+    PD_TRY(pd_gather_vec(ctx, nbr, w, nbr->s_u, false));
+    if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
+    if (fixed) PD_TRY(pd_gather_u8(ctx, nbr, fixed, nbr->s_fixed, 0));
+    PD_TRY(pd_tangent_sfc(ctx, nbr, mat, nbr->s_xv, alive ? nbr->s_alive : nullptr,
+                          fixed ? nbr->s_fixed : nullptr, nbr->s_u, nbr->s_f, nullptr));
+    PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, y));
+    return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// resident explicit simulation
+// ---------------------------------------------------------------------------
+static void sim_release(pd_sim s) {
+    if (!s) return;
+    pd_free(s->xv);
+    pd_free(s->u[0]);
+    pd_free(s->u[1]);
+    pd_free(s->v);
+    pd_free(s->bc_vel);
+    pd_free(s->b);
+    pd_free(s->bc);
+    pd_free(s->alive);
+    pd_free(s->scratch);
+    delete s;
+}
+
+extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                             const double *V, const double *u0, const double *v0,
+                             const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                             const double *notch, int nseg, int64_t ramp_steps, pd_sim *out) {
+    if (!out) return pd_set_error(ctx, PD_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    PD_TRY(pd_check_ctx(ctx));
+    if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
+    PD_TRY(check_material(ctx, nbr, mat));
+    if (!(mat->rho > 0.0) || !std::isfinite(mat->rho))
+        return pd_set_error(ctx, PD_EINVAL, "rho must be finite and positive");
+    PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
+    PD_TRY(pd_check_dev_ptr(ctx, V, "V"));
+    if (u0) PD_TRY(pd_check_dev_ptr(ctx, u0, "u0"));
+    if (v0) PD_TRY(pd_check_dev_ptr(ctx, v0, "v0"));
+    if (bc_kind) PD_TRY(pd_check_dev_ptr(ctx, bc_kind, "bc_kind"));
+    if (bc_kind && !bc_vel)
+        return pd_set_error(ctx, PD_EINVAL, "bc_vel is required with bc_kind");
+    if (bc_vel) PD_TRY(pd_check_dev_ptr(ctx, bc_vel, "bc_vel"));
+    if (b) PD_TRY(pd_check_dev_ptr(ctx, b, "b"));
+    if (nseg < 0 || nseg > 8) return pd_set_error(ctx, PD_EINVAL, "nseg must be in [0, 8]");
+    if (nseg > 0 && (!notch || nbr->dim != 2))
+        return pd_set_error(ctx, PD_EINVAL, "notch segments need dim 2 and a host array");
+    if (ramp_steps < 0) return pd_set_error(ctx, PD_EINVAL, "ramp_steps must be >= 0");
+    NotchSegs segs{};
+    for (int s = 0; s < nseg; ++s)
+        for (int k = 0; k < 4; ++k) {
+            segs.s[s][k] = notch[4 * s + k];
+            if (!std::isfinite(segs.s[s][k]))
+                return pd_set_error(ctx, PD_EINVAL, "notch coordinates must be finite");
+        }
+
+    pd_sim s = new (std::nothrow) pd_sim_s();
+    if (!s) return PD_ENOMEM;
+    s->ctx = ctx;
+    s->nbr = nbr;
+    s->mat = *mat;
+    s->ramp = ramp_steps;
+    const size_t n = nbr->n, us = nbr->dim == 3 ? 4 : 2;
+    int st = PD_OK;
+    if (st == PD_OK) st = pd_alloc(ctx, &s->xv, n * 4);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->u[0], n * us);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->u[1], n * us);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->v, n * us);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->bc, n);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->alive, nbr->nnz);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->scratch, 2 * n);
+    if (st == PD_OK && bc_vel) st = pd_alloc(ctx, &s->bc_vel, n * us);
+    if (st == PD_OK && b) st = pd_alloc(ctx, &s->b, n * us);
+    if (st == PD_OK) st = pd_gather_xv(ctx, nbr, X, V, s->xv);
+    if (st == PD_OK) st = pd_gather_vec(ctx, nbr, u0, s->u[0], true);
+    if (st == PD_OK) st = pd_gather_vec(ctx, nbr, v0, s->v, true);
+    if (st == PD_OK) st = pd_gather_u8(ctx, nbr, bc_kind, s->bc, PD_BC_FREE);
+    if (st == PD_OK && bc_vel) st = pd_gather_vec(ctx, nbr, bc_vel, s->bc_vel, true);
+    if (st == PD_OK && b) st = pd_gather_vec(ctx, nbr, b, s->b, true);
+    if (st == PD_OK) st = pd_alive_in(ctx, nbr, nullptr, s->alive);
+    if (st == PD_OK && nseg > 0) {
+        notch_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, ctx->stream>>>(
+            nbr->n, s->xv, nbr->row_ptr, nbr->col, nseg, segs, s->alive);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = pd_hip_error(ctx, e, "notch_k", __FILE__, __LINE__);
+    }
+    if (st == PD_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) st = pd_hip_error(ctx, e, "sim_create", __FILE__, __LINE__);
+    }
+    if (st != PD_OK) {
+        sim_release(s);
+        return st;
+    }
+    s->lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    *out = s;
+    return PD_OK;
+}
+
+static NodeArgs sim_args(pd_sim s) {
+    NodeArgs a = base_args(s->nbr, &s->mat);
+    a.xv = s->xv;
+    a.v = s->v;
+    a.alive = s->alive;
+    a.damage = s->mat.s_c > 0.0;
+    a.bc = s->bc;
+    a.bc_vel = s->bc_vel;
+    a.b = s->b;
+    a.flag = s->ctx->flag;
+    return a;
+}
+
+extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
+    if (!sim) return PD_EINVAL;
+    pd_ctx ctx = sim->ctx;
+    PD_TRY(pd_check_ctx(ctx));
+    if (nsteps < 0) return pd_set_error(ctx, PD_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return pd_set_error(ctx, PD_EINVAL, "dt must be > 0");
+    if (sim->v_half && dt != sim->last_dt)
+        return pd_set_error(ctx, PD_EINVAL,
+                            "dt changed mid-trajectory: read the state (pd_sim_get) first");
+    NodeArgs a = sim_args(sim);
+    a.dt = dt;
+    const bool mixed = sim->mat.precision == PD_MIXED;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        a.mode = sim->v_half ? M_STEP_CONT : M_STEP_FIRST;
+        a.u = sim->u[sim->cur];
+        a.u_out = sim->u[sim->cur ^ 1];
+        a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
+        PD_TRY(launch_node(ctx, sim->nbr->dim, a, sim->lanes, mixed));
+        sim->cur ^= 1;
+        sim->v_half = true;
+        sim->step += 1;
+    }
+    sim->last_dt = dt;
+    return PD_OK;
+}
+
+// completes the last step: force at u^N with the damage test, second half-kick
+static int sim_close(pd_sim sim) {
+    if (!sim->v_half) return PD_OK;
+    NodeArgs a = sim_args(sim);
+    a.dt = sim->last_dt;
+    a.mode = M_CLOSE;
+    a.u = sim->u[sim->cur];
+    a.r_full = ramp_factor((double)sim->step, sim->ramp);
+    PD_TRY(launch_node(sim->ctx, sim->nbr->dim, a, sim->lanes, sim->mat.precision == PD_MIXED));
+    sim->v_half = false;
+    return PD_OK;
+}
+
+extern "C" int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, double *ke_pe,
+                          int64_t *step) {
+    if (!sim) return PD_EINVAL;
+    pd_ctx ctx = sim->ctx;
+    PD_TRY(pd_check_ctx(ctx));
+    if (u) PD_TRY(pd_check_dev_ptr(ctx, u, "u"));
+    if (v) PD_TRY(pd_check_dev_ptr(ctx, v, "v"));
+    if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
+    PD_TRY(pd_flag_clear(ctx));
+    PD_TRY(sim_close(sim));
+    if (u) PD_TRY(pd_scatter_vec(ctx, sim->nbr, sim->u[sim->cur], u));
+    if (v) PD_TRY(pd_scatter_vec(ctx, sim->nbr, sim->v, v));
+    if (alive) PD_TRY(pd_alive_out(ctx, sim->nbr, sim->alive, alive));
+    if (ke_pe) {
+        NodeArgs a = sim_args(sim);
+        a.mode = M_ENERGY;
+        a.damage = 0;
+        a.u = sim->u[sim->cur];
+        a.e_out = sim->scratch;
+        PD_TRY(launch_node(ctx, sim->nbr->dim, a, sim->lanes, false));
+        PD_TRY(pd_sum(ctx, sim->scratch, sim->nbr->n, 2, ke_pe));
+    }
+    if (step) *step = sim->step;
+    int flag = 0;
+    PD_TRY(pd_flag_read(ctx, &flag));
+    if (flag & 1) return pd_set_error(ctx, PD_ENONFINITE, "non-finite displacement or velocity");
+    return PD_OK;
+}
+
+extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const uint8_t *alive,
+                          int64_t step) {
+    if (!sim) return PD_EINVAL;
+    pd_ctx ctx = sim->ctx;
+    PD_TRY(pd_check_ctx(ctx));
+    if (u) PD_TRY(pd_check_dev_ptr(ctx, u, "u"));
+    if (v) PD_TRY(pd_check_dev_ptr(ctx, v, "v"));
+    if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
+    if (step < 0) return pd_set_error(ctx, PD_EINVAL, "step must be >= 0");
+    PD_TRY(sim_close(sim));
+    if (u) PD_TRY(pd_gather_vec(ctx, sim->nbr, u, sim->u[sim->cur], false));
+    if (v) PD_TRY(pd_gather_vec(ctx, sim->nbr, v, sim->v, false));
+    if (alive) PD_TRY(pd_alive_in(ctx, sim->nbr, alive, sim->alive));
+    sim->step = step;
+    return PD_OK;
+}
+
+extern "C" int pd_sim_destroy(pd_sim sim) {
+    if (!sim) return PD_EINVAL;
+    (void)hipSetDevice(sim->ctx->device);
+    (void)hipStreamSynchronize(sim->ctx->stream);
+    sim_release(sim);
+    return PD_OK;
+}

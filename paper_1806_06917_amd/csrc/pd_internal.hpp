@@ -1,0 +1,170 @@
+// Internal declarations of the gfx950 peridynamics library (not installed).
+//
+// Data layout in HBM (internal "sfc" order = nodes sorted along a Morton
+// space-filling curve of their horizon-sized bins, so that the neighbours of
+// consecutive nodes are close in memory):
+//   XV      double[n][4]   {x, y, z, V} (3-d) or {x, y, V, 0} (2-d), constant
+//   u, v    double[n][US]  US = 4 in 3-d ({x, y, z, 0}), 2 in 2-d
+//   row_ptr uint32[n+1], col int32[nnz] (sfc ids), rows ascending by the
+//           neighbour's ORIGINAL id, so that a row's bond k maps to exported
+//           position ex_row_ptr[perm[i]] + k without a per-bond table
+//   alive   uint8[nnz]     1 = intact
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "pd.h"
+
+#define PD_VERSION_NUMBER 10000
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct pd_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int lanes = 0;          // 0: automatic
+    int failed = 0;         // sticky device failure
+    std::string last_error;
+    double *red = nullptr;  // device partial sums, PD_RED_BLOCKS * PD_RED_SLOTS
+    double *red_host = nullptr;  // pinned mirror of red
+    int *flag = nullptr;    // device status word (non-finite, coincident ...)
+    int *flag_host = nullptr;
+};
+
+struct pd_nbr_s {
+    pd_ctx ctx = nullptr;
+    int dim = 0;
+    uint32_t n = 0;
+    uint64_t nnz = 0;
+    int32_t max_row = 0;
+    double delta = 0, thr = 0;
+    int32_t *perm = nullptr;     // sfc -> original
+    int32_t *iperm = nullptr;    // original -> sfc
+    uint32_t *row_ptr = nullptr; // [n+1] sfc order
+    int32_t *col = nullptr;      // [nnz] sfc ids
+    uint32_t *ex_row_ptr = nullptr;  // [n+1] original order
+    // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
+    double *s_xv = nullptr, *s_u = nullptr, *s_f = nullptr, *s_U = nullptr;
+    uint8_t *s_alive = nullptr, *s_fixed = nullptr;
+};
+
+struct pd_sim_s {
+    pd_ctx ctx = nullptr;
+    pd_nbr nbr = nullptr;
+    pd_material mat{};
+    double *xv = nullptr;
+    double *u[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *v = nullptr;
+    double *bc_vel = nullptr;
+    double *b = nullptr;
+    uint8_t *bc = nullptr;
+    uint8_t *alive = nullptr;
+    double *scratch = nullptr;   // [n] per-node energies for diagnostics
+    int64_t step = 0;
+    int64_t ramp = 0;
+    double last_dt = 0;
+    bool v_half = false;         // v holds v^{k-1/2} (force at u^k still to be applied)
+    int lanes = 0;
+};
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+int pd_set_error(pd_ctx ctx, int status, const char *fmt, ...);
+int pd_hip_error(pd_ctx ctx, hipError_t e, const char *what, const char *file, int line);
+
+#define PD_HIP(ctx, call)                                                   \
+    do {                                                                    \
+        hipError_t e__ = (call);                                            \
+        if (e__ != hipSuccess) return pd_hip_error((ctx), e__, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define PD_TRY(expr)                 \
+    do {                             \
+        int s__ = (expr);            \
+        if (s__ != PD_OK) return s__; \
+    } while (0)
+
+#define PD_LAUNCH_CHECK(ctx) PD_HIP(ctx, hipGetLastError())
+
+template <class T>
+int pd_alloc(pd_ctx ctx, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return pd_set_error(ctx, PD_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                            hipGetErrorString(e));
+    }
+    return PD_OK;
+}
+
+template <class T>
+void pd_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+int pd_check_ctx(pd_ctx ctx);
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+constexpr int PD_BLOCK = 256;
+constexpr int PD_RED_BLOCKS = 512;
+constexpr int PD_RED_SLOTS = 4;
+
+inline unsigned pd_blocks(uint64_t threads, int block = PD_BLOCK) {
+    return (unsigned)((threads + block - 1) / block);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip.  This
+// remaps the hardware block index so that each XCD receives one contiguous
+// range of tiles (neighbouring nodes share that XCD's L2).
+__device__ __forceinline__ uint32_t pd_xcd_tile(uint32_t b, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t q = nb / X, r = nb % X, x = b % X, l = b / X;
+    return x * q + (x < r ? x : r) + l;
+}
+
+int pd_auto_lanes(pd_ctx ctx, uint64_t nnz, uint32_t n);
+
+// ---------------------------------------------------------------------------
+// shared host helpers (implemented in pd_runtime.hip)
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 counts -> uint64 offsets (out has n+1 entries)
+int pd_scan_u32(pd_ctx ctx, const uint32_t *in, uint64_t *out, uint32_t n);
+// out[k] = (uint32) in[k]
+int pd_narrow_u64(pd_ctx ctx, const uint64_t *in, uint32_t *out, uint32_t n);
+// sfc-order copies of original-order nodal arrays, and back
+int pd_gather_xv(pd_ctx ctx, const pd_nbr nbr, const double *X, const double *V, double *xv);
+int pd_gather_vec(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst, bool zero_if_null);
+int pd_scatter_vec(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst);
+int pd_gather_u8(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst, uint8_t fill);
+int pd_scatter_scalar(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst);
+// bond flags: exported order <-> internal order (src NULL: all 1)
+int pd_alive_in(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst);
+int pd_alive_out(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst);
+// deterministic sums of `slots` interleaved per-node values: data[i*slots + s]
+int pd_sum(pd_ctx ctx, const double *data, uint32_t n, int slots, double *out);
+// device status word
+int pd_flag_clear(pd_ctx ctx);
+int pd_flag_read(pd_ctx ctx, int *value);
+// checks that a device pointer is accessible device memory of ctx's device
+int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name);
+
+// sfc-order building blocks of the implicit solver (pd_force.hip)
+int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
+                   const uint8_t *alive_sfc, const uint8_t *fixed_sfc, const double *w, double *y,
+                   const int *done);
+int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
+                 const uint8_t *alive_sfc, const double *u, double *f);

@@ -1,0 +1,416 @@
+// Context, error reporting and the small data-movement kernels shared by the
+// entry points: scans, sfc <-> original order permutations, bond-flag
+// reordering and deterministic reductions.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "pd_internal.hpp"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+int pd_set_error(pd_ctx ctx, int status, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+        if (status == PD_EDEVICE) ctx->failed = 1;
+    }
+    return status;
+}
+
+int pd_hip_error(pd_ctx ctx, hipError_t e, const char *what, const char *file, int line) {
+    (void)hipGetLastError();
+    return pd_set_error(ctx, PD_EDEVICE, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file,
+                        line);
+}
+
+int pd_check_ctx(pd_ctx ctx) {
+    if (!ctx) return PD_EINVAL;
+    if (ctx->failed) return PD_EDEVICE;
+    PD_HIP(ctx, hipSetDevice(ctx->device));
+    return PD_OK;
+}
+
+int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name) {
+    if (!p) return pd_set_error(ctx, PD_EINVAL, "%s must not be NULL", name);
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return pd_set_error(ctx, PD_EINVAL, "%s is not device memory", name);
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return pd_set_error(ctx, PD_EINVAL, "%s is not device memory", name);
+    if (attr.device != ctx->device)
+        return pd_set_error(ctx, PD_EINVAL, "%s lives on device %d, context on %d", name,
+                            attr.device, ctx->device);
+    return PD_OK;
+}
+
+int pd_auto_lanes(pd_ctx ctx, uint64_t nnz, uint32_t n) {
+    if (ctx && ctx->lanes > 0) return ctx->lanes;
+    const double k = n ? (double)nnz / (double)n : 0.0;
+    int L = 1;
+    while (L < 32 && L * 6 < k) L *= 2;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// public: version, status strings, micromodulus, context
+// ---------------------------------------------------------------------------
+extern "C" int pd_version(void) { return PD_VERSION_NUMBER; }
+
+extern "C" const char *pd_status_string(int s) {
+    switch (s) {
+    case PD_OK: return "ok";
+    case PD_EINVAL: return "invalid argument";
+    case PD_ENOMEM: return "out of device memory";
+    case PD_EDEVICE: return "device error";
+    case PD_ENOCONV: return "no convergence";
+    case PD_ENONFINITE: return "non-finite state";
+    case PD_ECAPACITY: return "size limit exceeded";
+    default: return "unknown status";
+    }
+}
+
+extern "C" double pd_micromodulus(int dim, double E, double delta) {
+    const double pi = 3.14159265358979323846;
+    if (dim == 2) return 9.0 * E / (pi * delta * delta * delta);
+    if (dim == 3) return 12.0 * E / (pi * delta * delta * delta * delta);
+    return NAN;
+}
+
+extern "C" int pd_ctx_create(int device, void *hip_stream, pd_ctx *out) {
+    if (!out) return PD_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return PD_EDEVICE;
+    }
+    if (device < 0 || device >= count) return PD_EINVAL;
+    pd_ctx c = new (std::nothrow) pd_ctx_s();
+    if (!c) return PD_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return PD_EDEVICE;
+    }
+    int st = pd_alloc(c, &c->red, (size_t)PD_RED_BLOCKS * PD_RED_SLOTS);
+    if (st == PD_OK) st = pd_alloc(c, &c->flag, 1);
+    if (st == PD_OK &&
+        hipHostMalloc((void **)&c->red_host, sizeof(double) * PD_RED_BLOCKS * PD_RED_SLOTS) !=
+            hipSuccess)
+        st = PD_ENOMEM;
+    if (st == PD_OK && hipHostMalloc((void **)&c->flag_host, sizeof(int)) != hipSuccess)
+        st = PD_ENOMEM;
+    if (st != PD_OK) {
+        (void)hipGetLastError();
+        pd_ctx_destroy(c);
+        return st;
+    }
+    *out = c;
+    return PD_OK;
+}
+
+extern "C" int pd_ctx_destroy(pd_ctx ctx) {
+    if (!ctx) return PD_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    pd_free(ctx->red);
+    pd_free(ctx->flag);
+    if (ctx->red_host) (void)hipHostFree(ctx->red_host);
+    if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
+    delete ctx;
+    return PD_OK;
+}
+
+extern "C" const char *pd_last_error(pd_ctx ctx) {
+    if (!ctx) return "null context";
+    return ctx->last_error.c_str();
+}
+
+extern "C" int pd_ctx_set_lanes(pd_ctx ctx, int lanes) {
+    if (!ctx) return PD_EINVAL;
+    if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
+        return pd_set_error(ctx, PD_EINVAL, "lanes must be 0 or a power of two in [1, 64]");
+    ctx->lanes = lanes;
+    return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (three passes, 1024 items per block)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = PD_BLOCK * SCAN_ITEMS;
+
+__device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t *total) {
+    __shared__ uint64_t s[PD_BLOCK];
+    const int t = threadIdx.x;
+    s[t] = x;
+    __syncthreads();
+    for (int off = 1; off < PD_BLOCK; off <<= 1) {
+        uint64_t y = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += y;
+        __syncthreads();
+    }
+    const uint64_t incl = s[t];
+    *total = s[PD_BLOCK - 1];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ void scan_tile_sums(const uint32_t *in, uint32_t n, uint64_t *sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t acc = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) acc += in[base + k];
+    uint64_t total;
+    block_exclusive_scan(acc, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void scan_sums_serial(uint64_t *sums, uint32_t count) {
+    // single block: running exclusive scan over `count` tile sums
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < count; base += PD_BLOCK) {
+        const uint32_t k = base + threadIdx.x;
+        uint64_t x = k < count ? sums[k] : 0;
+        uint64_t total;
+        uint64_t ex = block_exclusive_scan(x, &total);
+        if (k < count) sums[k] = ex + carry;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void scan_apply(const uint32_t *in, uint32_t n, const uint64_t *sums, uint64_t *out) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t v[SCAN_ITEMS];
+    uint64_t acc = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        acc += v[k];
+    }
+    uint64_t total;
+    uint64_t ex = block_exclusive_scan(acc, &total) + sums[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == PD_BLOCK - 1) out[n] = ex;
+}
+
+__global__ void narrow_u64(const uint64_t *in, uint32_t *out, uint32_t n) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k <= n) out[k] = (uint32_t)in[k];
+}
+}  // namespace
+
+int pd_scan_u32(pd_ctx ctx, const uint32_t *in, uint64_t *out, uint32_t n) {
+    const uint32_t tiles = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE) + (n == 0);
+    uint64_t *sums = nullptr;
+    PD_TRY(pd_alloc(ctx, &sums, tiles));
+    scan_tile_sums<<<tiles, PD_BLOCK, 0, ctx->stream>>>(in, n, sums);
+    scan_sums_serial<<<1, PD_BLOCK, 0, ctx->stream>>>(sums, tiles);
+    scan_apply<<<tiles, PD_BLOCK, 0, ctx->stream>>>(in, n, sums, out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    pd_free(sums);
+    if (e != hipSuccess) return pd_hip_error(ctx, e, "scan", __FILE__, __LINE__);
+    return PD_OK;
+}
+
+int pd_narrow_u64(pd_ctx ctx, const uint64_t *in, uint32_t *out, uint32_t n) {
+    narrow_u64<<<pd_blocks((uint64_t)n + 1), PD_BLOCK, 0, ctx->stream>>>(in, out, n);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// permutations between the caller's order and the internal sfc order
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void gather_xv_k(const int32_t *perm, uint32_t n, int dim, const double *X,
+                            const double *V, double *xv) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = perm[s];
+    double4 r;
+    if (dim == 3) r = make_double4(X[3 * o], X[3 * o + 1], X[3 * o + 2], V ? V[o] : 0.0);
+    else r = make_double4(X[2 * o], X[2 * o + 1], V ? V[o] : 0.0, 0.0);
+    reinterpret_cast<double4 *>(xv)[s] = r;
+}
+
+// internal vectors use a padded stride: 4 doubles in 3-d, 2 in 2-d
+__global__ void gather_vec_k(const int32_t *perm, uint32_t n, int dim, const double *src,
+                             double *dst) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = perm[s];
+    if (dim == 3) {
+        double4 r = src ? make_double4(src[3 * o], src[3 * o + 1], src[3 * o + 2], 0.0)
+                        : make_double4(0, 0, 0, 0);
+        reinterpret_cast<double4 *>(dst)[s] = r;
+    } else {
+        double2 r = src ? make_double2(src[2 * o], src[2 * o + 1]) : make_double2(0, 0);
+        reinterpret_cast<double2 *>(dst)[s] = r;
+    }
+}
+
+__global__ void scatter_vec_k(const int32_t *perm, uint32_t n, int dim, const double *src,
+                              double *dst) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = perm[s];
+    if (dim == 3) {
+        const double4 r = reinterpret_cast<const double4 *>(src)[s];
+        dst[3 * o] = r.x;
+        dst[3 * o + 1] = r.y;
+        dst[3 * o + 2] = r.z;
+    } else {
+        const double2 r = reinterpret_cast<const double2 *>(src)[s];
+        dst[2 * o] = r.x;
+        dst[2 * o + 1] = r.y;
+    }
+}
+
+__global__ void scatter_scalar_k(const int32_t *perm, uint32_t n, const double *src, double *dst) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[perm[s]] = src[s];
+}
+
+__global__ void gather_u8_k(const int32_t *perm, uint32_t n, const uint8_t *src, uint8_t *dst,
+                            uint8_t fill) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = src ? src[perm[s]] : fill;
+}
+
+// one 64-lane wave per row; bond k of internal row s is bond k of exported
+// row perm[s] (both rows are sorted by the neighbour's original id)
+template <bool IN>
+__global__ void alive_move_k(const int32_t *perm, const uint32_t *row_ptr, const uint32_t *ex_row_ptr,
+                             uint32_t n, const uint8_t *src, uint8_t *dst) {
+    const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const uint32_t lane = threadIdx.x % 64;
+    if (s >= n) return;
+    const uint32_t a = row_ptr[s], e = row_ptr[s + 1];
+    const uint32_t x = ex_row_ptr[perm[s]];
+    for (uint32_t k = lane; k < e - a; k += 64) {
+        if (IN) dst[a + k] = src ? src[x + k] : (uint8_t)1;
+        else dst[x + k] = src[a + k];
+    }
+}
+
+__global__ void sum_partials_k(const double *data, uint32_t n, int slots, double *part) {
+    __shared__ double sh[PD_BLOCK];
+    for (int s = 0; s < slots; ++s) {
+        double acc = 0.0;
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (uint64_t)gridDim.x * blockDim.x)
+            acc += data[i * slots + s];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = PD_BLOCK / 2; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[s * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void flag_clear_k(int *flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = 0;
+}
+}  // namespace
+
+int pd_gather_xv(pd_ctx ctx, const pd_nbr nbr, const double *X, const double *V, double *xv) {
+    gather_xv_k<<<pd_blocks(nbr->n), PD_BLOCK, 0, ctx->stream>>>(nbr->perm, nbr->n, nbr->dim, X,
+                                                                  V, xv);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_gather_vec(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst, bool) {
+    gather_vec_k<<<pd_blocks(nbr->n), PD_BLOCK, 0, ctx->stream>>>(nbr->perm, nbr->n, nbr->dim,
+                                                                   src, dst);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_scatter_vec(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst) {
+    scatter_vec_k<<<pd_blocks(nbr->n), PD_BLOCK, 0, ctx->stream>>>(nbr->perm, nbr->n, nbr->dim,
+                                                                    src, dst);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_scatter_scalar(pd_ctx ctx, const pd_nbr nbr, const double *src, double *dst) {
+    scatter_scalar_k<<<pd_blocks(nbr->n), PD_BLOCK, 0, ctx->stream>>>(nbr->perm, nbr->n, src, dst);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_gather_u8(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst, uint8_t fill) {
+    gather_u8_k<<<pd_blocks(nbr->n), PD_BLOCK, 0, ctx->stream>>>(nbr->perm, nbr->n, src, dst, fill);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_alive_in(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst) {
+    alive_move_k<true><<<pd_blocks((uint64_t)nbr->n * 64), PD_BLOCK, 0, ctx->stream>>>(
+        nbr->perm, nbr->row_ptr, nbr->ex_row_ptr, nbr->n, src, dst);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_alive_out(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst) {
+    alive_move_k<false><<<pd_blocks((uint64_t)nbr->n * 64), PD_BLOCK, 0, ctx->stream>>>(
+        nbr->perm, nbr->row_ptr, nbr->ex_row_ptr, nbr->n, src, dst);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_sum(pd_ctx ctx, const double *data, uint32_t n, int slots, double *out) {
+    if (slots < 1 || slots > PD_RED_SLOTS) return pd_set_error(ctx, PD_EINVAL, "bad slot count");
+    sum_partials_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, ctx->stream>>>(data, n, slots, ctx->red);
+    PD_LAUNCH_CHECK(ctx);
+    PD_HIP(ctx, hipMemcpyAsync(ctx->red_host, ctx->red, sizeof(double) * PD_RED_BLOCKS * slots,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < slots; ++s) {
+        double acc = 0.0;
+        for (int k = 0; k < PD_RED_BLOCKS; ++k) acc += ctx->red_host[s * PD_RED_BLOCKS + k];
+        out[s] = acc;
+    }
+    return PD_OK;
+}
+
+int pd_flag_clear(pd_ctx ctx) {
+    flag_clear_k<<<1, 64, 0, ctx->stream>>>(ctx->flag);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_flag_read(pd_ctx ctx, int *value) {
+    PD_HIP(ctx, hipMemcpyAsync(ctx->flag_host, ctx->flag, sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *value = *ctx->flag_host;
+    return PD_OK;
+}

@@ -1,0 +1,249 @@
+"""Thin Python binding of ``libpd_hip.so`` (the C ABI declared in include/pd.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every computation runs in the library's HIP kernels.  Importing this
+module raises if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpd_hip.so")
+
+PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV, PD_ENONFINITE, PD_ECAPACITY = (
+    0, -1, -2, -3, -4, -5, -6)
+PD_FP64, PD_MIXED = 0, 1
+PD_BC_FREE, PD_BC_CLAMPED, PD_BC_VELOCITY = 0, 1, 2
+
+
+class PDError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("dim", C.c_int), ("precision", C.c_int), ("c", C.c_double),
+                ("rho", C.c_double), ("s_c", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int),
+                ("rel_residual", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_1806_06917_amd.build or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "pd_version": (i32, []),
+        "pd_status_string": (C.c_char_p, [i32]),
+        "pd_micromodulus": (dbl, [i32, dbl, dbl]),
+        "pd_ctx_create": (i32, [i32, vp, P(vp)]),
+        "pd_ctx_destroy": (i32, [vp]),
+        "pd_last_error": (C.c_char_p, [vp]),
+        "pd_ctx_set_lanes": (i32, [vp, i32]),
+        "pd_build_neighbors": (i32, [vp, i32, i64, vp, dbl, P(vp)]),
+        "pd_nbr_info": (i32, [vp, P(i64), P(C.c_int32)]),
+        "pd_nbr_export": (i32, [vp, vp, vp]),
+        "pd_nbr_permutation": (i32, [vp, vp]),
+        "pd_nbr_destroy": (i32, [vp]),
+        "pd_internal_force": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
+        "pd_sim_create": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, vp, vp, i32, i64,
+                                P(vp)]),
+        "pd_verlet_step": (i32, [vp, i64, dbl]),
+        "pd_sim_get": (i32, [vp, vp, vp, vp, vp, vp]),
+        "pd_sim_set": (i32, [vp, vp, vp, vp, i64]),
+        "pd_sim_destroy": (i32, [vp]),
+        "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
+        "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
+                                    P(SolveInfo)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def micromodulus(dim, E, delta):
+    return lib.pd_micromodulus(int(dim), float(E), float(delta))
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = device
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = lib.pd_ctx_create(int(device), C.c_void_p(self._stream.cuda_stream), C.byref(h))
+        if st != PD_OK:
+            raise PDError(st, f"pd_ctx_create: {lib.pd_status_string(st).decode()}")
+        self.h = h
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def check(self, st, what):
+        if st != PD_OK:
+            msg = lib.pd_last_error(self.h).decode(errors="replace")
+            raise PDError(st, f"{what}: {msg}")
+        return st
+
+    def set_lanes(self, lanes):
+        self.check(lib.pd_ctx_set_lanes(self.h, int(lanes)), "pd_ctx_set_lanes")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def material(dim, c, rho=1.0, s_c=0.0, precision="fp64"):
+    prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision] if isinstance(precision, str) \
+        else int(precision)
+    return Material(int(dim), prec, float(c), float(rho), float(s_c))
+
+
+class Neighbors:
+    """Neighbour lists built on the GPU (pd_build_neighbors)."""
+
+    def __init__(self, ctx: Context, X, delta):
+        self.ctx = ctx
+        self.X = X
+        self.n, self.dim = int(X.shape[0]), int(X.shape[1])
+        h = C.c_void_p()
+        ctx.check(lib.pd_build_neighbors(ctx.h, self.dim, self.n, _ptr(X), float(delta),
+                                         C.byref(h)), "pd_build_neighbors")
+        self.h = h
+        nnz, mr = C.c_int64(), C.c_int32()
+        lib.pd_nbr_info(h, C.byref(nnz), C.byref(mr))
+        self.nnz, self.max_row = nnz.value, mr.value
+
+    def export(self):
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(max(self.nnz, 1), np.int32)
+        self.ctx.check(lib.pd_nbr_export(self.h, rp.ctypes.data_as(C.c_void_p),
+                                         col.ctypes.data_as(C.c_void_p)), "pd_nbr_export")
+        return rp, col[: self.nnz]
+
+    def permutation(self):
+        p = np.zeros(self.n, np.int32)
+        self.ctx.check(lib.pd_nbr_permutation(self.h, p.ctypes.data_as(C.c_void_p)),
+                       "pd_nbr_permutation")
+        return p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pd_nbr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def internal_force(ctx, nbr, mat, X, V, u, f, alive=None, U=None):
+    ctx.check(lib.pd_internal_force(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(u),
+                                    _ptr(alive), _ptr(f), _ptr(U)), "pd_internal_force")
+
+
+def apply_tangent(ctx, nbr, mat, X, V, w, y, alive=None, fixed=None):
+    ctx.check(lib.pd_apply_tangent(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(alive),
+                                   _ptr(fixed), _ptr(w), _ptr(y)), "pd_apply_tangent")
+
+
+@dataclass
+class SolveResult:
+    status: int
+    outer: int
+    inner: int
+    rel_residual: float
+
+
+def solve_implicit(ctx, nbr, mat, X, V, b, u, fixed=None, alive=None, rtol=1e-10,
+                   maxit=100000, raise_on_noconv=True):
+    info = SolveInfo()
+    st = lib.pd_solve_implicit(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(alive),
+                               _ptr(fixed), _ptr(b), _ptr(u), float(rtol), int(maxit),
+                               C.byref(info))
+    if st != PD_ENOCONV or raise_on_noconv:
+        ctx.check(st, "pd_solve_implicit")
+    return SolveResult(st, info.outer_iters, info.inner_iters, info.rel_residual)
+
+
+class Simulation:
+    """Resident explicit simulation (pd_sim_create / pd_verlet_step / ...)."""
+
+    def __init__(self, ctx, nbr, mat, X, V, u0=None, v0=None, bc_kind=None, bc_vel=None, b=None,
+                 notch=None, ramp_steps=0):
+        self.ctx, self.nbr, self.mat = ctx, nbr, mat
+        seg = None
+        nseg = 0
+        if notch is not None and len(notch):
+            seg = np.ascontiguousarray(np.asarray(notch, np.float64).reshape(-1, 4))
+            nseg = seg.shape[0]
+        h = C.c_void_p()
+        ctx.check(lib.pd_sim_create(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(u0),
+                                    _ptr(v0), _ptr(bc_kind), _ptr(bc_vel), _ptr(b),
+                                    None if seg is None else seg.ctypes.data_as(C.c_void_p),
+                                    nseg, int(ramp_steps), C.byref(h)), "pd_sim_create")
+        self.h = h
+
+    def step(self, nsteps, dt):
+        self.ctx.check(lib.pd_verlet_step(self.h, int(nsteps), float(dt)), "pd_verlet_step")
+
+    def get(self, u=None, v=None, alive=None, energies=False, allow_nonfinite=False):
+        kp = np.zeros(2, np.float64)
+        step = C.c_int64()
+        st = lib.pd_sim_get(self.h, _ptr(u), _ptr(v), _ptr(alive),
+                            kp.ctypes.data_as(C.c_void_p) if energies else None, C.byref(step))
+        if not (allow_nonfinite and st == PD_ENONFINITE):
+            self.ctx.check(st, "pd_sim_get")
+        return {"ke": kp[0], "pe": kp[1], "step": step.value, "status": st}
+
+    def set(self, u=None, v=None, alive=None, step=0):
+        self.ctx.check(lib.pd_sim_set(self.h, _ptr(u), _ptr(v), _ptr(alive), int(step)),
+                       "pd_sim_set")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pd_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,3 +19,20 @@ def orc():
     if not os.path.exists(oracle.LIB):
         oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """(torch, pd, Context) on cuda:0.  Fails loudly without a GPU or library."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_1806_06917_amd import pd
+    ctx = pd.Context(0)
+    yield torch, pd, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def say(*args):
+    """Progress line naming the case, flushed before each GPU step."""
+    print("[case]", *args, flush=True)
