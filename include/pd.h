@@ -131,6 +131,20 @@ const char *pd_last_error(pd_ctx ctx);
 int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
 
 /*
+ * Tuning of the node kernels (results do not depend on it):
+ *   kernel  0 automatic, 1 plain gather from global memory, 2 LDS-staged
+ *           tiles (T consecutive nodes in the internal order share one
+ *           workgroup, which copies the records of every node their bonds
+ *           touch into LDS once per launch); automatic uses tiles whenever
+ *           the largest halo fits in LDS.
+ *   tile    nodes per tile, a power of two in [16, 4096]; 0 automatic.
+ *   block   threads per tile workgroup, a multiple of 64 in [64, 1024];
+ *           0 automatic.
+ * Takes effect for neighbour lists and simulations set up afterwards.
+ */
+int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block);
+
+/*
  * Build the neighbour lists B_delta(X_i) (Section "Discretization of
  * peridynamics equations") in the reference configuration, once.
  *   X      device, [n][dim] float64 reference coordinates

@@ -20,79 +20,16 @@
 // rounding error in a second float32, through the butterfly as well.
 #include <cmath>
 
-#include "pd_internal.hpp"
+#include "pd_kernels.hpp"
 
 namespace {
 
-enum Mode { M_FORCE = 0, M_STEP_FIRST = 1, M_STEP_CONT = 2, M_CLOSE = 3, M_ENERGY = 4, M_TANGENT = 5 };
+using namespace pdk;
 
-struct NodeArgs {
-    const double *__restrict__ xv;     // [n][4]
-    const double *__restrict__ u;      // [n][US]
-    double *__restrict__ u_out;        // [n][US]
-    double *__restrict__ v;            // [n][US]
-    const uint32_t *__restrict__ row_ptr;
-    const int32_t *__restrict__ col;
-    uint8_t *__restrict__ alive;       // NULL: all intact, no damage
-    const uint8_t *__restrict__ bc;    // NULL: all free (tangent mode: fixed flags)
-    const double *__restrict__ bc_vel; // [n][US]
-    const double *__restrict__ b;      // [n][US] or NULL
-    double *__restrict__ f_out;        // [n][US] force (M_FORCE) or y (M_TANGENT)
-    double *__restrict__ e_out;        // M_FORCE: U_i; M_ENERGY: {V_i U_i, KE_i} pairs
-    int *__restrict__ flag;            // non-finite report
-    const int *__restrict__ done;      // if set and *done != 0 the launch is a no-op
-    uint32_t n;
-    int mode;
-    int damage;
-    double c, s_c, rho, dt, r_half, r_full;
-    float c32, s_c32;
-};
-
-template <int DIM>
-struct US_ {
-    static constexpr int value = DIM == 3 ? 4 : 2;
-};
-
-struct Acc64 {
-    double x = 0, y = 0, z = 0, e = 0;
-};
-
-struct Acc32 {
-    float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0, e = 0;
-};
-
-// s + a = s' + err exactly (Knuth two-sum); err accumulates into c
-__device__ __forceinline__ void two_sum_acc(float &s, float &c, float a) {
-#pragma clang fp contract(off)
-    const float t = s + a;
-    const float z = t - s;
-    const float err = (s - (t - z)) + (a - z);
-    s = t;
-    c = c + err;
-}
-
-__device__ __forceinline__ double shfl_xor_d(double v, int m, int w) { return __shfl_xor(v, m, w); }
-__device__ __forceinline__ float shfl_xor_f(float v, int m, int w) { return __shfl_xor(v, m, w); }
-
-template <int DIM>
-__device__ __forceinline__ void load_vec(const double *p, uint32_t i, double &x, double &y,
-                                         double &z) {
-    if (DIM == 3) {
-        const double4 q = reinterpret_cast<const double4 *>(p)[i];
-        x = q.x; y = q.y; z = q.z;
-    } else {
-        const double2 q = reinterpret_cast<const double2 *>(p)[i];
-        x = q.x; y = q.y; z = 0.0;
-    }
-}
-
-template <int DIM>
-__device__ __forceinline__ void store_vec(double *p, uint32_t i, double x, double y, double z) {
-    if (DIM == 3) reinterpret_cast<double4 *>(p)[i] = make_double4(x, y, z, 0.0);
-    else reinterpret_cast<double2 *>(p)[i] = make_double2(x, y);
-}
-
-template <int DIM, int L, bool MIXED>
+// Gather kernel: bond columns are sfc ids, neighbour records come straight
+// from global memory (L2).  Used for rows too long for the LDS tiles and as
+// the reference layout.
+template <int DIM, int L, bool MIXED, bool WANT_E>
 __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
     if (a.done && *a.done) return;
     const uint32_t tile = pd_xcd_tile(blockIdx.x, gridDim.x);
@@ -101,7 +38,6 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
     const int lane = threadIdx.x & (L - 1);
     const bool valid = i < a.n;
     const bool tangent = a.mode == M_TANGENT;
-    const bool want_e = a.mode == M_ENERGY || (a.mode == M_FORCE && a.e_out);
 
     double xix = 0, xiy = 0, xiz = 0, Vi = 0, uix = 0, uiy = 0, uiz = 0;
     Acc64 s64;
@@ -116,161 +52,24 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
         if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
         const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
         for (uint32_t p = rs + lane; p < re; p += L) {
-            if (a.alive && !a.alive[p]) continue;
             const uint32_t j = (uint32_t)a.col[p];
+            const bool live = !a.alive || a.alive[p];
+            if (!live) continue;
             const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
             double ujx, ujy, ujz;
             load_vec<DIM>(a.u, j, ujx, ujy, ujz);
             if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
             const double Vj = DIM == 3 ? xj.w : xj.z;
-            const double dxx = xj.x - xix, dxy = xj.y - xiy, dxz = DIM == 3 ? xj.z - xiz : 0.0;
-            const double dux = ujx - uix, duy = ujy - uiy, duz = DIM == 3 ? ujz - uiz : 0.0;
-            if (!MIXED) {
-                const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
-                const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
-                const double inv = rsqrt(r2);
-                const double S = ex * (inv * inv);
-                if (a.damage && S > a.s_c) {
-                    a.alive[p] = 0;
-                    continue;
-                }
-                const double g = a.c * S * Vj * inv;
-                s64.x += g * dxx;
-                s64.y += g * dxy;
-                if (DIM == 3) s64.z += g * dxz;
-                if (want_e) s64.e += 0.25 * a.c * S * S * (r2 * inv) * Vj;
-            } else {
-                const float fx = (float)dxx, fy = (float)dxy, fz = (float)dxz;
-                const float ux = (float)dux, uy = (float)duy, uz = (float)duz;
-                const float r2 = DIM == 3 ? fx * fx + fy * fy + fz * fz : fx * fx + fy * fy;
-                const float ex = DIM == 3 ? ux * fx + uy * fy + uz * fz : ux * fx + uy * fy;
-                const float inv = rsqrtf(r2);
-                const float S = ex * (inv * inv);
-                if (a.damage && S > a.s_c32) {
-                    a.alive[p] = 0;
-                    continue;
-                }
-                const float g = a.c32 * S * (float)Vj * inv;
-                two_sum_acc(s32.x, s32.cx, g * fx);
-                two_sum_acc(s32.y, s32.cy, g * fy);
-                if (DIM == 3) two_sum_acc(s32.z, s32.cz, g * fz);
-                if (want_e) s32.e += 0.25f * a.c32 * S * S * (r2 * inv) * (float)Vj;
-            }
+            const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
+            if (bond<DIM, MIXED, WANT_E>(a, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
+                                         duz, Vj, s64, s32))
+                a.alive[p] = 0;
         }
     }
-
     double fx, fy, fz, Ue;
-    if (!MIXED) {
-#pragma unroll
-        for (int m = L / 2; m > 0; m >>= 1) {
-            s64.x += shfl_xor_d(s64.x, m, L);
-            s64.y += shfl_xor_d(s64.y, m, L);
-            if (DIM == 3) s64.z += shfl_xor_d(s64.z, m, L);
-            if (want_e) s64.e += shfl_xor_d(s64.e, m, L);
-        }
-        fx = s64.x; fy = s64.y; fz = s64.z; Ue = s64.e;
-    } else {
-#pragma unroll
-        for (int m = L / 2; m > 0; m >>= 1) {
-            const float ox = shfl_xor_f(s32.x, m, L), ocx = shfl_xor_f(s32.cx, m, L);
-            const float oy = shfl_xor_f(s32.y, m, L), ocy = shfl_xor_f(s32.cy, m, L);
-            two_sum_acc(s32.x, s32.cx, ox);
-            s32.cx += ocx;
-            two_sum_acc(s32.y, s32.cy, oy);
-            s32.cy += ocy;
-            if (DIM == 3) {
-                const float oz = shfl_xor_f(s32.z, m, L), ocz = shfl_xor_f(s32.cz, m, L);
-                two_sum_acc(s32.z, s32.cz, oz);
-                s32.cz += ocz;
-            }
-            if (want_e) s32.e += shfl_xor_f(s32.e, m, L);
-        }
-        fx = (double)s32.x + (double)s32.cx;
-        fy = (double)s32.y + (double)s32.cy;
-        fz = (double)s32.z + (double)s32.cz;
-        Ue = (double)s32.e;
-    }
+    group_reduce<DIM, L, MIXED, WANT_E>(s64, s32, fx, fy, fz, Ue);
     if (!valid || lane != 0) return;
-
-    switch (a.mode) {
-    case M_FORCE:
-        store_vec<DIM>(a.f_out, i, fx, fy, fz);
-        if (a.e_out) a.e_out[i] = Ue;
-        return;
-    case M_TANGENT: {
-        if (fixed_i) {
-            double wx, wy, wz;
-            load_vec<DIM>(a.u, i, wx, wy, wz);
-            store_vec<DIM>(a.f_out, i, wx, wy, wz);
-        } else {
-            store_vec<DIM>(a.f_out, i, -Vi * fx, -Vi * fy, -Vi * fz);
-        }
-        return;
-    }
-    case M_ENERGY: {
-        double vx, vy, vz;
-        load_vec<DIM>(a.v, i, vx, vy, vz);
-        const double vv = DIM == 3 ? vx * vx + vy * vy + vz * vz : vx * vx + vy * vy;
-        a.e_out[2 * (size_t)i] = 0.5 * a.rho * Vi * vv;
-        a.e_out[2 * (size_t)i + 1] = Vi * Ue;
-        return;
-    }
-    default: break;
-    }
-
-    // time integration (lane 0 of the group)
-    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
-    double vx, vy, vz;
-    load_vec<DIM>(a.v, i, vx, vy, vz);
-    const double hdt = 0.5 * a.dt;
-    if (a.mode == M_CLOSE) {
-        if (kind == PD_BC_FREE) {
-            double bx = 0, by = 0, bz = 0;
-            if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
-            vx = vx + hdt * (fx + bx) / a.rho;
-            vy = vy + hdt * (fy + by) / a.rho;
-            vz = vz + hdt * (fz + bz) / a.rho;
-        } else if (kind == PD_BC_CLAMPED) {
-            vx = vy = vz = 0.0;
-        } else {
-            double wx, wy, wz;
-            load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
-            vx = a.r_full * wx; vy = a.r_full * wy; vz = a.r_full * wz;
-        }
-        store_vec<DIM>(a.v, i, vx, vy, vz);
-        const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(uix) &&
-                         isfinite(uiy) && isfinite(uiz);
-        if (!fin) atomicOr(a.flag, 1);
-        return;
-    }
-    double nx, ny, nz;
-    if (kind == PD_BC_FREE) {
-        double bx = 0, by = 0, bz = 0;
-        if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
-        if (a.mode == M_STEP_CONT) {   // second half-kick of the previous step
-            vx = vx + hdt * (fx + bx) / a.rho;
-            vy = vy + hdt * (fy + by) / a.rho;
-            vz = vz + hdt * (fz + bz) / a.rho;
-        }
-        vx = vx + hdt * (fx + bx) / a.rho;   // first half-kick of this step
-        vy = vy + hdt * (fy + by) / a.rho;
-        vz = vz + hdt * (fz + bz) / a.rho;
-        nx = uix + a.dt * vx;
-        ny = uiy + a.dt * vy;
-        nz = uiz + a.dt * vz;
-    } else if (kind == PD_BC_CLAMPED) {
-        vx = vy = vz = 0.0;
-        nx = ny = nz = 0.0;
-    } else {
-        double wx, wy, wz;
-        load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
-        vx = a.r_half * wx; vy = a.r_half * wy; vz = a.r_half * wz;
-        nx = uix + a.dt * vx;
-        ny = uiy + a.dt * vy;
-        nz = uiz + a.dt * vz;
-    }
-    store_vec<DIM>(a.v, i, vx, vy, vz);
-    store_vec<DIM>(a.u_out, i, nx, ny, nz);
+    node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i);
 }
 
 // notch pre-crack: orientation tests in float64 without contraction, end
@@ -321,8 +120,14 @@ template <int DIM, int L>
 int launch_t(pd_ctx ctx, const NodeArgs &a, bool mixed) {
     const unsigned grid = pd_blocks((uint64_t)a.n * L);
     if (grid == 0) return PD_OK;
-    if (mixed) node_kernel<DIM, L, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
-    else node_kernel<DIM, L, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    const bool e = mode_wants_energy(a);
+    if (mixed) {
+        if (e) node_kernel<DIM, L, true, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+        else node_kernel<DIM, L, true, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    } else {
+        if (e) node_kernel<DIM, L, false, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+        else node_kernel<DIM, L, false, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    }
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;
 }
@@ -341,8 +146,64 @@ int launch_d(pd_ctx ctx, const NodeArgs &a, int lanes, bool mixed) {
     }
 }
 
-int launch_node(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mixed) {
+}  // namespace
+
+int pd_launch_gather(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mixed) {
     return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed) : launch_d<2>(ctx, a, lanes, mixed);
+}
+
+namespace {
+
+// Chooses the kernel for a neighbour list: LDS tiles when every tile's halo
+// fits in LDS (tried at the requested or automatic size, then halved), the
+// plain gather kernel otherwise.
+}  // namespace
+
+int pd_prepare_tiles(pd_ctx ctx, pd_nbr nbr) {
+    if (ctx->kernel == 1 || nbr->tiles_failed) return PD_OK;
+    if (nbr->lcol && nbr->users > 0) return PD_OK;   // simulations depend on the layout
+    const size_t lds_max = 160 * 1024;
+    uint32_t T = ctx->tile ? (uint32_t)ctx->tile : (nbr->dim == 3 ? 64u : 256u);
+    if (nbr->tile_T == T && nbr->lcol) return PD_OK;
+    for (; T >= 16; T >>= 1) {
+        const int st = pd_nbr_build_tiles(ctx, nbr, T);
+        if (st == PD_OK &&
+            tile_lds_bytes(nbr->dim, (nbr->halo_max + 31u) & ~31u, (nbr->bonds_max + 63u) & ~63u) <=
+                lds_max)
+            return PD_OK;
+        if (st != PD_OK && st != PD_ECAPACITY) return st;
+        if (ctx->tile) break;
+    }
+    nbr->tiles_failed = 1;
+    if (ctx->kernel == 2)
+        return pd_set_error(ctx, PD_ECAPACITY, "tile halo does not fit in LDS");
+    return PD_OK;
+}
+
+bool pd_use_tiles(pd_ctx ctx, const pd_nbr nbr) {
+    return ctx->kernel != 1 && nbr->lcol && !nbr->tiles_failed;
+}
+
+namespace {
+
+// a.bw set: tile kernel (the neighbour list has tiles); otherwise gather
+int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed) {
+    if (a.bw) {
+        a.halo_ptr = nbr->halo_ptr;
+        a.halo = nbr->halo;
+        a.self_off = nbr->self_off;
+        a.tile = nbr->tile_T;
+        a.hcap = (nbr->halo_max + 31u) & ~31u;
+        a.bcap = (nbr->bonds_max + 63u) & ~63u;
+        // automatic: two groups per tile node (extra threads speed up staging)
+        int block = ctx->block;
+        if (!block) {
+            block = 2 * (int)nbr->tile_T * lanes;
+            block = block < 256 ? 256 : (block > 1024 ? 1024 : block);
+        }
+        return pd_launch_tile(ctx, nbr->dim, a, lanes, mixed, block);
+    }
+    return pd_launch_gather(ctx, nbr->dim, a, lanes, mixed);
 }
 
 int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
@@ -376,6 +237,7 @@ int ensure_scratch(pd_ctx ctx, pd_nbr nbr) {
     if (!nbr->s_U) PD_TRY(pd_alloc(ctx, &nbr->s_U, (size_t)nbr->n));
     if (!nbr->s_alive) PD_TRY(pd_alloc(ctx, &nbr->s_alive, nbr->nnz));
     if (!nbr->s_fixed) PD_TRY(pd_alloc(ctx, &nbr->s_fixed, (size_t)nbr->n));
+    if (!nbr->s_bw && nbr->lcol) PD_TRY(pd_alloc(ctx, &nbr->s_bw, nbr->nnz));
     return PD_OK;
 }
 
@@ -403,23 +265,30 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_check_dev_ptr(ctx, f, "f"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (U) PD_TRY(pd_check_dev_ptr(ctx, U, "U"));
+    PD_TRY(pd_prepare_tiles(ctx, nbr));
     PD_TRY(ensure_scratch(ctx, nbr));
+    const bool tiled = pd_use_tiles(ctx, nbr);
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
     PD_TRY(pd_gather_vec(ctx, nbr, u, nbr->s_u, false));
     if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
+    if (tiled) PD_TRY(pd_bw_compose(ctx, nbr, alive ? nbr->s_alive : nullptr, nbr->s_bw));
     NodeArgs a = base_args(nbr, mat);
     a.xv = nbr->s_xv;
     a.u = nbr->s_u;
     a.alive = alive ? nbr->s_alive : nullptr;
+    a.bw = tiled ? nbr->s_bw : nullptr;
     a.damage = alive && mat->s_c > 0.0;
     a.f_out = nbr->s_f;
     a.e_out = U ? nbr->s_U : nullptr;
     a.mode = M_FORCE;
-    PD_TRY(launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
+    PD_TRY(launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
                        mat->precision == PD_MIXED));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, f));
     if (U) PD_TRY(pd_scatter_scalar(ctx, nbr, nbr->s_U, U));
-    if (alive && a.damage) PD_TRY(pd_alive_out(ctx, nbr, nbr->s_alive, alive));
+    if (alive && a.damage) {
+        if (tiled) PD_TRY(pd_bw_to_alive(ctx, nbr, nbr->s_bw, nbr->s_alive));
+        PD_TRY(pd_alive_out(ctx, nbr, nbr->s_alive, alive));
+    }
     return PD_OK;
 }
 
@@ -427,32 +296,34 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
 // tangent operator (used by the implicit solver as well)
 // ---------------------------------------------------------------------------
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                   const uint8_t *alive_sfc, const uint8_t *fixed_sfc, const double *w,
-                   double *y, const int *done) {
+                   const uint8_t *alive_sfc, uint16_t *bw, const uint8_t *fixed_sfc,
+                   const double *w, double *y, const int *done) {
     NodeArgs a = base_args(nbr, mat);
     a.done = done;
     a.xv = xv;
     a.u = w;
     a.alive = const_cast<uint8_t *>(alive_sfc);
+    a.bw = bw;
     a.damage = 0;
     a.bc = fixed_sfc;
     a.f_out = y;
     a.mode = M_TANGENT;
-    return launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
+    return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
                        mat->precision == PD_MIXED);
 }
 
 // internal force in sfc order, no damage: f = force(u) (implicit residuals)
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                 const uint8_t *alive_sfc, const double *u, double *f) {
+                 const uint8_t *alive_sfc, uint16_t *bw, const double *u, double *f) {
     NodeArgs a = base_args(nbr, mat);
     a.xv = xv;
     a.u = u;
     a.alive = const_cast<uint8_t *>(alive_sfc);
+    a.bw = bw;
     a.damage = 0;
     a.f_out = f;
     a.mode = M_FORCE;
-    return launch_node(ctx, nbr->dim, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false);
+    return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false);
 }
 
 extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
@@ -468,13 +339,17 @@ extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, 
     PD_TRY(pd_check_dev_ptr(ctx, y, "y"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (fixed) PD_TRY(pd_check_dev_ptr(ctx, fixed, "fixed"));
+    PD_TRY(pd_prepare_tiles(ctx, nbr));
     PD_TRY(ensure_scratch(ctx, nbr));
+    const bool tiled = pd_use_tiles(ctx, nbr);
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
     PD_TRY(pd_gather_vec(ctx, nbr, w, nbr->s_u, false));
     if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
+    if (tiled) PD_TRY(pd_bw_compose(ctx, nbr, alive ? nbr->s_alive : nullptr, nbr->s_bw));
     if (fixed) PD_TRY(pd_gather_u8(ctx, nbr, fixed, nbr->s_fixed, 0));
     PD_TRY(pd_tangent_sfc(ctx, nbr, mat, nbr->s_xv, alive ? nbr->s_alive : nullptr,
-                          fixed ? nbr->s_fixed : nullptr, nbr->s_u, nbr->s_f, nullptr));
+                          tiled ? nbr->s_bw : nullptr, fixed ? nbr->s_fixed : nullptr, nbr->s_u,
+                          nbr->s_f, nullptr));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, y));
     return PD_OK;
 }
@@ -492,7 +367,9 @@ static void sim_release(pd_sim s) {
     pd_free(s->b);
     pd_free(s->bc);
     pd_free(s->alive);
+    pd_free(s->bw);
     pd_free(s->scratch);
+    if (s->nbr && s->tiled) s->nbr->users -= 1;
     delete s;
 }
 
@@ -529,6 +406,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
                 return pd_set_error(ctx, PD_EINVAL, "notch coordinates must be finite");
         }
 
+    PD_TRY(pd_prepare_tiles(ctx, nbr));
     pd_sim s = new (std::nothrow) pd_sim_s();
     if (!s) return PD_ENOMEM;
     s->ctx = ctx;
@@ -559,6 +437,12 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "notch_k", __FILE__, __LINE__);
     }
+    if (st == PD_OK && pd_use_tiles(ctx, nbr)) {
+        s->tiled = true;
+        nbr->users += 1;
+        st = pd_alloc(ctx, &s->bw, nbr->nnz);
+        if (st == PD_OK) st = pd_bw_compose(ctx, nbr, s->alive, s->bw);
+    }
     if (st == PD_OK) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "sim_create", __FILE__, __LINE__);
@@ -577,6 +461,7 @@ static NodeArgs sim_args(pd_sim s) {
     a.xv = s->xv;
     a.v = s->v;
     a.alive = s->alive;
+    a.bw = s->tiled ? s->bw : nullptr;
     a.damage = s->mat.s_c > 0.0;
     a.bc = s->bc;
     a.bc_vel = s->bc_vel;
@@ -602,7 +487,7 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
         a.u = sim->u[sim->cur];
         a.u_out = sim->u[sim->cur ^ 1];
         a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
-        PD_TRY(launch_node(ctx, sim->nbr->dim, a, sim->lanes, mixed));
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, mixed));
         sim->cur ^= 1;
         sim->v_half = true;
         sim->step += 1;
@@ -619,7 +504,7 @@ static int sim_close(pd_sim sim) {
     a.mode = M_CLOSE;
     a.u = sim->u[sim->cur];
     a.r_full = ramp_factor((double)sim->step, sim->ramp);
-    PD_TRY(launch_node(sim->ctx, sim->nbr->dim, a, sim->lanes, sim->mat.precision == PD_MIXED));
+    PD_TRY(launch_node(sim->ctx, sim->nbr, a, sim->lanes, sim->mat.precision == PD_MIXED));
     sim->v_half = false;
     return PD_OK;
 }
@@ -636,14 +521,17 @@ extern "C" int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, doub
     PD_TRY(sim_close(sim));
     if (u) PD_TRY(pd_scatter_vec(ctx, sim->nbr, sim->u[sim->cur], u));
     if (v) PD_TRY(pd_scatter_vec(ctx, sim->nbr, sim->v, v));
-    if (alive) PD_TRY(pd_alive_out(ctx, sim->nbr, sim->alive, alive));
+    if (alive) {
+        if (sim->tiled) PD_TRY(pd_bw_to_alive(ctx, sim->nbr, sim->bw, sim->alive));
+        PD_TRY(pd_alive_out(ctx, sim->nbr, sim->alive, alive));
+    }
     if (ke_pe) {
         NodeArgs a = sim_args(sim);
         a.mode = M_ENERGY;
         a.damage = 0;
         a.u = sim->u[sim->cur];
         a.e_out = sim->scratch;
-        PD_TRY(launch_node(ctx, sim->nbr->dim, a, sim->lanes, false));
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, false));
         PD_TRY(pd_sum(ctx, sim->scratch, sim->nbr->n, 2, ke_pe));
     }
     if (step) *step = sim->step;
@@ -665,7 +553,10 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
     PD_TRY(sim_close(sim));
     if (u) PD_TRY(pd_gather_vec(ctx, sim->nbr, u, sim->u[sim->cur], false));
     if (v) PD_TRY(pd_gather_vec(ctx, sim->nbr, v, sim->v, false));
-    if (alive) PD_TRY(pd_alive_in(ctx, sim->nbr, alive, sim->alive));
+    if (alive) {
+        PD_TRY(pd_alive_in(ctx, sim->nbr, alive, sim->alive));
+        if (sim->tiled) PD_TRY(pd_bw_compose(ctx, sim->nbr, sim->alive, sim->bw));
+    }
     sim->step = step;
     return PD_OK;
 }

@@ -17,7 +17,7 @@
 #include <cmath>
 #include <vector>
 
-#include "pd_internal.hpp"
+#include "pd_kernels.hpp"
 
 namespace {
 
@@ -139,11 +139,12 @@ struct Work {
     double *xv = nullptr, *u = nullptr, *b = nullptr, *f = nullptr, *r = nullptr, *x = nullptr,
            *p = nullptr, *q = nullptr, *part_a = nullptr, *part_b = nullptr;
     uint8_t *alive = nullptr, *fixed = nullptr;
+    uint16_t *bw = nullptr;
     CgState *st = nullptr;
     CgState *st_host = nullptr;
     ~Work() {
         pd_free(xv); pd_free(u); pd_free(b); pd_free(f); pd_free(r); pd_free(x); pd_free(p);
-        pd_free(q); pd_free(part_a); pd_free(part_b); pd_free(alive); pd_free(fixed); pd_free(st);
+        pd_free(q); pd_free(part_a); pd_free(part_b); pd_free(alive); pd_free(fixed); pd_free(bw); pd_free(st);
         if (st_host) (void)hipHostFree(st_host);
     }
 };
@@ -184,7 +185,8 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, uint
         const int nrun = std::min(chunk, budget - it);
         for (int k = 0; k < nrun; ++k) {
             const int parity = (it + k) & 1;
-            PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.fixed, w.p, w.q, &w.st->done));
+            PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.fixed, w.p, w.q,
+                                  &w.st->done));
             dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.p, w.q, m, w.part_a, w.st);
             cg_update_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.x, w.r, w.p, w.q, m, w.part_a,
                                                           w.part_b, w.st, parity);
@@ -250,6 +252,11 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         PD_TRY(pd_alloc(ctx, &w.fixed, n));
         PD_TRY(pd_gather_u8(ctx, nbr, fixed, w.fixed, 0));
     }
+    PD_TRY(pd_prepare_tiles(ctx, nbr));
+    if (pd_use_tiles(ctx, nbr)) {
+        PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz));
+        PD_TRY(pd_bw_compose(ctx, nbr, w.alive, w.bw));
+    }
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, w.xv));
     PD_TRY(pd_gather_vec(ctx, nbr, u, w.u, false));
     PD_TRY(pd_gather_vec(ctx, nbr, b, w.b, false));
@@ -268,7 +275,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     int outer = 0, inner_total = 0, status = PD_ENOCONV;
     double rel = 0.0;
     while (true) {
-        PD_TRY(pd_force_sfc(ctx, nbr, mat, w.xv, w.alive, w.u, w.f));
+        PD_TRY(pd_force_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.u, w.f));
         residual_k<<<gm, PD_BLOCK, 0, ctx->stream>>>(n, us, dim, w.xv, w.f, w.b, w.fixed, w.r);
         PD_LAUNCH_CHECK(ctx);
         double rr = 0.0;

@@ -29,6 +29,9 @@ struct pd_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     int lanes = 0;          // 0: automatic
+    int kernel = 0;         // 0: automatic, 1: gather, 2: LDS tiles
+    int tile = 0;           // nodes per tile, 0: automatic
+    int block = 0;          // threads per tile workgroup, 0: automatic
     int failed = 0;         // sticky device failure
     std::string last_error;
     double *red = nullptr;  // device partial sums, PD_RED_BLOCKS * PD_RED_SLOTS
@@ -49,6 +52,16 @@ struct pd_nbr_s {
     uint32_t *row_ptr = nullptr; // [n+1] sfc order
     int32_t *col = nullptr;      // [nnz] sfc ids
     uint32_t *ex_row_ptr = nullptr;  // [n+1] original order
+    // LDS tiles (pd_tile.hip): T consecutive sfc nodes per tile
+    uint32_t tile_T = 0, ntiles = 0, halo_max = 0, bonds_max = 0;
+    uint64_t halo_total = 0;
+    uint32_t *halo_ptr = nullptr;  // [ntiles+1]
+    int32_t *halo = nullptr;       // sorted sfc ids of each tile's halo
+    uint32_t *self_off = nullptr;  // [ntiles] local index of the tile's first node
+    uint16_t *lcol = nullptr;      // [nnz] tile-local neighbour index
+    int tiles_failed = 0;          // halo too large for LDS at every tried size
+    int users = 0;                 // simulations attached (their bond words use the tiles)
+    uint16_t *s_bw = nullptr;      // scratch bond words for the stateless entry points
     // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
     double *s_xv = nullptr, *s_u = nullptr, *s_f = nullptr, *s_U = nullptr;
     uint8_t *s_alive = nullptr, *s_fixed = nullptr;
@@ -65,7 +78,10 @@ struct pd_sim_s {
     double *bc_vel = nullptr;
     double *b = nullptr;
     uint8_t *bc = nullptr;
-    uint8_t *alive = nullptr;
+    uint8_t *alive = nullptr;    // bond flags (gather kernel; export copy for tiles)
+    uint16_t *bw = nullptr;      // bond words (tile kernel): local index | dead bit
+    bool tiled = false;          // this simulation runs the tile kernel
+    bool bw_newer = false;       // bw holds damage not yet copied to alive
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
     int64_t step = 0;
     int64_t ramp = 0;
@@ -162,9 +178,16 @@ int pd_flag_read(pd_ctx ctx, int *value);
 // checks that a device pointer is accessible device memory of ctx's device
 int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name);
 
+int pd_nbr_build_tiles(pd_ctx ctx, pd_nbr nbr, uint32_t T);
+
 // sfc-order building blocks of the implicit solver (pd_force.hip)
+// bw: bond words for the tile kernel, or NULL to use the gather kernel
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                   const uint8_t *alive_sfc, const uint8_t *fixed_sfc, const double *w, double *y,
-                   const int *done);
+                   const uint8_t *alive_sfc, uint16_t *bw, const uint8_t *fixed_sfc,
+                   const double *w, double *y, const int *done);
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                 const uint8_t *alive_sfc, const double *u, double *f);
+                 const uint8_t *alive_sfc, uint16_t *bw, const double *u, double *f);
+// tile kernel usable for this neighbour list under the context's tuning
+bool pd_use_tiles(pd_ctx ctx, const pd_nbr nbr);
+// builds the tiles if the tuning allows (no-op when they exist and are in use)
+int pd_prepare_tiles(pd_ctx ctx, pd_nbr nbr);

@@ -1,0 +1,264 @@
+// Device code shared by the node kernels: bond law (Algorithm 1, linearised,
+// J = 1), damage test, per-node butterfly reduction and the node update
+// (force output, tangent output, energies, velocity-Verlet half-kicks and
+// drift with boundary data).
+#pragma once
+
+#include "pd_internal.hpp"
+
+namespace pdk {
+
+enum Mode { M_FORCE = 0, M_STEP_FIRST = 1, M_STEP_CONT = 2, M_CLOSE = 3, M_ENERGY = 4, M_TANGENT = 5 };
+
+struct NodeArgs {
+    const double *__restrict__ xv;     // [n][4]
+    const double *__restrict__ u;      // [n][US]
+    double *__restrict__ u_out;        // [n][US]
+    double *__restrict__ v;            // [n][US]
+    const uint32_t *__restrict__ row_ptr;
+    const int32_t *__restrict__ col;   // sfc ids (gather kernel)
+    uint16_t *__restrict__ bw;         // tile kernel bond words: local id | 0x8000 if broken
+    const uint32_t *__restrict__ halo_ptr;
+    const int32_t *__restrict__ halo;
+    const uint32_t *__restrict__ self_off;
+    uint8_t *__restrict__ alive;       // NULL: all intact, no damage
+    const uint8_t *__restrict__ bc;    // NULL: all free (tangent mode: fixed flags)
+    const double *__restrict__ bc_vel; // [n][US]
+    const double *__restrict__ b;      // [n][US] or NULL
+    double *__restrict__ f_out;        // [n][US] force (M_FORCE) or y (M_TANGENT)
+    double *__restrict__ e_out;        // M_FORCE: U_i; M_ENERGY: {KE_i, V_i U_i} pairs
+    int *__restrict__ flag;            // non-finite report
+    const int *__restrict__ done;      // if set and *done != 0 the launch is a no-op
+    uint32_t n;
+    uint32_t tile;                     // nodes per tile (tile kernel)
+    uint32_t hcap;                     // halo records held in LDS (tile kernel)
+    uint32_t bcap;                     // bonds per tile held in LDS (tile kernel)
+    int mode;
+    int damage;
+    double c, s_c, rho, dt, r_half, r_full;
+    float c32, s_c32;
+};
+
+struct Acc64 {
+    double x = 0, y = 0, z = 0, e = 0;
+};
+
+// float32 sums with their low-order parts (x + cx is the lane's sum)
+struct Acc32 {
+    float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0, e = 0;
+};
+
+constexpr uint16_t BW_DEAD = 0x8000;
+constexpr uint16_t BW_IDX = 0x7fff;
+
+// Kahan-compensated running sum: s + lo tracks the exact sum of the inputs
+// to within a few units of float32 rounding (lo = -c of Kahan's notation)
+__device__ __forceinline__ void kahan_acc(float &s, float &lo, float a) {
+#pragma clang fp contract(off)
+    const float y = a + lo;
+    const float t = s + y;
+    lo = y - (t - s);
+    s = t;
+}
+
+// s + a = s' + err exactly (Knuth two-sum); err accumulates into c
+__device__ __forceinline__ void two_sum_acc(float &s, float &c, float a) {
+#pragma clang fp contract(off)
+    const float t = s + a;
+    const float z = t - s;
+    const float err = (s - (t - z)) + (a - z);
+    s = t;
+    c = c + err;
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_vec(const double *p, uint32_t i, double &x, double &y,
+                                         double &z) {
+    if (DIM == 3) {
+        const double4 q = reinterpret_cast<const double4 *>(p)[i];
+        x = q.x; y = q.y; z = q.z;
+    } else {
+        const double2 q = reinterpret_cast<const double2 *>(p)[i];
+        x = q.x; y = q.y; z = 0.0;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ void store_vec(double *p, uint32_t i, double x, double y, double z) {
+    if (DIM == 3) reinterpret_cast<double4 *>(p)[i] = make_double4(x, y, z, 0.0);
+    else reinterpret_cast<double2 *>(p)[i] = make_double2(x, y);
+}
+
+// One bond: xi = X_j - X_i, eta = u_j - u_i (both formed in float64).
+// Returns true if the bond breaks now (S > s_c); otherwise accumulates
+// c S V_j xi/|xi| (and (c/4) S^2 |xi| V_j if want_e).
+template <int DIM, bool MIXED, bool WANT_E>
+__device__ __forceinline__ bool bond(const NodeArgs &a, double dxx, double dxy,
+                                     double dxz, double dux, double duy, double duz, double Vj,
+                                     Acc64 &s64, Acc32 &s32) {
+    if (!MIXED) {
+        const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
+        const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+        const double inv = rsqrt(r2);
+        const double S = ex * (inv * inv);
+        if (a.damage && S > a.s_c) return true;
+        const double g = a.c * S * Vj * inv;
+        s64.x += g * dxx;
+        s64.y += g * dxy;
+        if (DIM == 3) s64.z += g * dxz;
+        if (WANT_E) s64.e += 0.25 * a.c * S * S * (r2 * inv) * Vj;
+    } else {
+        const float fx = (float)dxx, fy = (float)dxy, fz = (float)dxz;
+        const float ux = (float)dux, uy = (float)duy, uz = (float)duz;
+        const float r2 = DIM == 3 ? fx * fx + fy * fy + fz * fz : fx * fx + fy * fy;
+        const float ex = DIM == 3 ? ux * fx + uy * fy + uz * fz : ux * fx + uy * fy;
+        const float inv = rsqrtf(r2);
+        const float S = ex * (inv * inv);
+        if (a.damage && S > a.s_c32) return true;
+        const float g = a.c32 * S * (float)Vj * inv;
+        kahan_acc(s32.x, s32.cx, g * fx);
+        kahan_acc(s32.y, s32.cy, g * fy);
+        if (DIM == 3) kahan_acc(s32.z, s32.cz, g * fz);
+        if (WANT_E) s32.e += 0.25f * a.c32 * S * S * (r2 * inv) * (float)Vj;
+    }
+    return false;
+}
+
+// xor butterfly over the L lanes of a group: every lane ends with the sum
+template <int DIM, int L, bool MIXED, bool WANT_E>
+__device__ __forceinline__ void group_reduce(Acc64 &s64, Acc32 &s32, double &fx,
+                                             double &fy, double &fz, double &Ue) {
+    if (!MIXED) {
+#pragma unroll
+        for (int m = L / 2; m > 0; m >>= 1) {
+            s64.x += __shfl_xor(s64.x, m, L);
+            s64.y += __shfl_xor(s64.y, m, L);
+            if (DIM == 3) s64.z += __shfl_xor(s64.z, m, L);
+            if (WANT_E) s64.e += __shfl_xor(s64.e, m, L);
+        }
+        fx = s64.x; fy = s64.y; fz = s64.z; Ue = s64.e;
+    } else {
+#pragma unroll
+        for (int m = L / 2; m > 0; m >>= 1) {
+            const float ox = __shfl_xor(s32.x, m, L), ocx = __shfl_xor(s32.cx, m, L);
+            const float oy = __shfl_xor(s32.y, m, L), ocy = __shfl_xor(s32.cy, m, L);
+            two_sum_acc(s32.x, s32.cx, ox);
+            s32.cx += ocx;
+            two_sum_acc(s32.y, s32.cy, oy);
+            s32.cy += ocy;
+            if (DIM == 3) {
+                const float oz = __shfl_xor(s32.z, m, L), ocz = __shfl_xor(s32.cz, m, L);
+                two_sum_acc(s32.z, s32.cz, oz);
+                s32.cz += ocz;
+            }
+            if (WANT_E) s32.e += __shfl_xor(s32.e, m, L);
+        }
+        fx = (double)s32.x + (double)s32.cx;
+        fy = (double)s32.y + (double)s32.cy;
+        fz = (double)s32.z + (double)s32.cz;
+        Ue = (double)s32.e;
+    }
+}
+
+// Node update by one lane, after the force density f_i is known.
+template <int DIM>
+__device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, double fx, double fy,
+                                            double fz, double Ue, double Vi, double uix,
+                                            double uiy, double uiz, bool fixed_i) {
+    switch (a.mode) {
+    case M_FORCE:
+        store_vec<DIM>(a.f_out, i, fx, fy, fz);
+        if (a.e_out) a.e_out[i] = Ue;
+        return;
+    case M_TANGENT: {
+        if (fixed_i) {
+            double wx, wy, wz;
+            load_vec<DIM>(a.u, i, wx, wy, wz);
+            store_vec<DIM>(a.f_out, i, wx, wy, wz);
+        } else {
+            store_vec<DIM>(a.f_out, i, -Vi * fx, -Vi * fy, -Vi * fz);
+        }
+        return;
+    }
+    case M_ENERGY: {
+        double vx, vy, vz;
+        load_vec<DIM>(a.v, i, vx, vy, vz);
+        const double vv = DIM == 3 ? vx * vx + vy * vy + vz * vz : vx * vx + vy * vy;
+        a.e_out[2 * (size_t)i] = 0.5 * a.rho * Vi * vv;
+        a.e_out[2 * (size_t)i + 1] = Vi * Ue;
+        return;
+    }
+    default: break;
+    }
+
+    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
+    double vx, vy, vz;
+    load_vec<DIM>(a.v, i, vx, vy, vz);
+    const double hdt = 0.5 * a.dt;
+    if (a.mode == M_CLOSE) {   // second half-kick of the last step
+        if (kind == PD_BC_FREE) {
+            double bx = 0, by = 0, bz = 0;
+            if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
+            vx = vx + hdt * (fx + bx) / a.rho;
+            vy = vy + hdt * (fy + by) / a.rho;
+            vz = vz + hdt * (fz + bz) / a.rho;
+        } else if (kind == PD_BC_CLAMPED) {
+            vx = vy = vz = 0.0;
+        } else {
+            double wx, wy, wz;
+            load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
+            vx = a.r_full * wx; vy = a.r_full * wy; vz = a.r_full * wz;
+        }
+        store_vec<DIM>(a.v, i, vx, vy, vz);
+        const bool fin = isfinite(vx) && isfinite(vy) && isfinite(vz) && isfinite(uix) &&
+                         isfinite(uiy) && isfinite(uiz);
+        if (!fin) atomicOr(a.flag, 1);
+        return;
+    }
+    double nx, ny, nz;
+    if (kind == PD_BC_FREE) {
+        double bx = 0, by = 0, bz = 0;
+        if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
+        if (a.mode == M_STEP_CONT) {   // second half-kick of the previous step
+            vx = vx + hdt * (fx + bx) / a.rho;
+            vy = vy + hdt * (fy + by) / a.rho;
+            vz = vz + hdt * (fz + bz) / a.rho;
+        }
+        vx = vx + hdt * (fx + bx) / a.rho;   // first half-kick of this step
+        vy = vy + hdt * (fy + by) / a.rho;
+        vz = vz + hdt * (fz + bz) / a.rho;
+        nx = uix + a.dt * vx;                // drift
+        ny = uiy + a.dt * vy;
+        nz = uiz + a.dt * vz;
+    } else if (kind == PD_BC_CLAMPED) {
+        vx = vy = vz = 0.0;
+        nx = ny = nz = 0.0;
+    } else {
+        double wx, wy, wz;
+        load_vec<DIM>(a.bc_vel, i, wx, wy, wz);
+        vx = a.r_half * wx; vy = a.r_half * wy; vz = a.r_half * wz;
+        nx = uix + a.dt * vx;
+        ny = uiy + a.dt * vy;
+        nz = uiz + a.dt * vz;
+    }
+    store_vec<DIM>(a.v, i, vx, vy, vz);
+    store_vec<DIM>(a.u_out, i, nx, ny, nz);
+}
+
+// modes that need the strain energy of every bond
+__host__ __device__ inline bool mode_wants_energy(const NodeArgs &a) {
+    return a.mode == M_ENERGY || (a.mode == M_FORCE && a.e_out != nullptr);
+}
+
+}  // namespace pdk
+
+// launchers (pd_force.hip, pd_tile.hip)
+
+int pd_launch_gather(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed);
+int pd_launch_tile(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed,
+                   int block);
+// LDS bytes the tile kernel needs for hcap halo records and bcap bonds
+size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap);
+// bond words of a tiled neighbour list: bw = lcol | BW_DEAD where alive == 0
+int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw);
+int pd_bw_to_alive(pd_ctx ctx, const pd_nbr nbr, const uint16_t *bw, uint8_t *alive_sfc);

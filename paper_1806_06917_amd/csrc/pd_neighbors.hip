@@ -252,6 +252,10 @@ static void nbr_release(pd_nbr b) {
     pd_free(b->row_ptr);
     pd_free(b->col);
     pd_free(b->ex_row_ptr);
+    pd_free(b->halo_ptr);
+    pd_free(b->halo);
+    pd_free(b->self_off);
+    pd_free(b->lcol);
     pd_free(b->s_xv);
     pd_free(b->s_u);
     pd_free(b->s_f);

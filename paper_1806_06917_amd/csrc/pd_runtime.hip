@@ -55,9 +55,11 @@ int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name) {
 
 int pd_auto_lanes(pd_ctx ctx, uint64_t nnz, uint32_t n) {
     if (ctx && ctx->lanes > 0) return ctx->lanes;
+    // about 16 bonds per lane: enough work per lane to amortise the
+    // butterfly, enough nodes per wavefront to keep the loads in flight
     const double k = n ? (double)nnz / (double)n : 0.0;
     int L = 1;
-    while (L < 32 && L * 6 < k) L *= 2;
+    while (L < 32 && L * 16 < k) L *= 2;
     return L;
 }
 
@@ -144,6 +146,19 @@ extern "C" int pd_ctx_set_lanes(pd_ctx ctx, int lanes) {
     if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))
         return pd_set_error(ctx, PD_EINVAL, "lanes must be 0 or a power of two in [1, 64]");
     ctx->lanes = lanes;
+    return PD_OK;
+}
+
+extern "C" int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block) {
+    if (!ctx) return PD_EINVAL;
+    if (kernel < 0 || kernel > 2) return pd_set_error(ctx, PD_EINVAL, "kernel must be 0, 1 or 2");
+    if (tile != 0 && (tile < 16 || tile > 4096 || (tile & (tile - 1))))
+        return pd_set_error(ctx, PD_EINVAL, "tile must be 0 or a power of two in [16, 4096]");
+    if (block != 0 && (block < 64 || block > 1024 || (block % 64)))
+        return pd_set_error(ctx, PD_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
+    ctx->kernel = kernel;
+    ctx->tile = tile;
+    ctx->block = block;
     return PD_OK;
 }
 

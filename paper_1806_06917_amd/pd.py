@@ -53,6 +53,7 @@ def _load():
         "pd_ctx_destroy": (i32, [vp]),
         "pd_last_error": (C.c_char_p, [vp]),
         "pd_ctx_set_lanes": (i32, [vp, i32]),
+        "pd_ctx_set_tuning": (i32, [vp, i32, i32, i32]),
         "pd_build_neighbors": (i32, [vp, i32, i64, vp, dbl, P(vp)]),
         "pd_nbr_info": (i32, [vp, P(i64), P(C.c_int32)]),
         "pd_nbr_export": (i32, [vp, vp, vp]),
@@ -115,6 +116,12 @@ class Context:
 
     def set_lanes(self, lanes):
         self.check(lib.pd_ctx_set_lanes(self.h, int(lanes)), "pd_ctx_set_lanes")
+
+    def set_tuning(self, kernel=0, tile=0, block=0):
+        """kernel: 0 auto, 1 gather, 2 LDS tiles; tile/block sizes (0 = auto)."""
+        kind = {"auto": 0, "gather": 1, "tile": 2}.get(kernel, kernel)
+        self.check(lib.pd_ctx_set_tuning(self.h, int(kind), int(tile), int(block)),
+                   "pd_ctx_set_tuning")
 
     def close(self):
         if getattr(self, "h", None):

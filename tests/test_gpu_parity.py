@@ -414,3 +414,37 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     same = np.array_equal(a, st["alive"])
     assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
     assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
+
+
+@pytest.mark.parametrize("wl,prec", [("plate", "fp64"), ("cube", "mixed"), ("cube", "fp64"),
+                                     ("notched", "mixed")])
+def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
+    """The LDS-tile kernel and the gather kernel sum every node's bonds in the
+    same order, so trajectories agree bit for bit for any tile size."""
+    torch, pd, ctx = gpu
+    if wl == "plate":
+        w = inputs.plate_2d(40, 3, seed=2, steps=0)
+    elif wl == "cube":
+        w = inputs.cube_3d(18, 3, steps=0, ramp_steps=4)
+        w.v0 = inputs.random_field(w.n, 3, 5, scale=2e-3)
+        w.v0[w.bc_kind == 2] = 0
+    else:
+        w = notched(N=72)
+    c = pd.micromodulus(w.dim, w.E, w.delta)
+    results = []
+    for kind, tile, block in [("gather", 0, 0), ("tile", 16, 64), ("tile", 64, 256),
+                              ("tile", 256, 512), ("tile", 0, 0)]:
+        say("tile vs gather", wl, prec, kind, tile, block)
+        ctx.set_tuning(kind, tile, block)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+            s = sim_from_workload(torch, pd, ctx, nb, w, c, prec)
+            s.step(25, w.dt)
+            results.append(read_state(torch, s, w.n, w.dim, nb.nnz)[:3])
+            s.close()
+            nb.close()
+        finally:
+            ctx.set_tuning(0, 0, 0)
+    for r in results[1:]:
+        for x, y in zip(results[0], r):
+            assert np.array_equal(x, y)
