@@ -14,8 +14,10 @@ per bond a 4-byte column index and a 1-byte flag, per node the row offset,
 X, V, u, v, the boundary kind read once and u', v' written once.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +27,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["pd_kernels.hpp", "pd_tile.hip", "pd_force.hip", "pd_internal.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_kernel_cube100_traffic.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1806_06917_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy kernel) -- only if the kernel sources are unchanged
+    since the counters were taken."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"```json\n(.*?)```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if rec.get("workload") != workload or rec.get("precision") != precision:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def algorithmic_bytes(n, nnz, dim):
@@ -43,6 +73,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                         "(reference kernel for scaling the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +143,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "launches": 5}))
+        return
+
     from paper_1806_06917_amd import inputs
     from paper_1806_06917_amd import pd
 
@@ -137,15 +180,17 @@ def main():
                    "horizon": f"{round(w.delta / w.h)}h", "damage_s_c": w.s_c,
                    "precision": precision, "dt": w.dt, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": B},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(w.name, precision),
+                     "algorithmic_bytes_per_launch": B,
+                     "kernel_source_hash": kernel_source_hash()},
         "neighbor_build_s": r["t_nbr_s"],
     }
     if not args.no_fp64_compare and precision == "mixed":
         r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
     if not args.no_cpu_baseline:
-        steps = args.cpu_steps or (3 if w.n > 100000 else 20)
+        steps = args.cpu_steps or (60 if w.n > 100000 else 200)
         out["cpu_baseline"] = cpu_baseline(w, steps)
     print(json.dumps(out), flush=True)
 
