@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--config", default="cube100", choices=["cube100", "notched512", "plate32"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tile"])
+    ap.add_argument("--tile", type=int, default=0, help="nodes per tile (0 = automatic)")
+    ap.add_argument("--block", type=int, default=0, help="threads per tile workgroup (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
@@ -83,10 +86,11 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def run_gpu(torch, pd, w, precision, steps, warmup, lanes):
+def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)):
     ctx = pd.Context(0)
     if lanes:
         ctx.set_lanes(lanes)
+    ctx.set_tuning(*tuning)
     Xd = dev(torch, w.X)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -112,7 +116,7 @@ def run_gpu(torch, pd, w, precision, steps, warmup, lanes):
     ms = e0.elapsed_time(e1)
     info = sim.get(energies=True)
     res = {"ms_total": ms, "wall_s": wall, "nnz": nb.nnz, "t_nbr_s": t_nbr,
-           "ke": info["ke"], "pe": info["pe"], "step": info["step"]}
+           "ke": info["ke"], "pe": info["pe"], "step": info["step"], "launch": sim.info()}
     sim.close()
     nb.close()
     ctx.close()
@@ -158,7 +162,8 @@ def main():
 
     w = inputs.CONFIGS[args.config]()
     precision = args.precision or ("mixed" if args.config == "cube100" else "fp64")
-    r = run_gpu(torch, pd, w, precision, args.steps, args.warmup, args.lanes)
+    tuning = (args.kernel, args.tile, args.block)
+    r = run_gpu(torch, pd, w, precision, args.steps, args.warmup, args.lanes, tuning)
     ms_step = r["ms_total"] / args.steps
     bonds_per_s = r["nnz"] / (ms_step * 1e-3)
     B = algorithmic_bytes(w.n, r["nnz"], w.dim)
@@ -185,9 +190,10 @@ def main():
                      "algorithmic_bytes_per_launch": B,
                      "kernel_source_hash": kernel_source_hash()},
         "neighbor_build_s": r["t_nbr_s"],
+        "launch": r["launch"],
     }
     if not args.no_fp64_compare and precision == "mixed":
-        r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes)
+        r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes, tuning)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (60 if w.n > 100000 else 200)

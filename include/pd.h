@@ -247,6 +247,13 @@ int pd_sim_set(pd_sim sim, const double *u, const double *v, const uint8_t *aliv
 int pd_sim_destroy(pd_sim sim);
 
 /*
+ * Launch configuration a simulation runs with (each output may be NULL):
+ * kernel 1 = gather, 2 = LDS tiles; tile = nodes per tile (0 for gather);
+ * block = threads per workgroup; lanes = lanes per node.
+ */
+int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes);
+
+/*
  * Matrix-free tangent operator of the quasi-static problem, y = H w with
  * H = -V (x) df/du (the paper's tangent equation; exact for the linearised
  * law):

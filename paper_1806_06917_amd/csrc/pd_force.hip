@@ -52,17 +52,18 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
         if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
         const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
         for (uint32_t p = rs + lane; p < re; p += L) {
+            // a dead bond adds exact zeros, like the tile kernel's dummy record
             const uint32_t j = (uint32_t)a.col[p];
             const bool live = !a.alive || a.alive[p];
-            if (!live) continue;
             const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
             double ujx, ujy, ujz;
             load_vec<DIM>(a.u, j, ujx, ujy, ujz);
             if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
-            const double Vj = DIM == 3 ? xj.w : xj.z;
+            const double cVj =
+                live ? (a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z)) : 0.0;
             const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
             if (bond<DIM, MIXED, WANT_E>(a, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
-                                         duz, Vj, s64, s32))
+                                         duz, cVj, s64, s32) && live)
                 a.alive[p] = 0;
         }
     }
@@ -152,57 +153,85 @@ int pd_launch_gather(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mix
     return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed) : launch_d<2>(ctx, a, lanes, mixed);
 }
 
-namespace {
+// threads per tile workgroup: the tuning value, else one lane group per tile
+// node (measured best on the 1M-node cube and the 512^2 plate)
+static int tile_block(pd_ctx ctx, uint32_t T, int lanes) {
+    if (ctx->block) return ctx->block;
+    int block = (int)T * lanes;
+    return block < 256 ? 256 : (block > 1024 ? 1024 : block);
+}
 
-// Chooses the kernel for a neighbour list: LDS tiles when every tile's halo
-// fits in LDS (tried at the requested or automatic size, then halved), the
-// plain gather kernel otherwise.
-}  // namespace
+static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int block) {
+    int rpt;
+    unsigned grid;
+    uint32_t mmax;
+    size_t lds;
+    return pd_tile_geometry(nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
+                            pd_tile_bcap(nbr), block, ctx->num_cu, &rpt, &grid, &mmax, &lds);
+}
 
-int pd_prepare_tiles(pd_ctx ctx, pd_nbr nbr) {
-    if (ctx->kernel == 1 || nbr->tiles_failed) return PD_OK;
-    if (nbr->lcol && nbr->users > 0) return PD_OK;   // simulations depend on the layout
-    const size_t lds_max = 160 * 1024;
-    uint32_t T = ctx->tile ? (uint32_t)ctx->tile : (nbr->dim == 3 ? 64u : 256u);
-    if (nbr->tile_T == T && nbr->lcol) return PD_OK;
+// Chooses the kernel for one call site: *block > 0 selects the LDS tile
+// kernel with that many threads per workgroup (tiles built, or rebuilt at the
+// requested or automatic size and then halved, until one layout fits),
+// *block = 0 the plain gather kernel.  A layout used by live simulations is
+// never rebuilt.
+int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
+    *block = 0;
+    const bool forced = ctx->kernel == 2;
+    if (ctx->kernel == 1) return PD_OK;
+    if (lanes < 2 || lanes > 32) {
+        if (forced) return pd_set_error(ctx, PD_EINVAL, "the tile kernel needs 2..32 lanes");
+        return PD_OK;
+    }
+    if (nbr->lcol && nbr->users > 0) {
+        const int B = tile_block(ctx, nbr->tile_T, lanes);
+        if (tile_fits(ctx, nbr, B)) *block = B;
+        else if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit");
+        return PD_OK;
+    }
+    const uint64_t key = ((uint64_t)(uint32_t)ctx->tile << 32) ^ ((uint64_t)ctx->block << 8) ^
+                         (uint64_t)lanes;
+    if (nbr->fail_key == key + 1) {
+        if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit in LDS");
+        return PD_OK;
+    }
+    uint32_t T = ctx->tile ? (uint32_t)ctx->tile : (nbr->dim == 3 ? 64u : 128u);
     for (; T >= 16; T >>= 1) {
-        const int st = pd_nbr_build_tiles(ctx, nbr, T);
-        if (st == PD_OK &&
-            tile_lds_bytes(nbr->dim, (nbr->halo_max + 31u) & ~31u, (nbr->bonds_max + 63u) & ~63u) <=
-                lds_max)
+        if (!(nbr->lcol && nbr->tile_T == T)) {
+            const int st = pd_nbr_build_tiles(ctx, nbr, T);
+            if (st != PD_OK && st != PD_ECAPACITY) return st;
+            if (st == PD_ECAPACITY) {
+                if (ctx->tile) break;
+                continue;
+            }
+        }
+        const int B = tile_block(ctx, T, lanes);
+        if (tile_fits(ctx, nbr, B)) {
+            *block = B;
             return PD_OK;
-        if (st != PD_OK && st != PD_ECAPACITY) return st;
+        }
         if (ctx->tile) break;
     }
-    nbr->tiles_failed = 1;
-    if (ctx->kernel == 2)
-        return pd_set_error(ctx, PD_ECAPACITY, "tile halo does not fit in LDS");
+    nbr->fail_key = key + 1;
+    if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit in LDS");
     return PD_OK;
 }
 
-bool pd_use_tiles(pd_ctx ctx, const pd_nbr nbr) {
-    return ctx->kernel != 1 && nbr->lcol && !nbr->tiles_failed;
-}
-
 namespace {
 
-// a.bw set: tile kernel (the neighbour list has tiles); otherwise gather
-int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed) {
-    if (a.bw) {
+// block > 0 (with a.bw set): tile kernel; otherwise the gather kernel
+int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed, int block) {
+    if (block > 0 && a.bw) {
         a.halo_ptr = nbr->halo_ptr;
         a.halo = nbr->halo;
         a.self_off = nbr->self_off;
         a.tile = nbr->tile_T;
-        a.hcap = (nbr->halo_max + 31u) & ~31u;
-        a.bcap = (nbr->bonds_max + 63u) & ~63u;
-        // automatic: two groups per tile node (extra threads speed up staging)
-        int block = ctx->block;
-        if (!block) {
-            block = 2 * (int)nbr->tile_T * lanes;
-            block = block < 256 ? 256 : (block > 1024 ? 1024 : block);
-        }
+        a.ntiles = nbr->ntiles;
+        a.hcap = pd_tile_hcap(nbr);
+        a.bcap = pd_tile_bcap(nbr);
         return pd_launch_tile(ctx, nbr->dim, a, lanes, mixed, block);
     }
+    a.bw = nullptr;
     return pd_launch_gather(ctx, nbr->dim, a, lanes, mixed);
 }
 
@@ -237,7 +266,7 @@ int ensure_scratch(pd_ctx ctx, pd_nbr nbr) {
     if (!nbr->s_U) PD_TRY(pd_alloc(ctx, &nbr->s_U, (size_t)nbr->n));
     if (!nbr->s_alive) PD_TRY(pd_alloc(ctx, &nbr->s_alive, nbr->nnz));
     if (!nbr->s_fixed) PD_TRY(pd_alloc(ctx, &nbr->s_fixed, (size_t)nbr->n));
-    if (!nbr->s_bw && nbr->lcol) PD_TRY(pd_alloc(ctx, &nbr->s_bw, nbr->nnz));
+    if (!nbr->s_bw && nbr->lcol) PD_TRY(pd_alloc(ctx, &nbr->s_bw, nbr->nnz + 2));
     return PD_OK;
 }
 
@@ -265,9 +294,11 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_check_dev_ptr(ctx, f, "f"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (U) PD_TRY(pd_check_dev_ptr(ctx, U, "U"));
-    PD_TRY(pd_prepare_tiles(ctx, nbr));
+    const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    int block = 0;
+    PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
     PD_TRY(ensure_scratch(ctx, nbr));
-    const bool tiled = pd_use_tiles(ctx, nbr);
+    const bool tiled = block > 0;
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
     PD_TRY(pd_gather_vec(ctx, nbr, u, nbr->s_u, false));
     if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
@@ -281,8 +312,7 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     a.f_out = nbr->s_f;
     a.e_out = U ? nbr->s_U : nullptr;
     a.mode = M_FORCE;
-    PD_TRY(launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
-                       mat->precision == PD_MIXED));
+    PD_TRY(launch_node(ctx, nbr, a, lanes, mat->precision == PD_MIXED, block));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, f));
     if (U) PD_TRY(pd_scatter_scalar(ctx, nbr, nbr->s_U, U));
     if (alive && a.damage) {
@@ -296,7 +326,7 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
 // tangent operator (used by the implicit solver as well)
 // ---------------------------------------------------------------------------
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                   const uint8_t *alive_sfc, uint16_t *bw, const uint8_t *fixed_sfc,
+                   const uint8_t *alive_sfc, uint16_t *bw, int block, const uint8_t *fixed_sfc,
                    const double *w, double *y, const int *done) {
     NodeArgs a = base_args(nbr, mat);
     a.done = done;
@@ -309,12 +339,12 @@ int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const d
     a.f_out = y;
     a.mode = M_TANGENT;
     return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n),
-                       mat->precision == PD_MIXED);
+                       mat->precision == PD_MIXED, block);
 }
 
 // internal force in sfc order, no damage: f = force(u) (implicit residuals)
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                 const uint8_t *alive_sfc, uint16_t *bw, const double *u, double *f) {
+                 const uint8_t *alive_sfc, uint16_t *bw, int block, const double *u, double *f) {
     NodeArgs a = base_args(nbr, mat);
     a.xv = xv;
     a.u = u;
@@ -323,7 +353,7 @@ int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const dou
     a.damage = 0;
     a.f_out = f;
     a.mode = M_FORCE;
-    return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false);
+    return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false, block);
 }
 
 extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
@@ -339,17 +369,18 @@ extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, 
     PD_TRY(pd_check_dev_ptr(ctx, y, "y"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (fixed) PD_TRY(pd_check_dev_ptr(ctx, fixed, "fixed"));
-    PD_TRY(pd_prepare_tiles(ctx, nbr));
+    int block = 0;
+    PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
     PD_TRY(ensure_scratch(ctx, nbr));
-    const bool tiled = pd_use_tiles(ctx, nbr);
+    const bool tiled = block > 0;
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
     PD_TRY(pd_gather_vec(ctx, nbr, w, nbr->s_u, false));
     if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
     if (tiled) PD_TRY(pd_bw_compose(ctx, nbr, alive ? nbr->s_alive : nullptr, nbr->s_bw));
     if (fixed) PD_TRY(pd_gather_u8(ctx, nbr, fixed, nbr->s_fixed, 0));
     PD_TRY(pd_tangent_sfc(ctx, nbr, mat, nbr->s_xv, alive ? nbr->s_alive : nullptr,
-                          tiled ? nbr->s_bw : nullptr, fixed ? nbr->s_fixed : nullptr, nbr->s_u,
-                          nbr->s_f, nullptr));
+                          tiled ? nbr->s_bw : nullptr, block, fixed ? nbr->s_fixed : nullptr,
+                          nbr->s_u, nbr->s_f, nullptr));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, y));
     return PD_OK;
 }
@@ -406,7 +437,9 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
                 return pd_set_error(ctx, PD_EINVAL, "notch coordinates must be finite");
         }
 
-    PD_TRY(pd_prepare_tiles(ctx, nbr));
+    const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    int block = 0;
+    PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
     pd_sim s = new (std::nothrow) pd_sim_s();
     if (!s) return PD_ENOMEM;
     s->ctx = ctx;
@@ -437,11 +470,18 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "notch_k", __FILE__, __LINE__);
     }
-    if (st == PD_OK && pd_use_tiles(ctx, nbr)) {
+    s->lanes = lanes;
+    s->block = block;
+    if (st == PD_OK && block > 0) {
         s->tiled = true;
         nbr->users += 1;
-        st = pd_alloc(ctx, &s->bw, nbr->nnz);
+        st = pd_alloc(ctx, &s->bw, nbr->nnz + 2);
         if (st == PD_OK) st = pd_bw_compose(ctx, nbr, s->alive, s->bw);
+    }
+    if (st == PD_OK) {
+        double Vu = 0.0;
+        st = pd_uniform_volume(ctx, nbr, s->xv, &Vu);
+        s->cv_uniform = mat->c * Vu;
     }
     if (st == PD_OK) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -451,7 +491,6 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         sim_release(s);
         return st;
     }
-    s->lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     *out = s;
     return PD_OK;
 }
@@ -462,6 +501,7 @@ static NodeArgs sim_args(pd_sim s) {
     a.v = s->v;
     a.alive = s->alive;
     a.bw = s->tiled ? s->bw : nullptr;
+    a.cv_uniform = s->cv_uniform;
     a.damage = s->mat.s_c > 0.0;
     a.bc = s->bc;
     a.bc_vel = s->bc_vel;
@@ -487,7 +527,7 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
         a.u = sim->u[sim->cur];
         a.u_out = sim->u[sim->cur ^ 1];
         a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
-        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, mixed));
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, mixed, sim->block));
         sim->cur ^= 1;
         sim->v_half = true;
         sim->step += 1;
@@ -504,7 +544,8 @@ static int sim_close(pd_sim sim) {
     a.mode = M_CLOSE;
     a.u = sim->u[sim->cur];
     a.r_full = ramp_factor((double)sim->step, sim->ramp);
-    PD_TRY(launch_node(sim->ctx, sim->nbr, a, sim->lanes, sim->mat.precision == PD_MIXED));
+    PD_TRY(launch_node(sim->ctx, sim->nbr, a, sim->lanes, sim->mat.precision == PD_MIXED,
+                       sim->block));
     sim->v_half = false;
     return PD_OK;
 }
@@ -531,7 +572,7 @@ extern "C" int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, doub
         a.damage = 0;
         a.u = sim->u[sim->cur];
         a.e_out = sim->scratch;
-        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, false));
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, false, sim->block));
         PD_TRY(pd_sum(ctx, sim->scratch, sim->nbr->n, 2, ke_pe));
     }
     if (step) *step = sim->step;
@@ -558,6 +599,15 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
         if (sim->tiled) PD_TRY(pd_bw_compose(ctx, sim->nbr, sim->alive, sim->bw));
     }
     sim->step = step;
+    return PD_OK;
+}
+
+extern "C" int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes) {
+    if (!sim) return PD_EINVAL;
+    if (kernel) *kernel = sim->tiled ? 2 : 1;
+    if (tile) *tile = sim->tiled ? (int)sim->nbr->tile_T : 0;
+    if (block) *block = sim->tiled ? sim->block : PD_BLOCK;
+    if (lanes) *lanes = sim->lanes;
     return PD_OK;
 }
 

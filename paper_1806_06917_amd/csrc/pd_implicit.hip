@@ -140,6 +140,7 @@ struct Work {
            *p = nullptr, *q = nullptr, *part_a = nullptr, *part_b = nullptr;
     uint8_t *alive = nullptr, *fixed = nullptr;
     uint16_t *bw = nullptr;
+    int block = 0;
     CgState *st = nullptr;
     CgState *st_host = nullptr;
     ~Work() {
@@ -185,8 +186,8 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, uint
         const int nrun = std::min(chunk, budget - it);
         for (int k = 0; k < nrun; ++k) {
             const int parity = (it + k) & 1;
-            PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.fixed, w.p, w.q,
-                                  &w.st->done));
+            PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.block, w.fixed, w.p,
+                                  w.q, &w.st->done));
             dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.p, w.q, m, w.part_a, w.st);
             cg_update_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.x, w.r, w.p, w.q, m, w.part_a,
                                                           w.part_b, w.st, parity);
@@ -252,9 +253,11 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         PD_TRY(pd_alloc(ctx, &w.fixed, n));
         PD_TRY(pd_gather_u8(ctx, nbr, fixed, w.fixed, 0));
     }
-    PD_TRY(pd_prepare_tiles(ctx, nbr));
-    if (pd_use_tiles(ctx, nbr)) {
-        PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz));
+    int block = 0;
+    PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
+    w.block = block;
+    if (block > 0) {
+        PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz + 2));
         PD_TRY(pd_bw_compose(ctx, nbr, w.alive, w.bw));
     }
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, w.xv));
@@ -275,7 +278,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     int outer = 0, inner_total = 0, status = PD_ENOCONV;
     double rel = 0.0;
     while (true) {
-        PD_TRY(pd_force_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.u, w.f));
+        PD_TRY(pd_force_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.block, w.u, w.f));
         residual_k<<<gm, PD_BLOCK, 0, ctx->stream>>>(n, us, dim, w.xv, w.f, w.b, w.fixed, w.r);
         PD_LAUNCH_CHECK(ctx);
         double rr = 0.0;

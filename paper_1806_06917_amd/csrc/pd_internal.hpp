@@ -6,8 +6,9 @@
 //   XV      double[n][4]   {x, y, z, V} (3-d) or {x, y, V, 0} (2-d), constant
 //   u, v    double[n][US]  US = 4 in 3-d ({x, y, z, 0}), 2 in 2-d
 //   row_ptr uint32[n+1], col int32[nnz] (sfc ids), rows ascending by the
-//           neighbour's ORIGINAL id, so that a row's bond k maps to exported
-//           position ex_row_ptr[perm[i]] + k without a per-bond table
+//           neighbour's sfc id (so the lanes of a node read nearby records);
+//           ex_pos uint32[nnz] maps each bond to its position in the exported
+//           CSR (original numbering, neighbours ascending by original id)
 //   alive   uint8[nnz]     1 = intact
 #pragma once
 
@@ -32,11 +33,14 @@ struct pd_ctx_s {
     int kernel = 0;         // 0: automatic, 1: gather, 2: LDS tiles
     int tile = 0;           // nodes per tile, 0: automatic
     int block = 0;          // threads per tile workgroup, 0: automatic
+    int num_cu = 256;       // compute units of the device
     int failed = 0;         // sticky device failure
     std::string last_error;
     double *red = nullptr;  // device partial sums, PD_RED_BLOCKS * PD_RED_SLOTS
     double *red_host = nullptr;  // pinned mirror of red
-    int *flag = nullptr;    // device status word (non-finite, coincident ...)
+    int *flag = nullptr;    // the common nodal volume if all n volumes are equal, else 0 (synchronises)
+int pd_uniform_volume(pd_ctx ctx, const pd_nbr nbr, const double *xv, double *V);
+// device status word (non-finite, coincident ...)
     int *flag_host = nullptr;
 };
 
@@ -52,6 +56,7 @@ struct pd_nbr_s {
     uint32_t *row_ptr = nullptr; // [n+1] sfc order
     int32_t *col = nullptr;      // [nnz] sfc ids
     uint32_t *ex_row_ptr = nullptr;  // [n+1] original order
+    uint32_t *ex_pos = nullptr;      // [nnz] exported position of each internal bond
     // LDS tiles (pd_tile.hip): T consecutive sfc nodes per tile
     uint32_t tile_T = 0, ntiles = 0, halo_max = 0, bonds_max = 0;
     uint64_t halo_total = 0;
@@ -59,7 +64,7 @@ struct pd_nbr_s {
     int32_t *halo = nullptr;       // sorted sfc ids of each tile's halo
     uint32_t *self_off = nullptr;  // [ntiles] local index of the tile's first node
     uint16_t *lcol = nullptr;      // [nnz] tile-local neighbour index
-    int tiles_failed = 0;          // halo too large for LDS at every tried size
+    uint64_t fail_key = 0;         // last tuning request no tile layout fitted (+1)
     int users = 0;                 // simulations attached (their bond words use the tiles)
     uint16_t *s_bw = nullptr;      // scratch bond words for the stateless entry points
     // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
@@ -81,6 +86,8 @@ struct pd_sim_s {
     uint8_t *alive = nullptr;    // bond flags (gather kernel; export copy for tiles)
     uint16_t *bw = nullptr;      // bond words (tile kernel): local index | dead bit
     bool tiled = false;          // this simulation runs the tile kernel
+    int block = 0;               // its tile-kernel workgroup size (0: gather kernel)
+    double cv_uniform = 0.0;     // c V if all volumes are equal, else 0
     bool bw_newer = false;       // bw holds damage not yet copied to alive
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
     int64_t step = 0;
@@ -172,6 +179,8 @@ int pd_alive_in(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst);
 int pd_alive_out(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst);
 // deterministic sums of `slots` interleaved per-node values: data[i*slots + s]
 int pd_sum(pd_ctx ctx, const double *data, uint32_t n, int slots, double *out);
+// the common nodal volume if all n volumes are equal, else 0 (synchronises)
+int pd_uniform_volume(pd_ctx ctx, const pd_nbr nbr, const double *xv, double *V);
 // device status word
 int pd_flag_clear(pd_ctx ctx);
 int pd_flag_read(pd_ctx ctx, int *value);
@@ -181,13 +190,12 @@ int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name);
 int pd_nbr_build_tiles(pd_ctx ctx, pd_nbr nbr, uint32_t T);
 
 // sfc-order building blocks of the implicit solver (pd_force.hip)
-// bw: bond words for the tile kernel, or NULL to use the gather kernel
+// bw + block > 0: tile kernel with bond words bw; otherwise the gather kernel
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                   const uint8_t *alive_sfc, uint16_t *bw, const uint8_t *fixed_sfc,
+                   const uint8_t *alive_sfc, uint16_t *bw, int block, const uint8_t *fixed_sfc,
                    const double *w, double *y, const int *done);
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
-                 const uint8_t *alive_sfc, uint16_t *bw, const double *u, double *f);
-// tile kernel usable for this neighbour list under the context's tuning
-bool pd_use_tiles(pd_ctx ctx, const pd_nbr nbr);
-// builds the tiles if the tuning allows (no-op when they exist and are in use)
-int pd_prepare_tiles(pd_ctx ctx, pd_nbr nbr);
+                 const uint8_t *alive_sfc, uint16_t *bw, int block, const double *u, double *f);
+// kernel choice for a call site under the context's tuning; *block > 0 means
+// the tile kernel with that workgroup size, 0 the gather kernel
+int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block);

@@ -17,7 +17,7 @@ struct NodeArgs {
     double *__restrict__ v;            // [n][US]
     const uint32_t *__restrict__ row_ptr;
     const int32_t *__restrict__ col;   // sfc ids (gather kernel)
-    uint16_t *__restrict__ bw;         // tile kernel bond words: local id | 0x8000 if broken
+    uint16_t *__restrict__ bw;         // tile kernel bond words: local id | 0x8000 once broken
     const uint32_t *__restrict__ halo_ptr;
     const int32_t *__restrict__ halo;
     const uint32_t *__restrict__ self_off;
@@ -33,9 +33,12 @@ struct NodeArgs {
     uint32_t tile;                     // nodes per tile (tile kernel)
     uint32_t hcap;                     // halo records held in LDS (tile kernel)
     uint32_t bcap;                     // bonds per tile held in LDS (tile kernel)
+    uint32_t ntiles;                   // tiles (tile kernel)
+    uint32_t mmax;                     // tiles per workgroup, upper bound (tile kernel)
     int mode;
     int damage;
     double c, s_c, rho, dt, r_half, r_full;
+    double cv_uniform;                 // c V when every node has volume V, else 0
     float c32, s_c32;
 };
 
@@ -47,9 +50,6 @@ struct Acc64 {
 struct Acc32 {
     float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0, e = 0;
 };
-
-constexpr uint16_t BW_DEAD = 0x8000;
-constexpr uint16_t BW_IDX = 0x7fff;
 
 // Kahan-compensated running sum: s + lo tracks the exact sum of the inputs
 // to within a few units of float32 rounding (lo = -c of Kahan's notation)
@@ -89,39 +89,49 @@ __device__ __forceinline__ void store_vec(double *p, uint32_t i, double x, doubl
     else reinterpret_cast<double2 *>(p)[i] = make_double2(x, y);
 }
 
-// One bond: xi = X_j - X_i, eta = u_j - u_i (both formed in float64).
-// Returns true if the bond breaks now (S > s_c); otherwise accumulates
-// c S V_j xi/|xi| (and (c/4) S^2 |xi| V_j if want_e).
+// 1/sqrt(r2) for finite r2 > 0: the hardware estimate refined by one
+// third-order correction, y = y0 + y0 e (1/2 + 3/8 e), e = 1 - r2 y0^2
+__device__ __forceinline__ double rsqrt_pos(double r2) {
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(y0 * -r2, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
+// One bond: xi = X_j - X_i, eta = u_j - u_i (both formed in float64) and
+// cVj = c V_j (0 for a bond that must not contribute).  Returns true if the
+// bond breaks now (S > s_c); a breaking bond contributes nothing.  Otherwise
+// accumulates c V_j S xi/|xi| (and (c/4) V_j S^2 |xi| if WANT_E).
 template <int DIM, bool MIXED, bool WANT_E>
 __device__ __forceinline__ bool bond(const NodeArgs &a, double dxx, double dxy,
-                                     double dxz, double dux, double duy, double duz, double Vj,
+                                     double dxz, double dux, double duy, double duz, double cVj,
                                      Acc64 &s64, Acc32 &s32) {
     if (!MIXED) {
         const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
         const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
-        const double inv = rsqrt(r2);
+        const double inv = rsqrt_pos(r2);
         const double S = ex * (inv * inv);
-        if (a.damage && S > a.s_c) return true;
-        const double g = a.c * S * Vj * inv;
+        const bool brk = a.damage && S > a.s_c;
+        const double g = brk ? 0.0 : cVj * S * inv;
         s64.x += g * dxx;
         s64.y += g * dxy;
         if (DIM == 3) s64.z += g * dxz;
-        if (WANT_E) s64.e += 0.25 * a.c * S * S * (r2 * inv) * Vj;
+        if (WANT_E) s64.e += brk ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
+        return brk;
     } else {
         const float fx = (float)dxx, fy = (float)dxy, fz = (float)dxz;
         const float ux = (float)dux, uy = (float)duy, uz = (float)duz;
         const float r2 = DIM == 3 ? fx * fx + fy * fy + fz * fz : fx * fx + fy * fy;
         const float ex = DIM == 3 ? ux * fx + uy * fy + uz * fz : ux * fx + uy * fy;
-        const float inv = rsqrtf(r2);
+        const float inv = __builtin_amdgcn_rsqf(r2);
         const float S = ex * (inv * inv);
-        if (a.damage && S > a.s_c32) return true;
-        const float g = a.c32 * S * (float)Vj * inv;
+        const bool brk = a.damage && S > a.s_c32;
+        const float g = brk ? 0.0f : (float)cVj * S * inv;
         kahan_acc(s32.x, s32.cx, g * fx);
         kahan_acc(s32.y, s32.cy, g * fy);
         if (DIM == 3) kahan_acc(s32.z, s32.cz, g * fz);
-        if (WANT_E) s32.e += 0.25f * a.c32 * S * S * (r2 * inv) * (float)Vj;
+        if (WANT_E) s32.e += brk ? 0.0f : 0.25f * (float)cVj * S * S * (r2 * inv);
+        return brk;
     }
-    return false;
 }
 
 // xor butterfly over the L lanes of a group: every lane ends with the sum
@@ -257,8 +267,16 @@ __host__ __device__ inline bool mode_wants_energy(const NodeArgs &a) {
 int pd_launch_gather(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed);
 int pd_launch_tile(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed,
                    int block);
-// LDS bytes the tile kernel needs for hcap halo records and bcap bonds
-size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap);
-// bond words of a tiled neighbour list: bw = lcol | BW_DEAD where alive == 0
+// LDS bytes of one tile-kernel workgroup
+size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint32_t mmax);
+// launch geometry of the persistent tile kernel; false if the layout does not fit
+bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
+                      int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
+                      size_t *lds);
+// LDS halo capacity of a tiled neighbour list
+inline uint32_t pd_tile_hcap(const pd_nbr nbr) { return (nbr->halo_max + 31u) & ~31u; }
+inline uint32_t pd_tile_bcap(const pd_nbr nbr) { return (nbr->bonds_max + 63u) & ~63u; }
+// bond words of a tiled neighbour list: bw = lcol | 0x8000 where alive == 0
+// (bw arrays hold nnz + 2 entries for the kernel's 32-bit reads)
 int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw);
 int pd_bw_to_alive(pd_ctx ctx, const pd_nbr nbr, const uint16_t *bw, uint8_t *alive_sfc);

@@ -209,20 +209,68 @@ __global__ void candidates_k(Grid g, double thr, uint32_t n, const double4 *xs,
     if (!FILL) cnt[s] = m;
 }
 
-// one thread per row: insertion sort of the row by the neighbour's original id
-__global__ void row_sort_k(uint32_t n, const uint32_t *row_ptr, const int32_t *perm, int32_t *col) {
+// one thread per row: insertion sort of the row by sfc id (the candidates
+// arrive bin by bin in curve order, so rows are nearly sorted already)
+__global__ void row_sort_k(uint32_t n, const uint32_t *row_ptr, int32_t *col) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint32_t a = row_ptr[s], e = row_ptr[s + 1];
     for (uint32_t p = a + 1; p < e; ++p) {
         const int32_t c = col[p];
-        const int32_t key = perm[c];
         uint32_t q = p;
-        while (q > a && perm[col[q - 1]] > key) {
+        while (q > a && col[q - 1] > c) {
             col[q] = col[q - 1];
             --q;
         }
         col[q] = c;
+    }
+}
+
+// exported rows (original numbering) filled unsorted, one wave per row ...
+__global__ void excol_fill_k(uint32_t n, const int32_t *perm, const uint32_t *row_ptr,
+                             const uint32_t *ex_row_ptr, const int32_t *col, int32_t *ex_col) {
+    const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const uint32_t lane = threadIdx.x % 64;
+    if (s >= n) return;
+    const uint32_t a = row_ptr[s], e = row_ptr[s + 1], x = ex_row_ptr[perm[s]];
+    for (uint32_t k = lane; k < e - a; k += 64) ex_col[x + k] = perm[col[a + k]];
+}
+
+// ... then sorted by original id, one thread per row
+__global__ void excol_sort_k(uint32_t n, const uint32_t *ex_row_ptr, int32_t *ex_col) {
+    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const uint32_t a = ex_row_ptr[o], e = ex_row_ptr[o + 1];
+    for (uint32_t p = a + 1; p < e; ++p) {
+        const int32_t c = ex_col[p];
+        uint32_t q = p;
+        while (q > a && ex_col[q - 1] > c) {
+            ex_col[q] = ex_col[q - 1];
+            --q;
+        }
+        ex_col[q] = c;
+    }
+}
+
+// exported position of every internal bond: binary search of the
+// neighbour's original id in its exported row (one wave per row)
+__global__ void ex_pos_k(uint32_t n, const int32_t *perm, const uint32_t *row_ptr,
+                         const uint32_t *ex_row_ptr, const int32_t *col, const int32_t *ex_col,
+                         uint32_t *ex_pos) {
+    const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const uint32_t lane = threadIdx.x % 64;
+    if (s >= n) return;
+    const uint32_t a = row_ptr[s], e = row_ptr[s + 1];
+    const uint32_t xa = ex_row_ptr[perm[s]], xe = ex_row_ptr[perm[s] + 1];
+    for (uint32_t p = a + lane; p < e; p += 64) {
+        const int32_t key = perm[col[p]];
+        uint32_t lo = xa, hi = xe;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ex_col[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        ex_pos[p] = lo;
     }
 }
 
@@ -234,13 +282,10 @@ __global__ void orig_counts_k(uint32_t n, const int32_t *perm, const uint32_t *c
     atomicMax(max_row, (int32_t)cnt[s]);
 }
 
-__global__ void export_cols_k(uint32_t n, const int32_t *perm, const uint32_t *row_ptr,
-                              const uint32_t *ex_row_ptr, const int32_t *col, int32_t *out) {
-    const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const uint32_t lane = threadIdx.x % 64;
-    if (s >= n) return;
-    const uint32_t a = row_ptr[s], e = row_ptr[s + 1], x = ex_row_ptr[perm[s]];
-    for (uint32_t k = lane; k < e - a; k += 64) out[x + k] = perm[col[a + k]];
+__global__ void export_cols_k(uint64_t nnz, const int32_t *perm, const int32_t *col,
+                              const uint32_t *ex_pos, int32_t *out) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) out[ex_pos[p]] = perm[col[p]];
 }
 
 }  // namespace
@@ -252,6 +297,7 @@ static void nbr_release(pd_nbr b) {
     pd_free(b->row_ptr);
     pd_free(b->col);
     pd_free(b->ex_row_ptr);
+    pd_free(b->ex_pos);
     pd_free(b->halo_ptr);
     pd_free(b->halo);
     pd_free(b->self_off);
@@ -274,7 +320,9 @@ struct Tmp {
     double4 *xs = nullptr;
     double *part = nullptr;
     int32_t *maxrow = nullptr;
+    int32_t *ex_col = nullptr;
     ~Tmp() {
+        pd_free(ex_col);
         pd_free(key); pd_free(bstart); pd_free(scan); pd_free(binm); pd_free(hist);
         pd_free(cursor); pd_free(cnt); pd_free(cnt_orig); pd_free(xs); pd_free(part);
         pd_free(maxrow);
@@ -373,7 +421,7 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     candidates_k<true><<<pd_blocks(n), PD_BLOCK, 0, st>>>(g, b->thr, n, t.xs, t.bstart, nullptr,
                                                          b->row_ptr, b->col, ctx->flag);
     PD_LAUNCH_CHECK(ctx);
-    row_sort_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->row_ptr, b->perm, b->col);
+    row_sort_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->row_ptr, b->col);
     PD_LAUNCH_CHECK(ctx);
 
     // exported (original-order) row offsets and the longest row
@@ -385,6 +433,19 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     PD_TRY(pd_scan_u32(ctx, t.cnt_orig, t.scan, n));
     PD_TRY(pd_alloc(ctx, &b->ex_row_ptr, (size_t)n + 1));
     PD_TRY(pd_narrow_u64(ctx, t.scan, b->ex_row_ptr, n));
+    // exported position of each internal bond (rows in original numbering,
+    // neighbours ascending by original id)
+    PD_TRY(pd_alloc(ctx, &t.ex_col, nnz));
+    PD_TRY(pd_alloc(ctx, &b->ex_pos, nnz));
+    excol_fill_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, st>>>(n, b->perm, b->row_ptr,
+                                                                    b->ex_row_ptr, b->col, t.ex_col);
+    PD_LAUNCH_CHECK(ctx);
+    excol_sort_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->ex_row_ptr, t.ex_col);
+    PD_LAUNCH_CHECK(ctx);
+    ex_pos_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, st>>>(n, b->perm, b->row_ptr,
+                                                                b->ex_row_ptr, b->col, t.ex_col,
+                                                                b->ex_pos);
+    PD_LAUNCH_CHECK(ctx);
     PD_HIP(ctx, hipMemcpyAsync(&b->max_row, t.maxrow, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     PD_HIP(ctx, hipStreamSynchronize(st));
     return PD_OK;
@@ -440,8 +501,8 @@ extern "C" int pd_nbr_export(pd_nbr nbr, int64_t *row_ptr, int32_t *col) {
     if (col && nbr->nnz) {
         int32_t *d = nullptr;
         PD_TRY(pd_alloc(ctx, &d, nbr->nnz));
-        export_cols_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, ctx->stream>>>(
-            n, nbr->perm, nbr->row_ptr, nbr->ex_row_ptr, nbr->col, d);
+        export_cols_k<<<pd_blocks(nbr->nnz), PD_BLOCK, 0, ctx->stream>>>(
+            nbr->nnz, nbr->perm, nbr->col, nbr->ex_pos, d);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess)
             e = hipMemcpyAsync(col, d, sizeof(int32_t) * nbr->nnz, hipMemcpyDeviceToHost,

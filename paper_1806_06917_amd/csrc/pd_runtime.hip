@@ -106,6 +106,11 @@ extern "C" int pd_ctx_create(int device, void *hip_stream, pd_ctx *out) {
         delete c;
         return PD_EDEVICE;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        c->num_cu = ncu;
+    (void)hipGetLastError();
     int st = pd_alloc(c, &c->red, (size_t)PD_RED_BLOCKS * PD_RED_SLOTS);
     if (st == PD_OK) st = pd_alloc(c, &c->flag, 1);
     if (st == PD_OK &&
@@ -315,20 +320,15 @@ __global__ void gather_u8_k(const int32_t *perm, uint32_t n, const uint8_t *src,
     if (s < n) dst[s] = src ? src[perm[s]] : fill;
 }
 
-// one 64-lane wave per row; bond k of internal row s is bond k of exported
-// row perm[s] (both rows are sorted by the neighbour's original id)
+// bond flags between exported and internal order through the exported
+// position of each internal bond
 template <bool IN>
-__global__ void alive_move_k(const int32_t *perm, const uint32_t *row_ptr, const uint32_t *ex_row_ptr,
-                             uint32_t n, const uint8_t *src, uint8_t *dst) {
-    const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const uint32_t lane = threadIdx.x % 64;
-    if (s >= n) return;
-    const uint32_t a = row_ptr[s], e = row_ptr[s + 1];
-    const uint32_t x = ex_row_ptr[perm[s]];
-    for (uint32_t k = lane; k < e - a; k += 64) {
-        if (IN) dst[a + k] = src ? src[x + k] : (uint8_t)1;
-        else dst[x + k] = src[a + k];
-    }
+__global__ void alive_move_k(const uint32_t *ex_pos, uint64_t nnz, const uint8_t *src,
+                             uint8_t *dst) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnz) return;
+    if (IN) dst[p] = src ? src[ex_pos[p]] : (uint8_t)1;
+    else dst[ex_pos[p]] = src[p];
 }
 
 __global__ void sum_partials_k(const double *data, uint32_t n, int slots, double *part) {
@@ -346,6 +346,31 @@ __global__ void sum_partials_k(const double *data, uint32_t n, int slots, double
         }
         if (threadIdx.x == 0) part[s * gridDim.x + blockIdx.x] = sh[0];
         __syncthreads();
+    }
+}
+
+__global__ void vol_range_k(const double *xv, uint32_t n, int vi, double *part) {
+    __shared__ double smin[PD_BLOCK], smax[PD_BLOCK];
+    double mn = INFINITY, mx = -INFINITY;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const double v = xv[4 * i + vi];
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = PD_BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + off]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = smin[0];
+        part[gridDim.x + blockIdx.x] = smax[0];
     }
 }
 
@@ -388,15 +413,15 @@ int pd_gather_u8(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst,
 }
 
 int pd_alive_in(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst) {
-    alive_move_k<true><<<pd_blocks((uint64_t)nbr->n * 64), PD_BLOCK, 0, ctx->stream>>>(
-        nbr->perm, nbr->row_ptr, nbr->ex_row_ptr, nbr->n, src, dst);
+    alive_move_k<true><<<pd_blocks(nbr->nnz), PD_BLOCK, 0, ctx->stream>>>(nbr->ex_pos, nbr->nnz,
+                                                                          src, dst);
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;
 }
 
 int pd_alive_out(pd_ctx ctx, const pd_nbr nbr, const uint8_t *src, uint8_t *dst) {
-    alive_move_k<false><<<pd_blocks((uint64_t)nbr->n * 64), PD_BLOCK, 0, ctx->stream>>>(
-        nbr->perm, nbr->row_ptr, nbr->ex_row_ptr, nbr->n, src, dst);
+    alive_move_k<false><<<pd_blocks(nbr->nnz), PD_BLOCK, 0, ctx->stream>>>(nbr->ex_pos, nbr->nnz,
+                                                                           src, dst);
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;
 }
@@ -413,6 +438,22 @@ int pd_sum(pd_ctx ctx, const double *data, uint32_t n, int slots, double *out) {
         for (int k = 0; k < PD_RED_BLOCKS; ++k) acc += ctx->red_host[s * PD_RED_BLOCKS + k];
         out[s] = acc;
     }
+    return PD_OK;
+}
+
+int pd_uniform_volume(pd_ctx ctx, const pd_nbr nbr, const double *xv, double *V) {
+    vol_range_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, ctx->stream>>>(xv, nbr->n, nbr->dim == 3 ? 3 : 2,
+                                                              ctx->red);
+    PD_LAUNCH_CHECK(ctx);
+    PD_HIP(ctx, hipMemcpyAsync(ctx->red_host, ctx->red, sizeof(double) * 2 * PD_RED_BLOCKS,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double mn = INFINITY, mx = -INFINITY;
+    for (int k = 0; k < PD_RED_BLOCKS; ++k) {
+        mn = fmin(mn, ctx->red_host[k]);
+        mx = fmax(mx, ctx->red_host[PD_RED_BLOCKS + k]);
+    }
+    *V = (nbr->n > 0 && mn == mx) ? mn : 0.0;
     return PD_OK;
 }
 

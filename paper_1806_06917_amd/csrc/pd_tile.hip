@@ -127,95 +127,235 @@ __global__ __launch_bounds__(TB_BUILD) void tile_fill_k(uint32_t n, uint32_t T,
 }
 
 // ---------------------------------------------------------------------------
-// tile kernel: stage the halo records and the tile's bond streams in LDS,
-// then one group of L lanes per node
+// tile kernel
+//
+// Persistent: workgroup b works through the tiles tbeg + l, tbeg + l + gx, ...
+// of the contiguous tile range its XCD owns (x = b mod 8, l = b / 8, gx
+// workgroups on that XCD), so neighbouring tiles share an L2.  Three-stage
+// software pipeline over those tiles:
+//   ids(k+2)  halo ids of the tile after next          -> registers
+//   recs(k+1) halo records, bond words, row offsets     -> registers
+//   tile k    from LDS: bond sums, then the node updates
+// so the HBM/L2 latency of staging a tile hides behind the previous tile's
+// arithmetic.  Per-tile metadata for all of the workgroup's tiles is read
+// into LDS once at the start, so no prefetch waits on a dependent load.
+// LDS holds each halo record as {x y z ux uy uz} (2-d: {x y ux uy} padded):
+// a 48-byte stride puts the 16-byte reads of eight consecutive records in
+// eight disjoint bank windows (rows are sorted by sfc id, so a node's lanes
+// mostly read consecutive records).  c V_j lives in its own array and is not
+// read at all when every node has the same volume.  A broken bond keeps its
+// index with bit 15 set and contributes exact zeros (c V_j taken as 0), so
+// the per-node sum is the same, bit for bit, as the gather kernel's.
 // ---------------------------------------------------------------------------
 template <int DIM>
 struct Rec {
-    static constexpr int NC = DIM == 3 ? 7 : 5;   // {x y [z] V ux uy [uz]}
-    static constexpr int V = DIM;                 // index of V
-    static constexpr int U = DIM + 1;             // index of ux
+    static constexpr int NC = 6;                  // doubles per record (48 bytes)
+    static constexpr int U = DIM;                 // index of ux
 };
 
-template <int DIM, int L, bool MIXED, bool WANT_E>
-__global__ void tile_kernel(NodeArgs a) {
-    if (a.done && *a.done) return;
-    extern __shared__ double lds[];
-    constexpr int NC = Rec<DIM>::NC, IV = Rec<DIM>::V, IU = Rec<DIM>::U;
-    double *rec = lds;                                            // [hcap][NC]
-    uint16_t *sbw = reinterpret_cast<uint16_t *>(lds + (size_t)a.hcap * NC);
-    const uint32_t t = pd_xcd_tile(blockIdx.x, gridDim.x);
-    const bool tangent = a.mode == M_TANGENT;
-    const uint32_t t0 = t * a.tile;
-    const uint32_t tn = min(a.tile, a.n - t0);
-    const uint32_t b0 = a.row_ptr[t0], bn = a.row_ptr[t0 + tn] - b0;
+constexpr int TILE_WPT = 8;          // 32-bit bond-word pairs staged per thread
+constexpr int TILE_META = 5;         // h0, hn, b0 (even), b1, self offset
+constexpr uint16_t BW_DEAD = 0x8000;
+constexpr uint16_t BW_IDX = 0x7fff;
 
-    // stage the halo records and the tile's bond words
-    const uint32_t h0 = a.halo_ptr[t], hn = a.halo_ptr[t + 1] - h0;
-    for (uint32_t k = threadIdx.x; k < hn; k += blockDim.x) {
-        const uint32_t id = (uint32_t)a.halo[h0 + k];
-        const double4 q = reinterpret_cast<const double4 *>(a.xv)[id];
-        double ux, uy, uz;
-        load_vec<DIM>(a.u, id, ux, uy, uz);
-        if (tangent && a.bc && a.bc[id]) { ux = 0; uy = 0; uz = 0; }
-        double *r = rec + (size_t)k * NC;
-        r[0] = q.x;
-        r[1] = q.y;
-        if (DIM == 3) { r[2] = q.z; r[IV] = q.w; } else { r[IV] = q.z; }
-        r[IU] = ux;
-        r[IU + 1] = uy;
-        if (DIM == 3) r[IU + 2] = uz;
+// record j as 16-byte LDS reads (the 48-byte stride keeps every record
+// 16-byte aligned)
+template <int DIM>
+__device__ __forceinline__ void read_rec(const double *rec, uint32_t j, double *A) {
+    const double2 *q = reinterpret_cast<const double2 *>(rec + (size_t)j * Rec<DIM>::NC);
+    const double2 a0 = q[0], a1 = q[1];
+    A[0] = a0.x; A[1] = a0.y; A[2] = a1.x; A[3] = a1.y;
+    if (DIM == 3) {
+        const double2 a2 = q[2];
+        A[4] = a2.x; A[5] = a2.y;
     }
-    for (uint32_t k = threadIdx.x; k < bn; k += blockDim.x) sbw[k] = a.bw[b0 + k];
+}
+
+template <int DIM, int L, bool MIXED, bool WANT_E, int RPT>
+__global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
+    if (a.done && *a.done) return;
+    extern __shared__ __attribute__((aligned(16))) double lds[];
+    constexpr int NC = Rec<DIM>::NC, IU = Rec<DIM>::U;
+    constexpr int WPT = TILE_WPT;
+    const uint32_t B = blockDim.x, tid = threadIdx.x;
+    const uint32_t H = a.hcap, T = a.tile;
+    const bool cv_uniform = a.cv_uniform != 0.0;
+    double *rec = lds;                                                   // H * NC
+    double *cv = rec + (size_t)H * NC;                                   // H
+    double *fres = cv + H;                                               // T * 4
+    uint32_t *meta = reinterpret_cast<uint32_t *>(fres + (size_t)T * 4);  // mmax * TILE_META
+    uint32_t *srp = meta + (size_t)a.mmax * TILE_META;                    // T + 1
+    uint32_t *sbw = srp + (T + 1);                                        // bond-word pairs
+    const uint16_t *sbw16 = reinterpret_cast<const uint16_t *>(sbw);
+    const uint32_t *bw32 = reinterpret_cast<const uint32_t *>(a.bw);
+    const bool tangent = a.mode == M_TANGENT;
+
+    const uint32_t nb = gridDim.x, x = blockIdx.x % 8, l = blockIdx.x / 8;
+    const uint32_t gx = nb / 8 + (x < nb % 8 ? 1u : 0u);
+    const uint32_t tq = a.ntiles / 8, tr = a.ntiles % 8;
+    const uint32_t tbeg = x * tq + (x < tr ? x : tr), tcnt = tq + (x < tr ? 1u : 0u);
+    const uint32_t K = l < tcnt ? (tcnt - l + gx - 1) / gx : 0u;
+    if (K == 0) return;
+
+    for (uint32_t k = tid; k < K; k += B) {
+        const uint32_t t = tbeg + l + k * gx, t0 = t * T, tn = min(T, a.n - t0);
+        const uint32_t h0 = a.halo_ptr[t];
+        uint32_t *m = meta + (size_t)k * TILE_META;
+        m[0] = h0;
+        m[1] = a.halo_ptr[t + 1] - h0;
+        m[2] = a.row_ptr[t0] & ~1u;
+        m[3] = a.row_ptr[t0 + tn];
+        m[4] = a.self_off[t];
+    }
     __syncthreads();
 
-    const uint32_t so = a.self_off[t];
-    const uint32_t groups = blockDim.x / L;
-    const uint32_t g = threadIdx.x / L;
-    const int lane = threadIdx.x & (L - 1);
-    for (uint32_t q = g; q < tn; q += groups) {
-        const uint32_t i = t0 + q;
-        const double *ri = rec + (size_t)(so + q) * NC;
-        const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0, Vi = ri[IV];
-        const double uix = ri[IU], uiy = ri[IU + 1], uiz = DIM == 3 ? ri[IU + 2] : 0.0;
-        const bool fixed_i = tangent && a.bc && a.bc[i];
-        Acc64 s64;
-        Acc32 s32;
-        const uint32_t rs = a.row_ptr[i] - b0, re = a.row_ptr[i + 1] - b0;
-        // each lane takes bonds rs+lane, rs+lane+L, ... in this order, two at a time
-        uint32_t p = rs + lane;
-        for (; p + L < re; p += 2 * L) {
-            const uint16_t w0 = sbw[p], w1 = sbw[p + L];
-            const double *r0 = rec + (size_t)(w0 & BW_IDX) * NC;
-            const double *r1 = rec + (size_t)(w1 & BW_IDX) * NC;
-            double A[NC], B[NC];
+    // pipeline registers
+    int32_t pid[RPT], pid_next[RPT];
+    double4 pxv[RPT];
+    double pux[RPT], puy[RPT], puz[RPT];
+    uint8_t pfix[RPT];
+    uint32_t pw[WPT];
+    uint32_t prp = 0;
+
+    auto fetch_ids = [&](uint32_t k, int32_t *ids) {
+        const uint32_t h0 = meta[k * TILE_META], hn = meta[k * TILE_META + 1];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) { A[c] = r0[c]; B[c] = r1[c]; }
-            if (!(w0 & BW_DEAD) &&
-                bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy, DIM == 3 ? A[2] - xiz : 0.0,
-                                         A[IU] - uix, A[IU + 1] - uiy,
-                                         DIM == 3 ? A[IU + 2] - uiz : 0.0, A[IV], s64, s32))
-                a.bw[b0 + p] = w0 | BW_DEAD;
-            if (!(w1 & BW_DEAD) &&
-                bond<DIM, MIXED, WANT_E>(a, B[0] - xix, B[1] - xiy, DIM == 3 ? B[2] - xiz : 0.0,
-                                         B[IU] - uix, B[IU + 1] - uiy,
-                                         DIM == 3 ? B[IU + 2] - uiz : 0.0, B[IV], s64, s32))
-                a.bw[b0 + p + L] = w1 | BW_DEAD;
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t q = tid + r * B;
+            ids[r] = q < hn ? a.halo[h0 + q] : 0;
         }
-        if (p < re) {
-            const uint16_t w0 = sbw[p];
-            const double *r0 = rec + (size_t)(w0 & BW_IDX) * NC;
-            if (!(w0 & BW_DEAD) &&
-                bond<DIM, MIXED, WANT_E>(a, r0[0] - xix, r0[1] - xiy, DIM == 3 ? r0[2] - xiz : 0.0,
-                                         r0[IU] - uix, r0[IU + 1] - uiy,
-                                         DIM == 3 ? r0[IU + 2] - uiz : 0.0, r0[IV], s64, s32))
-                a.bw[b0 + p] = w0 | BW_DEAD;
+    };
+    auto fetch_tile = [&](uint32_t k) {
+        const uint32_t t = tbeg + l + k * gx, t0 = t * T, tn = min(T, a.n - t0);
+        const uint32_t hn = meta[k * TILE_META + 1];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t q = tid + r * B;
+            if (q < hn) {
+                const uint32_t id = (uint32_t)pid[r];
+                pxv[r] = reinterpret_cast<const double4 *>(a.xv)[id];
+                load_vec<DIM>(a.u, id, pux[r], puy[r], puz[r]);
+                pfix[r] = (tangent && a.bc) ? a.bc[id] : (uint8_t)0;
+            }
         }
-        double fx, fy, fz, Ue;
-        group_reduce<DIM, L, MIXED, WANT_E>(s64, s32, fx, fy, fz, Ue);
-        if (lane == 0) {
-            // a fixed node's own w is zero in LDS; node_update re-reads it
-            node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i);
+        const uint32_t b0 = meta[k * TILE_META + 2], b1 = meta[k * TILE_META + 3];
+        const uint32_t nw = (b1 - b0 + 1) / 2;
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) {
+            const uint32_t q = tid + w * B;
+            if (q < nw) pw[w] = bw32[b0 / 2 + q];
+        }
+        if (tid <= tn) prp = a.row_ptr[t0 + tid];
+    };
+
+    fetch_ids(0, pid);
+    fetch_tile(0);
+    if (K > 1) fetch_ids(1, pid_next);
+
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t t = tbeg + l + k * gx, t0 = t * T, tn = min(T, a.n - t0);
+        const uint32_t hn = meta[k * TILE_META + 1], b0 = meta[k * TILE_META + 2];
+        const uint32_t b1 = meta[k * TILE_META + 3], so = meta[k * TILE_META + 4];
+        const uint32_t nw = (b1 - b0 + 1) / 2;
+        __syncthreads();                       // LDS free: tile k-1 is complete
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const uint32_t q = tid + r * B;
+            if (q < hn) {
+                double *rr = rec + (size_t)q * NC;
+                const bool fz = pfix[r] != 0;
+                rr[0] = pxv[r].x;
+                rr[1] = pxv[r].y;
+                if (DIM == 3) rr[2] = pxv[r].z;
+                rr[IU] = fz ? 0.0 : pux[r];
+                rr[IU + 1] = fz ? 0.0 : puy[r];
+                if (DIM == 3) rr[IU + 2] = fz ? 0.0 : puz[r];
+                if (!cv_uniform) cv[q] = a.c * (DIM == 3 ? pxv[r].w : pxv[r].z);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < WPT; ++w) {
+            const uint32_t q = tid + w * B;
+            if (q < nw) sbw[q] = pw[w];
+        }
+        if (tid <= tn) srp[tid] = prp - b0;
+        __syncthreads();
+
+        // prefetch: records of tile k+1 (ids already here), ids of tile k+2
+        if (k + 1 < K) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) pid[r] = pid_next[r];
+            fetch_tile(k + 1);
+            if (k + 2 < K) fetch_ids(k + 2, pid_next);
+        }
+
+        // bond sums of tile k
+        const uint32_t groups = B / L, g = tid / L;
+        const int lane = tid & (L - 1);
+        for (uint32_t q = g; q < tn; q += groups) {
+            const double *ri = rec + (size_t)(so + q) * NC;
+            const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
+            const double uix = ri[IU], uiy = ri[IU + 1], uiz = DIM == 3 ? ri[IU + 2] : 0.0;
+            Acc64 s64;
+            Acc32 s32;
+            const uint32_t rs = srp[q], re = srp[q + 1];
+            uint32_t p = rs + lane;
+            for (; p + L < re; p += 2 * L) {
+                const uint32_t w0 = sbw16[p], w1 = sbw16[p + L];
+                const uint32_t j0 = w0 & BW_IDX, j1 = w1 & BW_IDX;
+                double A[NC], C[NC];
+                read_rec<DIM>(rec, j0, A);
+                read_rec<DIM>(rec, j1, C);
+                const double cv0 = cv_uniform ? a.cv_uniform : cv[j0];
+                const double cv1 = cv_uniform ? a.cv_uniform : cv[j1];
+                if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                                             DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
+                                             A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
+                                             (w0 & BW_DEAD) ? 0.0 : cv0, s64, s32) &&
+                    !(w0 & BW_DEAD))
+                    a.bw[b0 + p] = (uint16_t)(w0 | BW_DEAD);
+                if (bond<DIM, MIXED, WANT_E>(a, C[0] - xix, C[1] - xiy,
+                                             DIM == 3 ? C[2] - xiz : 0.0, C[IU] - uix,
+                                             C[IU + 1] - uiy, DIM == 3 ? C[IU + 2] - uiz : 0.0,
+                                             (w1 & BW_DEAD) ? 0.0 : cv1, s64, s32) &&
+                    !(w1 & BW_DEAD))
+                    a.bw[b0 + p + L] = (uint16_t)(w1 | BW_DEAD);
+            }
+            if (p < re) {
+                const uint32_t w0 = sbw16[p], j0 = w0 & BW_IDX;
+                double A[NC];
+                read_rec<DIM>(rec, j0, A);
+                const double cv0 = cv_uniform ? a.cv_uniform : cv[j0];
+                if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                                             DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
+                                             A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
+                                             (w0 & BW_DEAD) ? 0.0 : cv0, s64, s32) &&
+                    !(w0 & BW_DEAD))
+                    a.bw[b0 + p] = (uint16_t)(w0 | BW_DEAD);
+            }
+            double fx, fy, fz, Ue;
+            group_reduce<DIM, L, MIXED, WANT_E>(s64, s32, fx, fy, fz, Ue);
+            if (lane == 0) {
+                double *fr = fres + (size_t)q * 4;
+                fr[0] = fx;
+                fr[1] = fy;
+                fr[2] = fz;
+                fr[3] = Ue;
+            }
+        }
+        __syncthreads();
+
+        // node updates of tile k
+        for (uint32_t q = tid; q < tn; q += B) {
+            const uint32_t i = t0 + q;
+            const double *ri = rec + (size_t)(so + q) * NC;
+            const double *fr = fres + (size_t)q * 4;
+            const bool fixed_i = tangent && a.bc && a.bc[i];
+            const double Vi = (a.mode == M_TANGENT || a.mode == M_ENERGY)
+                                  ? a.xv[4 * (size_t)i + (DIM == 3 ? 3 : 2)]
+                                  : 0.0;
+            node_update<DIM>(a, i, fr[0], fr[1], fr[2], fr[3], Vi, ri[IU], ri[IU + 1],
+                             DIM == 3 ? ri[IU + 2] : 0.0, fixed_i);
         }
     }
 }
@@ -223,7 +363,8 @@ __global__ void tile_kernel(NodeArgs a) {
 __global__ void bw_compose_k(uint64_t nnz, const uint16_t *lcol, const uint8_t *alive,
                              uint16_t *bw) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nnz) bw[p] = lcol[p] | ((alive && !alive[p]) ? BW_DEAD : (uint16_t)0);
+    if (p < nnz + 2)
+        bw[p] = p >= nnz ? BW_DEAD : (uint16_t)(lcol[p] | ((alive && !alive[p]) ? BW_DEAD : 0));
 }
 
 __global__ void bw_alive_k(uint64_t nnz, const uint16_t *bw, uint8_t *alive) {
@@ -231,52 +372,98 @@ __global__ void bw_alive_k(uint64_t nnz, const uint16_t *bw, uint8_t *alive) {
     if (p < nnz) alive[p] = (bw[p] & BW_DEAD) ? 0 : 1;
 }
 
+template <int DIM, int L, bool MIXED, bool WANT_E>
+void *pick_rpt(int rpt) {
+    return rpt == 1 ? (void *)tile_kernel<DIM, L, MIXED, WANT_E, 1>
+                    : (void *)tile_kernel<DIM, L, MIXED, WANT_E, 2>;
+}
 
 template <int DIM, int L>
-int launch_t(pd_ctx ctx, const NodeArgs &a, bool mixed, int block) {
-    const unsigned grid = (a.n + a.tile - 1) / a.tile;
-    if (grid == 0) return PD_OK;
-    const size_t lds = tile_lds_bytes(DIM, a.hcap, a.bcap);
-    void (*k)(NodeArgs);
-    const bool e = mode_wants_energy(a);
-    if (mixed) k = e ? tile_kernel<DIM, L, true, true> : tile_kernel<DIM, L, true, false>;
-    else k = e ? tile_kernel<DIM, L, false, true> : tile_kernel<DIM, L, false, false>;
-    (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    k<<<grid, block, lds, ctx->stream>>>(a);
-    PD_LAUNCH_CHECK(ctx);
-    return PD_OK;
+void *pick_kernel(bool mixed, bool e, int rpt) {
+    if (mixed) return e ? pick_rpt<DIM, L, true, true>(rpt) : pick_rpt<DIM, L, true, false>(rpt);
+    return e ? pick_rpt<DIM, L, false, true>(rpt) : pick_rpt<DIM, L, false, false>(rpt);
 }
 
 template <int DIM>
-int launch_d(pd_ctx ctx, const NodeArgs &a, int lanes, bool mixed, int block) {
+void *pick_lanes(int lanes, bool mixed, bool e, int rpt) {
     switch (lanes) {
-    case 1: return launch_t<DIM, 1>(ctx, a, mixed, block);
-    case 2: return launch_t<DIM, 2>(ctx, a, mixed, block);
-    case 4: return launch_t<DIM, 4>(ctx, a, mixed, block);
-    case 8: return launch_t<DIM, 8>(ctx, a, mixed, block);
-    case 16: return launch_t<DIM, 16>(ctx, a, mixed, block);
-    case 32: return launch_t<DIM, 32>(ctx, a, mixed, block);
-    case 64: return launch_t<DIM, 64>(ctx, a, mixed, block);
-    default: return pd_set_error(ctx, PD_EINVAL, "unsupported lane count %d", lanes);
+    case 2: return pick_kernel<DIM, 2>(mixed, e, rpt);
+    case 4: return pick_kernel<DIM, 4>(mixed, e, rpt);
+    case 8: return pick_kernel<DIM, 8>(mixed, e, rpt);
+    case 16: return pick_kernel<DIM, 16>(mixed, e, rpt);
+    case 32: return pick_kernel<DIM, 32>(mixed, e, rpt);
+    default: return nullptr;
     }
 }
 
 }  // namespace
 
-size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap) {
-    const int nc = dim == 3 ? 7 : 5;
-    return (size_t)hcap * nc * sizeof(double) + (size_t)bcap * sizeof(uint16_t);
+size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint32_t mmax) {
+    (void)dim;
+    return (size_t)hcap * 7 * sizeof(double) + (size_t)tile * 4 * sizeof(double) +
+           (size_t)mmax * TILE_META * sizeof(uint32_t) + (size_t)(tile + 1) * sizeof(uint32_t) +
+           (size_t)(bcap / 2 + 2) * sizeof(uint32_t);
 }
 
-int pd_launch_tile(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mixed, int block) {
-    return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed, block)
-                    : launch_d<2>(ctx, a, lanes, mixed, block);
+// Launch geometry of the persistent tile kernel: threads per workgroup,
+// records staged per thread (RPT), workgroups, and the per-workgroup tile
+// bound mmax.  Returns false if the layout does not fit.
+bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
+                      int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
+                      size_t *lds) {
+    const size_t lds_max = 160 * 1024;
+    *rpt = (hcap + (uint32_t)block - 1) / (uint32_t)block;
+    if (*rpt < 1) *rpt = 1;
+    if (*rpt > 2) return false;
+    if (bcap / 2 + 2 > (uint32_t)(TILE_WPT * block)) return false;
+    for (int per_cu = 2; per_cu >= 1; --per_cu) {
+        unsigned g = (unsigned)(num_cu * per_cu);
+        if (g > ntiles) g = ntiles;
+        if (g < 1) g = 1;
+        // largest tile count of one workgroup
+        uint32_t m = 0;
+        for (uint32_t x = 0; x < 8; ++x) {
+            const uint32_t gx = g / 8 + (x < g % 8 ? 1u : 0u);
+            const uint32_t tc = ntiles / 8 + (x < ntiles % 8 ? 1u : 0u);
+            if (gx == 0) {
+                if (tc) m = 0xffffffffu;
+                continue;
+            }
+            const uint32_t kk = (tc + gx - 1) / gx;
+            if (kk > m) m = kk;
+        }
+        if (m == 0xffffffffu) continue;
+        const size_t bytes = tile_lds_bytes(dim, hcap, bcap, tile, m);
+        if (bytes * (size_t)per_cu <= lds_max || (per_cu == 1 && bytes <= lds_max)) {
+            *grid = g;
+            *mmax = m;
+            *lds = bytes;
+            return true;
+        }
+    }
+    return false;
+}
+
+int pd_launch_tile(pd_ctx ctx, int dim, const NodeArgs &a0, int lanes, bool mixed, int block) {
+    NodeArgs a = a0;
+    int rpt = 0;
+    unsigned grid = 0;
+    size_t lds = 0;
+    if (!pd_tile_geometry(dim, a.ntiles, a.tile, a.hcap, a.bcap, block, ctx->num_cu, &rpt, &grid,
+                          &a.mmax, &lds))
+        return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit this launch");
+    const bool e = mode_wants_energy(a);
+    void *k = dim == 3 ? pick_lanes<3>(lanes, mixed, e, rpt) : pick_lanes<2>(lanes, mixed, e, rpt);
+    if (!k) return pd_set_error(ctx, PD_EINVAL, "tile kernel needs 2..32 lanes, got %d", lanes);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void *args[] = {&a};
+    PD_HIP(ctx, hipLaunchKernel(k, dim3(grid), dim3(block), args, lds, ctx->stream));
+    return PD_OK;
 }
 
 int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw) {
-    bw_compose_k<<<pd_blocks(nbr->nnz), PD_BLOCK, 0, ctx->stream>>>(nbr->nnz, nbr->lcol,
-                                                                     alive_sfc, bw);
+    bw_compose_k<<<pd_blocks(nbr->nnz + 2), PD_BLOCK, 0, ctx->stream>>>(nbr->nnz, nbr->lcol,
+                                                                         alive_sfc, bw);
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;
 }
@@ -295,6 +482,7 @@ int pd_nbr_build_tiles(pd_ctx ctx, pd_nbr nbr, uint32_t T) {
     pd_free(nbr->halo);
     pd_free(nbr->self_off);
     pd_free(nbr->lcol);
+    pd_free(nbr->s_bw);
     nbr->tile_T = 0;
     const uint32_t n = nbr->n;
     const uint32_t ntiles = (n + T - 1) / T;

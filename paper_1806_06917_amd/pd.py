@@ -66,6 +66,7 @@ def _load():
         "pd_sim_get": (i32, [vp, vp, vp, vp, vp, vp]),
         "pd_sim_set": (i32, [vp, vp, vp, vp, i64]),
         "pd_sim_destroy": (i32, [vp]),
+        "pd_sim_info": (i32, [vp, P(i32), P(i32), P(i32), P(i32)]),
         "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
         "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
                                     P(SolveInfo)]),
@@ -239,6 +240,14 @@ class Simulation:
         if not (allow_nonfinite and st == PD_ENONFINITE):
             self.ctx.check(st, "pd_sim_get")
         return {"ke": kp[0], "pe": kp[1], "step": step.value, "status": st}
+
+    def info(self):
+        """Launch configuration: kernel ('gather' | 'tile'), tile, block, lanes."""
+        k, t, b, l = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        self.ctx.check(lib.pd_sim_info(self.h, C.byref(k), C.byref(t), C.byref(b), C.byref(l)),
+                       "pd_sim_info")
+        return {"kernel": {1: "gather", 2: "tile"}[k.value], "tile": t.value, "block": b.value,
+                "lanes": l.value}
 
     def set(self, u=None, v=None, alive=None, step=0):
         self.ctx.check(lib.pd_sim_set(self.h, _ptr(u), _ptr(v), _ptr(alive), int(step)),

@@ -406,6 +406,7 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     w.v0 = v0
     sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(3, w.E, w.delta), prec)
+    assert sim.info()["kernel"] == "tile"          # the benchmark's launch configuration
     sim.step(3, w.dt)
     u, v, a, info = read_state(torch, sim, w.n, 3, nb.nnz)
     tol = TOL64 if prec == "fp64" else TOLMIX
@@ -432,13 +433,17 @@ def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
         w = notched(N=72)
     c = pd.micromodulus(w.dim, w.E, w.delta)
     results = []
-    for kind, tile, block in [("gather", 0, 0), ("tile", 16, 64), ("tile", 64, 256),
-                              ("tile", 256, 512), ("tile", 0, 0)]:
+    for kind, tile, block in [("gather", 0, 0), ("tile", 32, 0), ("tile", 64, 512),
+                              ("tile", 128, 0), ("tile", 0, 0)]:
         say("tile vs gather", wl, prec, kind, tile, block)
         ctx.set_tuning(kind, tile, block)
         try:
             nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
             s = sim_from_workload(torch, pd, ctx, nb, w, c, prec)
+            info = s.info()
+            assert info["kernel"] == ("gather" if kind == "gather" else "tile"), info
+            if tile:
+                assert info["tile"] == tile
             s.step(25, w.dt)
             results.append(read_state(torch, s, w.n, w.dim, nb.nnz)[:3])
             s.close()
