@@ -119,6 +119,13 @@ double pd_micromodulus(int dim, double E, double delta);
  * Returns PD_EDEVICE when no such device exists.
  */
 int pd_ctx_create(int device, void *hip_stream, pd_ctx *out);
+/*
+ * Synchronises the stream and releases the context.  If neighbour lists or
+ * simulations created on it are still alive, its memory is kept until the
+ * last of them is destroyed, and every later call that takes this context
+ * (directly or through those handles) fails with PD_EINVAL; destroying
+ * them stays valid.  A second destroy returns PD_EINVAL.
+ */
 int pd_ctx_destroy(pd_ctx ctx);
 const char *pd_last_error(pd_ctx ctx);
 
@@ -175,6 +182,9 @@ int pd_nbr_export(pd_nbr nbr, int64_t *row_ptr, int32_t *col);
  * internal space-filling-curve order (for diagnostics). */
 int pd_nbr_permutation(pd_nbr nbr, int32_t *perm);
 
+/* Synchronises the stream and releases the list; with simulations built on
+ * it still alive, its memory goes with the last of them (which keep working).
+ * A second destroy returns PD_EINVAL. */
 int pd_nbr_destroy(pd_nbr nbr);
 
 /*

@@ -41,7 +41,6 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
 
     double xix = 0, xiy = 0, xiz = 0, Vi = 0, uix = 0, uiy = 0, uiz = 0;
     Acc64 s64;
-    Acc32 s32;
     bool fixed_i = false;
     if (valid) {
         const double4 q = reinterpret_cast<const double4 *>(a.xv)[i];
@@ -59,18 +58,20 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
             double ujx, ujy, ujz;
             load_vec<DIM>(a.u, j, ujx, ujy, ujz);
             if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
-            const double cVj =
-                live ? (a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z)) : 0.0;
+            const double cVj = a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z);
             const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
             if (bond<DIM, MIXED, WANT_E>(a, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
-                                         duz, cVj, s64, s32) && live)
+                                         duz, cVj, !live, s64))
                 a.alive[p] = 0;
         }
     }
     double fx, fy, fz, Ue;
-    group_reduce<DIM, L, MIXED, WANT_E>(s64, s32, fx, fy, fz, Ue);
+    group_reduce<DIM, L, WANT_E>(s64, fx, fy, fz, Ue);
     if (!valid || lane != 0) return;
-    node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i);
+    double vx = 0, vy = 0, vz = 0;
+    if (mode_reads_v(a.mode)) load_vec<DIM>(a.v, i, vx, vy, vz);
+    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
+    node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i, vx, vy, vz, kind);
 }
 
 // notch pre-crack: orientation tests in float64 without contraction, end
@@ -153,14 +154,6 @@ int pd_launch_gather(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mix
     return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed) : launch_d<2>(ctx, a, lanes, mixed);
 }
 
-// threads per tile workgroup: the tuning value, else one lane group per tile
-// node (measured best on the 1M-node cube and the 512^2 plate)
-static int tile_block(pd_ctx ctx, uint32_t T, int lanes) {
-    if (ctx->block) return ctx->block;
-    int block = (int)T * lanes;
-    return block < 256 ? 256 : (block > 1024 ? 1024 : block);
-}
-
 static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int block) {
     int rpt;
     unsigned grid;
@@ -168,6 +161,18 @@ static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int block) {
     size_t lds;
     return pd_tile_geometry(nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
                             pd_tile_bcap(nbr), block, ctx->num_cu, &rpt, &grid, &mmax, &lds);
+}
+
+// threads per tile workgroup for the tiles nbr holds now: the tuning value,
+// else one lane group per tile node (measured best on the 1M-node cube and
+// the 512^2 plate), doubled while the halo or the bond words of the largest
+// tile need more threads than that to stage
+static int tile_block(pd_ctx ctx, const pd_nbr nbr, int lanes) {
+    if (ctx->block) return ctx->block;
+    int block = (int)nbr->tile_T * lanes;
+    block = block < 256 ? 256 : (block > 1024 ? 1024 : block);
+    while (block < 1024 && !tile_fits(ctx, nbr, block)) block *= 2;
+    return block;
 }
 
 // Chooses the kernel for one call site: *block > 0 selects the LDS tile
@@ -184,7 +189,7 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
         return PD_OK;
     }
     if (nbr->lcol && nbr->users > 0) {
-        const int B = tile_block(ctx, nbr->tile_T, lanes);
+        const int B = tile_block(ctx, nbr, lanes);
         if (tile_fits(ctx, nbr, B)) *block = B;
         else if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit");
         return PD_OK;
@@ -205,7 +210,7 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
                 continue;
             }
         }
-        const int B = tile_block(ctx, T, lanes);
+        const int B = tile_block(ctx, nbr, lanes);
         if (tile_fits(ctx, nbr, B)) {
             *block = B;
             return PD_OK;
@@ -285,6 +290,7 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
                                  const double *V, const double *u, uint8_t *alive, double *f,
                                  double *U) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
@@ -360,6 +366,7 @@ extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, 
                                 const double *V, const uint8_t *alive, const uint8_t *fixed,
                                 const double *w, double *y) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
@@ -401,7 +408,11 @@ static void sim_release(pd_sim s) {
     pd_free(s->bw);
     pd_free(s->scratch);
     if (s->nbr && s->tiled) s->nbr->users -= 1;
+    pd_ctx ctx = s->ctx;
+    pd_nbr nbr = s->nbr;
     delete s;
+    pd_nbr_unref(nbr);
+    pd_ctx_unref(ctx);
 }
 
 extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
@@ -411,6 +422,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (!out) return pd_set_error(ctx, PD_EINVAL, "out must not be NULL");
     *out = nullptr;
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
@@ -444,6 +456,8 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (!s) return PD_ENOMEM;
     s->ctx = ctx;
     s->nbr = nbr;
+    ctx->refs += 1;
+    nbr->refs += 1;
     s->mat = *mat;
     s->ramp = ramp_steps;
     const size_t n = nbr->n, us = nbr->dim == 3 ? 4 : 2;

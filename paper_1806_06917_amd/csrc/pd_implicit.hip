@@ -212,6 +212,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
                                  const double *b, double *u, double rtol, int maxit,
                                  pd_solve_info *info) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
+    if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     if (!mat || mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "bad material");

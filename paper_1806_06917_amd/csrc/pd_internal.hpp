@@ -38,10 +38,10 @@ struct pd_ctx_s {
     std::string last_error;
     double *red = nullptr;  // device partial sums, PD_RED_BLOCKS * PD_RED_SLOTS
     double *red_host = nullptr;  // pinned mirror of red
-    int *flag = nullptr;    // the common nodal volume if all n volumes are equal, else 0 (synchronises)
-int pd_uniform_volume(pd_ctx ctx, const pd_nbr nbr, const double *xv, double *V);
-// device status word (non-finite, coincident ...)
+    int *flag = nullptr;    // device status word (non-finite, coincident ...)
     int *flag_host = nullptr;
+    int refs = 0;           // neighbour lists and simulations created on this context
+    bool closing = false;   // destroyed while refs > 0: freed with the last of them
 };
 
 struct pd_nbr_s {
@@ -66,6 +66,8 @@ struct pd_nbr_s {
     uint16_t *lcol = nullptr;      // [nnz] tile-local neighbour index
     uint64_t fail_key = 0;         // last tuning request no tile layout fitted (+1)
     int users = 0;                 // simulations attached (their bond words use the tiles)
+    int refs = 0;                  // simulations built on this list
+    bool closing = false;          // destroyed while refs > 0: freed with the last of them
     uint16_t *s_bw = nullptr;      // scratch bond words for the stateless entry points
     // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
     double *s_xv = nullptr, *s_u = nullptr, *s_f = nullptr, *s_U = nullptr;
@@ -188,6 +190,11 @@ int pd_flag_read(pd_ctx ctx, int *value);
 int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name);
 
 int pd_nbr_build_tiles(pd_ctx ctx, pd_nbr nbr, uint32_t T);
+
+// handle lifetimes: a context or neighbour list destroyed while handles built
+// on it are alive is freed when the last of those goes
+void pd_ctx_unref(pd_ctx ctx);
+void pd_nbr_unref(pd_nbr nbr);
 
 // sfc-order building blocks of the implicit solver (pd_force.hip)
 // bw + block > 0: tile kernel with bond words bw; otherwise the gather kernel

@@ -42,34 +42,10 @@ struct NodeArgs {
     float c32, s_c32;
 };
 
+// per-lane FP64 running sums of the bond forces (and bond energies)
 struct Acc64 {
     double x = 0, y = 0, z = 0, e = 0;
 };
-
-// float32 sums with their low-order parts (x + cx is the lane's sum)
-struct Acc32 {
-    float x = 0, y = 0, z = 0, cx = 0, cy = 0, cz = 0, e = 0;
-};
-
-// Kahan-compensated running sum: s + lo tracks the exact sum of the inputs
-// to within a few units of float32 rounding (lo = -c of Kahan's notation)
-__device__ __forceinline__ void kahan_acc(float &s, float &lo, float a) {
-#pragma clang fp contract(off)
-    const float y = a + lo;
-    const float t = s + y;
-    lo = y - (t - s);
-    s = t;
-}
-
-// s + a = s' + err exactly (Knuth two-sum); err accumulates into c
-__device__ __forceinline__ void two_sum_acc(float &s, float &c, float a) {
-#pragma clang fp contract(off)
-    const float t = s + a;
-    const float z = t - s;
-    const float err = (s - (t - z)) + (a - z);
-    s = t;
-    c = c + err;
-}
 
 template <int DIM>
 __device__ __forceinline__ void load_vec(const double *p, uint32_t i, double &x, double &y,
@@ -97,84 +73,58 @@ __device__ __forceinline__ double rsqrt_pos(double r2) {
     return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
-// One bond: xi = X_j - X_i, eta = u_j - u_i (both formed in float64) and
-// cVj = c V_j (0 for a bond that must not contribute).  Returns true if the
-// bond breaks now (S > s_c); a breaking bond contributes nothing.  Otherwise
-// accumulates c V_j S xi/|xi| (and (c/4) V_j S^2 |xi| if WANT_E).
+// One bond: xi = X_j - X_i, eta = u_j - u_i, cVj = c V_j; `dead` marks a bond
+// broken earlier.  Returns true if the bond breaks now (S > s_c); a bond that
+// is dead or breaks now contributes exact zeros.  Otherwise adds
+// c V_j S xi/|xi| (and (c/4) V_j S^2 |xi| if WANT_E) to the lane's sums.
+// Everything runs in float64; mixed precision takes 1/|xi| from the hardware
+// reciprocal-square-root estimate alone (relative error below 2^-22), the
+// FP64 mode refines it to full double precision.
 template <int DIM, bool MIXED, bool WANT_E>
-__device__ __forceinline__ bool bond(const NodeArgs &a, double dxx, double dxy,
-                                     double dxz, double dux, double duy, double duz, double cVj,
-                                     Acc64 &s64, Acc32 &s32) {
-    if (!MIXED) {
-        const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
-        const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
-        const double inv = rsqrt_pos(r2);
-        const double S = ex * (inv * inv);
-        const bool brk = a.damage && S > a.s_c;
-        const double g = brk ? 0.0 : cVj * S * inv;
-        s64.x += g * dxx;
-        s64.y += g * dxy;
-        if (DIM == 3) s64.z += g * dxz;
-        if (WANT_E) s64.e += brk ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
-        return brk;
-    } else {
-        const float fx = (float)dxx, fy = (float)dxy, fz = (float)dxz;
-        const float ux = (float)dux, uy = (float)duy, uz = (float)duz;
-        const float r2 = DIM == 3 ? fx * fx + fy * fy + fz * fz : fx * fx + fy * fy;
-        const float ex = DIM == 3 ? ux * fx + uy * fy + uz * fz : ux * fx + uy * fy;
-        const float inv = __builtin_amdgcn_rsqf(r2);
-        const float S = ex * (inv * inv);
-        const bool brk = a.damage && S > a.s_c32;
-        const float g = brk ? 0.0f : (float)cVj * S * inv;
-        kahan_acc(s32.x, s32.cx, g * fx);
-        kahan_acc(s32.y, s32.cy, g * fy);
-        if (DIM == 3) kahan_acc(s32.z, s32.cz, g * fz);
-        if (WANT_E) s32.e += brk ? 0.0f : 0.25f * (float)cVj * S * S * (r2 * inv);
-        return brk;
-    }
+__device__ __forceinline__ bool bond(const NodeArgs &a, double dxx, double dxy, double dxz,
+                                     double dux, double duy, double duz, double cVj, bool dead,
+                                     Acc64 &s) {
+    const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
+    const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+    const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
+    const double S = ex * (inv * inv);
+    const bool brk = a.damage && S > a.s_c;
+    const bool off = brk || dead;
+    const double g = off ? 0.0 : cVj * S * inv;
+    s.x += g * dxx;
+    s.y += g * dxy;
+    if (DIM == 3) s.z += g * dxz;
+    if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
+    return brk && !dead;
 }
 
 // xor butterfly over the L lanes of a group: every lane ends with the sum
-template <int DIM, int L, bool MIXED, bool WANT_E>
-__device__ __forceinline__ void group_reduce(Acc64 &s64, Acc32 &s32, double &fx,
-                                             double &fy, double &fz, double &Ue) {
-    if (!MIXED) {
+template <int DIM, int L, bool WANT_E>
+__device__ __forceinline__ void group_reduce(Acc64 &s, double &fx, double &fy, double &fz,
+                                             double &Ue) {
 #pragma unroll
-        for (int m = L / 2; m > 0; m >>= 1) {
-            s64.x += __shfl_xor(s64.x, m, L);
-            s64.y += __shfl_xor(s64.y, m, L);
-            if (DIM == 3) s64.z += __shfl_xor(s64.z, m, L);
-            if (WANT_E) s64.e += __shfl_xor(s64.e, m, L);
-        }
-        fx = s64.x; fy = s64.y; fz = s64.z; Ue = s64.e;
-    } else {
-#pragma unroll
-        for (int m = L / 2; m > 0; m >>= 1) {
-            const float ox = __shfl_xor(s32.x, m, L), ocx = __shfl_xor(s32.cx, m, L);
-            const float oy = __shfl_xor(s32.y, m, L), ocy = __shfl_xor(s32.cy, m, L);
-            two_sum_acc(s32.x, s32.cx, ox);
-            s32.cx += ocx;
-            two_sum_acc(s32.y, s32.cy, oy);
-            s32.cy += ocy;
-            if (DIM == 3) {
-                const float oz = __shfl_xor(s32.z, m, L), ocz = __shfl_xor(s32.cz, m, L);
-                two_sum_acc(s32.z, s32.cz, oz);
-                s32.cz += ocz;
-            }
-            if (WANT_E) s32.e += __shfl_xor(s32.e, m, L);
-        }
-        fx = (double)s32.x + (double)s32.cx;
-        fy = (double)s32.y + (double)s32.cy;
-        fz = (double)s32.z + (double)s32.cz;
-        Ue = (double)s32.e;
+    for (int m = L / 2; m > 0; m >>= 1) {
+        s.x += __shfl_xor(s.x, m, L);
+        s.y += __shfl_xor(s.y, m, L);
+        if (DIM == 3) s.z += __shfl_xor(s.z, m, L);
+        if (WANT_E) s.e += __shfl_xor(s.e, m, L);
     }
+    fx = s.x; fy = s.y; fz = s.z; Ue = s.e;
 }
 
-// Node update by one lane, after the force density f_i is known.
+// modes whose node update reads v
+__host__ __device__ inline bool mode_reads_v(int mode) {
+    return mode == M_STEP_FIRST || mode == M_STEP_CONT || mode == M_CLOSE || mode == M_ENERGY;
+}
+
+// Node update by one lane, after the force density f_i is known.  (vx, vy,
+// vz) is v_i and `kind` the boundary kind of node i, both read by the caller
+// (v only in the modes of mode_reads_v).
 template <int DIM>
 __device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, double fx, double fy,
                                             double fz, double Ue, double Vi, double uix,
-                                            double uiy, double uiz, bool fixed_i) {
+                                            double uiy, double uiz, bool fixed_i, double vx,
+                                            double vy, double vz, int kind) {
     switch (a.mode) {
     case M_FORCE:
         store_vec<DIM>(a.f_out, i, fx, fy, fz);
@@ -191,8 +141,6 @@ __device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, doubl
         return;
     }
     case M_ENERGY: {
-        double vx, vy, vz;
-        load_vec<DIM>(a.v, i, vx, vy, vz);
         const double vv = DIM == 3 ? vx * vx + vy * vy + vz * vz : vx * vx + vy * vy;
         a.e_out[2 * (size_t)i] = 0.5 * a.rho * Vi * vv;
         a.e_out[2 * (size_t)i + 1] = Vi * Ue;
@@ -201,9 +149,6 @@ __device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, doubl
     default: break;
     }
 
-    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
-    double vx, vy, vz;
-    load_vec<DIM>(a.v, i, vx, vy, vz);
     const double hdt = 0.5 * a.dt;
     if (a.mode == M_CLOSE) {   // second half-kick of the last step
         if (kind == PD_BC_FREE) {

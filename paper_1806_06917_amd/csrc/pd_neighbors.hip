@@ -308,7 +308,9 @@ static void nbr_release(pd_nbr b) {
     pd_free(b->s_U);
     pd_free(b->s_alive);
     pd_free(b->s_fixed);
+    pd_ctx ctx = b->ctx;
     delete b;
+    pd_ctx_unref(ctx);
 }
 
 namespace {
@@ -466,6 +468,7 @@ extern "C" int pd_build_neighbors(pd_ctx ctx, int dim, int64_t n, const double *
     pd_nbr b = new (std::nothrow) pd_nbr_s();
     if (!b) return PD_ENOMEM;
     b->ctx = ctx;
+    ctx->refs += 1;
     b->dim = dim;
     b->n = (uint32_t)n;
     b->delta = delta;
@@ -487,7 +490,7 @@ extern "C" int pd_nbr_info(pd_nbr nbr, int64_t *nnz, int32_t *max_row) {
 }
 
 extern "C" int pd_nbr_export(pd_nbr nbr, int64_t *row_ptr, int32_t *col) {
-    if (!nbr) return PD_EINVAL;
+    if (!nbr || nbr->closing) return PD_EINVAL;
     pd_ctx ctx = nbr->ctx;
     PD_TRY(pd_check_ctx(ctx));
     const uint32_t n = nbr->n;
@@ -515,7 +518,7 @@ extern "C" int pd_nbr_export(pd_nbr nbr, int64_t *row_ptr, int32_t *col) {
 }
 
 extern "C" int pd_nbr_permutation(pd_nbr nbr, int32_t *perm) {
-    if (!nbr || !perm) return PD_EINVAL;
+    if (!nbr || nbr->closing || !perm) return PD_EINVAL;
     pd_ctx ctx = nbr->ctx;
     PD_TRY(pd_check_ctx(ctx));
     PD_HIP(ctx, hipMemcpyAsync(perm, nbr->perm, sizeof(int32_t) * nbr->n, hipMemcpyDeviceToHost,
@@ -524,10 +527,20 @@ extern "C" int pd_nbr_permutation(pd_nbr nbr, int32_t *perm) {
     return PD_OK;
 }
 
+void pd_nbr_unref(pd_nbr nbr) {
+    if (!nbr) return;
+    nbr->refs -= 1;
+    if (nbr->closing && nbr->refs <= 0) nbr_release(nbr);
+}
+
 extern "C" int pd_nbr_destroy(pd_nbr nbr) {
-    if (!nbr) return PD_EINVAL;
+    if (!nbr || nbr->closing) return PD_EINVAL;
     (void)hipSetDevice(nbr->ctx->device);
     (void)hipStreamSynchronize(nbr->ctx->stream);
+    if (nbr->refs > 0) {
+        nbr->closing = true;
+        return PD_OK;
+    }
     nbr_release(nbr);
     return PD_OK;
 }

@@ -31,6 +31,7 @@ int pd_hip_error(pd_ctx ctx, hipError_t e, const char *what, const char *file, i
 
 int pd_check_ctx(pd_ctx ctx) {
     if (!ctx) return PD_EINVAL;
+    if (ctx->closing) return pd_set_error(ctx, PD_EINVAL, "the context has been destroyed");
     if (ctx->failed) return PD_EDEVICE;
     PD_HIP(ctx, hipSetDevice(ctx->device));
     return PD_OK;
@@ -128,16 +129,30 @@ extern "C" int pd_ctx_create(int device, void *hip_stream, pd_ctx *out) {
     return PD_OK;
 }
 
-extern "C" int pd_ctx_destroy(pd_ctx ctx) {
-    if (!ctx) return PD_EINVAL;
-    (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    else (void)hipDeviceSynchronize();
+static void ctx_free(pd_ctx ctx) {
     pd_free(ctx->red);
     pd_free(ctx->flag);
     if (ctx->red_host) (void)hipHostFree(ctx->red_host);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
     delete ctx;
+}
+
+void pd_ctx_unref(pd_ctx ctx) {
+    if (!ctx) return;
+    ctx->refs -= 1;
+    if (ctx->closing && ctx->refs <= 0) ctx_free(ctx);
+}
+
+extern "C" int pd_ctx_destroy(pd_ctx ctx) {
+    if (!ctx || ctx->closing) return PD_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->refs > 0) {
+        ctx->closing = true;
+        return PD_OK;
+    }
+    ctx_free(ctx);
     return PD_OK;
 }
 

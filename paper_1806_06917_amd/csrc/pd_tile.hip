@@ -13,6 +13,7 @@
 // insert the ids into an LDS hash set, compact, bitonic-sort, then find each
 // bond's local index by binary search.
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 #include "pd_kernels.hpp"
@@ -156,10 +157,18 @@ struct Rec {
 constexpr int TILE_WPT = 8;          // 32-bit bond-word pairs staged per thread
 constexpr int TILE_META = 5;         // h0, hn, b0 (even), b1, self offset
 constexpr uint16_t BW_DEAD = 0x8000;
-constexpr uint16_t BW_IDX = 0x7fff;
 
 // record j as 16-byte LDS reads (the 48-byte stride keeps every record
 // 16-byte aligned)
+// Workgroup barrier that orders LDS only: global loads and stores in flight
+// stay in flight (a plain __syncthreads would wait for all of them).  Global
+// data is never passed between threads of one launch here.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int DIM>
 __device__ __forceinline__ void read_rec(const double *rec, uint32_t j, double *A) {
     const double2 *q = reinterpret_cast<const double2 *>(rec + (size_t)j * Rec<DIM>::NC);
@@ -184,11 +193,14 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
     double *cv = rec + (size_t)H * NC;                                   // H
     double *fres = cv + H;                                               // T * 4
     uint32_t *meta = reinterpret_cast<uint32_t *>(fres + (size_t)T * 4);  // mmax * TILE_META
-    uint32_t *srp = meta + (size_t)a.mmax * TILE_META;                    // T + 1
+    uint32_t *sflag = meta + (size_t)a.mmax * TILE_META;                  // 4: break flag
+    uint32_t *srp = sflag + 4;                                            // T + 1
     uint32_t *sbw = srp + (T + 1);                                        // bond-word pairs
     const uint16_t *sbw16 = reinterpret_cast<const uint16_t *>(sbw);
+    uint16_t *sbw16w = reinterpret_cast<uint16_t *>(sbw);
     const uint32_t *bw32 = reinterpret_cast<const uint32_t *>(a.bw);
     const bool tangent = a.mode == M_TANGENT;
+    const bool wants_v = mode_reads_v(a.mode);
 
     const uint32_t nb = gridDim.x, x = blockIdx.x % 8, l = blockIdx.x / 8;
     const uint32_t gx = nb / 8 + (x < nb % 8 ? 1u : 0u);
@@ -225,27 +237,26 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
             ids[r] = q < hn ? a.halo[h0 + q] : 0;
         }
     };
+    // every load below is unconditional, from a clamped (valid) index: a load
+    // under a branch makes the compiler copy its result at the branch merge,
+    // which waits for the load and so defeats the prefetch
     auto fetch_tile = [&](uint32_t k) {
         const uint32_t t = tbeg + l + k * gx, t0 = t * T, tn = min(T, a.n - t0);
-        const uint32_t hn = meta[k * TILE_META + 1];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const uint32_t q = tid + r * B;
-            if (q < hn) {
-                const uint32_t id = (uint32_t)pid[r];
-                pxv[r] = reinterpret_cast<const double4 *>(a.xv)[id];
-                load_vec<DIM>(a.u, id, pux[r], puy[r], puz[r]);
-                pfix[r] = (tangent && a.bc) ? a.bc[id] : (uint8_t)0;
-            }
+            const uint32_t id = (uint32_t)pid[r];      // 0 past the halo's end
+            pxv[r] = reinterpret_cast<const double4 *>(a.xv)[id];
+            load_vec<DIM>(a.u, id, pux[r], puy[r], puz[r]);
+            pfix[r] = (tangent && a.bc) ? a.bc[id] : (uint8_t)0;
         }
         const uint32_t b0 = meta[k * TILE_META + 2], b1 = meta[k * TILE_META + 3];
         const uint32_t nw = (b1 - b0 + 1) / 2;
 #pragma unroll
         for (int w = 0; w < WPT; ++w) {
             const uint32_t q = tid + w * B;
-            if (q < nw) pw[w] = bw32[b0 / 2 + q];
+            pw[w] = bw32[b0 / 2 + (q < nw ? q : 0u)];
         }
-        if (tid <= tn) prp = a.row_ptr[t0 + tid];
+        prp = a.row_ptr[t0 + min(tid, tn)];
     };
 
     fetch_ids(0, pid);
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
         const uint32_t hn = meta[k * TILE_META + 1], b0 = meta[k * TILE_META + 2];
         const uint32_t b1 = meta[k * TILE_META + 3], so = meta[k * TILE_META + 4];
         const uint32_t nw = (b1 - b0 + 1) / 2;
-        __syncthreads();                       // LDS free: tile k-1 is complete
+        lds_barrier();                         // LDS free: tile k-1 is complete
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const uint32_t q = tid + r * B;
@@ -279,7 +290,11 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
             if (q < nw) sbw[q] = pw[w];
         }
         if (tid <= tn) srp[tid] = prp - b0;
-        __syncthreads();
+        if (tid == 0) sflag[0] = 0;
+        lds_barrier();
+
+        // boundary kind of the node this thread updates after the bond sums
+        const int kind = (a.bc && tid < tn) ? a.bc[t0 + tid] : PD_BC_FREE;
 
         // prefetch: records of tile k+1 (ids already here), ids of tile k+2
         if (k + 1 < K) {
@@ -289,73 +304,93 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
             if (k + 2 < K) fetch_ids(k + 2, pid_next);
         }
 
-        // bond sums of tile k
+        // bond sums of tile k.  A bond that breaks gets its dead bit in the
+        // LDS copy of the bond words; tiles with a break write their words
+        // back afterwards (a store inside the bond loop would make every
+        // node wait for the prefetch loads still in flight).
         const uint32_t groups = B / L, g = tid / L;
         const int lane = tid & (L - 1);
-        for (uint32_t q = g; q < tn; q += groups) {
-            const double *ri = rec + (size_t)(so + q) * NC;
-            const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
-            const double uix = ri[IU], uiy = ri[IU + 1], uiz = DIM == 3 ? ri[IU + 2] : 0.0;
-            Acc64 s64;
-            Acc32 s32;
-            const uint32_t rs = srp[q], re = srp[q + 1];
-            uint32_t p = rs + lane;
-            for (; p + L < re; p += 2 * L) {
-                const uint32_t w0 = sbw16[p], w1 = sbw16[p + L];
-                const uint32_t j0 = w0 & BW_IDX, j1 = w1 & BW_IDX;
-                double A[NC], C[NC];
-                read_rec<DIM>(rec, j0, A);
-                read_rec<DIM>(rec, j1, C);
-                const double cv0 = cv_uniform ? a.cv_uniform : cv[j0];
-                const double cv1 = cv_uniform ? a.cv_uniform : cv[j1];
-                if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
-                                             DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
-                                             A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
-                                             (w0 & BW_DEAD) ? 0.0 : cv0, s64, s32) &&
-                    !(w0 & BW_DEAD))
-                    a.bw[b0 + p] = (uint16_t)(w0 | BW_DEAD);
-                if (bond<DIM, MIXED, WANT_E>(a, C[0] - xix, C[1] - xiy,
-                                             DIM == 3 ? C[2] - xiz : 0.0, C[IU] - uix,
-                                             C[IU + 1] - uiy, DIM == 3 ? C[IU + 2] - uiz : 0.0,
-                                             (w1 & BW_DEAD) ? 0.0 : cv1, s64, s32) &&
-                    !(w1 & BW_DEAD))
-                    a.bw[b0 + p + L] = (uint16_t)(w1 | BW_DEAD);
+        // one copy of the loop per volume layout, so the uniform case keeps c V
+        // in scalar registers
+        auto bond_sums = [&](auto uniform_volume) {
+            constexpr bool UV = decltype(uniform_volume)::value;
+            for (uint32_t q = g; q < tn; q += groups) {
+                const double *ri = rec + (size_t)(so + q) * NC;
+                const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
+                const double uix = ri[IU], uiy = ri[IU + 1], uiz = DIM == 3 ? ri[IU + 2] : 0.0;
+                Acc64 acc;
+                const uint32_t rs = srp[q], re = srp[q + 1];
+                uint32_t p = rs + lane;
+                for (; p + L < re; p += 2 * L) {
+                    const uint32_t w0 = sbw16[p], w1 = sbw16[p + L];
+                    const uint32_t j0 = __builtin_amdgcn_ubfe(w0, 0, 15);
+                    const uint32_t j1 = __builtin_amdgcn_ubfe(w1, 0, 15);
+                    double A[NC], C[NC];
+                    read_rec<DIM>(rec, j0, A);
+                    read_rec<DIM>(rec, j1, C);
+                    const double cv0 = UV ? a.cv_uniform : cv[j0];
+                    const double cv1 = UV ? a.cv_uniform : cv[j1];
+                    if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                                                 DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
+                                                 A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
+                                                 cv0, (w0 & BW_DEAD) != 0, acc)) {
+                        sbw16w[p] = (uint16_t)(w0 | BW_DEAD);
+                        sflag[0] = 1;
+                    }
+                    if (bond<DIM, MIXED, WANT_E>(a, C[0] - xix, C[1] - xiy,
+                                                 DIM == 3 ? C[2] - xiz : 0.0, C[IU] - uix,
+                                                 C[IU + 1] - uiy, DIM == 3 ? C[IU + 2] - uiz : 0.0,
+                                                 cv1, (w1 & BW_DEAD) != 0, acc)) {
+                        sbw16w[p + L] = (uint16_t)(w1 | BW_DEAD);
+                        sflag[0] = 1;
+                    }
+                }
+                if (p < re) {
+                    const uint32_t w0 = sbw16[p], j0 = __builtin_amdgcn_ubfe(w0, 0, 15);
+                    double A[NC];
+                    read_rec<DIM>(rec, j0, A);
+                    const double cv0 = UV ? a.cv_uniform : cv[j0];
+                    if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                                                 DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
+                                                 A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
+                                                 cv0, (w0 & BW_DEAD) != 0, acc)) {
+                        sbw16w[p] = (uint16_t)(w0 | BW_DEAD);
+                        sflag[0] = 1;
+                    }
+                }
+                double fx, fy, fz, Ue;
+                group_reduce<DIM, L, WANT_E>(acc, fx, fy, fz, Ue);
+                if (lane == 0) {
+                    double *fr = fres + (size_t)q * 4;
+                    fr[0] = fx;
+                    fr[1] = fy;
+                    fr[2] = fz;
+                    fr[3] = Ue;
+                }
             }
-            if (p < re) {
-                const uint32_t w0 = sbw16[p], j0 = w0 & BW_IDX;
-                double A[NC];
-                read_rec<DIM>(rec, j0, A);
-                const double cv0 = cv_uniform ? a.cv_uniform : cv[j0];
-                if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
-                                             DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
-                                             A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
-                                             (w0 & BW_DEAD) ? 0.0 : cv0, s64, s32) &&
-                    !(w0 & BW_DEAD))
-                    a.bw[b0 + p] = (uint16_t)(w0 | BW_DEAD);
-            }
-            double fx, fy, fz, Ue;
-            group_reduce<DIM, L, MIXED, WANT_E>(s64, s32, fx, fy, fz, Ue);
-            if (lane == 0) {
-                double *fr = fres + (size_t)q * 4;
-                fr[0] = fx;
-                fr[1] = fy;
-                fr[2] = fz;
-                fr[3] = Ue;
-            }
+        };
+        if (cv_uniform) bond_sums(std::true_type{});
+        else bond_sums(std::false_type{});
+        lds_barrier();
+        if (sflag[0]) {
+            // exactly this tile's bonds [row_ptr[t0], row_ptr[t0 + tn]) go back
+            const uint32_t rs = srp[0], re = srp[tn];
+            for (uint32_t q = rs + tid; q < re; q += B) a.bw[b0 + q] = sbw16[q];
         }
-        __syncthreads();
 
-        // node updates of tile k
-        for (uint32_t q = tid; q < tn; q += B) {
-            const uint32_t i = t0 + q;
+        // node updates of tile k (T <= B: thread q updates node q)
+        if (tid < tn) {
+            const uint32_t q = tid, i = t0 + q;
             const double *ri = rec + (size_t)(so + q) * NC;
             const double *fr = fres + (size_t)q * 4;
-            const bool fixed_i = tangent && a.bc && a.bc[i];
+            const bool fixed_i = tangent && a.bc && kind != 0;
             const double Vi = (a.mode == M_TANGENT || a.mode == M_ENERGY)
                                   ? a.xv[4 * (size_t)i + (DIM == 3 ? 3 : 2)]
                                   : 0.0;
+            double vx = 0, vy = 0, vz = 0;
+            if (wants_v) load_vec<DIM>(a.v, i, vx, vy, vz);
             node_update<DIM>(a, i, fr[0], fr[1], fr[2], fr[3], Vi, ri[IU], ri[IU + 1],
-                             DIM == 3 ? ri[IU + 2] : 0.0, fixed_i);
+                             DIM == 3 ? ri[IU + 2] : 0.0, fixed_i, vx, vy, vz, kind);
         }
     }
 }
@@ -401,8 +436,8 @@ void *pick_lanes(int lanes, bool mixed, bool e, int rpt) {
 size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint32_t mmax) {
     (void)dim;
     return (size_t)hcap * 7 * sizeof(double) + (size_t)tile * 4 * sizeof(double) +
-           (size_t)mmax * TILE_META * sizeof(uint32_t) + (size_t)(tile + 1) * sizeof(uint32_t) +
-           (size_t)(bcap / 2 + 2) * sizeof(uint32_t);
+           (size_t)(mmax * TILE_META + 4) * sizeof(uint32_t) +
+           (size_t)(tile + 1) * sizeof(uint32_t) + (size_t)(bcap / 2 + 2) * sizeof(uint32_t);
 }
 
 // Launch geometry of the persistent tile kernel: threads per workgroup,
@@ -412,6 +447,7 @@ bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, ui
                       int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
                       size_t *lds) {
     const size_t lds_max = 160 * 1024;
+    if ((uint32_t)block < tile) return false;   // one thread per tile node in the updates
     *rpt = (hcap + (uint32_t)block - 1) / (uint32_t)block;
     if (*rpt < 1) *rpt = 1;
     if (*rpt > 2) return false;
