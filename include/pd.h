@@ -142,8 +142,12 @@ int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
  *   kernel  0 automatic, 1 plain gather from global memory, 2 LDS-staged
  *           tiles (T consecutive nodes in the internal order share one
  *           workgroup, which copies the records of every node their bonds
- *           touch into LDS once per launch); automatic uses tiles whenever
- *           the largest halo fits in LDS.
+ *           touch into LDS once per launch), 3 streamed tiles for the
+ *           explicit steps (the same tiles, staged by asynchronous
+ *           global-to-LDS copies that overlap the bond sums; needs equal
+ *           nodal volumes, other calls of such a simulation use kind 2);
+ *           automatic uses streamed tiles for the steps where they apply,
+ *           LDS tiles elsewhere whenever the largest halo fits in LDS.
  *   tile    nodes per tile, a power of two in [16, 4096]; 0 automatic.
  *   block   threads per tile workgroup, a multiple of 64 in [64, 1024];
  *           0 automatic.
@@ -258,7 +262,8 @@ int pd_sim_destroy(pd_sim sim);
 
 /*
  * Launch configuration a simulation runs with (each output may be NULL):
- * kernel 1 = gather, 2 = LDS tiles; tile = nodes per tile (0 for gather);
+ * kernel 1 = gather, 2 = LDS tiles, 3 = streamed tiles for the steps;
+ * tile = nodes per tile (0 for gather);
  * block = threads per workgroup; lanes = lanes per node.
  */
 int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes);

@@ -160,7 +160,7 @@ static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int block) {
     uint32_t mmax;
     size_t lds;
     return pd_tile_geometry(nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                            pd_tile_bcap(nbr), block, ctx->num_cu, &rpt, &grid, &mmax, &lds);
+                            pd_tile_bcap(nbr), block, ctx->num_cu, &rpt, &grid, &mmax, &lds, 0);
 }
 
 // threads per tile workgroup for the tiles nbr holds now: the tuning value,
@@ -407,6 +407,8 @@ static void sim_release(pd_sim s) {
     pd_free(s->alive);
     pd_free(s->bw);
     pd_free(s->scratch);
+    pd_free(s->rec[0]);
+    pd_free(s->rec[1]);
     if (s->nbr && s->tiled) s->nbr->users -= 1;
     pd_ctx ctx = s->ctx;
     pd_nbr nbr = s->nbr;
@@ -466,7 +468,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (st == PD_OK) st = pd_alloc(ctx, &s->u[0], n * us);
     if (st == PD_OK) st = pd_alloc(ctx, &s->u[1], n * us);
     if (st == PD_OK) st = pd_alloc(ctx, &s->v, n * us);
-    if (st == PD_OK) st = pd_alloc(ctx, &s->bc, n);
+    if (st == PD_OK) st = pd_alloc(ctx, &s->bc, n + 16);   // whole 32-bit words for copies
     if (st == PD_OK) st = pd_alloc(ctx, &s->alive, nbr->nnz);
     if (st == PD_OK) st = pd_alloc(ctx, &s->scratch, 2 * n);
     if (st == PD_OK && bc_vel) st = pd_alloc(ctx, &s->bc_vel, n * us);
@@ -497,6 +499,22 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         st = pd_uniform_volume(ctx, nbr, s->xv, &Vu);
         s->cv_uniform = mat->c * Vu;
     }
+    if (st == PD_OK && s->tiled && s->cv_uniform != 0.0 && (ctx->kernel == 0 || ctx->kernel == 3) &&
+        pd_stream_geometry(ctx, nbr->dim, nbr->n, nbr->nnz, nbr->ntiles, nbr->tile_T,
+                           pd_tile_hcap(nbr), pd_tile_bcap(nbr), nbr->halo_total, lanes,
+                           mat->precision == PD_MIXED, &s->s_block, &s->s_grid, &s->s_mmax,
+                           &s->s_lds, &s->s_slots)) {
+        const size_t rd = nbr->dim == 3 ? 6 : 4;
+        st = pd_alloc(ctx, &s->rec[0], n * rd);
+        if (st == PD_OK) st = pd_alloc(ctx, &s->rec[1], n * rd);
+        // both buffers carry the positions; u is rewritten every step
+        if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[0]);
+        if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[1]);
+        s->stream = true;
+        s->rec_stale = false;
+    }
+    if (st == PD_OK && ctx->kernel == 3 && !s->stream)
+        st = pd_set_error(ctx, PD_ECAPACITY, "the streamed kernel cannot run this simulation");
     if (st == PD_OK) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "sim_create", __FILE__, __LINE__);
@@ -536,6 +554,36 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
     NodeArgs a = sim_args(sim);
     a.dt = dt;
     const bool mixed = sim->mat.precision == PD_MIXED;
+    if (sim->stream) {
+        const pd_nbr nbr = sim->nbr;
+        if (nsteps > 0 && sim->rec_stale) {
+            PD_TRY(pd_rec_pack(ctx, nbr->dim, nbr->n, sim->xv, sim->u[sim->cur],
+                               sim->rec[sim->cur]));
+            sim->rec_stale = false;
+        }
+        a.halo_ptr = nbr->halo_ptr;
+        a.halo = nbr->halo;
+        a.self_off = nbr->self_off;
+        a.tile = nbr->tile_T;
+        a.ntiles = nbr->ntiles;
+        a.hcap = pd_tile_hcap(nbr);
+        a.bcap = pd_tile_bcap(nbr);
+        a.mmax = sim->s_mmax;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            a.mode = sim->v_half ? M_STEP_CONT : M_STEP_FIRST;
+            a.rec = sim->rec[sim->cur];
+            a.rec_out = sim->rec[sim->cur ^ 1];
+            a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
+            PD_TRY(pd_launch_stream(ctx, nbr->dim, a, sim->lanes, mixed, sim->s_block,
+                                    sim->s_grid, sim->s_lds, sim->s_slots));
+            sim->cur ^= 1;
+            sim->v_half = true;
+            sim->step += 1;
+            sim->u_stale = true;
+        }
+        sim->last_dt = dt;
+        return PD_OK;
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         a.mode = sim->v_half ? M_STEP_CONT : M_STEP_FIRST;
         a.u = sim->u[sim->cur];
@@ -550,8 +598,18 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
     return PD_OK;
 }
 
+// u[cur] from the records after streamed steps
+static int sim_sync_u(pd_sim sim) {
+    if (!sim->u_stale) return PD_OK;
+    PD_TRY(pd_rec_unpack(sim->ctx, sim->nbr->dim, sim->nbr->n, sim->rec[sim->cur],
+                         sim->u[sim->cur]));
+    sim->u_stale = false;
+    return PD_OK;
+}
+
 // completes the last step: force at u^N with the damage test, second half-kick
 static int sim_close(pd_sim sim) {
+    PD_TRY(sim_sync_u(sim));
     if (!sim->v_half) return PD_OK;
     NodeArgs a = sim_args(sim);
     a.dt = sim->last_dt;
@@ -606,7 +664,10 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (step < 0) return pd_set_error(ctx, PD_EINVAL, "step must be >= 0");
     PD_TRY(sim_close(sim));
-    if (u) PD_TRY(pd_gather_vec(ctx, sim->nbr, u, sim->u[sim->cur], false));
+    if (u) {
+        PD_TRY(pd_gather_vec(ctx, sim->nbr, u, sim->u[sim->cur], false));
+        sim->rec_stale = true;
+    }
     if (v) PD_TRY(pd_gather_vec(ctx, sim->nbr, v, sim->v, false));
     if (alive) {
         PD_TRY(pd_alive_in(ctx, sim->nbr, alive, sim->alive));
@@ -618,9 +679,9 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
 
 extern "C" int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes) {
     if (!sim) return PD_EINVAL;
-    if (kernel) *kernel = sim->tiled ? 2 : 1;
+    if (kernel) *kernel = sim->stream ? 3 : (sim->tiled ? 2 : 1);
     if (tile) *tile = sim->tiled ? (int)sim->nbr->tile_T : 0;
-    if (block) *block = sim->tiled ? sim->block : PD_BLOCK;
+    if (block) *block = sim->stream ? sim->s_block : (sim->tiled ? sim->block : PD_BLOCK);
     if (lanes) *lanes = sim->lanes;
     return PD_OK;
 }

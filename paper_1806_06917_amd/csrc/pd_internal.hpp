@@ -30,7 +30,7 @@ struct pd_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     int lanes = 0;          // 0: automatic
-    int kernel = 0;         // 0: automatic, 1: gather, 2: LDS tiles
+    int kernel = 0;         // 0: automatic, 1: gather, 2: LDS tiles, 3: streamed tiles
     int tile = 0;           // nodes per tile, 0: automatic
     int block = 0;          // threads per tile workgroup, 0: automatic
     int num_cu = 256;       // compute units of the device
@@ -97,6 +97,16 @@ struct pd_sim_s {
     double last_dt = 0;
     bool v_half = false;         // v holds v^{k-1/2} (force at u^k still to be applied)
     int lanes = 0;
+    // streamed steps: node records {X, u} (ping-pong with u), launch geometry
+    double *rec[2] = {nullptr, nullptr};
+    bool stream = false;
+    bool u_stale = false;        // rec[cur] is newer than u[cur]
+    bool rec_stale = true;       // u[cur] is newer than rec[cur]
+    int s_block = 0;
+    unsigned s_grid = 0;
+    uint32_t s_mmax = 0;
+    size_t s_lds = 0;
+    int s_slots = 0;
 };
 
 // ---------------------------------------------------------------------------

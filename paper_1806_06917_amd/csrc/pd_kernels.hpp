@@ -29,6 +29,8 @@ struct NodeArgs {
     double *__restrict__ e_out;        // M_FORCE: U_i; M_ENERGY: {KE_i, V_i U_i} pairs
     int *__restrict__ flag;            // non-finite report
     const int *__restrict__ done;      // if set and *done != 0 the launch is a no-op
+    const double *__restrict__ rec;    // streamed kernel: records {X, u} per node
+    double *__restrict__ rec_out;      // streamed kernel: u^{k+1} goes into these records
     uint32_t n;
     uint32_t tile;                     // nodes per tile (tile kernel)
     uint32_t hcap;                     // halo records held in LDS (tile kernel)
@@ -197,7 +199,17 @@ __device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, doubl
         nz = uiz + a.dt * vz;
     }
     store_vec<DIM>(a.v, i, vx, vy, vz);
-    store_vec<DIM>(a.u_out, i, nx, ny, nz);
+    if (a.rec_out) {   // u part of the record {x y z ux uy uz} ({x y ux uy})
+        double *r = a.rec_out + (size_t)i * (DIM == 3 ? 6 : 4);
+        if (DIM == 3) {
+            r[3] = nx;
+            *reinterpret_cast<double2 *>(r + 4) = make_double2(ny, nz);
+        } else {
+            *reinterpret_cast<double2 *>(r + 2) = make_double2(nx, ny);
+        }
+    } else {
+        store_vec<DIM>(a.u_out, i, nx, ny, nz);
+    }
 }
 
 // modes that need the strain energy of every bond
@@ -207,7 +219,7 @@ __host__ __device__ inline bool mode_wants_energy(const NodeArgs &a) {
 
 }  // namespace pdk
 
-// launchers (pd_force.hip, pd_tile.hip)
+// launchers (pd_force.hip, pd_tile.hip, pd_stream.hip)
 
 int pd_launch_gather(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed);
 int pd_launch_tile(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed,
@@ -215,9 +227,20 @@ int pd_launch_tile(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool 
 // LDS bytes of one tile-kernel workgroup
 size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint32_t mmax);
 // launch geometry of the persistent tile kernel; false if the layout does not fit
+// (max_per_cu > 0 caps the workgroups per CU)
 bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
                       int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
-                      size_t *lds);
+                      size_t *lds, int max_per_cu);
+// streamed kernel (explicit steps with uniform volumes): launch geometry, false
+// if it cannot run this layout; launch; node records from / to xv and u
+bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t n, uint64_t nnz, uint32_t ntiles,
+                        uint32_t tile, uint32_t hcap, uint32_t bcap, uint64_t halo_total,
+                        int lanes, bool mixed, int *block, unsigned *grid, uint32_t *mmax,
+                        size_t *lds, int *slots);
+int pd_launch_stream(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed,
+                     int block, unsigned grid, size_t lds, int slots);
+int pd_rec_pack(pd_ctx ctx, int dim, uint32_t n, const double *xv, const double *u, double *rec);
+int pd_rec_unpack(pd_ctx ctx, int dim, uint32_t n, const double *rec, double *u);
 // LDS halo capacity of a tiled neighbour list
 inline uint32_t pd_tile_hcap(const pd_nbr nbr) { return (nbr->halo_max + 31u) & ~31u; }
 inline uint32_t pd_tile_bcap(const pd_nbr nbr) { return (nbr->bonds_max + 63u) & ~63u; }

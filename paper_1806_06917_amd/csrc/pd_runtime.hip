@@ -57,7 +57,8 @@ int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name) {
 int pd_auto_lanes(pd_ctx ctx, uint64_t nnz, uint32_t n) {
     if (ctx && ctx->lanes > 0) return ctx->lanes;
     // about 16 bonds per lane: enough work per lane to amortise the
-    // butterfly, enough nodes per wavefront to keep the loads in flight
+    // butterfly, and with 64-node (3-d) or 128-node (2-d) tiles 512-thread
+    // workgroups, two of which share a CU
     const double k = n ? (double)nnz / (double)n : 0.0;
     int L = 1;
     while (L < 32 && L * 16 < k) L *= 2;
@@ -171,7 +172,8 @@ extern "C" int pd_ctx_set_lanes(pd_ctx ctx, int lanes) {
 
 extern "C" int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block) {
     if (!ctx) return PD_EINVAL;
-    if (kernel < 0 || kernel > 2) return pd_set_error(ctx, PD_EINVAL, "kernel must be 0, 1 or 2");
+    if (kernel < 0 || kernel > 3)
+        return pd_set_error(ctx, PD_EINVAL, "kernel must be 0, 1, 2 or 3");
     if (tile != 0 && (tile < 16 || tile > 4096 || (tile & (tile - 1))))
         return pd_set_error(ctx, PD_EINVAL, "tile must be 0 or a power of two in [16, 4096]");
     if (block != 0 && (block < 64 || block > 1024 || (block % 64)))

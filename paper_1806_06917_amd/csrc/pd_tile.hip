@@ -445,14 +445,14 @@ size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint
 // bound mmax.  Returns false if the layout does not fit.
 bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
                       int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
-                      size_t *lds) {
+                      size_t *lds, int max_per_cu) {
     const size_t lds_max = 160 * 1024;
     if ((uint32_t)block < tile) return false;   // one thread per tile node in the updates
     *rpt = (hcap + (uint32_t)block - 1) / (uint32_t)block;
     if (*rpt < 1) *rpt = 1;
     if (*rpt > 2) return false;
     if (bcap / 2 + 2 > (uint32_t)(TILE_WPT * block)) return false;
-    for (int per_cu = 2; per_cu >= 1; --per_cu) {
+    for (int per_cu = max_per_cu > 0 && max_per_cu < 2 ? max_per_cu : 2; per_cu >= 1; --per_cu) {
         unsigned g = (unsigned)(num_cu * per_cu);
         if (g > ntiles) g = ntiles;
         if (g < 1) g = 1;
@@ -486,12 +486,25 @@ int pd_launch_tile(pd_ctx ctx, int dim, const NodeArgs &a0, int lanes, bool mixe
     unsigned grid = 0;
     size_t lds = 0;
     if (!pd_tile_geometry(dim, a.ntiles, a.tile, a.hcap, a.bcap, block, ctx->num_cu, &rpt, &grid,
-                          &a.mmax, &lds))
+                          &a.mmax, &lds, 0))
         return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit this launch");
     const bool e = mode_wants_energy(a);
     void *k = dim == 3 ? pick_lanes<3>(lanes, mixed, e, rpt) : pick_lanes<2>(lanes, mixed, e, rpt);
     if (!k) return pd_set_error(ctx, PD_EINVAL, "tile kernel needs 2..32 lanes, got %d", lanes);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // every workgroup of the persistent grid must be resident at once: cap the
+    // workgroups per CU by what registers and LDS allow for this kernel
+    int occ = 0;
+    PD_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, block, lds));
+    if (occ < 1) return pd_set_error(ctx, PD_ECAPACITY, "tile kernel cannot be resident");
+    if (grid > (unsigned)(ctx->num_cu * occ)) {
+        int rpt2 = 0;
+        if (!pd_tile_geometry(dim, a.ntiles, a.tile, a.hcap, a.bcap, block, ctx->num_cu, &rpt2,
+                              &grid, &a.mmax, &lds, occ) ||
+            rpt2 != rpt)
+            return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit this launch");
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
     void *args[] = {&a};
     PD_HIP(ctx, hipLaunchKernel(k, dim3(grid), dim3(block), args, lds, ctx->stream));
     return PD_OK;

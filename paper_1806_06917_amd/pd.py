@@ -119,8 +119,9 @@ class Context:
         self.check(lib.pd_ctx_set_lanes(self.h, int(lanes)), "pd_ctx_set_lanes")
 
     def set_tuning(self, kernel=0, tile=0, block=0):
-        """kernel: 0 auto, 1 gather, 2 LDS tiles; tile/block sizes (0 = auto)."""
-        kind = {"auto": 0, "gather": 1, "tile": 2}.get(kernel, kernel)
+        """kernel: 0 auto, 1 gather, 2 LDS tiles, 3 streamed tiles (steps); tile/block
+        sizes (0 = auto)."""
+        kind = {"auto": 0, "gather": 1, "tile": 2, "stream": 3}.get(kernel, kernel)
         self.check(lib.pd_ctx_set_tuning(self.h, int(kind), int(tile), int(block)),
                    "pd_ctx_set_tuning")
 
@@ -242,11 +243,12 @@ class Simulation:
         return {"ke": kp[0], "pe": kp[1], "step": step.value, "status": st}
 
     def info(self):
-        """Launch configuration: kernel ('gather' | 'tile'), tile, block, lanes."""
+        """Launch configuration: kernel ('gather' | 'tile' | 'stream'), tile, block, lanes."""
         k, t, b, l = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         self.ctx.check(lib.pd_sim_info(self.h, C.byref(k), C.byref(t), C.byref(b), C.byref(l)),
                        "pd_sim_info")
-        return {"kernel": {1: "gather", 2: "tile"}[k.value], "tile": t.value, "block": b.value,
+        return {"kernel": {1: "gather", 2: "tile", 3: "stream"}[k.value], "tile": t.value,
+                "block": b.value,
                 "lanes": l.value}
 
     def set(self, u=None, v=None, alive=None, step=0):

@@ -406,7 +406,7 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     w.v0 = v0
     sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(3, w.E, w.delta), prec)
-    assert sim.info()["kernel"] == "tile"          # the benchmark's launch configuration
+    assert sim.info()["kernel"] == "stream"        # the benchmark's launch configuration
     sim.step(3, w.dt)
     u, v, a, info = read_state(torch, sim, w.n, 3, nb.nnz)
     tol = TOL64 if prec == "fp64" else TOLMIX
@@ -420,8 +420,9 @@ def test_cube100_full_size_steps(gpu, orc, prec):
 @pytest.mark.parametrize("wl,prec", [("plate", "fp64"), ("cube", "mixed"), ("cube", "fp64"),
                                      ("notched", "mixed")])
 def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
-    """The LDS-tile kernel and the gather kernel sum every node's bonds in the
-    same order, so trajectories agree bit for bit for any tile size."""
+    """The LDS-tile kernels (register-staged and streamed) and the gather
+    kernel sum every node's bonds in the same order, so trajectories agree bit
+    for bit for any tile size."""
     torch, pd, ctx = gpu
     if wl == "plate":
         w = inputs.plate_2d(40, 3, seed=2, steps=0)
@@ -434,14 +435,15 @@ def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
     c = pd.micromodulus(w.dim, w.E, w.delta)
     results = []
     for kind, tile, block in [("gather", 0, 0), ("tile", 32, 0), ("tile", 64, 512),
-                              ("tile", 128, 0), ("tile", 0, 0)]:
+                              ("tile", 128, 0), ("tile", 0, 0), ("stream", 0, 0),
+                              ("stream", 32, 0)]:
         say("tile vs gather", wl, prec, kind, tile, block)
         ctx.set_tuning(kind, tile, block)
         try:
             nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
             s = sim_from_workload(torch, pd, ctx, nb, w, c, prec)
             info = s.info()
-            assert info["kernel"] == ("gather" if kind == "gather" else "tile"), info
+            assert info["kernel"] == kind, info
             if tile:
                 assert info["tile"] == tile
             s.step(25, w.dt)
