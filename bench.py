@@ -27,8 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["pd_kernels.hpp", "pd_tile.hip", "pd_force.hip", "pd_internal.hpp"]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_kernel_cube100_traffic.md")
+KERNEL_SOURCES = ["pd_kernels.hpp", "pd_stream.hip", "pd_tile.hip", "pd_force.hip",
+                  "pd_internal.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_kernel_cube100_traffic.md")
 
 
 def kernel_source_hash():

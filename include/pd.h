@@ -148,7 +148,7 @@ int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
  *           nodal volumes, other calls of such a simulation use kind 2);
  *           automatic uses streamed tiles for the steps where they apply,
  *           LDS tiles elsewhere whenever the largest halo fits in LDS.
- *   tile    nodes per tile, a power of two in [16, 4096]; 0 automatic.
+ *   tile    nodes per tile, a multiple of 16 in [16, 4096]; 0 automatic.
  *   block   threads per tile workgroup, a multiple of 64 in [64, 1024];
  *           0 automatic.
  * Takes effect for neighbour lists and simulations set up afterwards.

@@ -174,8 +174,8 @@ extern "C" int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block) {
     if (!ctx) return PD_EINVAL;
     if (kernel < 0 || kernel > 3)
         return pd_set_error(ctx, PD_EINVAL, "kernel must be 0, 1, 2 or 3");
-    if (tile != 0 && (tile < 16 || tile > 4096 || (tile & (tile - 1))))
-        return pd_set_error(ctx, PD_EINVAL, "tile must be 0 or a power of two in [16, 4096]");
+    if (tile != 0 && (tile < 16 || tile > 4096 || (tile % 16)))
+        return pd_set_error(ctx, PD_EINVAL, "tile must be 0 or a multiple of 16 in [16, 4096]");
     if (block != 0 && (block < 64 || block > 1024 || (block % 64)))
         return pd_set_error(ctx, PD_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
     ctx->kernel = kernel;
