@@ -67,6 +67,7 @@ enum { PD_BC_FREE = 0, PD_BC_CLAMPED = 1, PD_BC_VELOCITY = 2 };
 typedef struct pd_ctx_s *pd_ctx;
 typedef struct pd_nbr_s *pd_nbr;
 typedef struct pd_sim_s *pd_sim;
+typedef struct pd_batch_s *pd_batch;
 
 /*
  * Material and arithmetic of one model.
@@ -259,6 +260,27 @@ int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, double *ke_pe, 
 int pd_sim_set(pd_sim sim, const double *u, const double *v, const uint8_t *alive, int64_t step);
 
 int pd_sim_destroy(pd_sim sim);
+
+/*
+ * Batched explicit steps (serving several independent simulations at once).
+ * One launch per step covers the tiles of every simulation in the batch, so
+ * small meshes do not each pay a launch; with use_graph != 0 the chunk of
+ * nsteps launches is captured once in a hipGraph and replayed on later calls
+ * with the same batch shape.
+ *
+ * sims[k] takes steps[k] (0 <= steps[k] <= nsteps) velocity-Verlet steps of
+ * dt[k] (host arrays of length nsims); it then stands exactly where
+ * pd_verlet_step(sims[k], steps[k], dt[k]) would have left it, bit for bit.
+ * Every simulation must run the streamed step kernel (pd_sim_info kernel 3)
+ * on b's context, with one dim, precision, lane count and tile size.  The
+ * call is asynchronous on the context's stream.  A batch handle holds the
+ * descriptor buffer, the step counter and the captured graph; it must outlive
+ * its pending work and is freed by pd_batch_destroy (which synchronises).
+ */
+int pd_batch_create(pd_ctx ctx, pd_batch *out);
+int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t *steps, const double *dt,
+                  int64_t nsteps, int use_graph);
+int pd_batch_destroy(pd_batch b);
 
 /*
  * Launch configuration a simulation runs with (each output may be NULL):

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
             if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
             const double cVj = a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z);
             const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
-            if (bond<DIM, MIXED, WANT_E>(a, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
+            if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
                                          duz, cVj, !live, s64))
                 a.alive[p] = 0;
         }
@@ -500,10 +500,10 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         s->cv_uniform = mat->c * Vu;
     }
     if (st == PD_OK && s->tiled && s->cv_uniform != 0.0 && (ctx->kernel == 0 || ctx->kernel == 3) &&
-        pd_stream_geometry(ctx, nbr->dim, nbr->n, nbr->nnz, nbr->ntiles, nbr->tile_T,
-                           pd_tile_hcap(nbr), pd_tile_bcap(nbr), nbr->halo_total, lanes,
-                           mat->precision == PD_MIXED, &s->s_block, &s->s_grid, &s->s_mmax,
-                           &s->s_lds, &s->s_slots)) {
+        pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
+        pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
+                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false,
+                           &s->s_block, &s->s_grid, &s->s_mmax, &s->s_lds)) {
         const size_t rd = nbr->dim == 3 ? 6 : 4;
         st = pd_alloc(ctx, &s->rec[0], n * rd);
         if (st == PD_OK) st = pd_alloc(ctx, &s->rec[1], n * rd);
@@ -542,6 +542,56 @@ static NodeArgs sim_args(pd_sim s) {
     return a;
 }
 
+// static part of a simulation's streamed-batch descriptor
+StreamInst pd_stream_inst(const pd_sim s) {
+    const pd_nbr nbr = s->nbr;
+    StreamInst d{};
+    d.row_ptr = nbr->row_ptr;
+    d.halo_ptr = nbr->halo_ptr;
+    d.halo = nbr->halo;
+    d.self_off = nbr->self_off;
+    d.bw = s->bw;
+    d.rec[0] = s->rec[0];
+    d.rec[1] = s->rec[1];
+    d.v = s->v;
+    d.bc = s->bc;
+    d.bc_vel = s->bc_vel;
+    d.b = s->b;
+    d.n = nbr->n;
+    d.tile_begin = 0;
+    d.cv = s->cv_uniform;
+    d.s_c = s->mat.s_c;
+    d.rho = s->mat.rho;
+    d.damage = s->mat.s_c > 0.0;
+    d.ramp = s->ramp;
+    return d;
+}
+
+// launch arguments shared by every instance of a batch shaped like sim
+StreamArgs pd_stream_args(const pd_sim sim, const StreamInst *inst, uint32_t ninst,
+                          uint32_t ntiles) {
+    const pd_nbr nbr = sim->nbr;
+    StreamArgs sa{};
+    sa.inst = inst;
+    sa.ninst = ninst;
+    sa.ntiles = ntiles;
+    sa.tile = nbr->tile_T;
+    sa.hcap = pd_tile_hcap(nbr);
+    sa.bcap = pd_tile_bcap(nbr);
+    sa.mmax = sim->s_mmax;
+    return sa;
+}
+
+// host state after nsteps streamed steps at dt
+void pd_sim_advanced(pd_sim sim, int64_t nsteps, double dt) {
+    if (nsteps <= 0) return;
+    sim->step += nsteps;
+    sim->cur ^= (int)(nsteps & 1);
+    sim->v_half = true;
+    sim->u_stale = true;
+    sim->last_dt = dt;
+}
+
 extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
     if (!sim) return PD_EINVAL;
     pd_ctx ctx = sim->ctx;
@@ -561,27 +611,19 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
                                sim->rec[sim->cur]));
             sim->rec_stale = false;
         }
-        a.halo_ptr = nbr->halo_ptr;
-        a.halo = nbr->halo;
-        a.self_off = nbr->self_off;
-        a.tile = nbr->tile_T;
-        a.ntiles = nbr->ntiles;
-        a.hcap = pd_tile_hcap(nbr);
-        a.bcap = pd_tile_bcap(nbr);
-        a.mmax = sim->s_mmax;
+        StreamArgs sa = pd_stream_args(sim, nullptr, 1, nbr->ntiles);
+        sa.one = pd_stream_inst(sim);
+        sa.one.cur0 = sim->cur;
+        sa.one.vhalf0 = sim->v_half ? 1 : 0;
+        sa.one.dt = dt;
+        sa.one.step0 = sim->step;
+        sa.one.limit = nsteps;
         for (int64_t k = 0; k < nsteps; ++k) {
-            a.mode = sim->v_half ? M_STEP_CONT : M_STEP_FIRST;
-            a.rec = sim->rec[sim->cur];
-            a.rec_out = sim->rec[sim->cur ^ 1];
-            a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
-            PD_TRY(pd_launch_stream(ctx, nbr->dim, a, sim->lanes, mixed, sim->s_block,
-                                    sim->s_grid, sim->s_lds, sim->s_slots));
-            sim->cur ^= 1;
-            sim->v_half = true;
-            sim->step += 1;
-            sim->u_stale = true;
+            sa.step = k;
+            PD_TRY(pd_launch_stream(ctx, ctx->stream, nbr->dim, sa, sim->lanes, mixed,
+                                    sim->s_block, sim->s_grid, sim->s_lds));
         }
-        sim->last_dt = dt;
+        pd_sim_advanced(sim, nsteps, dt);
         return PD_OK;
     }
     for (int64_t k = 0; k < nsteps; ++k) {

@@ -106,7 +106,6 @@ struct pd_sim_s {
     unsigned s_grid = 0;
     uint32_t s_mmax = 0;
     size_t s_lds = 0;
-    int s_slots = 0;
 };
 
 // ---------------------------------------------------------------------------

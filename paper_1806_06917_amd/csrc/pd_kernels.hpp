@@ -76,21 +76,21 @@ __device__ __forceinline__ double rsqrt_pos(double r2) {
 }
 
 // One bond: xi = X_j - X_i, eta = u_j - u_i, cVj = c V_j; `dead` marks a bond
-// broken earlier.  Returns true if the bond breaks now (S > s_c); a bond that
+// broken earlier; damage on/off and the critical stretch s_c.  Returns true if the bond breaks now (S > s_c); a bond that
 // is dead or breaks now contributes exact zeros.  Otherwise adds
 // c V_j S xi/|xi| (and (c/4) V_j S^2 |xi| if WANT_E) to the lane's sums.
 // Everything runs in float64; mixed precision takes 1/|xi| from the hardware
 // reciprocal-square-root estimate alone (relative error below 2^-22), the
 // FP64 mode refines it to full double precision.
 template <int DIM, bool MIXED, bool WANT_E>
-__device__ __forceinline__ bool bond(const NodeArgs &a, double dxx, double dxy, double dxz,
+__device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double dxy, double dxz,
                                      double dux, double duy, double duz, double cVj, bool dead,
                                      Acc64 &s) {
     const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
     const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double S = ex * (inv * inv);
-    const bool brk = a.damage && S > a.s_c;
+    const bool brk = damage && S > s_c;
     const bool off = brk || dead;
     const double g = off ? 0.0 : cVj * S * inv;
     s.x += g * dxx;
@@ -217,6 +217,34 @@ __host__ __device__ inline bool mode_wants_energy(const NodeArgs &a) {
     return a.mode == M_ENERGY || (a.mode == M_FORCE && a.e_out != nullptr);
 }
 
+// one instance of a streamed batch (device memory).  The dynamic fields give
+// the instance's state at batch step 0: its step count, which record buffer
+// holds u, whether v holds v^{k-1/2}, and how many batch steps it takes.
+struct StreamInst {
+    const uint32_t *row_ptr;
+    const uint32_t *halo_ptr;
+    const int32_t *halo;
+    const uint32_t *self_off;
+    uint16_t *bw;
+    double *rec[2];
+    double *v;
+    const uint8_t *bc;          // padded to whole 32-bit words
+    const double *bc_vel;
+    const double *b;
+    uint32_t n, tile_begin;     // nodes; first tile in the batch numbering
+    double cv, s_c, rho, dt;
+    int damage, cur0, vhalf0, pad;
+    int64_t ramp, step0, limit;
+};
+
+struct StreamArgs {
+    const StreamInst *inst;     // batch launches: the instance descriptors
+    uint32_t ninst, ntiles, tile, hcap, bcap, mmax;
+    const int64_t *bstep;       // batch step from this counter, or `step` if NULL
+    int64_t step;
+    StreamInst one;             // single-simulation launches: the descriptor itself
+};
+
 }  // namespace pdk
 
 // launchers (pd_force.hip, pd_tile.hip, pd_stream.hip)
@@ -231,14 +259,25 @@ size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint
 bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
                       int block, int num_cu, int *rpt, unsigned *grid, uint32_t *mmax,
                       size_t *lds, int max_per_cu);
-// streamed kernel (explicit steps with uniform volumes): launch geometry, false
-// if it cannot run this layout; launch; node records from / to xv and u
-bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t n, uint64_t nnz, uint32_t ntiles,
-                        uint32_t tile, uint32_t hcap, uint32_t bcap, uint64_t halo_total,
-                        int lanes, bool mixed, int *block, unsigned *grid, uint32_t *mmax,
-                        size_t *lds, int *slots);
-int pd_launch_stream(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool mixed,
-                     int block, unsigned grid, size_t lds, int slots);
+// streamed kernel (explicit steps with uniform volumes) ----------------------
+
+// (batch: the kernel form that reads descriptors from device memory)
+bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, int *block,
+                        unsigned *grid, uint32_t *mmax, size_t *lds);
+bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total);
+int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const pdk::StreamArgs &sa, int lanes,
+                     bool mixed, int block, unsigned grid, size_t lds);
+// a simulation's streamed descriptor (static part), the launch arguments of a
+// batch shaped like it (inst NULL: single-simulation form), and its host state
+// after streamed steps
+pdk::StreamInst pd_stream_inst(const pd_sim s);
+pdk::StreamArgs pd_stream_args(const pd_sim sim, const pdk::StreamInst *inst, uint32_t ninst,
+                               uint32_t ntiles);
+void pd_sim_advanced(pd_sim sim, int64_t nsteps, double dt);
+// device step counter of a batch (set / add one), on stream st
+int pd_counter_set(pd_ctx ctx, hipStream_t st, int64_t *c, int64_t v);
+int pd_counter_tick(pd_ctx ctx, hipStream_t st, int64_t *c);
 int pd_rec_pack(pd_ctx ctx, int dim, uint32_t n, const double *xv, const double *u, double *rec);
 int pd_rec_unpack(pd_ctx ctx, int dim, uint32_t n, const double *rec, double *u);
 // LDS halo capacity of a tiled neighbour list

@@ -1,29 +1,32 @@
 // Streamed tiles: the explicit step (velocity Verlet with the bond-force
 // gather, critical-stretch damage and boundary data; Algorithm 4 with the
-// force of Algorithm 1) over LDS tiles whose staging runs asynchronously.
+// force of Algorithm 1) over LDS tiles whose staging runs asynchronously, for
+// one simulation or a batch of independent ones in the same launch.
 //
 // Same tiles as the register-staged tile kernel (T consecutive sfc nodes,
 // halo H_t, 16-bit tile-local bond words), but every global -> LDS copy is a
 // gfx950 LDS DMA (global_load_lds_dword / _dwordx4): the data goes from L2
-// straight into LDS without passing through registers, so the copies for tile
-// k+1 stay in flight while the workgroup sums the bonds of tile k.  LDS holds
-// one or two tile slots (records, bond words, row offsets, v and boundary
-// kinds) plus the halo ids one tile further ahead.
+// straight into LDS without passing through registers, and no registers are
+// held for prefetching, so two workgroups share each CU and cover each
+// other's copy latency.
 //
 // Node state lives in HBM as one record per node, {x y z ux uy uz} (2-d:
 // {x y ux uy}); a record is 3 (2) 16-byte chunks, so a halo record is three
 // (two) DMA lanes.  The node update writes u^{k+1} into the u part of the
 // other record buffer (the positions are never rewritten).
 //
-// Per workgroup iteration k, with two slots (tile k in slot k mod 2):
-//   wait for this wave's copies, barrier: tile k and the ids of tile k+1 are
-//   in LDS, the sums of tile k-1 are done; write back the bond words of tile
-//   k-1 that broke; issue the copies of tile k+1 into the other slot and of
-//   the ids of tile k+2; sum the bonds of tile k, one lane group per node in
-//   the gather kernel's summation order (so results are bit-identical to
-//   it), and let lane 0 of each group update its node (kick, drift, boundary
-//   data).  With one slot the copies of tile k+1 start after the sums of
-//   tile k, and the other workgroups on the CU fill the wait.
+// A batch is a list of instances (StreamInst); their tiles are numbered one
+// after the other and the persistent grid walks that list, so instances of
+// any size share the launch.  The step index comes from a device counter (or
+// the argument list), so a chunk of steps can be captured once in a hipGraph
+// and replayed.
+//
+// Per workgroup tile k: wait for this wave's copies, barrier (tile k and the
+// ids of tile k+1 are in LDS); sum the bonds, one lane group per node in the
+// gather kernel's summation order (so results are bit-identical to it), and
+// let L lanes of each group update their node (kick, drift, boundary data),
+// one component per lane; barrier; write back the bond words that broke;
+// issue the copies of tile k+1 and of the halo ids of tile k+2.
 #include <climits>
 
 #include "pd_kernels.hpp"
@@ -57,6 +60,42 @@ __device__ __forceinline__ void dma4(const void *base, uint32_t voff, uint32_t m
 }
 __device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+
+// an instance descriptor, read through the constant address space: scalar
+// loads, which complete on their own counter and never wait for the tile
+// copies or the node updates' stores in flight
+typedef const __attribute__((address_space(4))) StreamInst *cinst;
+__device__ __forceinline__ StreamInst load_inst(const StreamInst *base, uint32_t i) {
+    const cinst p = (cinst)(uintptr_t)(base + i);
+    StreamInst d;
+    d.row_ptr = p->row_ptr;
+    d.halo_ptr = p->halo_ptr;
+    d.halo = p->halo;
+    d.self_off = p->self_off;
+    d.bw = p->bw;
+    d.rec[0] = p->rec[0];
+    d.rec[1] = p->rec[1];
+    d.v = p->v;
+    d.bc = p->bc;
+    d.bc_vel = p->bc_vel;
+    d.b = p->b;
+    d.n = p->n;
+    d.tile_begin = p->tile_begin;
+    d.cv = p->cv;
+    d.s_c = p->s_c;
+    d.rho = p->rho;
+    d.dt = p->dt;
+    d.damage = p->damage;
+    d.cur0 = p->cur0;
+    d.vhalf0 = p->vhalf0;
+    d.pad = 0;
+    d.ramp = p->ramp;
+    d.step0 = p->step0;
+    d.limit = p->limit;
+    return d;
+}
+
+
 // barrier that orders LDS only (global traffic in flight stays in flight)
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -64,156 +103,186 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int META = 5;              // h0, hn, b0 (even), b1, self offset
+// per-tile metadata (32-bit words): h0, hn, b0 (even), b1, self offset,
+// instance, first node, node count
+constexpr int META = 8;
+enum { MT_H0, MT_HN, MT_B0, MT_B1, MT_SO, MT_INST, MT_T0, MT_TN };
 constexpr uint16_t BW_DEAD = 0x8000;
 constexpr uint32_t BRK_CAP = 256;    // broken bonds listed per tile (more: the whole tile)
 
 inline __host__ __device__ uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
 
-// LDS layout, in this order (every region a multiple of 16 bytes).  NS tile
-// slots (records, bond words, row offsets, v, boundary kinds), two halo-id
+// LDS layout, in this order (every region a multiple of 16 bytes): the tile
+// slot (records, bond words, row offsets, v, boundary kinds), two halo-id
 // slots, three break lists (tile k uses list k mod 3, so a list is cleared
-// one tile before its next use without an extra barrier).
+// one tile before its next use without an extra barrier), tile metadata.
 struct StreamLayout {
-    uint32_t NS, H, T, WB, TP, TB, MM, RD, US;
-    __host__ __device__ StreamLayout(int ns, int dim, uint32_t hcap, uint32_t bcap,
-                                     uint32_t tile, uint32_t mmax) {
-        NS = (uint32_t)ns;
+    uint32_t H, T, WB, TP, TB, MM, RD, US;
+    __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile,
+                                     uint32_t mmax) {
         H = hcap;                      // multiple of 32
         T = tile;
-        WB = round4(bcap / 2 + 2);     // 32-bit bond-word pairs per slot
-        TP = round4(tile + 1);         // row offsets per slot
-        TB = round4(tile / 4 + 1);     // 32-bit words of boundary kinds per slot
+        WB = round4(bcap / 2 + 2);     // 32-bit bond-word pairs
+        TP = round4(tile + 1);         // row offsets
+        TB = round4(tile / 4 + 1);     // 32-bit words of boundary kinds
         MM = round4(mmax * META);
         RD = dim == 3 ? 6 : 4;         // doubles per record
         US = dim == 3 ? 4 : 2;         // doubles per node in v
     }
     __host__ __device__ size_t bytes() const {
-        return (size_t)NS * H * RD * 8 + (size_t)2 * H * 4 + (size_t)NS * WB * 4 +
-               (size_t)NS * TP * 4 + (size_t)NS * T * US * 8 + (size_t)NS * TB * 4 +
-               (size_t)3 * (BRK_CAP + 4) * 4 + (size_t)MM * 4;
+        return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)WB * 4 + (size_t)TP * 4 +
+               (size_t)T * US * 8 + (size_t)TB * 4 + (size_t)3 * (BRK_CAP + 4) * 4 +
+               (size_t)MM * 4;
     }
 };
 
-// NS = 2: the copies of tile k+1 fly while tile k is summed (one workgroup
-// holds both slots).  NS = 1: one slot, copies start after the sums, and the
-// workgroups sharing a CU cover each other's waits.
-template <int DIM, int L, bool MIXED, int NS>
-__global__ __launch_bounds__(1024) void stream_kernel(NodeArgs a) {
+__device__ __forceinline__ double ramp_of(double s, int64_t ramp) {
+    if (ramp <= 0) return 1.0;
+    const double r = s / (double)ramp;
+    return r < 1.0 ? r : 1.0;
+}
+
+// BATCH = false: one simulation whose descriptor travels in the kernel
+// arguments (sa.one); true: sa.ninst descriptors in device memory.
+template <int DIM, int L, bool MIXED, bool BATCH>
+__global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     extern __shared__ __attribute__((aligned(16))) double lds[];
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
-    const StreamLayout lay(NS, DIM, a.hcap, a.bcap, a.tile, a.mmax);
-    const uint32_t H = lay.H, T = lay.T, WB = lay.WB, TP = lay.TP, TB = lay.TB;
+    const StreamLayout lay(DIM, sa.hcap, sa.bcap, sa.tile, sa.mmax);
+    const uint32_t H = lay.H, T = lay.T;
     const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u, wbase = tid - lane64;
-    double *recs = lds;                                                          // NS H RD
-    int32_t *ids = reinterpret_cast<int32_t *>(recs + (size_t)NS * H * RD);      // 2 H
-    uint32_t *words = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);         // NS WB
-    uint32_t *rowp = words + (size_t)NS * WB;                                    // NS TP
-    double *vbuf = reinterpret_cast<double *>(rowp + (size_t)NS * TP);           // NS T US
-    uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)NS * T * US);    // NS TB
-    uint32_t *brk = bcb + (size_t)NS * TB;                                       // 3 (4 + CAP)
+    double *rec = lds;                                                           // H RD
+    int32_t *ids = reinterpret_cast<int32_t *>(rec + (size_t)H * RD);            // 2 H
+    uint32_t *words = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);         // WB
+    uint32_t *rowp = words + lay.WB;                                             // TP
+    double *vbuf = reinterpret_cast<double *>(rowp + lay.TP);                    // T US
+    uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)T * US);         // TB
+    uint32_t *brk = bcb + lay.TB;                                                // 3 (4 + CAP)
     uint32_t *meta = brk + 3 * (BRK_CAP + 4);                                    // MM
-    const bool wants_v = mode_reads_v(a.mode);
-    auto slot = [&](uint32_t k) { return NS == 2 ? (k & 1u) : 0u; };
+    const StreamInst *inst = sa.inst;
+    const int64_t s = sa.bstep ? *sa.bstep : sa.step;   // batch step of this launch
+    // the record buffer holding u at this step
+    auto cur_of = [&](const StreamInst &I) { return (uint32_t)((I.cur0 + s) & 1); };
 
     // persistent schedule: the tiles of this XCD's contiguous range, strided
     // over the XCD's workgroups
     const uint32_t nb = gridDim.x, x = blockIdx.x % 8, l = blockIdx.x / 8;
     const uint32_t gx = nb / 8 + (x < nb % 8 ? 1u : 0u);
-    const uint32_t tq = a.ntiles / 8, tr = a.ntiles % 8;
+    const uint32_t tq = sa.ntiles / 8, tr = sa.ntiles % 8;
     const uint32_t tbeg = x * tq + (x < tr ? x : tr), tcnt = tq + (x < tr ? 1u : 0u);
     const uint32_t K = l < tcnt ? (tcnt - l + gx - 1) / gx : 0u;
     if (K == 0) return;
-    auto tile_of = [&](uint32_t k) { return tbeg + l + k * gx; };
 
+    // metadata of every tile of this workgroup; tiles of instances that take
+    // no step at this batch step get hn = 0 and are skipped
     for (uint32_t k = tid; k < K; k += B) {
-        const uint32_t t = tile_of(k), t0 = t * T, tn = min(T, a.n - t0);
-        const uint32_t h0 = a.halo_ptr[t];
+        const uint32_t g = tbeg + l + k * gx;
+        uint32_t lo = 0, hi = BATCH ? sa.ninst : 1u;   // last instance with tile_begin <= g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (inst[mid].tile_begin <= g) lo = mid;
+            else hi = mid;
+        }
+        const StreamInst I = BATCH ? load_inst(inst, lo) : sa.one;
+        const uint32_t t = g - I.tile_begin, t0 = t * T, tn = min(T, I.n - t0);
+        const uint32_t h0 = I.halo_ptr[t];
         uint32_t *m = meta + (size_t)k * META;
-        m[0] = h0;
-        m[1] = a.halo_ptr[t + 1] - h0;
-        m[2] = a.row_ptr[t0] & ~1u;
-        m[3] = a.row_ptr[t0 + tn];
-        m[4] = a.self_off[t];
+        m[MT_H0] = h0;
+        m[MT_HN] = s < I.limit ? I.halo_ptr[t + 1] - h0 : 0u;
+        m[MT_B0] = I.row_ptr[t0] & ~1u;
+        m[MT_B1] = I.row_ptr[t0 + tn];
+        m[MT_SO] = I.self_off[t];
+        m[MT_INST] = lo;
+        m[MT_T0] = t0;
+        m[MT_TN] = tn;
     }
+    // descriptor of tile k's instance (the index is the same in every lane)
+    auto inst_of = [&](uint32_t k) {
+        if (!BATCH) return sa.one;
+        return load_inst(inst, (uint32_t)__builtin_amdgcn_readfirstlane(meta[k * META + MT_INST]));
+    };
     auto blist = [&](uint32_t k) { return brk + (k % 3u) * (BRK_CAP + 4); };
     if (tid < 3) brk[tid * (BRK_CAP + 4)] = 0;
     __syncthreads();
 
+
     // halo ids of tile k -> ids slot k mod 2
     auto issue_ids = [&](uint32_t k) {
-        const uint32_t h0 = meta[k * META], hn = meta[k * META + 1];
+        const StreamInst I = inst_of(k);
+        const void *halo = I.halo;
+        const uint32_t h0 = meta[k * META + MT_H0], hn = meta[k * META + MT_HN];
         int32_t *dst = ids + (size_t)(k & 1u) * H;
         for (uint32_t c0 = wbase; c0 < hn; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(dst + c0));
-            if (c0 + lane64 < hn) dma4(a.halo, (h0 + c0 + lane64) * 4u, m0);
+            if (c0 + lane64 < hn) dma4(halo, (h0 + c0 + lane64) * 4u, m0);
         }
     };
-    // records, bond words, row offsets, v and boundary kinds of tile k ->
-    // its slot (the ids of tile k are in ids slot k mod 2)
+    // records, bond words, row offsets, v and boundary kinds of tile k (the
+    // ids of tile k are in ids slot k mod 2)
     auto issue_tile = [&](uint32_t k) {
-        const uint32_t s = slot(k), t = tile_of(k), t0 = t * T, tn = min(T, a.n - t0);
-        const uint32_t hn = meta[k * META + 1], b0 = meta[k * META + 2], b1 = meta[k * META + 3];
+        const uint32_t hn = meta[k * META + MT_HN];
+        if (hn == 0) return;
+        const uint32_t t0 = meta[k * META + MT_T0], tn = meta[k * META + MT_TN];
+        const uint32_t b0 = meta[k * META + MT_B0], b1 = meta[k * META + MT_B1];
         const int32_t *hid = ids + (size_t)(k & 1u) * H;
-        double *rdst = recs + (size_t)s * H * RD;
+        const StreamInst I = inst_of(k);
+        const void *src = cur_of(I) ? I.rec[1] : I.rec[0], *bw = I.bw;
+        const void *rp = I.row_ptr, *vv = I.v, *bc = I.bc;
         const uint32_t nrc = hn * NCH;
         for (uint32_t c0 = wbase; c0 < nrc; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rdst + 2 * (size_t)c0));
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rec + 2 * (size_t)c0));
             const uint32_t c = c0 + lane64;
             if (c < nrc) {
                 const uint32_t r = c / NCH, part = c - r * NCH;
-                dma16(a.rec, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
+                dma16(src, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
             }
         }
         const uint32_t nw = (b1 - b0 + 1) / 2;
-        uint32_t *wdst = words + (size_t)s * WB;
         for (uint32_t c0 = wbase; c0 < nw; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(wdst + c0));
-            if (c0 + lane64 < nw) dma4(a.bw, (b0 / 2 + c0 + lane64) * 4u, m0);
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(words + c0));
+            if (c0 + lane64 < nw) dma4(bw, (b0 / 2 + c0 + lane64) * 4u, m0);
         }
-        uint32_t *pdst = rowp + (size_t)s * TP;
         for (uint32_t c0 = wbase; c0 <= tn; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(pdst + c0));
-            if (c0 + lane64 <= tn) dma4(a.row_ptr, (t0 + c0 + lane64) * 4u, m0);
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rowp + c0));
+            if (c0 + lane64 <= tn) dma4(rp, (t0 + c0 + lane64) * 4u, m0);
         }
-        if (wants_v) {
-            const uint32_t nvc = tn * US / 2;
-            double *vdst = vbuf + (size_t)s * T * US;
-            for (uint32_t c0 = wbase; c0 < nvc; c0 += B) {
-                const uint32_t m0 =
-                    __builtin_amdgcn_readfirstlane(lds_addr(vdst + 2 * (size_t)c0));
-                if (c0 + lane64 < nvc) dma16(a.v, (t0 * US + 2 * (c0 + lane64)) * 8u, m0);
-            }
+        const uint32_t nvc = tn * US / 2;
+        for (uint32_t c0 = wbase; c0 < nvc; c0 += B) {
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(vbuf + 2 * (size_t)c0));
+            if (c0 + lane64 < nvc) dma16(vv, (t0 * US + 2 * (c0 + lane64)) * 8u, m0);
         }
-        if (a.bc) {
-            const uint32_t nbw = (tn + 3) / 4;   // the array is padded to whole words
-            uint32_t *bdst = bcb + (size_t)s * TB;
-            for (uint32_t c0 = wbase; c0 < nbw; c0 += B) {
-                const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(bdst + c0));
-                if (c0 + lane64 < nbw) dma4(a.bc, t0 + 4 * (c0 + lane64), m0);
-            }
+        const uint32_t nbw = (tn + 3) / 4;   // the array is padded to whole words
+        for (uint32_t c0 = wbase; c0 < nbw; c0 += B) {
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(bcb + c0));
+            if (c0 + lane64 < nbw) dma4(bc, t0 + 4 * (c0 + lane64), m0);
         }
     };
 
-    // bond sums of tile k; lane 0 of each node's group then updates the node
-    // (kick, drift, boundary data).  A bond that breaks gets its dead bit in
-    // the slot's copy of the words and goes on the tile's break list.
+    // bond sums of tile k; then L lanes of each node's group update the node
+    // (kick, drift, boundary data), one component per lane, with the same
+    // arithmetic as node_update's explicit-step branch.  A bond that breaks
+    // gets its dead bit in the LDS copy of the words and goes on the list.
     auto sum_and_update = [&](uint32_t k) {
-        const uint32_t s = slot(k), t = tile_of(k), t0 = t * T, tn = min(T, a.n - t0);
-        const uint32_t b0 = meta[k * META + 2], so = meta[k * META + 4];
-        const double *rec = recs + (size_t)s * H * RD;
-        uint16_t *w16 = reinterpret_cast<uint16_t *>(words + (size_t)s * WB);
-        const uint32_t *rp = rowp + (size_t)s * TP;
+        if (meta[k * META + MT_HN] == 0) return;
+        const StreamInst I = inst_of(k);
+        const uint32_t t0 = meta[k * META + MT_T0], tn = meta[k * META + MT_TN];
+        const uint32_t b0 = meta[k * META + MT_B0], so = meta[k * META + MT_SO];
+        const uint32_t cur = cur_of(I);
+        double *out = cur ? I.rec[0] : I.rec[1];
+        const int mode = (s > 0 || I.vhalf0) ? M_STEP_CONT : M_STEP_FIRST;
+        const double r_half = ramp_of((double)(I.step0 + s) + 0.5, I.ramp);
+        const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho;
+        const int damage = I.damage;
+        uint16_t *w16 = reinterpret_cast<uint16_t *>(words);
         uint32_t *bl = blist(k);
         const uint32_t groups = B / L, g = tid / L;
         const int lane = tid & (L - 1);
-        const double cv = a.cv_uniform;
         for (uint32_t q = g; q < tn; q += groups) {
             const double *ri = rec + (size_t)(so + q) * RD;
             const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
             const double uix = ri[DIM], uiy = ri[DIM + 1], uiz = DIM == 3 ? ri[DIM + 2] : 0.0;
             Acc64 acc;
-            const uint32_t rs = rp[q] - b0, re = rp[q + 1] - b0;
+            const uint32_t rs = rowp[q] - b0, re = rowp[q + 1] - b0;
             for (uint32_t p = rs + lane; p < re; p += L) {
                 const uint32_t w = w16[p];
                 const double2 *rj =
@@ -228,9 +297,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(NodeArgs a) {
                     dxx = c0.x - xix; dxy = c0.y - xiy; dxz = 0.0;
                     dux = c1.x - uix; duy = c1.y - uiy; duz = 0.0;
                 }
-                if (bond<DIM, MIXED, false>(a, dxx, dxy, dxz, dux, duy, duz, cv,
+                if (bond<DIM, MIXED, false>(damage, s_c, dxx, dxy, dxz, dux, duy, duz, cv,
                                             (w & BW_DEAD) != 0, acc)) {
-                    // a break: dead bit in the slot's copy, entry on the list
                     const uint32_t nw = (uint32_t)(w | BW_DEAD);
                     w16[p] = (uint16_t)nw;
                     const uint32_t e = atomicAdd(bl, 1u);
@@ -239,54 +307,48 @@ __global__ __launch_bounds__(1024) void stream_kernel(NodeArgs a) {
             }
             double fx, fy, fz, Ue;
             group_reduce<DIM, L, false>(acc, fx, fy, fz, Ue);
-            // node update, one lane per component (the same arithmetic as
-            // node_update's explicit-step branch, so results stay identical)
             if (lane < (int)DIM) {
                 const uint32_t d = (uint32_t)lane, i = t0 + q;
                 const double fd = d == 0 ? fx : (d == 1 ? fy : fz);
                 const double ud = ri[DIM + d];
-                double vd = wants_v ? vbuf[(size_t)s * T * US + (size_t)q * US + d] : 0.0;
-                const int kind =
-                    a.bc ? (int)reinterpret_cast<const uint8_t *>(bcb + (size_t)s * TB)[q]
-                         : PD_BC_FREE;
-                const double hdt = 0.5 * a.dt;
+                double vd = vbuf[(size_t)q * US + d];
+                const int kind = (int)reinterpret_cast<const uint8_t *>(bcb)[q];
+                const double hdt = 0.5 * dt;
                 double nd;
                 if (kind == PD_BC_FREE) {
-                    const double bd = a.b ? a.b[(size_t)i * US + d] : 0.0;
-                    if (a.mode == M_STEP_CONT) vd = vd + hdt * (fd + bd) / a.rho;
-                    vd = vd + hdt * (fd + bd) / a.rho;
-                    nd = ud + a.dt * vd;
+                    const double bd = I.b ? I.b[(size_t)i * US + d] : 0.0;
+                    if (mode == M_STEP_CONT) vd = vd + hdt * (fd + bd) / rho;
+                    vd = vd + hdt * (fd + bd) / rho;
+                    nd = ud + dt * vd;
                 } else if (kind == PD_BC_CLAMPED) {
                     vd = 0.0;
                     nd = 0.0;
                 } else {
-                    vd = a.r_half * a.bc_vel[(size_t)i * US + d];
-                    nd = ud + a.dt * vd;
+                    vd = r_half * I.bc_vel[(size_t)i * US + d];
+                    nd = ud + dt * vd;
                 }
-                a.v[(size_t)i * US + d] = vd;
-                a.rec_out[(size_t)i * RD + DIM + d] = nd;
+                I.v[(size_t)i * US + d] = vd;
+                out[(size_t)i * RD + DIM + d] = nd;
             }
         }
     };
 
     // the bond words of tile k that broke go back to HBM; a tile with more
-    // breaks than the list holds writes back all its words from its slot
-    // (the caller guarantees that slot is still intact)
-    auto write_back = [&](uint32_t k, bool from_slot) {
+    // breaks than the list holds writes back all its words from LDS
+    auto write_back = [&](uint32_t k, uint32_t nbk) {
+        uint16_t *bw = inst_of(k).bw;
         const uint32_t *bl = blist(k);
-        const uint32_t b0 = meta[k * META + 2];
-        if (!from_slot) {
-            const uint32_t ne = min(bl[0], BRK_CAP);
-            for (uint32_t e = tid; e < ne; e += B) {
+        const uint32_t b0 = meta[k * META + MT_B0];
+        if (nbk <= BRK_CAP) {
+            for (uint32_t e = tid; e < nbk; e += B) {
                 const uint32_t v = bl[4 + e];
-                a.bw[b0 + (v >> 16)] = (uint16_t)(v & 0xffffu);
+                bw[b0 + (v >> 16)] = (uint16_t)(v & 0xffffu);
             }
         } else {
-            const uint32_t s = slot(k), t0 = tile_of(k) * T, tn = min(T, a.n - t0);
-            const uint32_t *rp = rowp + (size_t)s * TP;
-            const uint16_t *w16 = reinterpret_cast<const uint16_t *>(words + (size_t)s * WB);
-            const uint32_t rs = rp[0] - b0, re = rp[tn] - b0;
-            for (uint32_t q = rs + tid; q < re; q += B) a.bw[b0 + q] = w16[q];
+            const uint32_t tn = meta[k * META + MT_TN];
+            const uint16_t *w16 = reinterpret_cast<const uint16_t *>(words);
+            const uint32_t rs = rowp[0] - b0, re = rowp[tn] - b0;
+            for (uint32_t q = rs + tid; q < re; q += B) bw[b0 + q] = w16[q];
         }
     };
 
@@ -299,40 +361,32 @@ __global__ __launch_bounds__(1024) void stream_kernel(NodeArgs a) {
         dma_wait();
         lds_barrier();                       // tile k and the ids of tile k+1 are in LDS
         if (tid == 0) blist(k + 1)[0] = 0;   // last read for tile k-2
-        if (NS == 2) {
-            if (k > 0) {                     // breaks of tile k-1, whose slot is reused below
-                const uint32_t nbk = blist(k - 1)[0];
-                if (nbk) write_back(k - 1, nbk > BRK_CAP);
-                if (nbk > BRK_CAP) lds_barrier();
-            }
-            if (k + 1 < K) issue_tile(k + 1);
-            if (k + 2 < K) issue_ids(k + 2);
-            sum_and_update(k);
-        } else {
-            sum_and_update(k);
-            lds_barrier();                   // the slot is free once the sums are done
-            const uint32_t nbk = blist(k)[0];
-            if (nbk) write_back(k, nbk > BRK_CAP);
-            if (nbk > BRK_CAP) lds_barrier();
-            if (k + 1 < K) issue_tile(k + 1);
-            if (k + 2 < K) issue_ids(k + 2);
-        }
-    }
-    if (NS == 2) {
-        lds_barrier();
-        const uint32_t nbk = blist(K - 1)[0];
-        if (nbk) write_back(K - 1, nbk > BRK_CAP);
+        sum_and_update(k);
+        lds_barrier();                       // the slot is free once the sums are done
+        const uint32_t nbk = blist(k)[0];
+        if (nbk) write_back(k, nbk);
+        if (nbk > BRK_CAP) lds_barrier();    // the words were read from the slot
+        if (k + 1 < K) issue_tile(k + 1);
+        if (k + 2 < K) issue_ids(k + 2);
     }
 }
 
+__global__ void counter_set_k(int64_t *c, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[threadIdx.x] = v;
+}
+__global__ void counter_tick_k(int64_t *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[threadIdx.x] += 1;
+}
+
 template <int DIM>
-void *pick_stream(int lanes, bool mixed, int ns) {
+void *pick_stream(int lanes, bool mixed, bool batch) {
 #define PD_SK(Lv)                                                                          \
     case Lv:                                                                               \
-        if (ns == 2)                                                                       \
-            return mixed ? (void *)stream_kernel<DIM, Lv, true, 2>                         \
-                         : (void *)stream_kernel<DIM, Lv, false, 2>;                       \
-        return mixed ? (void *)stream_kernel<DIM, Lv, true, 1> : (void *)stream_kernel<DIM, Lv, false, 1>;
+        if (batch)                                                                         \
+            return mixed ? (void *)stream_kernel<DIM, Lv, true, true>                      \
+                         : (void *)stream_kernel<DIM, Lv, false, true>;                    \
+        return mixed ? (void *)stream_kernel<DIM, Lv, true, false>                         \
+                     : (void *)stream_kernel<DIM, Lv, false, false>;
     switch (lanes) {
         PD_SK(2)
         PD_SK(4)
@@ -366,24 +420,17 @@ __global__ void rec_unpack_k(uint32_t n, const double *rec, double *u) {
 
 }  // namespace
 
-// tile slots per workgroup: 1 lets two or more workgroups share a CU
-constexpr int STREAM_SLOTS = 1;
-
-// Launch geometry of the streamed kernel; false if it cannot run this layout.
-bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t n, uint64_t nnz, uint32_t ntiles,
-                        uint32_t tile, uint32_t hcap, uint32_t bcap, uint64_t halo_total,
-                        int lanes, bool mixed, int *block, unsigned *grid, uint32_t *mmax,
-                        size_t *lds, int *slots) {
+// Launch geometry of the streamed kernel for ntiles tiles in total; false if
+// it cannot run this layout.
+bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, int *block,
+                        unsigned *grid, uint32_t *mmax, size_t *lds) {
     const uint32_t B = tile * (uint32_t)lanes;
     if (B < 64 || B > 1024 || B % 64 != 0) return false;
     if (lanes < dim) return false;   // the node update takes one lane per component
-    const uint32_t RB = dim == 3 ? 48u : 32u;
-    // 32-bit byte offsets of every copy; 16-bit tile-local bond positions
-    if ((uint64_t)n * RB >= (1ull << 32) || 2 * nnz + 16 >= (1ull << 32) ||
-        halo_total * 4 >= (1ull << 32) || bcap >= (1u << 16))
-        return false;
-    const int ns = STREAM_SLOTS;
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, ns) : pick_stream<2>(lanes, mixed, ns);
+    if (bcap >= (1u << 16)) return false;   // 16-bit tile-local bond positions
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch)
+                       : pick_stream<2>(lanes, mixed, batch);
     if (!k) return false;
     for (int pass = 0; pass < 2; ++pass) {
         // first pass: one workgroup per CU gives the tile bound; second pass:
@@ -391,7 +438,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t n, uint64_t nnz, uint32_t 
         unsigned g = (unsigned)ctx->num_cu;
         if (pass == 1) {
             int per_cu = 0;
-            const size_t bytes = StreamLayout(ns, dim, hcap, bcap, tile, *mmax).bytes();
+            const size_t bytes = StreamLayout(dim, hcap, bcap, tile, *mmax).bytes();
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, (int)B,
                                                              bytes) != hipSuccess)
@@ -413,26 +460,45 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t n, uint64_t nnz, uint32_t 
             const uint32_t kk = (tc + gx - 1) / gx;
             if (kk > m) m = kk;
         }
-        const size_t bytes = StreamLayout(ns, dim, hcap, bcap, tile, m).bytes();
+        const size_t bytes = StreamLayout(dim, hcap, bcap, tile, m).bytes();
         if (bytes > 160 * 1024) return false;
         *mmax = m;
         *lds = bytes;
         *grid = g;
     }
     *block = (int)B;
-    *slots = ns;
     return true;
 }
 
-int pd_launch_stream(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mixed, int block,
-                     unsigned grid, size_t lds, int slots) {
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, slots)
-                       : pick_stream<2>(lanes, mixed, slots);
+// a neighbour list's record and copy offsets fit the kernel's 32-bit forms
+bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total) {
+    const uint64_t RB = dim == 3 ? 48u : 32u;
+    return (uint64_t)n * RB < (1ull << 32) && 2 * nnz + 16 < (1ull << 32) &&
+           halo_total * 4 < (1ull << 32);
+}
+
+int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const StreamArgs &sa, int lanes,
+                     bool mixed, int block, unsigned grid, size_t lds) {
+    const bool batch = sa.inst != nullptr;
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch)
+                       : pick_stream<2>(lanes, mixed, batch);
     if (!k) return pd_set_error(ctx, PD_EINVAL, "streamed kernel needs 2..32 lanes");
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    NodeArgs args = a;
+    StreamArgs args = sa;
     void *argv[] = {&args};
-    PD_HIP(ctx, hipLaunchKernel(k, dim3(grid), dim3(block), argv, lds, ctx->stream));
+    PD_HIP(ctx, hipLaunchKernel(k, dim3(grid), dim3(block), argv, lds, st));
+    return PD_OK;
+}
+
+int pd_counter_set(pd_ctx ctx, hipStream_t st, int64_t *c, int64_t v) {
+    counter_set_k<<<1, 64, 0, st>>>(c, v);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int pd_counter_tick(pd_ctx ctx, hipStream_t st, int64_t *c) {
+    counter_tick_k<<<1, 64, 0, st>>>(c);
+    PD_LAUNCH_CHECK(ctx);
     return PD_OK;
 }
 

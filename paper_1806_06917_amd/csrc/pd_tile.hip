@@ -330,14 +330,14 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
                     read_rec<DIM>(rec, j1, C);
                     const double cv0 = UV ? a.cv_uniform : cv[j0];
                     const double cv1 = UV ? a.cv_uniform : cv[j1];
-                    if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                    if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, A[0] - xix, A[1] - xiy,
                                                  DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
                                                  A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
                                                  cv0, (w0 & BW_DEAD) != 0, acc)) {
                         sbw16w[p] = (uint16_t)(w0 | BW_DEAD);
                         sflag[0] = 1;
                     }
-                    if (bond<DIM, MIXED, WANT_E>(a, C[0] - xix, C[1] - xiy,
+                    if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, C[0] - xix, C[1] - xiy,
                                                  DIM == 3 ? C[2] - xiz : 0.0, C[IU] - uix,
                                                  C[IU + 1] - uiy, DIM == 3 ? C[IU + 2] - uiz : 0.0,
                                                  cv1, (w1 & BW_DEAD) != 0, acc)) {
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
                     double A[NC];
                     read_rec<DIM>(rec, j0, A);
                     const double cv0 = UV ? a.cv_uniform : cv[j0];
-                    if (bond<DIM, MIXED, WANT_E>(a, A[0] - xix, A[1] - xiy,
+                    if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, A[0] - xix, A[1] - xiy,
                                                  DIM == 3 ? A[2] - xiz : 0.0, A[IU] - uix,
                                                  A[IU + 1] - uiy, DIM == 3 ? A[IU + 2] - uiz : 0.0,
                                                  cv0, (w0 & BW_DEAD) != 0, acc)) {

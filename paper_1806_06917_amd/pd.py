@@ -67,6 +67,9 @@ def _load():
         "pd_sim_set": (i32, [vp, vp, vp, vp, i64]),
         "pd_sim_destroy": (i32, [vp]),
         "pd_sim_info": (i32, [vp, P(i32), P(i32), P(i32), P(i32)]),
+        "pd_batch_create": (i32, [vp, P(vp)]),
+        "pd_batch_step": (i32, [vp, vp, i32, vp, vp, i64, i32]),
+        "pd_batch_destroy": (i32, [vp]),
         "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
         "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
                                     P(SolveInfo)]),
@@ -258,6 +261,39 @@ class Simulation:
     def close(self):
         if getattr(self, "h", None):
             lib.pd_sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched explicit steps of several simulations (pd_batch_*)."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(lib.pd_batch_create(ctx.h, C.byref(h)), "pd_batch_create")
+        self.h = h
+
+    def step(self, sims, steps, dts, nsteps, graph=True):
+        """sims[k] takes steps[k] <= nsteps steps of dts[k]; one launch per step."""
+        n = len(sims)
+        handles = (C.c_void_p * n)(*[s.h for s in sims])
+        st = np.ascontiguousarray(steps, dtype=np.int64)
+        dt = np.ascontiguousarray(dts, dtype=np.float64)
+        assert st.shape == (n,) and dt.shape == (n,)
+        self.ctx.check(lib.pd_batch_step(self.h, C.cast(handles, C.c_void_p), n,
+                                         st.ctypes.data_as(C.c_void_p),
+                                         dt.ctypes.data_as(C.c_void_p), int(nsteps),
+                                         1 if graph else 0), "pd_batch_step")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pd_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
