@@ -8,6 +8,12 @@ resident in HBM before the timed region; the neighbour build is one-off and
 reported separately.  Both precisions compute in float64; "mixed" takes 1/|xi|
 from the hardware reciprocal-square-root estimate without refinement.
 
+Then (unless --no-serve) the serving workload: independent notched-plate
+requests through pd_server_* under a device-memory budget, first all at
+once (saturated throughput), then with Poisson arrivals at a fraction of that
+rate; completion latency (arrival to result) p50/p99 and aggregate bond
+evaluations per second go into the line's "serving" object.
+
 Prints one JSON line.  `roofline` prices the step kernel against HBM with the
 algorithmic byte model B = nnz * 5 + n * (93 | 133) bytes (2-d | 3-d):
 per bond a 4-byte column index and a 1-byte flag, per node the row offset,
@@ -77,6 +83,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-count", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serve-chunk", type=int, default=100)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="Poisson arrival rate as a fraction of the saturated request rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times "
                          "(reference kernel for scaling the HBM byte counters)")
@@ -122,6 +134,56 @@ def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)
     nb.close()
     ctx.close()
     return res
+
+
+def serve(pd, reqs, budget, chunk, rate=None):
+    """Runs the requests through pd_server_* with arrivals at their Poisson
+    times (rate given) or all at once; returns completion-latency statistics
+    and the aggregate bond-evaluation rate."""
+    from paper_1806_06917_amd import inputs
+    loads = []
+    for q in reqs:
+        w = inputs.serving_workload(q)
+        loads.append((w, pd.micromodulus(w.dim, w.E, w.delta)))
+    ctx = pd.Context(0)
+    srv = pd.Server(ctx, budget, chunk_steps=chunk, lanes=4)
+    t0 = pd.Server.clock()
+    ids, k, most, rounds = [], 0, 0, 0
+    while True:
+        now = pd.Server.clock() - t0
+        while k < len(reqs) and (rate is None or reqs[k].arrival <= now):
+            w, c = loads[k]
+            t_arr = t0 + (reqs[k].arrival if rate is not None else 0.0)
+            ids.append(srv.submit(w.X, w.V, pd.material(w.dim, c, w.rho, w.s_c, "mixed"),
+                                  w.delta, w.dt, w.steps, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
+                                  notch=w.notch, ramp_steps=w.ramp_steps,
+                                  t_arrival=max(t_arr, 1e-9)))
+            k += 1
+        running, queued = srv.pump()
+        rounds += 1
+        most = max(most, running)
+        if running == 0 and queued == 0:
+            if k == len(reqs):
+                break
+            wait = t0 + reqs[k].arrival - pd.Server.clock()
+            if wait > 0:
+                time.sleep(wait)
+    t_end = pd.Server.clock()
+    infos = [srv.info(i) for i in ids]
+    _, peak = srv.usage()
+    srv.close()
+    ctx.close()
+    ok = [f for f in infos if f["state"] == pd.PD_REQ_DONE]
+    lat = np.array([f["t_done"] - f["t_submit"] for f in ok])
+    queue = np.array([f["t_admit"] - f["t_submit"] for f in ok])
+    evals = sum(f["bonds"] * q.steps for f, q in zip(infos, reqs)
+                if f["state"] == pd.PD_REQ_DONE)
+    span = t_end - t0
+    return {"requests": len(reqs), "completed": len(ok), "makespan_s": span,
+            "bond_evals_per_s": evals / span, "requests_per_s": len(ok) / span,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "queue_p50_s": float(np.percentile(queue, 50)),
+            "max_running": most, "rounds": rounds, "peak_bytes": peak}
 
 
 def cpu_baseline(w, steps):
@@ -196,6 +258,20 @@ def main():
     if not args.no_fp64_compare and precision == "mixed":
         r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes, tuning)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
+    if not args.no_serve:
+        from paper_1806_06917_amd import inputs
+        budget = int(args.serve_budget_gib * (1 << 30))
+        burst = serve(pd, inputs.serving_requests(args.serve_count), budget, args.serve_chunk)
+        rate = args.serve_load * burst["requests_per_s"]
+        poisson = serve(pd, inputs.serving_requests(args.serve_count, rate=rate), budget,
+                        args.serve_chunk, rate)
+        out["serving"] = {
+            "workload": f"{args.serve_count} notched plates, side U{{64..512}}, delta in "
+                        "{3h,4h}, s_c ~ U[5e-4,2e-3], 1k-5k steps, mixed precision, lanes 4",
+            "budget_bytes": budget, "chunk_steps": args.serve_chunk,
+            "burst": burst, "poisson": dict(poisson, rate_per_s=rate, load=args.serve_load),
+            "p50_s": poisson["p50_s"], "p99_s": poisson["p99_s"],
+            "bond_evals_per_s": poisson["bond_evals_per_s"]}
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (60 if w.n > 100000 else 200)
         out["cpu_baseline"] = cpu_baseline(w, steps)

@@ -68,6 +68,7 @@ typedef struct pd_ctx_s *pd_ctx;
 typedef struct pd_nbr_s *pd_nbr;
 typedef struct pd_sim_s *pd_sim;
 typedef struct pd_batch_s *pd_batch;
+typedef struct pd_server_s *pd_server;
 
 /*
  * Material and arithmetic of one model.
@@ -281,6 +282,85 @@ int pd_batch_create(pd_ctx ctx, pd_batch *out);
 int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t *steps, const double *dt,
                   int64_t nsteps, int use_graph);
 int pd_batch_destroy(pd_batch b);
+
+/*
+ * Serving: independent explicit simulations submitted as requests.
+ *
+ * pd_server_create(ctx, hbm_budget, chunk_steps, lanes, &srv)
+ *   hbm_budget   device bytes the running simulations may hold together;
+ *   chunk_steps  steps per scheduling round;
+ *   lanes        lane count for every simulation (0: automatic per mesh; a
+ *                fixed value lets meshes of different horizons share one
+ *                batched launch).
+ * pd_server_submit copies the request's host arrays and queues it (arrival
+ *   order).  A request's state: PD_REQ_QUEUED -> PD_REQ_RUNNING ->
+ *   PD_REQ_DONE, or PD_REQ_FAILED with info.status (PD_ECAPACITY if its
+ *   device memory exceeds the whole budget).  The request's arrays are not
+ *   referenced after the call returns.
+ * pd_server_pump runs one scheduling round and returns when it is done
+ *   (synchronises): admits queued requests in arrival order while the head's
+ *   device-memory estimate fits the free budget; a request whose built size
+ *   (known after its neighbour list is built) does not fit after all is freed
+ *   and waits at the head with that size, so the charged bytes never exceed
+ *   hbm_budget (continuous batching:
+ *   requests join the running set as memory frees up), advances every running
+ *   simulation by up to chunk_steps steps in batched launches (one per group
+ *   of simulations with the same dimension, lane count, tile size and
+ *   precision; a chunk whose
+ *   set of simulations did not change since the last round replays a
+ *   captured hipGraph), and retires those that reached their step count,
+ *   freeing their memory.  A result is bit for bit the same as the request
+ *   run alone with pd_verlet_step at the same lane count.
+ * pd_server_info: timestamps (pd_server_clock seconds, a monotonic clock)
+ *   of submission (or the request's t_arrival if > 0), admission and
+ *   completion; device bytes charged; directed bonds.
+ * pd_server_result: the final u and v (host [n][dim], original node order)
+ *   of a finished request submitted with keep_state != 0.
+ * pd_server_usage: device bytes charged now and at most so far.
+ * pd_server_destroy frees every request (queued, running or done).
+ * Errors: PD_EINVAL for a malformed request or unknown id; a device error
+ *   while building or stepping is returned by pd_server_pump; an error
+ *   building one request fails only that request.
+ */
+enum { PD_REQ_QUEUED = 0, PD_REQ_RUNNING = 1, PD_REQ_DONE = 2, PD_REQ_FAILED = 3 };
+
+typedef struct {
+    int dim;                /* 2 or 3 */
+    int64_t n;              /* nodes */
+    const double *X;        /* host [n][dim] reference positions */
+    const double *V;        /* host [n] nodal volumes */
+    const double *u0, *v0;  /* host [n][dim] or NULL (zero) */
+    const uint8_t *bc_kind; /* host [n] PD_BC_* or NULL (all free) */
+    const double *bc_vel;   /* host [n][dim], required with bc_kind */
+    const double *notch;    /* host [nseg][4] pre-crack segments (2-d) or NULL */
+    int nseg;
+    double delta;           /* horizon */
+    pd_material mat;
+    double dt;
+    int64_t nsteps;         /* velocity-Verlet steps to run */
+    int64_t ramp_steps;     /* boundary-velocity ramp (0: none) */
+    int keep_state;         /* keep the final u, v for pd_server_result */
+    double t_arrival;       /* > 0: arrival time on pd_server_clock */
+} pd_request;
+
+typedef struct {
+    int64_t id;
+    int state;              /* PD_REQ_* */
+    int status;             /* PD_OK, or why the request failed */
+    int64_t bytes;          /* device bytes charged against the budget */
+    int64_t bonds;          /* directed bonds of its mesh */
+    double t_submit, t_admit, t_done;
+} pd_request_info;
+
+double pd_server_clock(void);
+int pd_server_create(pd_ctx ctx, int64_t hbm_budget, int64_t chunk_steps, int lanes,
+                     pd_server *out);
+int pd_server_submit(pd_server srv, const pd_request *req, int64_t *id);
+int pd_server_pump(pd_server srv, int *n_running, int *n_queued);
+int pd_server_info(pd_server srv, int64_t id, pd_request_info *info);
+int pd_server_result(pd_server srv, int64_t id, double *u, double *v);
+int pd_server_usage(pd_server srv, int64_t *used, int64_t *peak);
+int pd_server_destroy(pd_server srv);
 
 /*
  * Launch configuration a simulation runs with (each output may be NULL):

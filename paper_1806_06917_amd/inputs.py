@@ -202,17 +202,27 @@ def serving_requests(count=256, seed=5, rate=None, nmin=64, nmax=512):
     {3h, 4h}, s_c ~ U[5e-4, 2e-3], steps ~ U{1000..5000}.  ``rate`` = Poisson
     arrival rate (requests per second); ``None`` means all arrive at t = 0.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
+    # sizes and arrival gaps from independent streams: the same seed gives
+    # the same simulations at any arrival rate
+    sz, gap = (np.random.Generator(np.random.PCG64(s))
+               for s in np.random.SeedSequence(seed).spawn(2))
     out: List[Request] = []
     t = 0.0
     for r in range(count):
         if rate is not None:
-            t += rng.exponential(1.0 / rate)
-        out.append(Request(rid=r, N=int(rng.integers(nmin, nmax + 1)),
-                           m=int(rng.choice([3, 4])),
-                           s_c=float(rng.uniform(5e-4, 2e-3)),
-                           steps=int(rng.integers(1000, 5001)), arrival=t))
+            t += gap.exponential(1.0 / rate)
+        out.append(Request(rid=r, N=int(sz.integers(nmin, nmax + 1)),
+                           m=int(sz.choice([3, 4])),
+                           s_c=float(sz.uniform(5e-4, 2e-3)),
+                           steps=int(sz.integers(1000, 5001)), arrival=t))
     return out
+
+
+def serving_workload(req: "Request") -> Workload:
+    """The notched plate of one serving request (edge loading ramped over the
+    first fifth of its steps)."""
+    return notched_plate_2d(N=req.N, m=req.m, s_c=req.s_c, steps=req.steps,
+                            ramp_steps=req.steps // 5, precision="mixed")
 
 
 CONFIGS = {

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpd_hip.so")
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV, PD_ENONFINITE, PD_ECAPACITY = (
     0, -1, -2, -3, -4, -5, -6)
 PD_FP64, PD_MIXED = 0, 1
+PD_REQ_QUEUED, PD_REQ_RUNNING, PD_REQ_DONE, PD_REQ_FAILED = 0, 1, 2, 3
 PD_BC_FREE, PD_BC_CLAMPED, PD_BC_VELOCITY = 0, 1, 2
 
 
@@ -30,6 +31,21 @@ class PDError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [("dim", C.c_int), ("precision", C.c_int), ("c", C.c_double),
                 ("rho", C.c_double), ("s_c", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int64), ("X", C.c_void_p), ("V", C.c_void_p),
+                ("u0", C.c_void_p), ("v0", C.c_void_p), ("bc_kind", C.c_void_p),
+                ("bc_vel", C.c_void_p), ("notch", C.c_void_p), ("nseg", C.c_int),
+                ("delta", C.c_double), ("mat", Material), ("dt", C.c_double),
+                ("nsteps", C.c_int64), ("ramp_steps", C.c_int64), ("keep_state", C.c_int),
+                ("t_arrival", C.c_double)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("id", C.c_int64), ("state", C.c_int), ("status", C.c_int),
+                ("bytes", C.c_int64), ("bonds", C.c_int64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -70,6 +86,14 @@ def _load():
         "pd_batch_create": (i32, [vp, P(vp)]),
         "pd_batch_step": (i32, [vp, vp, i32, vp, vp, i64, i32]),
         "pd_batch_destroy": (i32, [vp]),
+        "pd_server_clock": (dbl, []),
+        "pd_server_create": (i32, [vp, i64, i64, i32, P(vp)]),
+        "pd_server_submit": (i32, [vp, P(Request), P(i64)]),
+        "pd_server_pump": (i32, [vp, P(i32), P(i32)]),
+        "pd_server_info": (i32, [vp, i64, P(RequestInfo)]),
+        "pd_server_result": (i32, [vp, i64, vp, vp]),
+        "pd_server_usage": (i32, [vp, P(i64), P(i64)]),
+        "pd_server_destroy": (i32, [vp]),
         "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
         "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
                                     P(SolveInfo)]),
@@ -294,6 +318,78 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib.pd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+class Server:
+    """Serving loop over the C ABI (pd_server_*): requests with host arrays."""
+
+    def __init__(self, ctx: Context, hbm_budget, chunk_steps=100, lanes=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx.check(lib.pd_server_create(ctx.h, int(hbm_budget), int(chunk_steps), int(lanes),
+                                       C.byref(h)), "pd_server_create")
+        self.h = h
+
+    @staticmethod
+    def clock():
+        return lib.pd_server_clock()
+
+    def submit(self, X, V, mat, delta, dt, nsteps, u0=None, v0=None, bc_kind=None,
+               bc_vel=None, notch=None, ramp_steps=0, keep_state=False, t_arrival=0.0):
+        X = _host(X, np.float64)
+        n, dim = X.shape
+        arrs = dict(V=_host(V, np.float64), u0=_host(u0, np.float64), v0=_host(v0, np.float64),
+                    bc_kind=_host(bc_kind, np.uint8), bc_vel=_host(bc_vel, np.float64),
+                    notch=_host(notch, np.float64))
+        ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        nseg = 0 if arrs["notch"] is None else arrs["notch"].reshape(-1, 4).shape[0]
+        req = Request(dim, n, ptr(X), ptr(arrs["V"]), ptr(arrs["u0"]), ptr(arrs["v0"]),
+                      ptr(arrs["bc_kind"]), ptr(arrs["bc_vel"]), ptr(arrs["notch"]), nseg,
+                      float(delta), mat, float(dt), int(nsteps), int(ramp_steps),
+                      1 if keep_state else 0, float(t_arrival))
+        rid = C.c_int64()
+        self.ctx.check(lib.pd_server_submit(self.h, C.byref(req), C.byref(rid)),
+                       "pd_server_submit")
+        return rid.value
+
+    def pump(self):
+        """One scheduling round; returns (running, queued)."""
+        r, q = C.c_int(), C.c_int()
+        self.ctx.check(lib.pd_server_pump(self.h, C.byref(r), C.byref(q)), "pd_server_pump")
+        return r.value, q.value
+
+    def info(self, rid):
+        i = RequestInfo()
+        self.ctx.check(lib.pd_server_info(self.h, int(rid), C.byref(i)), "pd_server_info")
+        return {k: getattr(i, k) for k, _ in RequestInfo._fields_}
+
+    def result(self, rid, n, dim):
+        u = np.zeros((n, dim))
+        v = np.zeros((n, dim))
+        self.ctx.check(lib.pd_server_result(self.h, int(rid), u.ctypes.data_as(C.c_void_p),
+                                            v.ctypes.data_as(C.c_void_p)), "pd_server_result")
+        return u, v
+
+    def usage(self):
+        used, peak = C.c_int64(), C.c_int64()
+        self.ctx.check(lib.pd_server_usage(self.h, C.byref(used), C.byref(peak)),
+                       "pd_server_usage")
+        return used.value, peak.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.pd_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

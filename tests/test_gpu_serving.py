@@ -96,3 +96,94 @@ def test_batch_rejects_mismatch(gpu):
     b.close()
     for x in (s, s2, nb, nb2):
         x.close()
+
+
+def _submit(pd, srv, w, prec, keep=True):
+    c = pd.micromodulus(w.dim, w.E, w.delta)
+    return srv.submit(w.X, w.V, pd.material(w.dim, c, w.rho, w.s_c, prec), w.delta, w.dt,
+                      w.steps, u0=w.u0, v0=w.v0, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
+                      notch=w.notch, ramp_steps=w.ramp_steps, keep_state=keep)
+
+
+def _serve(pd, ctx, ws, prec, budget, chunk):
+    srv = pd.Server(ctx, budget, chunk_steps=chunk, lanes=4)
+    ids = [_submit(pd, srv, w, prec) for w in ws]
+    most = 0
+    for _ in range(10000):
+        running, queued = srv.pump()
+        most = max(most, running)
+        if running == 0 and queued == 0:
+            break
+    infos = [srv.info(i) for i in ids]
+    results = [srv.result(i, w.n, w.dim) if f["state"] == pd.PD_REQ_DONE else None
+               for i, w, f in zip(ids, ws, infos)]
+    used, peak = srv.usage()
+    srv.close()
+    return infos, results, most, used, peak
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_served_equals_alone(gpu, prec):
+    """Requests served together under a memory budget end where each would
+    have ended alone; the budget is never exceeded and admission follows
+    arrival order."""
+    torch, pd, ctx = gpu
+    ws = _plates() + [inputs.notched_plate_2d(N=48, m=3, s_c=1e-3, v0=2e-3, steps=0,
+                                              ramp_steps=5)]
+    for w, k in zip(ws, [60, 47, 60, 33]):
+        w.steps = k
+    ctx.set_lanes(4)
+    try:
+        alone = []
+        for w in ws:
+            nb, s = _make(torch, pd, ctx, w, prec)
+            s.step(w.steps, w.dt)
+            alone.append(_state(torch, s, w, nb.nnz)[:2])
+            s.close()
+            nb.close()
+    finally:
+        ctx.set_lanes(0)
+    say("serve: unlimited", prec)
+    infos, res, most, used, peak = _serve(pd, ctx, ws, prec, 1 << 40, 25)
+    assert most == len(ws) and used == 0
+    sizes = [f["bytes"] for f in infos]
+    assert all(b > 0 for b in sizes) and peak == sum(sizes)
+    for f, r, a in zip(infos, res, alone):
+        assert f["state"] == pd.PD_REQ_DONE and f["status"] == pd.PD_OK
+        assert f["t_submit"] <= f["t_admit"] <= f["t_done"]
+        assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
+    # a budget that holds the largest request plus a little: queueing
+    budget = max(sizes) + min(sizes) // 2
+    say("serve: budget", budget, prec)
+    infos2, res2, most2, used2, peak2 = _serve(pd, ctx, ws, prec, budget, 20)
+    assert peak2 <= budget and used2 == 0 and most2 < len(ws)
+    admits = [f["t_admit"] for f in infos2]
+    assert admits == sorted(admits)
+    for f, r, a in zip(infos2, res2, alone):
+        assert f["state"] == pd.PD_REQ_DONE
+        assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
+
+
+def test_served_too_large(gpu):
+    torch, pd, ctx = gpu
+    small = inputs.notched_plate_2d(N=24, m=3, steps=5, ramp_steps=0)
+    big = inputs.notched_plate_2d(N=96, m=4, steps=5, ramp_steps=0)
+    srv = pd.Server(ctx, 1 << 40, chunk_steps=10)
+    i0 = _submit(pd, srv, small, "mixed")
+    while srv.pump() != (0, 0):
+        pass
+    budget = srv.info(i0)["bytes"] * 2
+    srv.close()
+    srv = pd.Server(ctx, budget, chunk_steps=10)
+    ib = _submit(pd, srv, big, "mixed")
+    i1 = _submit(pd, srv, small, "fp64", keep=False)
+    while srv.pump() != (0, 0):
+        pass
+    fb, f1 = srv.info(ib), srv.info(i1)
+    assert fb["state"] == pd.PD_REQ_FAILED and fb["status"] == pd.PD_ECAPACITY
+    assert f1["state"] == pd.PD_REQ_DONE
+    with pytest.raises(pd.PDError):
+        srv.result(i1, small.n, small.dim)       # submitted without keep_state
+    with pytest.raises(pd.PDError):
+        srv.info(12345)
+    srv.close()
