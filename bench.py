@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="built-in launch heuristics instead of the autotuner's choice")
     ap.add_argument("--serve-count", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--serve-chunk", type=int, default=100)
@@ -99,12 +101,18 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)):
+def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0), tune=True):
     ctx = pd.Context(0)
     if lanes:
         ctx.set_lanes(lanes)
     ctx.set_tuning(*tuning)
     Xd = dev(torch, w.X)
+    tuned = None
+    if tune and not lanes and tuning == ("auto", 0, 0):
+        # launch shape from the autotuner (cached in ctx for this mesh's kind)
+        t0 = time.perf_counter()
+        best, table = ctx.autotune(Xd, dev(torch, w.V), w.delta, precision, steps=20)
+        tuned = {"best": best, "candidates": table, "search_s": time.perf_counter() - t0}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nb = pd.Neighbors(ctx, Xd, w.delta)
@@ -129,7 +137,8 @@ def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)
     ms = e0.elapsed_time(e1)
     info = sim.get(energies=True)
     res = {"ms_total": ms, "wall_s": wall, "nnz": nb.nnz, "t_nbr_s": t_nbr,
-           "ke": info["ke"], "pe": info["pe"], "step": info["step"], "launch": sim.info()}
+           "ke": info["ke"], "pe": info["pe"], "step": info["step"], "launch": sim.info(),
+           "autotune": tuned}
     sim.close()
     nb.close()
     ctx.close()
@@ -226,7 +235,8 @@ def main():
     w = inputs.CONFIGS[args.config]()
     precision = args.precision or ("mixed" if args.config == "cube100" else "fp64")
     tuning = (args.kernel, args.tile, args.block)
-    r = run_gpu(torch, pd, w, precision, args.steps, args.warmup, args.lanes, tuning)
+    r = run_gpu(torch, pd, w, precision, args.steps, args.warmup, args.lanes, tuning,
+                not args.no_autotune)
     ms_step = r["ms_total"] / args.steps
     bonds_per_s = r["nnz"] / (ms_step * 1e-3)
     B = algorithmic_bytes(w.n, r["nnz"], w.dim)
@@ -254,10 +264,13 @@ def main():
                      "kernel_source_hash": kernel_source_hash()},
         "neighbor_build_s": r["t_nbr_s"],
         "launch": r["launch"],
+        "autotune": r["autotune"],
     }
     if not args.no_fp64_compare and precision == "mixed":
-        r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes, tuning)
+        r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes, tuning,
+                      not args.no_autotune)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
+        out["fp64_launch"] = r64["launch"]
     if not args.no_serve:
         from paper_1806_06917_amd import inputs
         budget = int(args.serve_budget_gib * (1 << 30))

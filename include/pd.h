@@ -158,6 +158,46 @@ int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
 int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block);
 
 /*
+ * Autotuner for the explicit step (launch-shape search; the method's
+ * arithmetic is unchanged, only the order of each node's bond sum).
+ *
+ * pd_autotune builds the neighbour list of (X, V, delta) -- device arrays as
+ * in pd_build_neighbors -- and, for each candidate tile size x lanes per node
+ * (T * lanes in [256, 1024]: 32x8, 32x16, 64x4, 64x8, 64x16, 128x2, 128x4,
+ * 128x8, 256x2, 256x4), creates a simulation at rest with damage on, runs 2
+ * warm-up steps and times `steps` explicit steps (pd_verlet_step) with HIP
+ * events on the context's stream.  The fastest is cached in the context
+ * under (dim, mean-neighbour-count bucket, precision), the buckets split
+ * at 8, 20, 36, 64, 96, 176, 384 and 768 neighbours per node;
+ * from then on pd_sim_create uses it for meshes of that bucket whenever the
+ * context's lanes and tuning are automatic (0).  The search synchronises and
+ * restores the context's tuning.
+ *   table, table_cap, ntable  optional: every candidate in the order above
+ *     (us_per_step < 0: the tile size does not fit this mesh);
+ *   best  the winner.
+ * PD_ECAPACITY if no candidate fits; argument errors as in
+ * pd_build_neighbors.
+ * pd_tune_lookup: the cached choice for a (dim, mean neighbour count,
+ *   precision); tile = lanes = 0 if there is none.
+ * pd_tune_set installs a choice (e.g. one saved from an earlier search);
+ *   (tile, lanes) must be a candidate above.  pd_tune_clear empties the cache.
+ */
+typedef struct {
+    int tile;            /* nodes per tile */
+    int lanes;           /* lanes per node */
+    int kernel;          /* what ran: 3 streamed tiles, 2 LDS tiles, 1 none (did not fit) */
+    double us_per_step;  /* measured microseconds per step, < 0 if not run */
+} pd_tune_result;
+
+int pd_autotune(pd_ctx ctx, int dim, int64_t n, const double *X, const double *V, double delta,
+                int precision, int steps, pd_tune_result *table, int table_cap, int *ntable,
+                pd_tune_result *best);
+int pd_tune_lookup(pd_ctx ctx, int dim, double mean_neighbors, int precision,
+                   pd_tune_result *out);
+int pd_tune_set(pd_ctx ctx, int dim, double mean_neighbors, int precision, int tile, int lanes);
+int pd_tune_clear(pd_ctx ctx);
+
+/*
  * Build the neighbour lists B_delta(X_i) (Section "Discretization of
  * peridynamics equations") in the reference configuration, once.
  *   X      device, [n][dim] float64 reference coordinates

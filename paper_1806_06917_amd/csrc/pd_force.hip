@@ -451,9 +451,24 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
                 return pd_set_error(ctx, PD_EINVAL, "notch coordinates must be finite");
         }
 
-    const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    // automatic tuning: the autotuner's tile size and lane count for meshes
+    // like this one, if it measured any (else the built-in heuristics); a
+    // tuned tile size that does not fit this mesh falls back to automatic
+    int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
-    PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+    const pd_tune_entry *te = nullptr;
+    if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
+        te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);
+    if (te) {
+        lanes = te->lanes;
+        ctx->tile = te->tile;
+        const int st = pd_plan_kernel(ctx, nbr, lanes, &block);
+        ctx->tile = 0;
+        PD_TRY(st);
+        if (block == 0) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+    } else {
+        PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+    }
     pd_sim s = new (std::nothrow) pd_sim_s();
     if (!s) return PD_ENOMEM;
     s->ctx = ctx;

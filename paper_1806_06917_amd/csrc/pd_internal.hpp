@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "pd.h"
 
@@ -26,6 +27,14 @@
 // ---------------------------------------------------------------------------
 // handles
 // ---------------------------------------------------------------------------
+// one autotuner result: the fastest tile size and lane count measured for
+// meshes of a dimension, neighbour-count bucket and precision
+struct pd_tune_entry {
+    int dim = 0, bucket = 0, precision = 0;
+    int tile = 0, lanes = 0;
+    double us = 0.0;
+};
+
 struct pd_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -42,6 +51,7 @@ struct pd_ctx_s {
     int *flag_host = nullptr;
     int refs = 0;           // neighbour lists and simulations created on this context
     bool closing = false;   // destroyed while refs > 0: freed with the last of them
+    std::vector<pd_tune_entry> tuned;   // autotuner cache
 };
 
 struct pd_nbr_s {
@@ -215,3 +225,7 @@ int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const dou
 // kernel choice for a call site under the context's tuning; *block > 0 means
 // the tile kernel with that workgroup size, 0 the gather kernel
 int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block);
+
+// autotuner cache (pd_tune.hip): neighbour-count bucket of a mesh, lookup
+int pd_tune_bucket(double mean_neighbors);
+const pd_tune_entry *pd_tune_find(pd_ctx ctx, int dim, double mean_neighbors, int precision);

@@ -48,6 +48,11 @@ class RequestInfo(C.Structure):
                 ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("tile", C.c_int), ("lanes", C.c_int), ("kernel", C.c_int),
+                ("us_per_step", C.c_double)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double)]
@@ -86,6 +91,11 @@ def _load():
         "pd_batch_create": (i32, [vp, P(vp)]),
         "pd_batch_step": (i32, [vp, vp, i32, vp, vp, i64, i32]),
         "pd_batch_destroy": (i32, [vp]),
+        "pd_autotune": (i32, [vp, i32, i64, vp, vp, dbl, i32, i32, P(TuneResult), i32, P(i32),
+                              P(TuneResult)]),
+        "pd_tune_lookup": (i32, [vp, i32, dbl, i32, P(TuneResult)]),
+        "pd_tune_set": (i32, [vp, i32, dbl, i32, i32, i32]),
+        "pd_tune_clear": (i32, [vp]),
         "pd_server_clock": (dbl, []),
         "pd_server_create": (i32, [vp, i64, i64, i32, P(vp)]),
         "pd_server_submit": (i32, [vp, P(Request), P(i64)]),
@@ -151,6 +161,35 @@ class Context:
         kind = {"auto": 0, "gather": 1, "tile": 2, "stream": 3}.get(kernel, kernel)
         self.check(lib.pd_ctx_set_tuning(self.h, int(kind), int(tile), int(block)),
                    "pd_ctx_set_tuning")
+
+    def autotune(self, X, V, delta, precision="mixed", steps=20):
+        """Times every tile size x lanes candidate on the mesh (X, V, delta) and
+        caches the fastest for meshes of its kind (pd_autotune).  Returns
+        (best, table) as dicts."""
+        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        table = (TuneResult * 16)()
+        nt = C.c_int()
+        best = TuneResult()
+        self.check(lib.pd_autotune(self.h, int(X.shape[1]), int(X.shape[0]), _ptr(X), _ptr(V),
+                                   float(delta), prec, int(steps), table, 16, C.byref(nt),
+                                   C.byref(best)), "pd_autotune")
+        row = lambda r: {k: getattr(r, k) for k, _ in TuneResult._fields_}  # noqa: E731
+        return row(best), [row(table[i]) for i in range(nt.value)]
+
+    def tune_lookup(self, dim, mean_neighbors, precision="mixed"):
+        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        r = TuneResult()
+        self.check(lib.pd_tune_lookup(self.h, int(dim), float(mean_neighbors), prec,
+                                      C.byref(r)), "pd_tune_lookup")
+        return (r.tile, r.lanes) if r.tile else None
+
+    def tune_set(self, dim, mean_neighbors, tile, lanes, precision="mixed"):
+        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        self.check(lib.pd_tune_set(self.h, int(dim), float(mean_neighbors), prec, int(tile),
+                                   int(lanes)), "pd_tune_set")
+
+    def tune_clear(self):
+        self.check(lib.pd_tune_clear(self.h), "pd_tune_clear")
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,106 @@
+"""The autotuner (pd_autotune): every candidate launch shape it can pick
+steps in parity with the FP64 oracle, the fastest lands in the context's
+cache, and simulations created afterwards on meshes of the same kind use it
+and step bit for bit like the same shape chosen by hand."""
+import numpy as np
+import pytest
+
+from conftest import say
+from paper_1806_06917_amd import inputs
+from test_gpu_parity import TOL64, TOLMIX, dev, read_state, relL2, sim_from_workload
+
+pytestmark = pytest.mark.gpu
+
+CANDIDATES = [(32, 8), (32, 16), (64, 4), (64, 8), (64, 16),
+              (128, 2), (128, 4), (128, 8), (256, 2), (256, 4)]
+
+
+def moving_plate(N, m):
+    # notched plate with a random initial velocity and no breaks: every launch
+    # shape differs from the oracle only in the order of each node's sum
+    w = inputs.notched_plate_2d(N=N, m=m, s_c=1.0, v0=2e-3, steps=0, ramp_steps=5)
+    w.v0 = inputs.random_field(w.n, 2, 11, scale=2e-3)
+    w.v0[w.bc_kind == 2] = 0
+    return w
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+def test_every_candidate_matches_oracle(gpu, orc, prec, tol):
+    torch, pd, ctx = gpu
+    w = moving_plate(64, 3)
+    mesh = orc.Mesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    st = mesh.start(w.u0, w.v0, c, w.s_c, mesh.notch_cut(w.notch, mesh.all_alive()))
+    mesh.verlet(st, c, w.rho, w.s_c, w.dt, 20, w.bc_kind, w.bc_vel, None, w.ramp_steps)
+    for tile, lanes in CANDIDATES:
+        say("candidate", prec, tile, lanes)
+        ctx.set_lanes(lanes)
+        ctx.set_tuning("auto", tile, 0)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+            s = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(2, w.E, w.delta), prec)
+            info = s.info()
+            assert info["kernel"] in ("stream", "tile")
+            assert (info["tile"], info["lanes"]) == (tile, lanes)
+            s.step(20, w.dt)
+            u, v, _, _ = read_state(torch, s, w.n, 2, nb.nnz)
+            s.close()
+            nb.close()
+        finally:
+            ctx.set_lanes(0)
+            ctx.set_tuning(0, 0, 0)
+        assert relL2(u, st["u"]) <= tol, (tile, lanes)
+        assert relL2(v, st["v"]) <= tol, (tile, lanes)
+
+
+def test_autotune_cache_and_use(gpu):
+    torch, pd, _ = gpu
+    ctx = pd.Context(0)                 # a context of its own: the cache is per context
+    try:
+        w = moving_plate(64, 3)
+        say("autotune search")
+        best, table = ctx.autotune(dev(torch, w.X), dev(torch, w.V), w.delta, "mixed", steps=5)
+        assert [(r["tile"], r["lanes"]) for r in table] == CANDIDATES
+        ran = [r for r in table if r["us_per_step"] > 0]
+        assert ran and all(r["kernel"] in (2, 3) for r in ran)
+        assert best["us_per_step"] == min(r["us_per_step"] for r in ran)
+        nb0 = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+        k = nb0.nnz / w.n
+        nb0.close()
+        assert ctx.tune_lookup(2, k, "mixed") == (best["tile"], best["lanes"])
+        assert ctx.tune_lookup(2, k, "fp64") is None
+        assert ctx.tune_lookup(3, k, "mixed") is None
+        # another mesh of the same kind (2-d, delta = 3h) takes the tuned shape
+        w2 = moving_plate(80, 3)
+        c = pd.micromodulus(2, w2.E, w2.delta)
+        say("tuned simulation", best["tile"], best["lanes"])
+        nb = pd.Neighbors(ctx, dev(torch, w2.X), w2.delta)
+        s = sim_from_workload(torch, pd, ctx, nb, w2, c, "mixed")
+        info = s.info()
+        assert (info["tile"], info["lanes"]) == (best["tile"], best["lanes"])
+        s.step(30, w2.dt)
+        tuned = read_state(torch, s, w2.n, 2, nb.nnz)[:3]
+        s.close()
+        nb.close()
+        # the same shape by hand: bit for bit
+        ctx.tune_clear()
+        assert ctx.tune_lookup(2, k, "mixed") is None
+        ctx.set_lanes(best["lanes"])
+        ctx.set_tuning("auto", best["tile"], 0)
+        nb = pd.Neighbors(ctx, dev(torch, w2.X), w2.delta)
+        s = sim_from_workload(torch, pd, ctx, nb, w2, c, "mixed")
+        s.step(30, w2.dt)
+        by_hand = read_state(torch, s, w2.n, 2, nb.nnz)[:3]
+        s.close()
+        nb.close()
+        for x, y in zip(tuned, by_hand):
+            assert np.array_equal(x, y)
+        ctx.set_lanes(0)
+        ctx.set_tuning(0, 0, 0)
+        # an installed choice is used the same way; non-candidates are refused
+        ctx.tune_set(2, k, 128, 2, "mixed")
+        assert ctx.tune_lookup(2, k, "mixed") == (128, 2)
+        with pytest.raises(pd.PDError):
+            ctx.tune_set(2, k, 48, 3, "mixed")
+    finally:
+        ctx.close()
