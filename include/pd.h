@@ -357,6 +357,7 @@ int pd_batch_destroy(pd_batch b);
  * pd_server_result: the final u and v (host [n][dim], original node order)
  *   of a finished request submitted with keep_state != 0.
  * pd_server_usage: device bytes charged now and at most so far.
+ * pd_server_get_stats: where the pump's time went (cumulative).
  * pd_server_destroy frees every request (queued, running or done).
  * Errors: PD_EINVAL for a malformed request or unknown id; a device error
  *   while building or stepping is returned by pd_server_pump; an error
@@ -392,6 +393,16 @@ typedef struct {
     double t_submit, t_admit, t_done;
 } pd_request_info;
 
+typedef struct {
+    double admit_s;     /* host wall time building admitted requests */
+    double step_s;      /* launching chunks and waiting for them */
+    double retire_s;    /* reading back and freeing finished requests */
+    int64_t rounds;     /* pd_server_pump calls */
+    int64_t admitted;
+    int64_t launches;   /* batched chunks */
+    int64_t replays;    /* of them, replays of a captured graph */
+} pd_server_stats;
+
 double pd_server_clock(void);
 int pd_server_create(pd_ctx ctx, int64_t hbm_budget, int64_t chunk_steps, int lanes,
                      pd_server *out);
@@ -400,6 +411,7 @@ int pd_server_pump(pd_server srv, int *n_running, int *n_queued);
 int pd_server_info(pd_server srv, int64_t id, pd_request_info *info);
 int pd_server_result(pd_server srv, int64_t id, double *u, double *v);
 int pd_server_usage(pd_server srv, int64_t *used, int64_t *peak);
+int pd_server_get_stats(pd_server srv, pd_server_stats *out);
 int pd_server_destroy(pd_server srv);
 
 /*

@@ -95,6 +95,7 @@ struct pd_server_s {
     std::vector<Req *> running;
     std::map<int64_t, Req *> all;
     std::map<GroupKey, Group> groups;
+    pd_server_stats stats{};
 };
 
 extern "C" double pd_server_clock(void) { return now_s(); }
@@ -286,7 +287,10 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         }
         if (s->used + r->estimate > s->budget) break;
         s->queue.pop_front();
+        const double ta = now_s();
         const int st = admit(s, r);
+        s->stats.admit_s += now_s() - ta;
+        s->stats.admitted += 1;
         if (st != PD_OK) {
             if (st == PD_EDEVICE) return st;
             r->info.state = PD_REQ_FAILED;
@@ -329,6 +333,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         int64_t nsteps = 0;
     };
     std::map<GroupKey, Chunk> chunks;
+    const double t_step = now_s();
     for (Req *r : s->running) {
         const int64_t k = std::min(s->chunk, r->nsteps - r->done);
         if (k <= 0) continue;
@@ -353,10 +358,15 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         const bool same = c.sims == g.last_sims && c.nsteps == g.last_nsteps;
         PD_TRY(pd_batch_step(g.batch, c.sims.data(), (int)c.sims.size(), c.steps.data(),
                              c.dts.data(), c.nsteps, same ? 1 : 0));
+        s->stats.launches += 1;
+        s->stats.replays += same ? 1 : 0;
         g.last_sims = c.sims;
         g.last_nsteps = c.nsteps;
     }
     if (!s->running.empty()) PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    s->stats.step_s += now_s() - t_step;
+    s->stats.rounds += 1;
+    const double t_ret = now_s();
     // retire the finished ones
     std::vector<Req *> keep;
     for (Req *r : s->running) {
@@ -368,6 +378,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         }
     }
     s->running.swap(keep);
+    s->stats.retire_s += now_s() - t_ret;
     if (n_running) *n_running = (int)s->running.size();
     if (n_queued) *n_queued = (int)s->queue.size();
     return PD_OK;
@@ -386,6 +397,12 @@ extern "C" int pd_server_usage(pd_server s, int64_t *used, int64_t *peak) {
     if (!s) return PD_EINVAL;
     if (used) *used = s->used;
     if (peak) *peak = s->peak;
+    return PD_OK;
+}
+
+extern "C" int pd_server_get_stats(pd_server s, pd_server_stats *out) {
+    if (!s || !out) return PD_EINVAL;
+    *out = s->stats;
     return PD_OK;
 }
 

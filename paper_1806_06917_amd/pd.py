@@ -53,6 +53,12 @@ class TuneResult(C.Structure):
                 ("us_per_step", C.c_double)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("admit_s", C.c_double), ("step_s", C.c_double), ("retire_s", C.c_double),
+                ("rounds", C.c_int64), ("admitted", C.c_int64), ("launches", C.c_int64),
+                ("replays", C.c_int64)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_iters", C.c_int),
                 ("rel_residual", C.c_double)]
@@ -104,6 +110,7 @@ def _load():
         "pd_server_result": (i32, [vp, i64, vp, vp]),
         "pd_server_usage": (i32, [vp, P(i64), P(i64)]),
         "pd_server_destroy": (i32, [vp]),
+        "pd_server_get_stats": (i32, [vp, P(ServerStats)]),
         "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
         "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
                                     P(SolveInfo)]),
@@ -425,6 +432,11 @@ class Server:
         self.ctx.check(lib.pd_server_usage(self.h, C.byref(used), C.byref(peak)),
                        "pd_server_usage")
         return used.value, peak.value
+
+    def stats(self):
+        st = ServerStats()
+        self.ctx.check(lib.pd_server_get_stats(self.h, C.byref(st)), "pd_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def close(self):
         if getattr(self, "h", None):
