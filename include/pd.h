@@ -315,8 +315,10 @@ int pd_sim_destroy(pd_sim sim);
  * Every simulation must run the streamed step kernel (pd_sim_info kernel 3)
  * on b's context, with one dim, precision, lane count and tile size.  The
  * call is asynchronous on the context's stream.  A batch handle holds the
- * descriptor buffer, the step counter and the captured graph; it must outlive
- * its pending work and is freed by pd_batch_destroy (which synchronises).
+ * descriptor buffer (each simulation's state at the start of the chunk,
+ * uploaded by every call) and the captured graph (whose k-th launch carries
+ * its step index k); it must outlive its pending work and is freed by
+ * pd_batch_destroy (which synchronises).
  */
 int pd_batch_create(pd_ctx ctx, pd_batch *out);
 int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t *steps, const double *dt,

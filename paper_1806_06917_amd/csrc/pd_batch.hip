@@ -18,7 +18,6 @@ struct pd_batch_s {
     StreamInst *dev = nullptr;      // descriptors, capacity cap
     StreamInst *host = nullptr;     // pinned staging of the descriptors
     int cap = 0;
-    int64_t *counter = nullptr;     // batch step of the running launch
     hipEvent_t uploaded = nullptr;  // the staging buffer may be rewritten after this
     bool pending = false;
     hipStream_t capture = nullptr;  // graphs are captured here, launched on ctx->stream
@@ -45,8 +44,8 @@ extern "C" int pd_batch_create(pd_ctx ctx, pd_batch *out) {
     if (!b) return PD_ENOMEM;
     b->ctx = ctx;
     ctx->refs += 1;
-    int st = pd_alloc(ctx, &b->counter, 1);
-    if (st == PD_OK && hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess)
+    int st = PD_OK;
+    if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess)
         st = pd_set_error(ctx, PD_EDEVICE, "hipEventCreate failed");
     if (st == PD_OK && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
         st = pd_set_error(ctx, PD_EDEVICE, "hipStreamCreate failed");
@@ -65,7 +64,6 @@ extern "C" int pd_batch_destroy(pd_batch b) {
     (void)hipStreamSynchronize(ctx->stream);
     batch_free_graph(b);
     pd_free(b->dev);
-    pd_free(b->counter);
     if (b->host) (void)hipHostFree(b->host);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
     if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -74,13 +72,12 @@ extern "C" int pd_batch_destroy(pd_batch b) {
     return PD_OK;
 }
 
-// the launches of one chunk: counter = 0, then nsteps x (step kernel, counter + 1)
-static int batch_enqueue(pd_batch b, hipStream_t st, int dim, const StreamArgs &sa, int lanes,
+// the launches of one chunk: nsteps step kernels, the k-th told it is step k
+static int batch_enqueue(pd_batch b, hipStream_t st, int dim, StreamArgs sa, int lanes,
                          bool mixed, int block, unsigned grid, size_t lds, int64_t nsteps) {
-    PD_TRY(pd_counter_set(b->ctx, st, b->counter, 0));
     for (int64_t k = 0; k < nsteps; ++k) {
+        sa.step = k;
         PD_TRY(pd_launch_stream(b->ctx, st, dim, sa, lanes, mixed, block, grid, lds));
-        PD_TRY(pd_counter_tick(b->ctx, st, b->counter));
     }
     return PD_OK;
 }
@@ -178,7 +175,6 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
     sa.hcap = hcap;
     sa.bcap = bcap;
     sa.mmax = mmax;
-    sa.bstep = b->counter;
     if (!use_graph) {
         PD_TRY(batch_enqueue(b, ctx->stream, dim, sa, lanes, mixed, block, grid, lds, nsteps));
     } else {

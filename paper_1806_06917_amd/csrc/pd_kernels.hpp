@@ -240,8 +240,7 @@ struct StreamInst {
 struct StreamArgs {
     const StreamInst *inst;     // batch launches: the instance descriptors
     uint32_t ninst, ntiles, tile, hcap, bcap, mmax;
-    const int64_t *bstep;       // batch step from this counter, or `step` if NULL
-    int64_t step;
+    int64_t step;               // step of this launch within its chunk
     StreamInst one;             // single-simulation launches: the descriptor itself
 };
 
@@ -275,9 +274,6 @@ pdk::StreamInst pd_stream_inst(const pd_sim s);
 pdk::StreamArgs pd_stream_args(const pd_sim sim, const pdk::StreamInst *inst, uint32_t ninst,
                                uint32_t ntiles);
 void pd_sim_advanced(pd_sim sim, int64_t nsteps, double dt);
-// device step counter of a batch (set / add one), on stream st
-int pd_counter_set(pd_ctx ctx, hipStream_t st, int64_t *c, int64_t v);
-int pd_counter_tick(pd_ctx ctx, hipStream_t st, int64_t *c);
 int pd_rec_pack(pd_ctx ctx, int dim, uint32_t n, const double *xv, const double *u, double *rec);
 int pd_rec_unpack(pd_ctx ctx, int dim, uint32_t n, const double *rec, double *u);
 // LDS halo capacity of a tiled neighbour list

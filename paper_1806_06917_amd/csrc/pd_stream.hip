@@ -17,9 +17,10 @@
 //
 // A batch is a list of instances (StreamInst); their tiles are numbered one
 // after the other and the persistent grid walks that list, so instances of
-// any size share the launch.  The step index comes from a device counter (or
-// the argument list), so a chunk of steps can be captured once in a hipGraph
-// and replayed.
+// any size share the launch.  The step index within a chunk is a launch
+// argument (each captured launch of a hipGraph keeps its own), and the
+// per-instance state at the start of the chunk sits in device descriptors,
+// so a chunk of steps can be captured once and replayed.
 //
 // Per workgroup tile k: wait for this wave's copies, barrier (tile k and the
 // ids of tile k+1 are in LDS); sum the bonds, one lane group per node in the
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     uint32_t *brk = bcb + lay.TB;                                                // 3 (4 + CAP)
     uint32_t *meta = brk + 3 * (BRK_CAP + 4);                                    // MM
     const StreamInst *inst = sa.inst;
-    const int64_t s = sa.bstep ? *sa.bstep : sa.step;   // batch step of this launch
+    const int64_t s = sa.step;                          // step of this launch in its chunk
     // the record buffer holding u at this step
     auto cur_of = [&](const StreamInst &I) { return (uint32_t)((I.cur0 + s) & 1); };
 
@@ -371,13 +372,6 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     }
 }
 
-__global__ void counter_set_k(int64_t *c, int64_t v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) c[threadIdx.x] = v;
-}
-__global__ void counter_tick_k(int64_t *c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) c[threadIdx.x] += 1;
-}
-
 template <int DIM>
 void *pick_stream(int lanes, bool mixed, bool batch) {
 #define PD_SK(Lv)                                                                          \
@@ -490,17 +484,6 @@ int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const StreamArgs &sa, 
     return PD_OK;
 }
 
-int pd_counter_set(pd_ctx ctx, hipStream_t st, int64_t *c, int64_t v) {
-    counter_set_k<<<1, 64, 0, st>>>(c, v);
-    PD_LAUNCH_CHECK(ctx);
-    return PD_OK;
-}
-
-int pd_counter_tick(pd_ctx ctx, hipStream_t st, int64_t *c) {
-    counter_tick_k<<<1, 64, 0, st>>>(c);
-    PD_LAUNCH_CHECK(ctx);
-    return PD_OK;
-}
 
 int pd_rec_pack(pd_ctx ctx, int dim, uint32_t n, const double *xv, const double *u, double *rec) {
     if (dim == 3) rec_pack_k<3><<<pd_blocks(n), PD_BLOCK, 0, ctx->stream>>>(n, xv, u, rec);
