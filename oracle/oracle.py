@@ -70,6 +70,18 @@ def lib():
         L.or_solve_implicit.restype = i32
         L.or_solve_implicit.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, ptr, ptr, ptr, ptr,
                                         dbl, dbl, i32, i32, ptr, ptr, ptr]
+        L.or_force_law.restype = None
+        L.or_force_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, i32, dbl, i32,
+                                   ptr, ptr, ptr]
+        L.or_tangent_law.restype = None
+        L.or_tangent_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, ptr, ptr, ptr,
+                                     ptr, ptr]
+        L.or_residual_law.restype = dbl
+        L.or_residual_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, ptr, ptr,
+                                      ptr, ptr, ptr]
+        L.or_solve_law.restype = i32
+        L.or_solve_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, ptr, ptr, ptr,
+                                   ptr, dbl, dbl, i32, i32, ptr, ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -208,6 +220,63 @@ class Mesh:
                                      _p(self.X), _p(self.V), float(c), _p(alive), _p(fixed),
                                      _p(b), _p(u), float(rtol), float(inner_rtol), int(maxit),
                                      int(max_outer), C.byref(o), C.byref(i), C.byref(rel))
+        return u, {"status": st, "outer": o.value, "inner": i.value, "relres": rel.value}
+
+
+LAW_LINEAR, LAW_NP = 0, 1
+STRETCH_LINEARISED, STRETCH_EXACT = 0, 1
+
+
+class LawMesh(Mesh):
+    """The general pairwise law of Algorithm 1: linear or NP potential,
+    linearised or exact stretch (``or_force_law`` and friends)."""
+
+    def force_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, s_c=0.0,
+                  alive=None, energy=False):
+        u = _f64(u)
+        f = np.zeros_like(self.X)
+        U = np.zeros(self.n) if energy else None
+        lib().or_force_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                           _p(self.V), _p(u), float(c), float(s_c), int(law), float(beta),
+                           int(stretch), _p(alive), _p(f), _p(U))
+        return (f, U) if energy else f
+
+    def energy_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, alive=None):
+        """Total strain energy sum_i V_i U_i."""
+        _, U = self.force_law(u, c, law, beta, stretch, 0.0, alive, energy=True)
+        return lib().or_potential(self.n, _p(self.V), _p(U))
+
+    def tangent_law(self, w, c, law=LAW_NP, beta=1.0, ulin=None, fixed=None, alive=None):
+        w = _f64(w)
+        y = np.zeros_like(w)
+        ulin = None if ulin is None else _f64(ulin)
+        fixed = None if fixed is None else np.ascontiguousarray(fixed, np.uint8)
+        lib().or_tangent_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                             _p(self.V), float(c), int(law), float(beta), _p(ulin), _p(alive),
+                             _p(fixed), _p(w), _p(y))
+        return y
+
+    def residual_law(self, u, c, b, law=LAW_NP, beta=1.0, fixed=None, alive=None):
+        u = _f64(u)
+        r = np.zeros_like(u)
+        fixed = None if fixed is None else np.ascontiguousarray(fixed, np.uint8)
+        b = None if b is None else _f64(b)
+        nrm = lib().or_residual_law(self.dim, self.n, _p(self.row_ptr), _p(self.col),
+                                    _p(self.X), _p(self.V), float(c), int(law), float(beta),
+                                    _p(alive), _p(fixed), _p(b), _p(u), _p(r))
+        return r, nrm
+
+    def solve_law(self, u0, c, b, fixed, law=LAW_NP, beta=1.0, alive=None, rtol=1e-10,
+                  inner_rtol=1e-12, maxit=200000, max_outer=50):
+        u = _f64(u0).copy()
+        fixed = np.ascontiguousarray(fixed, np.uint8)
+        b = _f64(b)
+        o, i, rel = C.c_int(0), C.c_int(0), C.c_double(0)
+        st = lib().or_solve_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                                _p(self.V), float(c), int(law), float(beta), _p(alive),
+                                _p(fixed), _p(b), _p(u), float(rtol), float(inner_rtol),
+                                int(maxit), int(max_outer), C.byref(o), C.byref(i),
+                                C.byref(rel))
         return u, {"status": st, "outer": o.value, "inner": i.value, "relres": rel.value}
 
 

@@ -18,6 +18,9 @@
  *   eta = u_j - u_i          bond deformation
  *   S   = (eta . xi)/|xi|^2  linearised bond strain (Algorithm 1)
  *   c   = 4 psi'(0) / (delta |B_delta(0)|)  micromodulus of the linearised law
+ *   NP  = the nonlinear potential psi(r) = C (1 - exp(-beta r)) of the
+ *         validation section, used in Algorithm 1 by or_force_law (with the
+ *         exact-stretch variant), or_tangent_law and or_solve_law
  *
  * Readings of points the paper leaves open (each one is also listed in the
  * design notes):
@@ -498,6 +501,190 @@ int or_solve_implicit(int dim, int64_t n, const int64_t *row_ptr, const int32_t 
     if (inner) *inner = it_in;
     if (relres) *relres = rel;
     free(r); free(du);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* General pairwise law of Algorithm 1 (the NP model of the validation       */
+/* section): with J = 1 on the ball,                                         */
+/*   f_i += 4/(delta |B_delta(0)|) psi'(|xi| S^2) S e V_j                    */
+/*   U_i += 1/(delta |B_delta(0)|) psi(|xi| S^2) V_j                         */
+/* and the NP potential psi(r) = C (1 - exp(-beta r)), psi'(0) = C beta.     */
+/* Written with the micromodulus c = 4 psi'(0)/(delta |B_delta(0)|):         */
+/*   f_i += c exp(-beta r) S e V_j,  U_i += c/(4 beta) (1 - exp(-beta r)) V_j */
+/* with r = |xi| S^2.  law 0 is the linearised law (psi' = psi'(0), the      */
+/* exponential factor 1 and the energy (c/4) r V_j); law 1 is NP.            */
+/* stretch 0: S = eta.xi/|xi|^2 and e = xi/|xi| (Algorithm 1); stretch 1:    */
+/* the exact stretch S = (|xi+eta| - |xi|)/|xi| acting along the deformed    */
+/* bond, e = (xi+eta)/|xi+eta| (the PMB form the paper names).               */
+/* Damage as in or_force: with alive given and s_c > 0 a live bond with      */
+/* S > s_c breaks before it contributes.                                     */
+/* ------------------------------------------------------------------------ */
+void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *X, const double *V, const double *u, double c, double s_c,
+                  int law, double beta, int stretch, uint8_t *alive, double *f, double *U) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0};
+        double Ui = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (alive && !alive[p]) continue;
+            int64_t j = col[p];
+            double xi[3] = {0, 0, 0}, eta[3] = {0, 0, 0}, y[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) {
+                xi[k] = X[j * dim + k] - X[i * dim + k];
+                eta[k] = u[j * dim + k] - u[i * dim + k];
+                y[k] = xi[k] + eta[k];
+            }
+            double r2 = 0.0, ex = 0.0, y2 = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                r2 = r2 + xi[k] * xi[k];
+                ex = ex + eta[k] * xi[k];
+                y2 = y2 + y[k] * y[k];
+            }
+            double len = sqrt(r2);
+            double S, e[3] = {0, 0, 0};
+            if (stretch == 0) {
+                S = ex / r2;
+                for (int k = 0; k < dim; ++k) e[k] = xi[k] / len;
+            } else {
+                double ylen = sqrt(y2);
+                S = (ylen - len) / len;
+                for (int k = 0; k < dim; ++k) e[k] = y[k] / ylen;
+            }
+            if (alive && s_c > 0.0 && S > s_c) {
+                alive[p] = 0;
+                continue;
+            }
+            double r = len * S * S;
+            double phi = law == 1 ? exp(-beta * r) : 1.0;
+            for (int k = 0; k < dim; ++k) fi[k] = fi[k] + c * phi * S * e[k] * V[j];
+            if (U) {
+                double psi = law == 1 ? (1.0 - exp(-beta * r)) / beta : r;
+                Ui = Ui + 0.25 * c * psi * V[j];
+            }
+        }
+        for (int k = 0; k < dim; ++k) f[i * dim + k] = fi[k];
+        if (U) U[i] = Ui;
+    }
+}
+
+/* Tangent of the linearised-stretch law at the displacement ulin:          */
+/* d/d eta [psi'(|xi| S^2) S] = (psi'(r) + 2 r psi''(r)) dS/d eta with      */
+/* dS/d eta = xi/|xi|^2, so each bond acts with the stiffness               */
+/*   k = c exp(-beta r) (1 - 2 beta r)   (NP),   k = c   (linear),          */
+/* r = |xi| S(ulin)^2, and H = -V (x) df/du applies as                      */
+/*   y_i = -V_i sum_j k ((w_j - w_i).xi/|xi|^2) (xi/|xi|) V_j   (free i)    */
+/*   y_i = w_i   (fixed i), w_j read as 0 at fixed j.                       */
+void or_tangent_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *X, const double *V, double c, int law, double beta,
+                    const double *ulin, const uint8_t *alive, const uint8_t *fixed,
+                    const double *w, double *y) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        if (fixed && fixed[i]) {
+            for (int k = 0; k < dim; ++k) y[i * dim + k] = w[i * dim + k];
+            continue;
+        }
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (alive && !alive[p]) continue;
+            int64_t j = col[p];
+            int jfix = fixed ? fixed[j] : 0;
+            double xi[3] = {0, 0, 0}, dw[3] = {0, 0, 0}, eta[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) {
+                xi[k] = X[j * dim + k] - X[i * dim + k];
+                dw[k] = (jfix ? 0.0 : w[j * dim + k]) - w[i * dim + k];
+                eta[k] = ulin ? ulin[j * dim + k] - ulin[i * dim + k] : 0.0;
+            }
+            double r2 = 0.0, ew = 0.0, eu = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                r2 = r2 + xi[k] * xi[k];
+                ew = ew + dw[k] * xi[k];
+                eu = eu + eta[k] * xi[k];
+            }
+            double len = sqrt(r2);
+            double Su = eu / r2;
+            double r = len * Su * Su;
+            double kb = law == 1 ? c * exp(-beta * r) * (1.0 - 2.0 * beta * r) : c;
+            double Sw = ew / r2;
+            for (int k = 0; k < dim; ++k) acc[k] = acc[k] + kb * Sw * (xi[k] / len) * V[j];
+        }
+        for (int k = 0; k < dim; ++k) y[i * dim + k] = -V[i] * acc[k];
+    }
+}
+
+/* Residual r_i = V_i (f_i(u) + b_i) on free nodes (0 on fixed), for a law. */
+double or_residual_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                       const double *X, const double *V, double c, int law, double beta,
+                       const uint8_t *alive, const uint8_t *fixed, const double *b,
+                       const double *u, double *r) {
+    or_force_law(dim, n, row_ptr, col, X, V, u, c, 0.0, law, beta, 0, (uint8_t *)alive, r,
+                 NULL);
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < dim; ++k) {
+            int64_t q = i * dim + k;
+            if (fixed && fixed[i]) r[q] = 0.0;
+            else r[q] = V[i] * (r[q] + (b ? b[q] : 0.0));
+            s = s + r[q] * r[q];
+        }
+    return sqrt(s);
+}
+
+/* Newton's method of the implicit flow chart for a law: while              */
+/* ||r(u)|| > rtol ||V b||, solve H(u) du = r(u) by conjugate gradients      */
+/* (to inner_rtol relative) and set u <- u + du.  H(u) is the tangent at the */
+/* current iterate (symmetric; positive definite on the free DOFs while     */
+/* every bond has 2 beta r < 1).  Returns 0 on convergence, 1 otherwise.     */
+int or_solve_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                 const double *X, const double *V, double c, int law, double beta,
+                 const uint8_t *alive, const uint8_t *fixed, const double *b, double *u,
+                 double rtol, double inner_rtol, int maxit, int max_outer, int *outer,
+                 int *inner, double *relres) {
+    int64_t m = n * dim;
+    double *r = (double *)malloc(sizeof(double) * m);
+    double *du = (double *)malloc(sizeof(double) * m);
+    double *res = (double *)malloc(sizeof(double) * m);
+    double *p = (double *)malloc(sizeof(double) * m);
+    double *q = (double *)malloc(sizeof(double) * m);
+    double bn = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < dim; ++k) {
+            double t = (fixed && fixed[i]) ? 0.0 : V[i] * (b ? b[i * dim + k] : 0.0);
+            bn = bn + t * t;
+        }
+    bn = sqrt(bn);
+    if (bn == 0.0) bn = 1.0;
+    int it_out = 0, it_in = 0, status = 1;
+    double rel = 0.0;
+    while (1) {
+        rel = or_residual_law(dim, n, row_ptr, col, X, V, c, law, beta, alive, fixed, b, u, r) / bn;
+        if (rel <= rtol) { status = 0; break; }
+        if (it_out >= max_outer) break;
+        /* conjugate gradients on H(u) du = r from du = 0 */
+        double rn = sqrt(or_dot(m, r, r));
+        for (int64_t k = 0; k < m; ++k) { du[k] = 0.0; res[k] = r[k]; p[k] = r[k]; }
+        double rr = or_dot(m, res, res);
+        int it = 0;
+        while (sqrt(rr) > inner_rtol * rn && it < maxit) {
+            or_tangent_law(dim, n, row_ptr, col, X, V, c, law, beta, u, alive, fixed, p, q);
+            double alpha = rr / or_dot(m, p, q);
+            for (int64_t k = 0; k < m; ++k) { du[k] = du[k] + alpha * p[k]; res[k] = res[k] - alpha * q[k]; }
+            double rr_new = or_dot(m, res, res);
+            double beta_cg = rr_new / rr;
+            rr = rr_new;
+            for (int64_t k = 0; k < m; ++k) p[k] = res[k] + beta_cg * p[k];
+            ++it;
+        }
+        it_in += it;
+        for (int64_t k = 0; k < m; ++k) u[k] = u[k] + du[k];
+        ++it_out;
+    }
+    if (outer) *outer = it_out;
+    if (inner) *inner = it_in;
+    if (relres) *relres = rel;
+    free(r); free(du); free(res); free(p); free(q);
     return status;
 }
 
