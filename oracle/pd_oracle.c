@@ -512,6 +512,7 @@ int or_solve_implicit(int dim, int64_t n, const int64_t *row_ptr, const int32_t 
 /* and the NP potential psi(r) = C (1 - exp(-beta r)), psi'(0) = C beta.     */
 /* Written with the micromodulus c = 4 psi'(0)/(delta |B_delta(0)|):         */
 /*   f_i += c exp(-beta r) S e V_j,  U_i += c/(4 beta) (1 - exp(-beta r)) V_j */
+/* (1 - exp(-beta r) evaluated as -expm1(-beta r), free of cancellation).   */
 /* with r = |xi| S^2.  law 0 is the linearised law (psi' = psi'(0), the      */
 /* exponential factor 1 and the energy (c/4) r V_j); law 1 is NP.            */
 /* stretch 0: S = eta.xi/|xi|^2 and e = xi/|xi| (Algorithm 1); stretch 1:    */
@@ -560,7 +561,7 @@ void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col
             double phi = law == 1 ? exp(-beta * r) : 1.0;
             for (int k = 0; k < dim; ++k) fi[k] = fi[k] + c * phi * S * e[k] * V[j];
             if (U) {
-                double psi = law == 1 ? (1.0 - exp(-beta * r)) / beta : r;
+                double psi = law == 1 ? -expm1(-beta * r) / beta : r;
                 Ui = Ui + 0.25 * c * psi * V[j];
             }
         }
