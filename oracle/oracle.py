@@ -82,6 +82,9 @@ def lib():
         L.or_solve_law.restype = i32
         L.or_solve_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, ptr, ptr, ptr,
                                    ptr, dbl, dbl, i32, i32, ptr, ptr, ptr]
+        L.or_verlet_law.restype = None
+        L.or_verlet_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32,
+                                    ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -255,6 +258,27 @@ class LawMesh(Mesh):
                              _p(self.V), float(c), int(law), float(beta), _p(ulin), _p(alive),
                              _p(fixed), _p(w), _p(y))
         return y
+
+    def start_law(self, u0, v0, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, s_c=0.0,
+                  alive=None):
+        alive = self.all_alive() if alive is None else np.ascontiguousarray(alive, np.uint8).copy()
+        u = _f64(u0).copy()
+        v = _f64(v0).copy()
+        f = self.force_law(u, c, law, beta, stretch, s_c, alive)
+        return {"u": u, "v": v, "f": f, "alive": alive, "step": 0}
+
+    def verlet_law(self, state, c, rho, s_c, dt, nsteps, law=LAW_NP, beta=1.0,
+                   stretch=STRETCH_LINEARISED, bc_kind=None, bc_vel=None, b=None, ramp=0):
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        lib().or_verlet_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                            _p(self.V), float(rho), float(c), float(s_c), int(law), float(beta),
+                            int(stretch), _p(bc_kind), _p(bc_vel), _p(b), int(ramp), float(dt),
+                            int(state["step"]), int(nsteps), _p(state["u"]), _p(state["v"]),
+                            _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
 
     def residual_law(self, u, c, b, law=LAW_NP, beta=1.0, fixed=None, alive=None):
         u = _f64(u)

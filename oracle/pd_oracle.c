@@ -312,11 +312,19 @@ static double or_ramp(double s, int64_t ramp) {
     return r < 1.0 ? r : 1.0;
 }
 
-void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
-               const double *X, const double *V, double rho, double c, double s_c,
-               const uint8_t *bc_kind, const double *bc_vel, const double *b,
-               int64_t ramp, double dt, int64_t step0, int64_t nsteps,
-               double *u, double *v, double *f, uint8_t *alive) {
+/* or_verlet_law: the same steps with the force of a general pairwise law  */
+/* (or_force_law); or_verlet is the linearised law (law 0, stretch 0), for  */
+/* which or_force_law and or_force agree bit for bit.                       */
+void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *X, const double *V, const double *u, double c, double s_c,
+                  int law, double beta, int stretch, uint8_t *alive, double *f, double *U);
+
+void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const double *X, const double *V, double rho, double c, double s_c,
+                   int law, double beta, int stretch,
+                   const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                   int64_t ramp, double dt, int64_t step0, int64_t nsteps,
+                   double *u, double *v, double *f, uint8_t *alive) {
     for (int64_t k = step0; k < step0 + nsteps; ++k) {
         double rh = or_ramp((double)k + 0.5, ramp);
         double r1 = or_ramp((double)(k + 1), ramp);
@@ -339,7 +347,7 @@ void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
                 }
             }
         }
-        or_force(dim, n, row_ptr, col, X, V, u, c, s_c, alive, f, NULL);
+        or_force_law(dim, n, row_ptr, col, X, V, u, c, s_c, law, beta, stretch, alive, f, NULL);
         for (int64_t i = 0; i < n; ++i) {
             int kind = bc_kind ? bc_kind[i] : OR_BC_FREE;
             for (int d = 0; d < dim; ++d) {
@@ -355,6 +363,15 @@ void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
             }
         }
     }
+}
+
+void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+               const double *X, const double *V, double rho, double c, double s_c,
+               const uint8_t *bc_kind, const double *bc_vel, const double *b,
+               int64_t ramp, double dt, int64_t step0, int64_t nsteps,
+               double *u, double *v, double *f, uint8_t *alive) {
+    or_verlet_law(dim, n, row_ptr, col, X, V, rho, c, s_c, 0, 0.0, 0, bc_kind, bc_vel, b, ramp,
+                  dt, step0, nsteps, u, v, f, alive);
 }
 
 /* ------------------------------------------------------------------------ */

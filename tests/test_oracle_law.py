@@ -176,3 +176,33 @@ def test_np_newton_reaches_equilibrium(orc):
     # the linear solution is not an NP equilibrium
     _, r_lin = mesh.residual_law(u_lin, c, w.b, orc.LAW_NP, beta, w.fixed)
     assert r_lin > 1e-4 * bn
+
+
+def test_verlet_law_linear_is_verlet_and_np_conserves_energy(orc):
+    """The integrator with the general law: the linear law reproduces the
+    linearised integrator bit for bit; with the NP law (no damage, free
+    plate) the total energy KE + sum V_i U_i drifts at second order in dt."""
+    w = inputs.plate_2d(20, 3, seed=1, steps=0)
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    v0 = inputs.random_field(mesh.n, 2, 71, scale=5e-2)
+    a = mesh.start(w.u0, v0, c)
+    b = mesh.start_law(w.u0, v0, c, orc.LAW_LINEAR, 1.0)
+    mesh.verlet(a, c, w.rho, 0.0, w.dt, 40)
+    mesh.verlet_law(b, c, w.rho, 0.0, w.dt, 40, orc.LAW_LINEAR, 1.0)
+    assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["v"], b["v"])
+    # NP: beta set so that beta r reaches about 1 during the run
+    probe = mesh.start(w.u0, v0, c)
+    mesh.verlet(probe, c, w.rho, 0.0, w.dt, 40)
+    beta = 1.0 / bond_r(mesh, probe["u"]).max()
+
+    def drift(dt, steps):
+        st = mesh.start_law(w.u0, v0, c, orc.LAW_NP, beta)
+        e0 = mesh.kinetic(st["v"], w.rho) + mesh.energy_law(st["u"], c, orc.LAW_NP, beta)
+        mesh.verlet_law(st, c, w.rho, 0.0, dt, steps, orc.LAW_NP, beta)
+        e1 = mesh.kinetic(st["v"], w.rho) + mesh.energy_law(st["u"], c, orc.LAW_NP, beta)
+        return abs(e1 - e0) / e0
+
+    d1, d2 = drift(w.dt, 40), drift(w.dt / 2, 80)
+    assert d1 < 1e-3
+    assert 2.5 < d1 / d2 < 6.0                         # second order: ratio about 4
