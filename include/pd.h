@@ -73,23 +73,47 @@ typedef struct pd_server_s *pd_server;
 /*
  * Material and arithmetic of one model.
  *   dim        2 or 3
- *   precision  PD_FP64: every bond computed in float64.
- *              PD_MIXED: bond vectors xi = X_j - X_i and eta = u_j - u_i are
- *              formed in float64, then the bond strain, the damage test and
- *              the bond force are computed in float32 and each node's sum is
- *              accumulated with compensated (two-sum) float32 arithmetic.
- *              Positions, velocities and the time integration stay float64.
+ *   precision  PD_FP64: every bond computed in float64, 1/|xi| to full
+ *              double precision.
+ *              PD_MIXED: the same float64 arithmetic, except that 1/|xi| is
+ *              the hardware reciprocal-square-root estimate without
+ *              refinement (relative error below 2^-22).  Positions,
+ *              velocities, sums and the time integration are float64 in
+ *              both modes.
  *   c          micromodulus c = 4 psi'(0)/(delta |B_delta(0)|) (Algorithm 1);
  *              see pd_micromodulus.
  *   rho        mass density (velocity-Verlet equations), > 0
  *   s_c        critical stretch; <= 0 disables damage
+ *   law        pairwise potential psi of Algorithm 1 (J = 1 on the ball):
+ *              PD_LAW_LINEAR  psi'(|xi| S^2) taken as psi'(0): bond force
+ *                             c S e V_j, energy (c/4) |xi| S^2 V_j;
+ *              PD_LAW_NP      psi(r) = C (1 - exp(-beta r)) (the nonlinear
+ *                             model of the paper's validation section):
+ *                             bond force c exp(-beta r) S e V_j, energy
+ *                             c/(4 beta) (1 - exp(-beta r)) V_j, r = |xi| S^2
+ *                             (C enters through c = 4 C beta/(delta|B|)).
+ *   stretch    PD_STRETCH_LINEARISED  S = eta.xi/|xi|^2, e = xi/|xi|
+ *                             (Algorithm 1);
+ *              PD_STRETCH_EXACT  S = (|xi+eta| - |xi|)/|xi| along the
+ *                             deformed bond, e = (xi+eta)/|xi+eta|.
+ *   beta       PD_LAW_NP only: beta > 0.
+ * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
+ * tiled kernels run that law; any other combination runs on the gather
+ * kernel (pd_sim_info kernel 1), and the tangent and the implicit solve take
+ * the linearised stretch only (PD_EINVAL otherwise).
  */
+enum { PD_LAW_LINEAR = 0, PD_LAW_NP = 1 };
+enum { PD_STRETCH_LINEARISED = 0, PD_STRETCH_EXACT = 1 };
+
 typedef struct {
     int dim;
     int precision;
     double c;
     double rho;
     double s_c;
+    int law;
+    int stretch;
+    double beta;
 } pd_material;
 
 typedef struct {
@@ -426,25 +450,34 @@ int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes);
 
 /*
  * Matrix-free tangent operator of the quasi-static problem, y = H w with
- * H = -V (x) df/du (the paper's tangent equation; exact for the linearised
- * law):
- *   y_i = -V_i sum_j mu_ij c ((w_j - w_i).xi/|xi|^2) (xi/|xi|) V_j  (free i)
- *   y_i = w_i                                                       (fixed i)
- * with w_j read as 0 at fixed nodes.  fixed: device uint8[n] (NULL = none),
- * alive: device uint8[nnz] exported order (NULL = all intact).  w, y device
- * [n][dim] float64.  mat->precision selects float64 or float32 bond
- * arithmetic (float64 differences, float64 sums).  Asynchronous.
+ * H = -V (x) df/du (the paper's tangent equation, evaluated analytically):
+ *   y_i = -V_i sum_j mu_ij k_ij ((w_j - w_i).xi/|xi|^2) (xi/|xi|) V_j  (free i)
+ *   y_i = w_i                                                          (fixed i)
+ * with w_j read as 0 at fixed nodes and the bond stiffness k_ij = c for the
+ * linearised law.  fixed: device uint8[n] (NULL = none), alive: device
+ * uint8[nnz] exported order (NULL = all intact).  w, y device [n][dim]
+ * float64.  Asynchronous.
+ * pd_apply_tangent_at linearises at the displacement u (device [n][dim]):
+ * for PD_LAW_NP k_ij = c exp(-beta r)(1 - 2 beta r), r = |xi| S(u)^2 (from
+ * psi'(r) + 2 r psi''(r)); for the linear law it equals pd_apply_tangent.
  */
 int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
                      const double *V, const uint8_t *alive, const uint8_t *fixed,
                      const double *w, double *y);
+int pd_apply_tangent_at(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                        const double *V, const double *u, const uint8_t *alive,
+                        const uint8_t *fixed, const double *w, double *y);
 
 /*
  * Quasi-static solve (implicit scheme of the paper, one load step): find u
  * with u = given values on fixed nodes and f(u) + b = 0 on free nodes, by
- * Newton steps H du = V (f(u) + b) solved with conjugate gradients.
- *   precision PD_FP64: float64 CG.  PD_MIXED: float32 inner CG (float32
- *   tangent, float64 dot products) inside float64 iterative refinement.
+ * Newton steps H(u) du = V (f(u) + b) solved with conjugate gradients,
+ * H(u) the tangent at the current iterate (one step for the linearised law;
+ * for PD_LAW_NP a Newton-Krylov iteration, which needs a positive definite
+ * tangent: 2 beta r < 1 on the bonds that carry load).
+ *   precision PD_FP64: float64 CG solving each Newton system to the target.
+ *   PD_MIXED: an inner CG with the estimate-only tangent, each correction to
+ *   1e-5 relative, inside float64 iterative refinement.
  *   u      device [n][dim], in: initial guess holding the fixed values,
  *          out: solution (or last iterate)
  *   b      device [n][dim] body force density

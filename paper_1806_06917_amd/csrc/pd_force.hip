@@ -50,19 +50,42 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
         if (tangent && a.bc) fixed_i = a.bc[i] != 0;
         if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
         const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
-        for (uint32_t p = rs + lane; p < re; p += L) {
-            // a dead bond adds exact zeros, like the tile kernel's dummy record
-            const uint32_t j = (uint32_t)a.col[p];
-            const bool live = !a.alive || a.alive[p];
-            const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
-            double ujx, ujy, ujz;
-            load_vec<DIM>(a.u, j, ujx, ujy, ujz);
-            if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
-            const double cVj = a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z);
-            const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
-            if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
-                                         duz, cVj, !live, s64))
-                a.alive[p] = 0;
+        if (a.law == PD_LAW_LINEAR && a.stretch == PD_STRETCH_LINEARISED) {
+            for (uint32_t p = rs + lane; p < re; p += L) {
+                // a dead bond adds exact zeros, like the tile kernel's dummy record
+                const uint32_t j = (uint32_t)a.col[p];
+                const bool live = !a.alive || a.alive[p];
+                const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+                double ujx, ujy, ujz;
+                load_vec<DIM>(a.u, j, ujx, ujy, ujz);
+                if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
+                const double cVj = a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z);
+                const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
+                if (bond<DIM, MIXED, WANT_E>(a.damage, a.s_c, xj.x - xix, xj.y - xiy, dxz, ujx - uix,
+                                             ujy - uiy, duz, cVj, !live, s64))
+                    a.alive[p] = 0;
+            }
+        } else {
+            // general law; the tangent's linearisation point, if any
+            const bool lin = tangent && a.u_lin;
+            double lix = 0, liy = 0, liz = 0;
+            if (lin) load_vec<DIM>(a.u_lin, i, lix, liy, liz);
+            for (uint32_t p = rs + lane; p < re; p += L) {
+                const uint32_t j = (uint32_t)a.col[p];
+                const bool live = !a.alive || a.alive[p];
+                const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+                double ujx, ujy, ujz, ljx = 0, ljy = 0, ljz = 0;
+                load_vec<DIM>(a.u, j, ujx, ujy, ujz);
+                if (tangent && a.bc && a.bc[j]) { ujx = 0; ujy = 0; ujz = 0; }
+                if (lin) load_vec<DIM>(a.u_lin, j, ljx, ljy, ljz);
+                const double cVj = a.cv_uniform != 0.0 ? a.cv_uniform : a.c * (DIM == 3 ? xj.w : xj.z);
+                const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
+                if (bond_law<DIM, MIXED, WANT_E>(a.law, a.stretch, a.beta, a.damage, a.s_c, tangent,
+                                                 xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
+                                                 duz, ljx - lix, ljy - liy, ljz - liz, cVj, !live,
+                                                 s64))
+                    a.alive[p] = 0;
+            }
         }
     }
     double fx, fy, fz, Ue;
@@ -247,7 +270,7 @@ int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
         return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
     if (!std::isfinite(mat->c) || !std::isfinite(mat->s_c))
         return pd_set_error(ctx, PD_EINVAL, "c and s_c must be finite");
-    return PD_OK;
+    return pd_check_law(ctx, mat);
 }
 
 NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
@@ -256,10 +279,11 @@ NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
     a.col = nbr->col;
     a.n = nbr->n;
     a.c = mat->c;
-    a.c32 = (float)mat->c;
     a.s_c = mat->s_c;
-    a.s_c32 = (float)mat->s_c;
     a.rho = mat->rho;
+    a.law = mat->law;
+    a.stretch = mat->stretch;
+    a.beta = mat->beta;
     return a;
 }
 
@@ -302,7 +326,7 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     if (U) PD_TRY(pd_check_dev_ptr(ctx, U, "U"));
     const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
-    PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+    if (!pd_general_law(mat)) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
     PD_TRY(ensure_scratch(ctx, nbr));
     const bool tiled = block > 0;
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
@@ -333,9 +357,10 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
 // ---------------------------------------------------------------------------
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
                    const uint8_t *alive_sfc, uint16_t *bw, int block, const uint8_t *fixed_sfc,
-                   const double *w, double *y, const int *done) {
+                   const double *w, double *y, const int *done, const double *u_lin) {
     NodeArgs a = base_args(nbr, mat);
     a.done = done;
+    a.u_lin = mat->law == PD_LAW_NP ? u_lin : nullptr;
     a.xv = xv;
     a.u = w;
     a.alive = const_cast<uint8_t *>(alive_sfc);
@@ -362,34 +387,55 @@ int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const dou
     return launch_node(ctx, nbr, a, pd_auto_lanes(ctx, nbr->nnz, nbr->n), false, block);
 }
 
-extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
-                                const double *V, const uint8_t *alive, const uint8_t *fixed,
-                                const double *w, double *y) {
+static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                         const double *V, const double *u, const uint8_t *alive,
+                         const uint8_t *fixed, const double *w, double *y) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
+    if (mat->stretch != PD_STRETCH_LINEARISED)
+        return pd_set_error(ctx, PD_EINVAL, "the tangent takes the linearised stretch only");
     PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
     PD_TRY(pd_check_dev_ptr(ctx, V, "V"));
     PD_TRY(pd_check_dev_ptr(ctx, w, "w"));
     PD_TRY(pd_check_dev_ptr(ctx, y, "y"));
+    if (u) PD_TRY(pd_check_dev_ptr(ctx, u, "u"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (fixed) PD_TRY(pd_check_dev_ptr(ctx, fixed, "fixed"));
+    const bool np = mat->law == PD_LAW_NP;
     int block = 0;
-    PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
+    if (!pd_general_law(mat))
+        PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
     PD_TRY(ensure_scratch(ctx, nbr));
     const bool tiled = block > 0;
+    if (np && !nbr->s_ulin) PD_TRY(pd_alloc(ctx, &nbr->s_ulin, (size_t)nbr->n * (nbr->dim == 3 ? 4 : 2)));
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
     PD_TRY(pd_gather_vec(ctx, nbr, w, nbr->s_u, false));
+    if (np) PD_TRY(pd_gather_vec(ctx, nbr, u, nbr->s_ulin, true));
     if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, nbr->s_alive));
     if (tiled) PD_TRY(pd_bw_compose(ctx, nbr, alive ? nbr->s_alive : nullptr, nbr->s_bw));
     if (fixed) PD_TRY(pd_gather_u8(ctx, nbr, fixed, nbr->s_fixed, 0));
     PD_TRY(pd_tangent_sfc(ctx, nbr, mat, nbr->s_xv, alive ? nbr->s_alive : nullptr,
                           tiled ? nbr->s_bw : nullptr, block, fixed ? nbr->s_fixed : nullptr,
-                          nbr->s_u, nbr->s_f, nullptr));
+                          nbr->s_u, nbr->s_f, nullptr, np ? nbr->s_ulin : nullptr));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, y));
     return PD_OK;
+}
+
+extern "C" int pd_apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                                const double *V, const uint8_t *alive, const uint8_t *fixed,
+                                const double *w, double *y) {
+    return apply_tangent(ctx, nbr, mat, X, V, nullptr, alive, fixed, w, y);
+}
+
+extern "C" int pd_apply_tangent_at(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
+                                   const double *X, const double *V, const double *u,
+                                   const uint8_t *alive, const uint8_t *fixed, const double *w,
+                                   double *y) {
+    if (!u) return pd_set_error(ctx, PD_EINVAL, "u must not be NULL");
+    return apply_tangent(ctx, nbr, mat, X, V, u, alive, fixed, w, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,9 +503,13 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
     const pd_tune_entry *te = nullptr;
+    const bool general = pd_general_law(mat);     // gather kernel only
     if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);
-    if (te) {
+    if (general) {
+        if (ctx->kernel == 2 || ctx->kernel == 3)
+            return pd_set_error(ctx, PD_ECAPACITY, "the tiled kernels take the linearised law only");
+    } else if (te) {
         lanes = te->lanes;
         ctx->tile = te->tile;
         const int st = pd_plan_kernel(ctx, nbr, lanes, &block);

@@ -1,8 +1,9 @@
 // Quasi-static solve (Section "Implicit time integration"): Newton steps
-// H du = r with r_i = V_i (f_i(u) + b_i) on free nodes, the tangent H applied
-// matrix-free (the paper assembles it by central differences; for the
-// linearised law the operator is exact and needs no storage), each Newton
-// system solved by conjugate gradients.
+// H(u) du = r with r_i = V_i (f_i(u) + b_i) on free nodes, the tangent H(u)
+// applied matrix-free at the current iterate (the paper assembles it by
+// central differences; here it is the analytic derivative of the bond force,
+// constant for the linearised law and c exp(-beta r)(1 - 2 beta r) per bond
+// for the NP law), each Newton system solved by conjugate gradients.
 //
 // CG runs entirely on the device: per iteration one tangent launch and three
 // small vector kernels; the scalars alpha, beta and r.r live in device memory
@@ -12,8 +13,10 @@
 // the host looks at the state once per chunk.
 //
 // Precision: PD_FP64 runs every part in float64.  PD_MIXED applies the
-// tangent with float32 bond arithmetic inside the CG (float64 vectors and dot
-// products) and wraps it in iterative refinement with float64 residuals.
+// tangent with the unrefined reciprocal-square-root estimate inside the CG
+// (float64 vectors and dot products) and wraps it in iterative refinement
+// with full-precision float64 residuals.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -187,7 +190,7 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, uint
         for (int k = 0; k < nrun; ++k) {
             const int parity = (it + k) & 1;
             PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.block, w.fixed, w.p,
-                                  w.q, &w.st->done));
+                                  w.q, &w.st->done, w.u));
             dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.p, w.q, m, w.part_a, w.st);
             cg_update_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.x, w.r, w.p, w.q, m, w.part_a,
                                                           w.part_b, w.st, parity);
@@ -218,6 +221,9 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     if (!mat || mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "bad material");
     if (mat->precision != PD_FP64 && mat->precision != PD_MIXED)
         return pd_set_error(ctx, PD_EINVAL, "bad precision");
+    PD_TRY(pd_check_law(ctx, mat));
+    if (mat->stretch != PD_STRETCH_LINEARISED)
+        return pd_set_error(ctx, PD_EINVAL, "the implicit solve takes the linearised stretch only");
     if (!(rtol > 0.0) || !(rtol < 1.0)) return pd_set_error(ctx, PD_EINVAL, "rtol must be in (0,1)");
     if (maxit <= 0) return pd_set_error(ctx, PD_EINVAL, "maxit must be positive");
     PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
@@ -255,7 +261,9 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         PD_TRY(pd_gather_u8(ctx, nbr, fixed, w.fixed, 0));
     }
     int block = 0;
-    PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
+    const bool np = mat->law == PD_LAW_NP;
+    if (!pd_general_law(mat))
+        PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
     w.block = block;
     if (block > 0) {
         PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz + 2));
@@ -275,7 +283,9 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
 
     pd_material inner = *mat;
     const bool mixed = mat->precision == PD_MIXED;
-    const int max_outer = mixed ? 30 : 4;
+    // Newton steps: one suffices for the linearised law (a few more for
+    // iterative refinement); NP converges quadratically near the solution
+    const int max_outer = np ? 60 : (mixed ? 30 : 4);
     int outer = 0, inner_total = 0, status = PD_ENOCONV;
     double rel = 0.0;
     while (true) {
@@ -296,7 +306,10 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         if (outer >= max_outer || inner_total >= maxit) break;
         // inner target: FP64 solves straight to the requested accuracy (with a
         // small margin); mixed solves each correction to 1e-5 relative
-        const double target = mixed ? 1e-5 * std::sqrt(rr) : 0.5 * rtol * bnorm;
+        // (NP: the Newton system to 1e-6 relative or the final target, the
+        // looser of the two, keeps Newton's convergence fast)
+        double target = mixed ? 1e-5 * std::sqrt(rr) : 0.5 * rtol * bnorm;
+        if (np) target = std::max(target, 1e-6 * std::sqrt(rr));
         int k = 0;
         PD_TRY(cg_solve(ctx, nbr, &inner, w, m, target, maxit - inner_total, &k));
         inner_total += k;

@@ -81,6 +81,7 @@ struct pd_nbr_s {
     uint16_t *s_bw = nullptr;      // scratch bond words for the stateless entry points
     // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
     double *s_xv = nullptr, *s_u = nullptr, *s_f = nullptr, *s_U = nullptr;
+    double *s_ulin = nullptr;    // linearisation point of the NP tangent
     uint8_t *s_alive = nullptr, *s_fixed = nullptr;
 };
 
@@ -219,12 +220,19 @@ void pd_nbr_unref(pd_nbr nbr);
 // bw + block > 0: tile kernel with bond words bw; otherwise the gather kernel
 int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
                    const uint8_t *alive_sfc, uint16_t *bw, int block, const uint8_t *fixed_sfc,
-                   const double *w, double *y, const int *done);
+                   const double *w, double *y, const int *done, const double *u_lin = nullptr);
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
                  const uint8_t *alive_sfc, uint16_t *bw, int block, const double *u, double *f);
 // kernel choice for a call site under the context's tuning; *block > 0 means
 // the tile kernel with that workgroup size, 0 the gather kernel
 int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block);
+
+// the material's pairwise law is not the linearised law of the tiled kernels
+inline bool pd_general_law(const pd_material *m) {
+    return m->law != PD_LAW_LINEAR || m->stretch != PD_STRETCH_LINEARISED;
+}
+// law, stretch and beta are valid (pd_runtime.hip)
+int pd_check_law(pd_ctx ctx, const pd_material *m);
 
 // autotuner cache (pd_tune.hip): neighbour-count bucket of a mesh, lookup
 int pd_tune_bucket(double mean_neighbors);

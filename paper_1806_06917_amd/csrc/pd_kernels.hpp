@@ -41,7 +41,11 @@ struct NodeArgs {
     int damage;
     double c, s_c, rho, dt, r_half, r_full;
     double cv_uniform;                 // c V when every node has volume V, else 0
-    float c32, s_c32;
+    // general pairwise law (gather kernel): PD_LAW_*, PD_STRETCH_*, NP beta,
+    // and the linearisation point of the tangent ([n][US], sfc order)
+    int law, stretch;
+    double beta;
+    const double *__restrict__ u_lin;
 };
 
 // per-lane FP64 running sums of the bond forces (and bond energies)
@@ -97,6 +101,61 @@ __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double 
     s.y += g * dxy;
     if (DIM == 3) s.z += g * dxz;
     if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
+    return brk && !dead;
+}
+
+// One bond under the general pairwise law of Algorithm 1 (gather kernel):
+// the NP potential psi(r) = C (1 - exp(-beta r)) and/or the exact stretch.
+// Force and damage as in `bond` with S the chosen stretch, e its direction
+// (xi/|xi|, or (xi+eta)/|xi+eta| for the exact stretch) and the bond force
+// c V_j exp(-beta r) S e (factor 1 for the linear law), r = |xi| S^2; energy
+// c V_j/(4 beta) (1 - exp(-beta r)) (linear law: (c/4) V_j r).
+// Tangent mode (du = w_j - w_i, linearised stretch): the bond acts with the
+// stiffness c exp(-beta r)(1 - 2 beta r) of the linearisation point
+// (dl = ulin_j - ulin_i), i.e. psi'(r) + 2 r psi''(r) over psi'(0).
+template <int DIM, bool MIXED, bool WANT_E>
+__device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int damage,
+                                         double s_c, bool tangent, double dxx, double dxy,
+                                         double dxz, double dux, double duy, double duz,
+                                         double dlx, double dly, double dlz, double cVj,
+                                         bool dead, Acc64 &s) {
+    const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
+    const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
+    const double len = r2 * inv;
+    const bool np = law == PD_LAW_NP;
+    if (tangent) {
+        const double el = DIM == 3 ? dlx * dxx + dly * dxy + dlz * dxz : dlx * dxx + dly * dxy;
+        const double Su = el * (inv * inv);
+        const double r = len * Su * Su;
+        const double k = np ? exp(-beta * r) * (1.0 - 2.0 * beta * r) : 1.0;
+        const double ew = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+        const double g = dead ? 0.0 : cVj * k * (ew * (inv * inv)) * inv;
+        s.x += g * dxx;
+        s.y += g * dxy;
+        if (DIM == 3) s.z += g * dxz;
+        return false;
+    }
+    double S, ex, ey, ez;
+    if (stretch == PD_STRETCH_EXACT) {
+        const double yx = dxx + dux, yy = dxy + duy, yz = DIM == 3 ? dxz + duz : 0.0;
+        const double y2 = DIM == 3 ? yx * yx + yy * yy + yz * yz : yx * yx + yy * yy;
+        const double iy = MIXED ? __builtin_amdgcn_rsq(y2) : rsqrt_pos(y2);
+        S = (y2 * iy - len) * inv;
+        ex = yx * iy; ey = yy * iy; ez = yz * iy;
+    } else {
+        const double e_ = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+        S = e_ * (inv * inv);
+        ex = dxx * inv; ey = dxy * inv; ez = dxz * inv;
+    }
+    const bool brk = damage && S > s_c;
+    const bool off = brk || dead;
+    const double r = len * S * S;
+    const double phi = np ? exp(-beta * r) : 1.0;
+    const double g = off ? 0.0 : cVj * phi * S;
+    s.x += g * ex;
+    s.y += g * ey;
+    if (DIM == 3) s.z += g * ez;
+    if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * (np ? -expm1(-beta * r) / beta : r);
     return brk && !dead;
 }
 

@@ -162,6 +162,17 @@ extern "C" const char *pd_last_error(pd_ctx ctx) {
     return ctx->last_error.c_str();
 }
 
+int pd_check_law(pd_ctx ctx, const pd_material *m) {
+    if (m->law != PD_LAW_LINEAR && m->law != PD_LAW_NP)
+        return pd_set_error(ctx, PD_EINVAL, "law must be PD_LAW_LINEAR or PD_LAW_NP");
+    if (m->stretch != PD_STRETCH_LINEARISED && m->stretch != PD_STRETCH_EXACT)
+        return pd_set_error(ctx, PD_EINVAL,
+                            "stretch must be PD_STRETCH_LINEARISED or PD_STRETCH_EXACT");
+    if (m->law == PD_LAW_NP && (!(m->beta > 0.0) || !std::isfinite(m->beta)))
+        return pd_set_error(ctx, PD_EINVAL, "PD_LAW_NP needs a finite beta > 0");
+    return PD_OK;
+}
+
 extern "C" int pd_ctx_set_lanes(pd_ctx ctx, int lanes) {
     if (!ctx) return PD_EINVAL;
     if (lanes != 0 && (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))))

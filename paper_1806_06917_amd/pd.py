@@ -30,7 +30,8 @@ class PDError(RuntimeError):
 
 class Material(C.Structure):
     _fields_ = [("dim", C.c_int), ("precision", C.c_int), ("c", C.c_double),
-                ("rho", C.c_double), ("s_c", C.c_double)]
+                ("rho", C.c_double), ("s_c", C.c_double), ("law", C.c_int),
+                ("stretch", C.c_int), ("beta", C.c_double)]
 
 
 class Request(C.Structure):
@@ -112,6 +113,7 @@ def _load():
         "pd_server_destroy": (i32, [vp]),
         "pd_server_get_stats": (i32, [vp, P(ServerStats)]),
         "pd_apply_tangent": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
+        "pd_apply_tangent_at": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, vp]),
         "pd_solve_implicit": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, dbl, i32,
                                     P(SolveInfo)]),
     }
@@ -210,10 +212,20 @@ class Context:
             pass
 
 
-def material(dim, c, rho=1.0, s_c=0.0, precision="fp64"):
+PD_LAW_LINEAR, PD_LAW_NP = 0, 1
+PD_STRETCH_LINEARISED, PD_STRETCH_EXACT = 0, 1
+
+
+def material(dim, c, rho=1.0, s_c=0.0, precision="fp64", law="linear", beta=0.0,
+             stretch="linearised"):
+    """law: "linear" | "np" (psi(r) = C (1 - exp(-beta r))); stretch:
+    "linearised" | "exact"."""
     prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
-    return Material(int(dim), prec, float(c), float(rho), float(s_c))
+    lw = {"linear": PD_LAW_LINEAR, "np": PD_LAW_NP}[law] if isinstance(law, str) else int(law)
+    sk = {"linearised": PD_STRETCH_LINEARISED, "exact": PD_STRETCH_EXACT}[stretch] \
+        if isinstance(stretch, str) else int(stretch)
+    return Material(int(dim), prec, float(c), float(rho), float(s_c), lw, sk, float(beta))
 
 
 class Neighbors:
@@ -264,6 +276,13 @@ def internal_force(ctx, nbr, mat, X, V, u, f, alive=None, U=None):
 def apply_tangent(ctx, nbr, mat, X, V, w, y, alive=None, fixed=None):
     ctx.check(lib.pd_apply_tangent(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(alive),
                                    _ptr(fixed), _ptr(w), _ptr(y)), "pd_apply_tangent")
+
+
+def apply_tangent_at(ctx, nbr, mat, X, V, u, w, y, alive=None, fixed=None):
+    """Tangent linearised at the displacement u (NP law; linear: as apply_tangent)."""
+    ctx.check(lib.pd_apply_tangent_at(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(u),
+                                      _ptr(alive), _ptr(fixed), _ptr(w), _ptr(y)),
+              "pd_apply_tangent_at")
 
 
 @dataclass
