@@ -8,6 +8,8 @@ resident in HBM before the timed region; the neighbour build is one-off and
 reported separately.  Both precisions compute in float64; "mixed" takes 1/|xi|
 from the hardware reciprocal-square-root estimate without refinement.
 
+Then (unless --no-law) the NP pairwise law: explicit steps on the notched
+512^2 plate and the Newton-Krylov solve of the 400 x 40 bar ("law" object).
 Then (unless --no-serve) the serving workload: independent notched-plate
 requests through pd_server_* under a device-memory budget, first all at
 once (saturated throughput), then with Poisson arrivals at a fraction of that
@@ -85,6 +87,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-law", action="store_true",
+                    help="skip the NP-law measurements (explicit steps, Newton-Krylov)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="built-in launch heuristics instead of the autotuner's choice")
     ap.add_argument("--serve-count", type=int, default=256)
@@ -203,6 +207,67 @@ def serve(pd, reqs, budget, chunk, rate=None):
             "max_running": most, "rounds": rounds, "peak_bytes": peak, "server": stats}
 
 
+def law_runs(torch, pd, steps):
+    """The general pairwise law (gather kernel): NP explicit steps on the
+    notched 512^2 plate, and the NP Newton-Krylov solve of the 400 x 40 bar
+    (beta set so that beta |xi| S^2 reaches 0.1 at the linear solution)."""
+    from paper_1806_06917_amd import inputs
+    out = {}
+    ctx = pd.Context(0)
+    w = inputs.CONFIGS["notched512"]()
+    progress("NP law, explicit steps,", w.name)
+    X = dev(torch, w.X)
+    nb = pd.Neighbors(ctx, X, w.delta)
+    c = pd.micromodulus(w.dim, w.E, w.delta)
+    for prec in ("mixed", "fp64"):
+        mat = pd.material(w.dim, c, w.rho, 0.0, prec, law="np", beta=1e3)
+        sim = pd.Simulation(ctx, nb, mat, X, dev(torch, w.V), dev(torch, w.u0),
+                            dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                            bc_vel=dev(torch, w.bc_vel), notch=w.notch,
+                            ramp_steps=w.ramp_steps)
+        sim.step(10, w.dt)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(ctx.stream)
+        sim.step(steps, w.dt)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"np_step_{prec}"] = {"workload": w.name, "ms_per_step": ms,
+                                  "bond_evals_per_s": nb.nnz / (ms * 1e-3),
+                                  "launch": sim.info(), "beta": 1e3}
+        sim.close()
+    nb.close()
+    wb = inputs.CONFIGS["bar400x40"]()
+    progress("NP law, Newton-Krylov,", wb.name)
+    Xb, Vb, bb = dev(torch, wb.X), dev(torch, wb.V), dev(torch, wb.b)
+    fixed = dev(torch, wb.fixed)
+    nb = pd.Neighbors(ctx, Xb, wb.delta)
+    cb = pd.micromodulus(2, wb.E, wb.delta)
+    u = dev(torch, wb.u0)
+    pd.solve_implicit(ctx, nb, pd.material(2, cb), Xb, Vb, bb, u, fixed=fixed, rtol=1e-10)
+    rp, col = nb.export()
+    ul = u.cpu().numpy()
+    i = np.repeat(np.arange(wb.n), np.diff(rp))
+    xi = wb.X[col] - wb.X[i]
+    S = np.sum(xi * (ul[col] - ul[i]), 1) / np.sum(xi * xi, 1)
+    beta = 0.1 / float(np.max(np.sqrt(np.sum(xi * xi, 1)) * S * S))
+    for prec in ("fp64", "mixed"):
+        u = dev(torch, wb.u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pd.solve_implicit(ctx, nb, pd.material(2, cb, precision=prec, law="np", beta=beta),
+                                Xb, Vb, bb, u, fixed=fixed, rtol=1e-10)
+        t = time.perf_counter() - t0
+        out[f"np_newton_{prec}"] = {"workload": wb.name, "seconds": t, "newton_steps": res.outer,
+                                    "cg_iterations": res.inner,
+                                    "rel_residual": res.rel_residual, "beta": beta}
+    nb.close()
+    ctx.close()
+    return out
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle, as it stands, on the same workload for a few steps."""
     from oracle import oracle as orc
@@ -280,6 +345,8 @@ def main():
                       not args.no_autotune)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
         out["fp64_launch"] = r64["launch"]
+    if not args.no_law:
+        out["law"] = law_runs(torch, pd, 200)
     if not args.no_serve:
         from paper_1806_06917_amd import inputs
         budget = int(args.serve_budget_gib * (1 << 30))
