@@ -85,6 +85,11 @@ def lib():
         L.or_verlet_law.restype = None
         L.or_verlet_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32,
                                     ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
+        L.or_lps.restype = None
+        L.or_lps.argtypes = [i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, ptr, ptr, ptr, ptr, ptr]
+        L.or_verlet_lps.restype = None
+        L.or_verlet_lps.argtypes = [i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, ptr, ptr, ptr, i64,
+                                    dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -302,6 +307,47 @@ class LawMesh(Mesh):
                                 int(maxit), int(max_outer), C.byref(o), C.byref(i),
                                 C.byref(rel))
         return u, {"status": st, "outer": o.value, "inner": i.value, "relres": rel.value}
+
+
+def lps_moduli(E, nu):
+    """Bulk and shear modulus of an isotropic solid."""
+    return E / (3.0 * (1.0 - 2.0 * nu)), E / (2.0 * (1.0 + nu))
+
+
+class LpsMesh(Mesh):
+    """The linear peridynamic solid of Algorithm 2 (3-d), ``or_lps``."""
+
+    def lps(self, u, K, mu, alive=None):
+        """(m, theta, f, W) at the displacement u."""
+        u = _f64(u)
+        m, th, W = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        f = np.zeros_like(self.X)
+        lib().or_lps(self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V), _p(u),
+                     float(K), float(mu), _p(alive), _p(m), _p(th), _p(f), _p(W))
+        return m, th, f, W
+
+    def energy_lps(self, u, K, mu, alive=None):
+        _, _, _, W = self.lps(u, K, mu, alive)
+        return lib().or_potential(self.n, _p(self.V), _p(W))
+
+    def start_lps(self, u0, v0, K, mu, alive=None):
+        alive = self.all_alive() if alive is None else np.ascontiguousarray(alive, np.uint8).copy()
+        u = _f64(u0).copy()
+        v = _f64(v0).copy()
+        f = self.lps(u, K, mu, alive)[2]
+        return {"u": u, "v": v, "f": f, "alive": alive, "step": 0}
+
+    def verlet_lps(self, state, K, mu, rho, dt, nsteps, bc_kind=None, bc_vel=None, b=None,
+                   ramp=0):
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        lib().or_verlet_lps(self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V),
+                            float(rho), float(K), float(mu), _p(bc_kind), _p(bc_vel), _p(b),
+                            int(ramp), float(dt), int(state["step"]), int(nsteps),
+                            _p(state["u"]), _p(state["v"]), _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
 
 
 def num_threads():

@@ -312,19 +312,42 @@ static double or_ramp(double s, int64_t ramp) {
     return r < 1.0 ? r : 1.0;
 }
 
-/* or_verlet_law: the same steps with the force of a general pairwise law  */
-/* (or_force_law); or_verlet is the linearised law (law 0, stretch 0), for  */
-/* which or_force_law and or_force agree bit for bit.                       */
+/* or_verlet_law / or_verlet_lps: the same steps with the force of the     */
+/* general pairwise law (or_force_law) or of the linear peridynamic solid   */
+/* (or_lps); or_verlet is the linearised law (law 0, stretch 0), for which  */
+/* or_force_law and or_force agree bit for bit.                             */
 void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
                   const double *X, const double *V, const double *u, double c, double s_c,
                   int law, double beta, int stretch, uint8_t *alive, double *f, double *U);
+void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
+            const double *V, const double *u, double K, double mu, const uint8_t *alive,
+            double *m, double *theta, double *f, double *W);
 
-void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
-                   const double *X, const double *V, double rho, double c, double s_c,
-                   int law, double beta, int stretch,
-                   const uint8_t *bc_kind, const double *bc_vel, const double *b,
-                   int64_t ramp, double dt, int64_t step0, int64_t nsteps,
-                   double *u, double *v, double *f, uint8_t *alive) {
+typedef struct {
+    int dim, law, stretch;
+    int64_t n;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *X, *V;
+    double c, s_c, beta, K, mu;
+    int lps;
+} or_model;
+
+static void or_model_force(const or_model *md, const double *u, uint8_t *alive, double *f) {
+    if (md->lps)
+        or_lps(md->n, md->row_ptr, md->col, md->X, md->V, u, md->K, md->mu, alive, NULL, NULL,
+               f, NULL);
+    else
+        or_force_law(md->dim, md->n, md->row_ptr, md->col, md->X, md->V, u, md->c, md->s_c,
+                     md->law, md->beta, md->stretch, alive, f, NULL);
+}
+
+static void or_verlet_core(const or_model *md, double rho, const uint8_t *bc_kind,
+                           const double *bc_vel, const double *b, int64_t ramp, double dt,
+                           int64_t step0, int64_t nsteps, double *u, double *v, double *f,
+                           uint8_t *alive) {
+    const int dim = md->dim;
+    const int64_t n = md->n;
     for (int64_t k = step0; k < step0 + nsteps; ++k) {
         double rh = or_ramp((double)k + 0.5, ramp);
         double r1 = or_ramp((double)(k + 1), ramp);
@@ -347,7 +370,7 @@ void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *co
                 }
             }
         }
-        or_force_law(dim, n, row_ptr, col, X, V, u, c, s_c, law, beta, stretch, alive, f, NULL);
+        or_model_force(md, u, alive, f);
         for (int64_t i = 0; i < n; ++i) {
             int kind = bc_kind ? bc_kind[i] : OR_BC_FREE;
             for (int d = 0; d < dim; ++d) {
@@ -363,6 +386,25 @@ void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *co
             }
         }
     }
+}
+
+void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const double *X, const double *V, double rho, double c, double s_c,
+                   int law, double beta, int stretch,
+                   const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                   int64_t ramp, double dt, int64_t step0, int64_t nsteps,
+                   double *u, double *v, double *f, uint8_t *alive) {
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0};
+    or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
+}
+
+void or_verlet_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
+                   const double *V, double rho, double K, double mu, const uint8_t *bc_kind,
+                   const double *bc_vel, const double *b, int64_t ramp, double dt,
+                   int64_t step0, int64_t nsteps, double *u, double *v, double *f,
+                   uint8_t *alive) {
+    or_model md = {3, 0, 0, n, row_ptr, col, X, V, 0.0, 0.0, 0.0, K, mu, 1};
+    or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
 void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -704,6 +746,112 @@ int or_solve_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
     if (relres) *relres = rel;
     free(r); free(du); free(res); free(p); free(q);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear peridynamic solid, Algorithm 2 (3-d, influence function 1), with  */
+/* the bulk and shear moduli K and mu:                                       */
+/*   m_i     = sum_j |xi|^2 V_j                       (weighted volume)     */
+/*   e       = |xi + eta| - |xi|                      (extension)           */
+/*   theta_i = (3/m_i) sum_j |xi| e V_j               (dilatation)          */
+/*   e^d     = e - theta_i |xi|/3                                           */
+/*   t       = (3/m_i) K theta_i |xi| + (15 mu/m_i) e^d                     */
+/*   M       = (xi + eta)/|xi + eta|                                        */
+/*   f_i += t M V_j  and  f_j -= t M V_i   over every bond (i, j) of i      */
+/* The force loop is the paper's scatter, run sequentially.  The strain     */
+/* energy density (the paper's energy line is garbled; this is the LPS      */
+/* energy of the cited state-based theory, of which t is the derivative):   */
+/*   W_i = (K/2) theta_i^2 + (15 mu/(2 m_i)) sum_j (e^d)^2 V_j              */
+/* Bonds with alive[p] == 0 are left out of every sum.  A node without      */
+/* bonds has m = theta = 0 and no force.  Any output may be NULL.           */
+/* ------------------------------------------------------------------------ */
+void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
+            const double *V, const double *u, double K, double mu, const uint8_t *alive,
+            double *m_out, double *theta_out, double *f, double *W) {
+    double *m = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *th = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double mi = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (alive && !alive[p]) continue;
+            int64_t j = col[p];
+            double r2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double x = X[j * 3 + k] - X[i * 3 + k];
+                r2 = r2 + x * x;
+            }
+            mi = mi + r2 * V[j];
+        }
+        m[i] = mi;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            if (alive && !alive[p]) continue;
+            int64_t j = col[p];
+            double r2 = 0.0, y2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double x = X[j * 3 + k] - X[i * 3 + k];
+                double y = x + (u[j * 3 + k] - u[i * 3 + k]);
+                r2 = r2 + x * x;
+                y2 = y2 + y * y;
+            }
+            double len = sqrt(r2);
+            double e = sqrt(y2) - len;
+            s = s + len * e * V[j];
+        }
+        th[i] = m[i] > 0.0 ? 3.0 / m[i] * s : 0.0;
+    }
+    if (f) {
+        for (int64_t q = 0; q < 3 * n; ++q) f[q] = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(m[i] > 0.0)) continue;
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                if (alive && !alive[p]) continue;
+                int64_t j = col[p];
+                double xi[3], y[3], r2 = 0.0, y2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    xi[k] = X[j * 3 + k] - X[i * 3 + k];
+                    y[k] = xi[k] + (u[j * 3 + k] - u[i * 3 + k]);
+                    r2 = r2 + xi[k] * xi[k];
+                    y2 = y2 + y[k] * y[k];
+                }
+                double len = sqrt(r2), ylen = sqrt(y2);
+                double e = ylen - len;
+                double ed = e - th[i] * len / 3.0;
+                double t = 3.0 / m[i] * K * th[i] * len + 15.0 * mu / m[i] * ed;
+                for (int k = 0; k < 3; ++k) {
+                    double Mk = y[k] / ylen;
+                    f[i * 3 + k] = f[i * 3 + k] + t * Mk * V[j];
+                    f[j * 3 + k] = f[j * 3 + k] - t * Mk * V[i];
+                }
+            }
+        }
+    }
+    if (W) {
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+                if (alive && !alive[p]) continue;
+                int64_t j = col[p];
+                double r2 = 0.0, y2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double x = X[j * 3 + k] - X[i * 3 + k];
+                    double y = x + (u[j * 3 + k] - u[i * 3 + k]);
+                    r2 = r2 + x * x;
+                    y2 = y2 + y * y;
+                }
+                double len = sqrt(r2);
+                double ed = (sqrt(y2) - len) - th[i] * len / 3.0;
+                s = s + ed * ed * V[j];
+            }
+            W[i] = m[i] > 0.0 ? 0.5 * K * th[i] * th[i] + 15.0 * mu / (2.0 * m[i]) * s : 0.0;
+        }
+    }
+    if (m_out) for (int64_t i = 0; i < n; ++i) m_out[i] = m[i];
+    if (theta_out) for (int64_t i = 0; i < n; ++i) theta_out[i] = th[i];
+    free(m);
+    free(th);
 }
 
 int or_num_threads(void) {
