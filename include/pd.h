@@ -97,12 +97,24 @@ typedef struct pd_server_s *pd_server;
  *              PD_STRETCH_EXACT  S = (|xi+eta| - |xi|)/|xi| along the
  *                             deformed bond, e = (xi+eta)/|xi+eta|.
  *   beta       PD_LAW_NP only: beta > 0.
+ *   law = PD_LAW_LPS  the linear peridynamic solid of Algorithm 2 (dim 3,
+ *              influence function 1, bulk modulus `bulk` > 0 and shear
+ *              modulus `shear` >= 0; c, beta and stretch are not used).  Per
+ *              node m_i = sum |xi|^2 V_j and theta_i = (3/m_i) sum |xi| e V_j
+ *              with the extension e = |xi+eta| - |xi|; the bond force state
+ *              t = (3/m_i) K theta_i |xi| + (15 mu/m_i)(e - theta_i |xi|/3)
+ *              along M = (xi+eta)/|xi+eta|, summed as the gather
+ *              f_i = sum_j (t_ij + t_ji) M V_j (the paper's scatter read from
+ *              node i; it needs symmetric bond flags, as cut and damage
+ *              flags are); energy W_i = (K/2) theta_i^2 +
+ *              (15 mu/(2 m_i)) sum (e - theta_i |xi|/3)^2 V_j.  No damage
+ *              (s_c must be <= 0), no tangent or implicit solve.
  * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
  * tiled kernels run that law; any other combination runs on the gather
  * kernel (pd_sim_info kernel 1), and the tangent and the implicit solve take
- * the linearised stretch only (PD_EINVAL otherwise).
+ * the linearised stretch of a pairwise law only (PD_EINVAL otherwise).
  */
-enum { PD_LAW_LINEAR = 0, PD_LAW_NP = 1 };
+enum { PD_LAW_LINEAR = 0, PD_LAW_NP = 1, PD_LAW_LPS = 2 };
 enum { PD_STRETCH_LINEARISED = 0, PD_STRETCH_EXACT = 1 };
 
 typedef struct {
@@ -114,6 +126,8 @@ typedef struct {
     int law;
     int stretch;
     double beta;
+    double bulk;
+    double shear;
 } pd_material;
 
 typedef struct {

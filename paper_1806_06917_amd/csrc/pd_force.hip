@@ -65,6 +65,34 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                                              ujy - uiy, duz, cVj, !live, s64))
                     a.alive[p] = 0;
             }
+        } else if (DIM == 3 && a.law == PD_LAW_LPS) {
+            // linear peridynamic solid: the scatter of the paper read from
+            // node i, f_i = sum_j (t_ij + t_ji) M V_j, with {m, theta} of
+            // both ends from the state pass
+            const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
+            const double ci = si.x > 0.0 ? 3.0 * a.bulk * si.y / si.x : 0.0;
+            const double di = si.x > 0.0 ? 15.0 * a.shear / si.x : 0.0;
+            for (uint32_t p = rs + lane; p < re; p += L) {
+                const uint32_t j = (uint32_t)a.col[p];
+                const bool live = !a.alive || a.alive[p];
+                const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+                double ujx, ujy, ujz;
+                load_vec<DIM>(a.u, j, ujx, ujy, ujz);
+                const double dxx = xj.x - xix, dxy = xj.y - xiy, dxz = xj.z - xiz;
+                const double dux = ujx - uix, duy = ujy - uiy, duz = ujz - uiz;
+                double len, e, iy;
+                lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
+                const double2 sj = reinterpret_cast<const double2 *>(a.lps)[j];
+                const double cj = sj.x > 0.0 ? 3.0 * a.bulk * sj.y / sj.x : 0.0;
+                const double dj = sj.x > 0.0 ? 15.0 * a.shear / sj.x : 0.0;
+                const double edi = e - si.y * len / 3.0, edj = e - sj.y * len / 3.0;
+                const double t = (ci * len + di * edi) + (cj * len + dj * edj);
+                const double g = live ? t * xj.w * iy : 0.0;
+                s64.x = fma(g, dxx + dux, s64.x);
+                s64.y = fma(g, dxy + duy, s64.y);
+                s64.z = fma(g, dxz + duz, s64.z);
+                if (WANT_E) s64.e += live ? edi * edi * xj.w : 0.0;
+            }
         } else {
             // general law; the tangent's linearisation point, if any
             const bool lin = tangent && a.u_lin;
@@ -91,10 +119,73 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
     double fx, fy, fz, Ue;
     group_reduce<DIM, L, WANT_E>(s64, fx, fy, fz, Ue);
     if (!valid || lane != 0) return;
+    if (WANT_E && DIM == 3 && a.law == PD_LAW_LPS) {
+        const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
+        Ue = si.x > 0.0 ? 0.5 * a.bulk * si.y * si.y + 7.5 * a.shear / si.x * Ue : 0.0;
+    }
     double vx = 0, vy = 0, vz = 0;
     if (mode_reads_v(a.mode)) load_vec<DIM>(a.v, i, vx, vy, vz);
     const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
     node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i, vx, vy, vz, kind);
+}
+
+// Linear peridynamic solid, first pass (Algorithm 2, weighted volume and
+// dilatation): per node m_i = sum |xi|^2 V_j and theta_i = (3/m_i) sum |xi| e V_j
+// over live bonds, stored as {m, theta} in a.lps.
+template <int L, bool MIXED>
+__global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
+    const uint32_t tile = pd_xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = (tile * PD_BLOCK + threadIdx.x) / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool valid = i < a.n;
+    double m = 0.0, s = 0.0;
+    if (valid) {
+        const double4 q = reinterpret_cast<const double4 *>(a.xv)[i];
+        double uix, uiy, uiz;
+        load_vec<3>(a.u, i, uix, uiy, uiz);
+        for (uint32_t p = a.row_ptr[i] + lane; p < a.row_ptr[i + 1]; p += L) {
+            if (a.alive && !a.alive[p]) continue;
+            const uint32_t j = (uint32_t)a.col[p];
+            const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+            double ujx, ujy, ujz;
+            load_vec<3>(a.u, j, ujx, ujy, ujz);
+            double len, e, iy;
+            lps_bond<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
+                            ujz - uiz, len, e, iy);
+            m += len * len * xj.w;
+            s += len * e * xj.w;
+        }
+    }
+#pragma unroll
+    for (int k = L / 2; k > 0; k >>= 1) {
+        m += __shfl_xor(m, k, L);
+        s += __shfl_xor(s, k, L);
+    }
+    if (valid && lane == 0)
+        reinterpret_cast<double2 *>(a.lps)[i] = make_double2(m, m > 0.0 ? 3.0 / m * s : 0.0);
+}
+
+template <int L>
+int launch_lps_l(pd_ctx ctx, const NodeArgs &a, bool mixed) {
+    const unsigned grid = pd_blocks((uint64_t)a.n * L);
+    if (grid == 0) return PD_OK;
+    if (mixed) lps_state_k<L, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    else lps_state_k<L, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+int launch_lps_state(pd_ctx ctx, const NodeArgs &a, int lanes, bool mixed) {
+    switch (lanes) {
+    case 1: return launch_lps_l<1>(ctx, a, mixed);
+    case 2: return launch_lps_l<2>(ctx, a, mixed);
+    case 4: return launch_lps_l<4>(ctx, a, mixed);
+    case 8: return launch_lps_l<8>(ctx, a, mixed);
+    case 16: return launch_lps_l<16>(ctx, a, mixed);
+    case 32: return launch_lps_l<32>(ctx, a, mixed);
+    case 64: return launch_lps_l<64>(ctx, a, mixed);
+    default: return pd_set_error(ctx, PD_EINVAL, "unsupported lane count %d", lanes);
+    }
 }
 
 // notch pre-crack: orientation tests in float64 without contraction, end
@@ -260,6 +351,8 @@ int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed,
         return pd_launch_tile(ctx, nbr->dim, a, lanes, mixed, block);
     }
     a.bw = nullptr;
+    // the solid's state pass at the same displacement, then the force pass
+    if (nbr->dim == 3 && a.law == PD_LAW_LPS) PD_TRY(launch_lps_state(ctx, a, lanes, mixed));
     return pd_launch_gather(ctx, nbr->dim, a, lanes, mixed);
 }
 
@@ -284,6 +377,8 @@ NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
     a.law = mat->law;
     a.stretch = mat->stretch;
     a.beta = mat->beta;
+    a.bulk = mat->bulk;
+    a.shear = mat->shear;
     return a;
 }
 
@@ -342,6 +437,10 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     a.f_out = nbr->s_f;
     a.e_out = U ? nbr->s_U : nullptr;
     a.mode = M_FORCE;
+    if (mat->law == PD_LAW_LPS) {
+        if (!nbr->s_lps) PD_TRY(pd_alloc(ctx, &nbr->s_lps, (size_t)nbr->n * 2));
+        a.lps = nbr->s_lps;
+    }
     PD_TRY(launch_node(ctx, nbr, a, lanes, mat->precision == PD_MIXED, block));
     PD_TRY(pd_scatter_vec(ctx, nbr, nbr->s_f, f));
     if (U) PD_TRY(pd_scatter_scalar(ctx, nbr, nbr->s_U, U));
@@ -395,8 +494,9 @@ static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const d
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
-    if (mat->stretch != PD_STRETCH_LINEARISED)
-        return pd_set_error(ctx, PD_EINVAL, "the tangent takes the linearised stretch only");
+    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS)
+        return pd_set_error(ctx, PD_EINVAL,
+                            "the tangent takes a pairwise law with the linearised stretch only");
     PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
     PD_TRY(pd_check_dev_ptr(ctx, V, "V"));
     PD_TRY(pd_check_dev_ptr(ctx, w, "w"));
@@ -455,6 +555,7 @@ static void sim_release(pd_sim s) {
     pd_free(s->scratch);
     pd_free(s->rec[0]);
     pd_free(s->rec[1]);
+    pd_free(s->lps);
     if (s->nbr && s->tiled) s->nbr->users -= 1;
     pd_ctx ctx = s->ctx;
     pd_nbr nbr = s->nbr;
@@ -538,6 +639,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (st == PD_OK) st = pd_alloc(ctx, &s->scratch, 2 * n);
     if (st == PD_OK && bc_vel) st = pd_alloc(ctx, &s->bc_vel, n * us);
     if (st == PD_OK && b) st = pd_alloc(ctx, &s->b, n * us);
+    if (st == PD_OK && mat->law == PD_LAW_LPS) st = pd_alloc(ctx, &s->lps, n * 2);
     if (st == PD_OK) st = pd_gather_xv(ctx, nbr, X, V, s->xv);
     if (st == PD_OK) st = pd_gather_vec(ctx, nbr, u0, s->u[0], true);
     if (st == PD_OK) st = pd_gather_vec(ctx, nbr, v0, s->v, true);
@@ -604,6 +706,7 @@ static NodeArgs sim_args(pd_sim s) {
     a.bc_vel = s->bc_vel;
     a.b = s->b;
     a.flag = s->ctx->flag;
+    a.lps = s->lps;
     return a;
 }
 

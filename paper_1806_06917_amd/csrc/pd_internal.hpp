@@ -82,6 +82,7 @@ struct pd_nbr_s {
     // scratch for the stateless entry points (pd_internal_force, pd_apply_tangent)
     double *s_xv = nullptr, *s_u = nullptr, *s_f = nullptr, *s_U = nullptr;
     double *s_ulin = nullptr;    // linearisation point of the NP tangent
+    double *s_lps = nullptr;     // {m, theta} per node of the peridynamic solid
     uint8_t *s_alive = nullptr, *s_fixed = nullptr;
 };
 
@@ -103,6 +104,7 @@ struct pd_sim_s {
     double cv_uniform = 0.0;     // c V if all volumes are equal, else 0
     bool bw_newer = false;       // bw holds damage not yet copied to alive
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
+    double *lps = nullptr;       // [n][2] {m, theta} (linear peridynamic solid)
     int64_t step = 0;
     int64_t ramp = 0;
     double last_dt = 0;

@@ -46,6 +46,9 @@ struct NodeArgs {
     int law, stretch;
     double beta;
     const double *__restrict__ u_lin;
+    // linear peridynamic solid: moduli and {m, theta} per node ([n][2], sfc)
+    double bulk, shear;
+    double *__restrict__ lps;
 };
 
 // per-lane FP64 running sums of the bond forces (and bond energies)
@@ -79,6 +82,16 @@ __device__ __forceinline__ double rsqrt_pos(double r2) {
     return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
+// Dot products with a fixed fused order, a.x*b.x first, then each further
+// product fused into the sum: every kernel rounds a bond's arithmetic the
+// same way whatever the compiler's contraction choices around it (the tile,
+// streamed and gather kernels must agree bit for bit).
+template <int DIM>
+__device__ __forceinline__ double dotf(double ax, double ay, double az, double bx, double by,
+                                       double bz) {
+    return DIM == 3 ? fma(az, bz, fma(ay, by, ax * bx)) : fma(ay, by, ax * bx);
+}
+
 // One bond: xi = X_j - X_i, eta = u_j - u_i, cVj = c V_j; `dead` marks a bond
 // broken earlier; damage on/off and the critical stretch s_c.  Returns true if the bond breaks now (S > s_c); a bond that
 // is dead or breaks now contributes exact zeros.  Otherwise adds
@@ -90,16 +103,16 @@ template <int DIM, bool MIXED, bool WANT_E>
 __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double dxy, double dxz,
                                      double dux, double duy, double duz, double cVj, bool dead,
                                      Acc64 &s) {
-    const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
-    const double ex = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+    const double r2 = dotf<DIM>(dxx, dxy, dxz, dxx, dxy, dxz);
+    const double ex = dotf<DIM>(dux, duy, duz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double S = ex * (inv * inv);
     const bool brk = damage && S > s_c;
     const bool off = brk || dead;
     const double g = off ? 0.0 : cVj * S * inv;
-    s.x += g * dxx;
-    s.y += g * dxy;
-    if (DIM == 3) s.z += g * dxz;
+    s.x = fma(g, dxx, s.x);
+    s.y = fma(g, dxy, s.y);
+    if (DIM == 3) s.z = fma(g, dxz, s.z);
     if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
     return brk && !dead;
 }
@@ -119,31 +132,35 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
                                          double dxz, double dux, double duy, double duz,
                                          double dlx, double dly, double dlz, double cVj,
                                          bool dead, Acc64 &s) {
-    const double r2 = DIM == 3 ? dxx * dxx + dxy * dxy + dxz * dxz : dxx * dxx + dxy * dxy;
+    const double r2 = dotf<DIM>(dxx, dxy, dxz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double len = r2 * inv;
     const bool np = law == PD_LAW_NP;
     if (tangent) {
-        const double el = DIM == 3 ? dlx * dxx + dly * dxy + dlz * dxz : dlx * dxx + dly * dxy;
+        const double el = dotf<DIM>(dlx, dly, dlz, dxx, dxy, dxz);
         const double Su = el * (inv * inv);
         const double r = len * Su * Su;
         const double k = np ? exp(-beta * r) * (1.0 - 2.0 * beta * r) : 1.0;
-        const double ew = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+        const double ew = dotf<DIM>(dux, duy, duz, dxx, dxy, dxz);
         const double g = dead ? 0.0 : cVj * k * (ew * (inv * inv)) * inv;
-        s.x += g * dxx;
-        s.y += g * dxy;
-        if (DIM == 3) s.z += g * dxz;
+        s.x = fma(g, dxx, s.x);
+        s.y = fma(g, dxy, s.y);
+        if (DIM == 3) s.z = fma(g, dxz, s.z);
         return false;
     }
     double S, ex, ey, ez;
     if (stretch == PD_STRETCH_EXACT) {
+        // S = (|xi+eta| - |xi|)/|xi| in the cancellation-free form
+        // (2 xi.eta + eta.eta)/((|xi+eta| + |xi|) |xi|)
         const double yx = dxx + dux, yy = dxy + duy, yz = DIM == 3 ? dxz + duz : 0.0;
-        const double y2 = DIM == 3 ? yx * yx + yy * yy + yz * yz : yx * yx + yy * yy;
+        const double y2 = dotf<DIM>(yx, yy, yz, yx, yy, yz);
         const double iy = MIXED ? __builtin_amdgcn_rsq(y2) : rsqrt_pos(y2);
-        S = (y2 * iy - len) * inv;
+        const double xe = dotf<DIM>(dxx, dxy, dxz, dux, duy, duz);
+        const double ee = dotf<DIM>(dux, duy, duz, dux, duy, duz);
+        S = (2.0 * xe + ee) / (y2 * iy + len) * inv;
         ex = yx * iy; ey = yy * iy; ez = yz * iy;
     } else {
-        const double e_ = DIM == 3 ? dux * dxx + duy * dxy + duz * dxz : dux * dxx + duy * dxy;
+        const double e_ = dotf<DIM>(dux, duy, duz, dxx, dxy, dxz);
         S = e_ * (inv * inv);
         ex = dxx * inv; ey = dxy * inv; ez = dxz * inv;
     }
@@ -152,11 +169,29 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
     const double r = len * S * S;
     const double phi = np ? exp(-beta * r) : 1.0;
     const double g = off ? 0.0 : cVj * phi * S;
-    s.x += g * ex;
-    s.y += g * ey;
-    if (DIM == 3) s.z += g * ez;
+    s.x = fma(g, ex, s.x);
+    s.y = fma(g, ey, s.y);
+    if (DIM == 3) s.z = fma(g, ez, s.z);
     if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * (np ? -expm1(-beta * r) / beta : r);
     return brk && !dead;
+}
+
+// Linear peridynamic solid: bond length |xi|, extension e = |xi+eta| - |xi|
+// in the cancellation-free form (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), and
+// 1/|xi+eta| (the direction M = (xi+eta)/|xi+eta|).
+template <bool MIXED>
+__device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, double dux,
+                                         double duy, double duz, double &len, double &e,
+                                         double &iy) {
+    const double r2 = dotf<3>(dxx, dxy, dxz, dxx, dxy, dxz);
+    const double yx = dxx + dux, yy = dxy + duy, yz = dxz + duz;
+    const double y2 = dotf<3>(yx, yy, yz, yx, yy, yz);
+    const double ix = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
+    iy = MIXED ? __builtin_amdgcn_rsq(y2) : rsqrt_pos(y2);
+    len = r2 * ix;
+    const double xe = dotf<3>(dxx, dxy, dxz, dux, duy, duz);
+    const double ee = dotf<3>(dux, duy, duz, dux, duy, duz);
+    e = (2.0 * xe + ee) / (y2 * iy + len);
 }
 
 // xor butterfly over the L lanes of a group: every lane ends with the sum

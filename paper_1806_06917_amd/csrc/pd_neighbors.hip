@@ -307,6 +307,7 @@ static void nbr_release(pd_nbr b) {
     pd_free(b->s_f);
     pd_free(b->s_U);
     pd_free(b->s_ulin);
+    pd_free(b->s_lps);
     pd_free(b->s_alive);
     pd_free(b->s_fixed);
     pd_ctx ctx = b->ctx;

@@ -163,8 +163,16 @@ extern "C" const char *pd_last_error(pd_ctx ctx) {
 }
 
 int pd_check_law(pd_ctx ctx, const pd_material *m) {
-    if (m->law != PD_LAW_LINEAR && m->law != PD_LAW_NP)
-        return pd_set_error(ctx, PD_EINVAL, "law must be PD_LAW_LINEAR or PD_LAW_NP");
+    if (m->law != PD_LAW_LINEAR && m->law != PD_LAW_NP && m->law != PD_LAW_LPS)
+        return pd_set_error(ctx, PD_EINVAL, "law must be PD_LAW_LINEAR, PD_LAW_NP or PD_LAW_LPS");
+    if (m->law == PD_LAW_LPS) {
+        if (m->dim != 3) return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS is the 3-d solid");
+        if (!(m->bulk > 0.0) || !std::isfinite(m->bulk) || !(m->shear >= 0.0) ||
+            !std::isfinite(m->shear))
+            return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS needs bulk > 0 and shear >= 0");
+        if (m->s_c > 0.0) return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS takes no damage");
+        return PD_OK;
+    }
     if (m->stretch != PD_STRETCH_LINEARISED && m->stretch != PD_STRETCH_EXACT)
         return pd_set_error(ctx, PD_EINVAL,
                             "stretch must be PD_STRETCH_LINEARISED or PD_STRETCH_EXACT");

@@ -31,7 +31,8 @@ class PDError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [("dim", C.c_int), ("precision", C.c_int), ("c", C.c_double),
                 ("rho", C.c_double), ("s_c", C.c_double), ("law", C.c_int),
-                ("stretch", C.c_int), ("beta", C.c_double)]
+                ("stretch", C.c_int), ("beta", C.c_double), ("bulk", C.c_double),
+                ("shear", C.c_double)]
 
 
 class Request(C.Structure):
@@ -212,20 +213,23 @@ class Context:
             pass
 
 
-PD_LAW_LINEAR, PD_LAW_NP = 0, 1
+PD_LAW_LINEAR, PD_LAW_NP, PD_LAW_LPS = 0, 1, 2
 PD_STRETCH_LINEARISED, PD_STRETCH_EXACT = 0, 1
 
 
 def material(dim, c, rho=1.0, s_c=0.0, precision="fp64", law="linear", beta=0.0,
-             stretch="linearised"):
-    """law: "linear" | "np" (psi(r) = C (1 - exp(-beta r))); stretch:
-    "linearised" | "exact"."""
+             stretch="linearised", bulk=0.0, shear=0.0):
+    """law: "linear" | "np" (psi(r) = C (1 - exp(-beta r))) | "lps" (the
+    3-d linear peridynamic solid with moduli bulk, shear; c unused);
+    stretch: "linearised" | "exact"."""
     prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
-    lw = {"linear": PD_LAW_LINEAR, "np": PD_LAW_NP}[law] if isinstance(law, str) else int(law)
+    lw = {"linear": PD_LAW_LINEAR, "np": PD_LAW_NP, "lps": PD_LAW_LPS}[law] \
+        if isinstance(law, str) else int(law)
     sk = {"linearised": PD_STRETCH_LINEARISED, "exact": PD_STRETCH_EXACT}[stretch] \
         if isinstance(stretch, str) else int(stretch)
-    return Material(int(dim), prec, float(c), float(rho), float(s_c), lw, sk, float(beta))
+    return Material(int(dim), prec, float(c), float(rho), float(s_c), lw, sk, float(beta),
+                    float(bulk), float(shear))
 
 
 class Neighbors:

@@ -1,0 +1,113 @@
+"""GPU parity of the linear peridynamic solid (Algorithm 2, 3-d) against the
+FP64 oracle: the two-pass gather (state pass, then f_i = sum (t_ij + t_ji) M V_j)
+against the oracle's literal scatter, the strain energy, and explicit steps.
+Bars: rel-L2 1e-12 in FP64, 1e-5 mixed."""
+import numpy as np
+import pytest
+
+from conftest import say
+from paper_1806_06917_amd import inputs
+from test_gpu_parity import TOL64, TOLMIX, dev, host, read_state, relL2
+
+pytestmark = pytest.mark.gpu
+
+
+def cube(orc, N, seed, m=3):
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * 3, h, jitter=0.05, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    V = h ** 3 * rng.uniform(0.8, 1.2, X.shape[0])
+    return X, V, m * h, orc.LpsMesh(X, V, m * h)
+
+
+def symmetric_dead(mesh, frac, seed):
+    """Bond flags with a random set of bonds cut in both directions."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    alive = np.ones(mesh.nnz, np.uint8)
+    i = np.repeat(np.arange(mesh.n), np.diff(mesh.row_ptr))
+    j = mesh.col.astype(np.int64)
+    cut = (rng.uniform(size=mesh.nnz) < frac) & (i < j)
+    for p in np.nonzero(cut)[0]:
+        a, b = i[p], j[p]
+        q = mesh.row_ptr[b] + np.searchsorted(mesh.col[mesh.row_ptr[b]:mesh.row_ptr[b + 1]], a)
+        alive[p] = 0
+        alive[q] = 0
+    return alive
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dead", [0.0, 0.05])
+def test_lps_force_energy_parity(gpu, orc, prec, dead):
+    torch, pd, ctx = gpu
+    X, V, delta, mesh = cube(orc, 14, 101)
+    K, mu = orc.lps_moduli(1.0, 0.3)
+    u = inputs.random_field(mesh.n, 3, 102, scale=1e-3 / 14)
+    alive = symmetric_dead(mesh, dead, 103)
+    _, _, ref_f, ref_W = mesh.lps(u, K, mu, alive)
+    say("LPS force", prec, dead)
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    mat = pd.material(3, 0.0, 1.0, 0.0, prec, law="lps", bulk=K, shear=mu)
+    f = torch.zeros((mesh.n, 3), dtype=torch.float64, device="cuda")
+    W = torch.zeros(mesh.n, dtype=torch.float64, device="cuda")
+    pd.internal_force(ctx, nb, mat, dev(torch, X), dev(torch, V), dev(torch, u), f,
+                      alive=dev(torch, alive), U=W)
+    torch.cuda.synchronize()
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(host(f), ref_f) <= tol
+    assert relL2(host(W), ref_W) <= tol
+    nb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lps_explicit_steps(gpu, orc, prec):
+    torch, pd, ctx = gpu
+    X, V, delta, mesh = cube(orc, 10, 105)
+    K, mu = orc.lps_moduli(1.0, 0.3)
+    v0 = inputs.random_field(mesh.n, 3, 106, scale=1e-2)
+    dt = 0.02 / 10
+    st = mesh.start_lps(np.zeros_like(v0), v0, K, mu)
+    mesh.verlet_lps(st, K, mu, 1.0, dt, 30)
+    say("LPS steps", prec)
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    mat = pd.material(3, 0.0, 1.0, 0.0, prec, law="lps", bulk=K, shear=mu)
+    sim = pd.Simulation(ctx, nb, mat, dev(torch, X), dev(torch, V), None, dev(torch, v0))
+    assert sim.info()["kernel"] == "gather"
+    sim.step(30, dt)
+    u, v, _, info = read_state(torch, sim, mesh.n, 3, nb.nnz)
+    sim.close()
+    nb.close()
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert info["step"] == 30
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
+    ke = mesh.kinetic(st["v"], 1.0)
+    pe = mesh.energy_lps(st["u"], K, mu)
+    assert abs(info["ke"] - ke) <= 10 * tol * ke
+    assert abs(info["pe"] - pe) <= 10 * tol * pe
+
+
+def test_lps_argument_errors(gpu):
+    torch, pd, ctx = gpu
+    X2 = inputs.grid_coords((8, 8), 1.0 / 8)
+    nb2 = pd.Neighbors(ctx, dev(torch, X2), 3.0 / 8)
+    y2 = torch.zeros((64, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(pd.PDError) as e:                   # the solid is 3-d
+        pd.internal_force(ctx, nb2, pd.material(2, 0.0, law="lps", bulk=1.0, shear=1.0),
+                          dev(torch, X2), dev(torch, np.full(64, 1 / 64.0)), y2, y2)
+    assert e.value.status == pd.PD_EINVAL
+    nb2.close()
+    X = inputs.grid_coords((6, 6, 6), 1.0 / 6)
+    n = X.shape[0]
+    Xd, Vd = dev(torch, X), dev(torch, np.full(n, 1 / 216.0))
+    nb = pd.Neighbors(ctx, Xd, 2.0 / 6)
+    y = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    for bad in (pd.material(3, 0.0, law="lps", bulk=0.0, shear=1.0),
+                pd.material(3, 0.0, s_c=1e-3, law="lps", bulk=1.0, shear=1.0)):
+        with pytest.raises(pd.PDError) as e:
+            pd.internal_force(ctx, nb, bad, Xd, Vd, y, y)
+        assert e.value.status == pd.PD_EINVAL
+    lps = pd.material(3, 0.0, law="lps", bulk=1.0, shear=1.0)
+    with pytest.raises(pd.PDError) as e:
+        pd.apply_tangent(ctx, nb, lps, Xd, Vd, y, torch.zeros_like(y))
+    assert e.value.status == pd.PD_EINVAL
+    nb.close()
