@@ -8,8 +8,9 @@ resident in HBM before the timed region; the neighbour build is one-off and
 reported separately.  Both precisions compute in float64; "mixed" takes 1/|xi|
 from the hardware reciprocal-square-root estimate without refinement.
 
-Then (unless --no-law) the NP pairwise law: explicit steps on the notched
-512^2 plate and the Newton-Krylov solve of the 400 x 40 bar ("law" object).
+Then (unless --no-law) the other material laws: NP explicit steps on the
+notched 512^2 plate, linear-peridynamic-solid steps on the cube, and the NP
+Newton-Krylov solve of the 400 x 40 bar ("law" object).
 Then (unless --no-serve) the serving workload: independent notched-plate
 requests through pd_server_* under a device-memory budget, first all at
 once (saturated throughput), then with Poisson arrivals at a fraction of that
@@ -208,8 +209,9 @@ def serve(pd, reqs, budget, chunk, rate=None):
 
 
 def law_runs(torch, pd, steps):
-    """The general pairwise law (gather kernel): NP explicit steps on the
-    notched 512^2 plate, and the NP Newton-Krylov solve of the 400 x 40 bar
+    """The other material laws (gather kernel): NP explicit steps on the
+    notched 512^2 plate, linear-peridynamic-solid steps (two passes per step)
+    on the 1M-node cube, and the NP Newton-Krylov solve of the 400 x 40 bar
     (beta set so that beta |xi| S^2 reaches 0.1 at the linear solution)."""
     from paper_1806_06917_amd import inputs
     out = {}
@@ -237,6 +239,30 @@ def law_runs(torch, pd, steps):
         out[f"np_step_{prec}"] = {"workload": w.name, "ms_per_step": ms,
                                   "bond_evals_per_s": nb.nnz / (ms * 1e-3),
                                   "launch": sim.info(), "beta": 1e3}
+        sim.close()
+    nb.close()
+    wc = inputs.CONFIGS["cube100"]()
+    progress("linear peridynamic solid, explicit steps,", wc.name)
+    Xc = dev(torch, wc.X)
+    nb = pd.Neighbors(ctx, Xc, wc.delta)
+    K, mu = wc.E / (3 * (1 - 2 * 0.25)), wc.E / (2 * (1 + 0.25))
+    for prec in ("mixed", "fp64"):
+        mat = pd.material(3, 0.0, wc.rho, 0.0, prec, law="lps", bulk=K, shear=mu)
+        sim = pd.Simulation(ctx, nb, mat, Xc, dev(torch, wc.V), dev(torch, wc.u0),
+                            dev(torch, wc.v0), bc_kind=dev(torch, wc.bc_kind),
+                            bc_vel=dev(torch, wc.bc_vel), ramp_steps=wc.ramp_steps)
+        sim.step(5, wc.dt)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(ctx.stream)
+        sim.step(steps // 4, wc.dt)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (steps // 4)
+        out[f"lps_step_{prec}"] = {"workload": wc.name, "ms_per_step": ms,
+                                   "bond_evals_per_s": nb.nnz / (ms * 1e-3),
+                                   "launch": sim.info(), "nu": 0.25}
         sim.close()
     nb.close()
     wb = inputs.CONFIGS["bar400x40"]()
