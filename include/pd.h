@@ -110,9 +110,11 @@ typedef struct pd_server_s *pd_server;
  *              (15 mu/(2 m_i)) sum (e - theta_i |xi|/3)^2 V_j.  No damage
  *              (s_c must be <= 0), no tangent or implicit solve.
  * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
- * tiled kernels run that law; any other combination runs on the gather
- * kernel (pd_sim_info kernel 1), and the tangent and the implicit solve take
- * the linearised stretch of a pairwise law only (PD_EINVAL otherwise).
+ * tiled kernels run that law, and the streamed step kernel also the NP law
+ * with the linearised stretch and no damage (its other calls then run on the
+ * gather kernel); every other combination runs on the gather kernel
+ * (pd_sim_info kernel 1).  The tangent and the implicit solve take the
+ * linearised stretch of a pairwise law only (PD_EINVAL otherwise).
  */
 enum { PD_LAW_LINEAR = 0, PD_LAW_NP = 1, PD_LAW_LPS = 2 };
 enum { PD_STRETCH_LINEARISED = 0, PD_STRETCH_EXACT = 1 };
@@ -351,7 +353,7 @@ int pd_sim_destroy(pd_sim sim);
  * dt[k] (host arrays of length nsims); it then stands exactly where
  * pd_verlet_step(sims[k], steps[k], dt[k]) would have left it, bit for bit.
  * Every simulation must run the streamed step kernel (pd_sim_info kernel 3)
- * on b's context, with one dim, precision, lane count and tile size.  The
+ * on b's context, with one dim, precision, law, lane count and tile size.  The
  * call is asynchronous on the context's stream.  A batch handle holds the
  * descriptor buffer (each simulation's state at the start of the chunk,
  * uploaded by every call) and the captured graph (whose k-th launch carries
@@ -385,8 +387,8 @@ int pd_batch_destroy(pd_batch b);
  *   hbm_budget (continuous batching:
  *   requests join the running set as memory frees up), advances every running
  *   simulation by up to chunk_steps steps in batched launches (one per group
- *   of simulations with the same dimension, lane count, tile size and
- *   precision; a chunk whose
+ *   of simulations with the same dimension, lane count, tile size,
+ *   precision and law; a chunk whose
  *   set of simulations did not change since the last round replays a
  *   captured hipGraph), and retires those that reached their step count,
  *   freeing their memory.  A result is bit for bit the same as the request

@@ -604,9 +604,15 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
     const pd_tune_entry *te = nullptr;
-    const bool general = pd_general_law(mat);     // gather kernel only
+    // the NP law without damage also runs on the streamed kernel (its other
+    // calls, and every other general law, on the gather kernel)
+    const bool np_stream = mat->law == PD_LAW_NP && mat->stretch == PD_STRETCH_LINEARISED &&
+                           !(mat->s_c > 0.0);
+    const bool general = pd_general_law(mat) && !np_stream;
     if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);
+    if (np_stream && ctx->kernel == 2)
+        return pd_set_error(ctx, PD_ECAPACITY, "the LDS tile kernel takes the linearised law only");
     if (general) {
         if (ctx->kernel == 2 || ctx->kernel == 3)
             return pd_set_error(ctx, PD_ECAPACITY, "the tiled kernels take the linearised law only");
@@ -654,7 +660,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "notch_k", __FILE__, __LINE__);
     }
     s->lanes = lanes;
-    s->block = block;
+    s->block = np_stream ? 0 : block;      // the tile kernel for the other calls
     if (st == PD_OK && block > 0) {
         s->tiled = true;
         nbr->users += 1;
@@ -669,7 +675,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (st == PD_OK && s->tiled && s->cv_uniform != 0.0 && (ctx->kernel == 0 || ctx->kernel == 3) &&
         pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
         pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false,
+                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false, np_stream,
                            &s->s_block, &s->s_grid, &s->s_mmax, &s->s_lds)) {
         const size_t rd = nbr->dim == 3 ? 6 : 4;
         st = pd_alloc(ctx, &s->rec[0], n * rd);
@@ -731,6 +737,7 @@ StreamInst pd_stream_inst(const pd_sim s) {
     d.s_c = s->mat.s_c;
     d.rho = s->mat.rho;
     d.damage = s->mat.s_c > 0.0;
+    d.beta = s->mat.beta;
     d.ramp = s->ramp;
     return d;
 }
@@ -789,7 +796,8 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
         for (int64_t k = 0; k < nsteps; ++k) {
             sa.step = k;
             PD_TRY(pd_launch_stream(ctx, ctx->stream, nbr->dim, sa, sim->lanes, mixed,
-                                    sim->s_block, sim->s_grid, sim->s_lds));
+                                    sim->mat.law == PD_LAW_NP, sim->s_block, sim->s_grid,
+                                    sim->s_lds));
         }
         pd_sim_advanced(sim, nsteps, dt);
         return PD_OK;
@@ -889,9 +897,9 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
 
 extern "C" int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes) {
     if (!sim) return PD_EINVAL;
-    if (kernel) *kernel = sim->stream ? 3 : (sim->tiled ? 2 : 1);
-    if (tile) *tile = sim->tiled ? (int)sim->nbr->tile_T : 0;
-    if (block) *block = sim->stream ? sim->s_block : (sim->tiled ? sim->block : PD_BLOCK);
+    if (kernel) *kernel = sim->stream ? 3 : (sim->tiled && sim->block > 0 ? 2 : 1);
+    if (tile) *tile = sim->stream || (sim->tiled && sim->block > 0) ? (int)sim->nbr->tile_T : 0;
+    if (block) *block = sim->stream ? sim->s_block : (sim->block > 0 ? sim->block : PD_BLOCK);
     if (lanes) *lanes = sim->lanes;
     return PD_OK;
 }

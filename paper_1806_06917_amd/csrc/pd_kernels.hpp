@@ -99,21 +99,25 @@ __device__ __forceinline__ double dotf(double ax, double ay, double az, double b
 // Everything runs in float64; mixed precision takes 1/|xi| from the hardware
 // reciprocal-square-root estimate alone (relative error below 2^-22), the
 // FP64 mode refines it to full double precision.
-template <int DIM, bool MIXED, bool WANT_E>
+// With NP the force carries the factor exp(-beta r), r = |xi| S^2, of the
+// NP potential (linearised stretch; the streamed kernel's NP form).
+template <int DIM, bool MIXED, bool WANT_E, bool NP = false>
 __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double dxy, double dxz,
                                      double dux, double duy, double duz, double cVj, bool dead,
-                                     Acc64 &s) {
+                                     Acc64 &s, double beta = 0.0) {
     const double r2 = dotf<DIM>(dxx, dxy, dxz, dxx, dxy, dxz);
     const double ex = dotf<DIM>(dux, duy, duz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double S = ex * (inv * inv);
     const bool brk = damage && S > s_c;
     const bool off = brk || dead;
-    const double g = off ? 0.0 : cVj * S * inv;
+    double g = off ? 0.0 : cVj * S * inv;
+    if (NP) g *= exp(-beta * ((r2 * inv) * S * S));
     s.x = fma(g, dxx, s.x);
     s.y = fma(g, dxy, s.y);
     if (DIM == 3) s.z = fma(g, dxz, s.z);
-    if (WANT_E) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
+    if (WANT_E && !NP) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
+    if (WANT_E && NP) s.e += off ? 0.0 : 0.25 * cVj * (-expm1(-beta * ((r2 * inv) * S * S)) / beta);
     return brk && !dead;
 }
 
@@ -327,6 +331,7 @@ struct StreamInst {
     const double *b;
     uint32_t n, tile_begin;     // nodes; first tile in the batch numbering
     double cv, s_c, rho, dt;
+    double beta;                // NP law (launches of the NP kernel only)
     int damage, cur0, vhalf0, pad;
     int64_t ramp, step0, limit;
 };
@@ -356,11 +361,11 @@ bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, ui
 
 // (batch: the kernel form that reads descriptors from device memory)
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, int *block,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, bool np, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds);
 bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total);
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const pdk::StreamArgs &sa, int lanes,
-                     bool mixed, int block, unsigned grid, size_t lds);
+                     bool mixed, bool np, int block, unsigned grid, size_t lds);
 // a simulation's streamed descriptor (static part), the launch arguments of a
 // batch shaped like it (inst NULL: single-simulation form), and its host state
 // after streamed steps

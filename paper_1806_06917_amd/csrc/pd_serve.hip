@@ -2,7 +2,7 @@
 // in arrival order while their device memory fits a budget, advanced
 // together (continuous batching: one batched launch per step covers every
 // running simulation of a launch group -- same dimension, lane count, tile
-// size and precision -- and simulations that arrive while others run join at
+// size, precision and law -- and simulations that arrive while others run join at
 // the next chunk), retired as soon as they reach their step count.
 //
 // Host code only; the GPU work is pd_build_neighbors, pd_sim_create and
@@ -75,8 +75,8 @@ int64_t estimate(const Req &r) {
 }  // namespace
 
 // simulations that can share one streamed launch: dim, lanes, tile size,
-// precision
-using GroupKey = std::tuple<int, int, uint32_t, int>;
+// precision, law
+using GroupKey = std::tuple<int, int, uint32_t, int, int>;
 
 struct Group {
     pd_batch batch = nullptr;
@@ -340,7 +340,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         const pd_sim m = r->sim;
         if (m->stream) {
             Chunk &c = chunks[GroupKey(m->nbr->dim, m->lanes, m->nbr->tile_T,
-                                       (int)m->mat.precision)];
+                                       (int)m->mat.precision, m->mat.law)];
             c.sims.push_back(m);
             c.steps.push_back(k);
             c.dts.push_back(r->dt);

@@ -86,6 +86,7 @@ __device__ __forceinline__ StreamInst load_inst(const StreamInst *base, uint32_t
     d.s_c = p->s_c;
     d.rho = p->rho;
     d.dt = p->dt;
+    d.beta = p->beta;
     d.damage = p->damage;
     d.cur0 = p->cur0;
     d.vhalf0 = p->vhalf0;
@@ -145,7 +146,7 @@ __device__ __forceinline__ double ramp_of(double s, int64_t ramp) {
 
 // BATCH = false: one simulation whose descriptor travels in the kernel
 // arguments (sa.one); true: sa.ninst descriptors in device memory.
-template <int DIM, int L, bool MIXED, bool BATCH>
+template <int DIM, int L, bool MIXED, bool BATCH, bool NP>
 __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     extern __shared__ __attribute__((aligned(16))) double lds[];
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         double *out = cur ? I.rec[0] : I.rec[1];
         const int mode = (s > 0 || I.vhalf0) ? M_STEP_CONT : M_STEP_FIRST;
         const double r_half = ramp_of((double)(I.step0 + s) + 0.5, I.ramp);
-        const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho;
+        const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho, beta = I.beta;
         const int damage = I.damage;
         uint16_t *w16 = reinterpret_cast<uint16_t *>(words);
         uint32_t *bl = blist(k);
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     dxx = c0.x - xix; dxy = c0.y - xiy; dxz = 0.0;
                     dux = c1.x - uix; duy = c1.y - uiy; duz = 0.0;
                 }
-                if (bond<DIM, MIXED, false>(damage, s_c, dxx, dxy, dxz, dux, duy, duz, cv,
-                                            (w & BW_DEAD) != 0, acc)) {
+                if (bond<DIM, MIXED, false, NP>(damage, s_c, dxx, dxy, dxz, dux, duy, duz, cv,
+                                                (w & BW_DEAD) != 0, acc, beta)) {
                     const uint32_t nw = (uint32_t)(w | BW_DEAD);
                     w16[p] = (uint16_t)nw;
                     const uint32_t e = atomicAdd(bl, 1u);
@@ -373,14 +374,18 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
 }
 
 template <int DIM>
-void *pick_stream(int lanes, bool mixed, bool batch) {
+void *pick_np(int lanes, bool mixed, bool batch);
+
+template <int DIM>
+void *pick_stream(int lanes, bool mixed, bool batch, bool np) {
+    if (np) return pick_np<DIM>(lanes, mixed, batch);
 #define PD_SK(Lv)                                                                          \
     case Lv:                                                                               \
         if (batch)                                                                         \
-            return mixed ? (void *)stream_kernel<DIM, Lv, true, true>                      \
-                         : (void *)stream_kernel<DIM, Lv, false, true>;                    \
-        return mixed ? (void *)stream_kernel<DIM, Lv, true, false>                         \
-                     : (void *)stream_kernel<DIM, Lv, false, false>;
+            return mixed ? (void *)stream_kernel<DIM, Lv, true, true, false>               \
+                         : (void *)stream_kernel<DIM, Lv, false, true, false>;             \
+        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, false>                  \
+                     : (void *)stream_kernel<DIM, Lv, false, false, false>;
     switch (lanes) {
         PD_SK(2)
         PD_SK(4)
@@ -390,6 +395,27 @@ void *pick_stream(int lanes, bool mixed, bool batch) {
     default: return nullptr;
     }
 #undef PD_SK
+}
+
+// the NP-law instances of the streamed kernel
+template <int DIM>
+void *pick_np(int lanes, bool mixed, bool batch) {
+#define PD_SKN(Lv)                                                                         \
+    case Lv:                                                                               \
+        if (batch)                                                                         \
+            return mixed ? (void *)stream_kernel<DIM, Lv, true, true, true>                \
+                         : (void *)stream_kernel<DIM, Lv, false, true, true>;              \
+        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, true>                   \
+                     : (void *)stream_kernel<DIM, Lv, false, false, true>;
+    switch (lanes) {
+        PD_SKN(2)
+        PD_SKN(4)
+        PD_SKN(8)
+        PD_SKN(16)
+        PD_SKN(32)
+    default: return nullptr;
+    }
+#undef PD_SKN
 }
 
 // records {x y z ux uy uz} (2-d {x y ux uy}) from xv and u
@@ -417,14 +443,14 @@ __global__ void rec_unpack_k(uint32_t n, const double *rec, double *u) {
 // Launch geometry of the streamed kernel for ntiles tiles in total; false if
 // it cannot run this layout.
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, int *block,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, bool np, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds) {
     const uint32_t B = tile * (uint32_t)lanes;
     if (B < 64 || B > 1024 || B % 64 != 0) return false;
     if (lanes < dim) return false;   // the node update takes one lane per component
     if (bcap >= (1u << 16)) return false;   // 16-bit tile-local bond positions
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch)
-                       : pick_stream<2>(lanes, mixed, batch);
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, np)
+                       : pick_stream<2>(lanes, mixed, batch, np);
     if (!k) return false;
     for (int pass = 0; pass < 2; ++pass) {
         // first pass: one workgroup per CU gives the tile bound; second pass:
@@ -472,10 +498,10 @@ bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total) {
 }
 
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const StreamArgs &sa, int lanes,
-                     bool mixed, int block, unsigned grid, size_t lds) {
+                     bool mixed, bool np, int block, unsigned grid, size_t lds) {
     const bool batch = sa.inst != nullptr;
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch)
-                       : pick_stream<2>(lanes, mixed, batch);
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, np)
+                       : pick_stream<2>(lanes, mixed, batch, np);
     if (!k) return pd_set_error(ctx, PD_EINVAL, "streamed kernel needs 2..32 lanes");
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     StreamArgs args = sa;

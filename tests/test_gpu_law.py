@@ -96,7 +96,9 @@ def test_law_explicit_steps(gpu, orc, law, stretch, prec):
                       beta=beta, stretch=stretch)
     sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
                         dev(torch, w.v0))
-    assert sim.info()["kernel"] == "gather"
+    # the NP law (linearised stretch, no damage) runs on the streamed kernel
+    assert sim.info()["kernel"] == ("stream" if (law, stretch) == ("np", "linearised")
+                                    else "gather")
     sim.step(40, w.dt)
     u, v, _, info = read_state(torch, sim, w.n, 2, nb.nnz)
     sim.close()
@@ -187,8 +189,74 @@ def test_law_argument_errors(gpu):
     ctx.set_tuning("stream", 0, 0)
     try:
         with pytest.raises(pd.PDError) as e:
+            pd.Simulation(ctx, nb, pd.material(2, c, law="np", beta=1.0, stretch="exact"), X, V)
+        assert e.value.status == pd.PD_ECAPACITY
+    finally:
+        ctx.set_tuning(0, 0, 0)
+    ctx.set_tuning("tile", 0, 0)
+    try:
+        with pytest.raises(pd.PDError) as e:
             pd.Simulation(ctx, nb, pd.material(2, c, law="np", beta=1.0), X, V)
         assert e.value.status == pd.PD_ECAPACITY
     finally:
         ctx.set_tuning(0, 0, 0)
     nb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_np_stream_equals_gather_within_tolerance_and_batches(gpu, orc, prec):
+    """The NP law on the streamed kernel against the same law forced onto the
+    gather kernel and against the oracle, and NP simulations batched in one
+    launch equal the same simulations stepped alone, bit for bit."""
+    torch, pd, ctx = gpu
+    ws = [inputs.plate_2d(N, 3, seed=s, steps=0) for N, s in ((36, 4), (28, 5))]
+    for k, w in enumerate(ws):
+        w.v0 = inputs.random_field(w.n, 2, 110 + k, scale=5e-2)
+    beta = 2e4
+    ctx.set_lanes(4)
+    try:
+        alone, sims = [], []
+        for k, w in enumerate(ws):
+            nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+            mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, 0.0, prec, law="np",
+                              beta=beta)
+            s = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), None,
+                              dev(torch, w.v0))
+            assert s.info()["kernel"] == "stream"
+            s.step(30, w.dt)
+            alone.append(read_state(torch, s, w.n, 2, nb.nnz)[:2])
+            s.close()
+            sims.append((nb, pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), None,
+                                           dev(torch, w.v0))))
+        say("NP batch", prec)
+        b = pd.Batch(ctx)
+        b.step([s for _, s in sims], [30, 30], [w.dt for w in ws], 30)
+        b.close()
+        for (nb, s), w, ref in zip(sims, ws, alone):
+            got = read_state(torch, s, w.n, 2, nb.nnz)[:2]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+            s.close()
+        # the same law on the gather kernel, and the oracle
+        w = ws[0]
+        ctx.set_tuning("gather", 0, 0)
+        nb, _ = sims[0]
+        mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, 0.0, prec, law="np",
+                          beta=beta)
+        s = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), None, dev(torch, w.v0))
+        assert s.info()["kernel"] == "gather"
+        s.step(30, w.dt)
+        gat = read_state(torch, s, w.n, 2, nb.nnz)[:2]
+        s.close()
+    finally:
+        ctx.set_lanes(0)
+        ctx.set_tuning(0, 0, 0)
+    for nb, _ in sims:
+        nb.close()
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    st = mesh.start_law(w.u0, w.v0, c, orc.LAW_NP, beta)
+    mesh.verlet_law(st, c, w.rho, 0.0, w.dt, 30, orc.LAW_NP, beta)
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    for got in (alone[0], gat):
+        assert relL2(got[0], st["u"]) <= tol
+        assert relL2(got[1], st["v"]) <= tol
