@@ -100,7 +100,10 @@ __device__ __forceinline__ double dotf(double ax, double ay, double az, double b
 // reciprocal-square-root estimate alone (relative error below 2^-22), the
 // FP64 mode refines it to full double precision.
 // With NP the force carries the factor exp(-beta r), r = |xi| S^2, of the
-// NP potential (linearised stretch; the streamed kernel's NP form).
+// NP potential (linearised stretch; the streamed kernel's NP form).  Mixed
+// precision takes the factor from the hardware float32 exp2 (relative error
+// about 1e-7 for the exponents that matter; the factor underflows to 0 below
+// exp(-87), where the bond carries no force anyway).
 template <int DIM, bool MIXED, bool WANT_E, bool NP = false>
 __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double dxy, double dxz,
                                      double dux, double duy, double duz, double cVj, bool dead,
@@ -112,7 +115,10 @@ __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double 
     const bool brk = damage && S > s_c;
     const bool off = brk || dead;
     double g = off ? 0.0 : cVj * S * inv;
-    if (NP) g *= exp(-beta * ((r2 * inv) * S * S));
+    if (NP) {
+        const double x = -beta * ((r2 * inv) * S * S);
+        g *= MIXED ? (double)__builtin_amdgcn_exp2f((float)(x * 1.4426950408889634)) : exp(x);
+    }
     s.x = fma(g, dxx, s.x);
     s.y = fma(g, dxy, s.y);
     if (DIM == 3) s.z = fma(g, dxz, s.z);
