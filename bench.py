@@ -90,6 +90,10 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-law", action="store_true",
                     help="skip the NP-law measurements (explicit steps, Newton-Krylov)")
+    ap.add_argument("--convergence", action="store_true",
+                    help="run only the 2-d convergence study (LP and NP, both initial "
+                         "conditions, t = 0..2) and print its rates")
+    ap.add_argument("--convergence-t", type=float, default=2.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="built-in launch heuristics instead of the autotuner's choice")
     ap.add_argument("--serve-count", type=int, default=256)
@@ -294,6 +298,61 @@ def law_runs(torch, pd, steps):
     return out
 
 
+def convergence(torch, pd, law, ic, t_end=2.0, every=0.25, chunk=500):
+    """The paper's 2-d convergence study on the GPU: the plate with the
+    clamped collar at h = delta/2, delta/4, delta/8, stepped together in
+    batched launches; at every checkpoint the rate
+    alpha = (log||u1 - u2|| - log||u2 - u3||) / log 2, the norms over [0,1]^2
+    on the coarser grid of each pair (finer solution averaged onto it)."""
+    from paper_1806_06917_amd import inputs
+    ws = [inputs.convergence_plate(m, ic) for m in (2, 4, 8)]
+    delta = ws[0].delta
+    c = 4.0 / (np.pi * delta ** 3)          # 4 psi'(0)/(delta |B_delta|), psi'(0) = C beta = 1
+    ctx = pd.Context(0)
+    ctx.set_lanes(8)              # one launch shape for the three meshes
+    ctx.set_tuning("auto", 64, 0)
+    made = []
+    for w in ws:
+        nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+        mat = pd.material(2, c, 1.0, 0.0, "fp64", law=law, beta=1.0)
+        sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                            dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                            bc_vel=dev(torch, w.bc_vel))
+        made.append((nb, sim))
+    sims = [s for _, s in made]
+    batch = pd.Batch(ctx)
+    dt = ws[0].dt
+    per = int(round(every / dt))
+    rows = []
+    t0 = time.perf_counter()
+    step = 0
+    while step * dt < t_end - 1e-12:
+        for _ in range(per // chunk):
+            batch.step(sims, [chunk] * 3, [dt] * 3, chunk)
+        step += per
+        us = []
+        for w, (nb, s) in zip(ws, made):
+            u = torch.zeros((w.n, 2), dtype=torch.float64, device="cuda")
+            s.get(u)
+            us.append(u.cpu().numpy())
+        norms = []
+        for k in range(2):
+            N = ws[k].shape[0]
+            d = us[k] - inputs.coarsen(us[k + 1], N)
+            inside = ws[k].bc_kind == inputs.BC_FREE
+            norms.append(float(np.sqrt(np.sum(d[inside] ** 2) * ws[k].h ** 2)))
+        rows.append({"t": round(step * dt, 6), "diff12": norms[0], "diff23": norms[1],
+                     "alpha": float(np.log(norms[0] / norms[1]) / np.log(2.0))})
+    secs = time.perf_counter() - t0
+    batch.close()
+    for nb, s in made:
+        s.close()
+        nb.close()
+    ctx.close()
+    return {"law": law, "ic": ic, "steps": step, "dt": dt, "seconds": secs,
+            "nodes": [w.n for w in ws], "rates": rows}
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle, as it stands, on the same workload for a few steps."""
     from oracle import oracle as orc
@@ -331,6 +390,15 @@ def main():
 
     from paper_1806_06917_amd import inputs
     from paper_1806_06917_amd import pd
+
+    if args.convergence:
+        res = []
+        for law in ("linear", "np"):
+            for ic in (1, 2):
+                progress("convergence study", law, "IC", ic)
+                res.append(convergence(torch, pd, law, ic, args.convergence_t))
+        print(json.dumps({"validation": "2-d convergence study", "runs": res}), flush=True)
+        return
 
     w = inputs.CONFIGS[args.config]()
     precision = args.precision or ("mixed" if args.config == "cube100" else "fp64")
@@ -387,6 +455,16 @@ def main():
             "burst": burst, "poisson": dict(poisson, rate_per_s=rate, load=args.serve_load),
             "p50_s": poisson["p50_s"], "p99_s": poisson["p99_s"],
             "bond_evals_per_s": poisson["bond_evals_per_s"]}
+    if not args.no_law:
+        runs = []
+        for law, ic in (("linear", 1), ("np", 2)):
+            progress("convergence study", law, "IC", ic)
+            r = convergence(torch, pd, law, ic, args.convergence_t)
+            runs.append({"law": law, "ic": ic, "seconds": r["seconds"], "steps": r["steps"],
+                         "alpha": [round(x["alpha"], 3) for x in r["rates"]],
+                         "t": [x["t"] for x in r["rates"]]})
+        out["validation"] = {"study": "2-d convergence, h = delta/2, delta/4, delta/8",
+                             "runs": runs}
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (60 if w.n > 100000 else 200)
         out["cpu_baseline"] = cpu_baseline(w, steps)

@@ -176,6 +176,43 @@ def bar_2d(nx=400, ny=40, m=3, traction=1e-3, clamp_cols=3):
         u0=np.zeros((n, 2)), b=b, fixed=fixed, traction=traction)
 
 
+# Initial conditions of the paper's 2-d convergence study: a Gaussian pulse
+# exp(-|X - x_c|^2 / b) (a1, a2), zero velocity.
+CONVERGENCE_ICS = {
+    1: {"a": (0.001, 0.0), "xc": (0.5, 0.5), "b": 0.003},
+    2: {"a": (0.0002, 0.0007), "xc": (0.25, 0.25), "b": 0.01},
+}
+
+
+def convergence_plate(m, ic, delta=0.1):
+    """The 2-d convergence study: material domain [0,1]^2 with the nonlocal
+    collar [-delta, 1+delta]^2 - [0,1]^2 clamped (u = 0), h = delta/m on a
+    cell-centred grid of the whole square (so meshes with m and 2m nest: each
+    coarse cell holds 2 x 2 fine cells), rho = 1, dt = 1e-5, initial
+    displacement from CONVERGENCE_ICS[ic] inside [0,1]^2."""
+    h = delta / m
+    N = int(round((1.0 + 2.0 * delta) / h))
+    X = grid_coords((N, N), h) - delta
+    n = X.shape[0]
+    inside = np.all((X > 0.0) & (X < 1.0), axis=1)
+    kind = np.where(inside, BC_FREE, BC_CLAMPED).astype(np.uint8)
+    p = CONVERGENCE_ICS[ic]
+    g = np.exp(-np.sum((X - np.array(p["xc"])) ** 2, axis=1) / p["b"])
+    u0 = np.zeros((n, 2))
+    u0[inside] = g[inside, None] * np.array(p["a"])[None, :]
+    return Workload(
+        name=f"convergence2d_m{m}_ic{ic}", dim=2, shape=(N, N), h=h, X=X,
+        V=np.full(n, h * h), delta=delta, E=1.0, rho=1.0, s_c=0.0, dt=1e-5,
+        steps=200000, u0=u0, v0=np.zeros((n, 2)), bc_kind=kind, bc_vel=np.zeros((n, 2)))
+
+
+def coarsen(u, N):
+    """Average of the 2 x 2 fine cells under each coarse cell (x fastest
+    cell-centred grids of N and 2N per side)."""
+    f = u.reshape(2 * N, 2 * N, -1)           # [y][x][component]
+    return 0.25 * (f[0::2, 0::2] + f[1::2, 0::2] + f[0::2, 1::2] + f[1::2, 1::2]).reshape(N * N, -1)
+
+
 def random_cloud(n, dim, seed, box=1.0):
     """Uniform random points in [0, box)^dim (for neighbour-search checks)."""
     rng = np.random.Generator(np.random.PCG64(seed))
