@@ -90,6 +90,9 @@ def lib():
         L.or_verlet_lps.restype = None
         L.or_verlet_lps.argtypes = [i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, ptr, ptr, ptr, i64,
                                     dbl, i64, i64, ptr, ptr, ptr, ptr]
+        L.or_central_law.restype = None
+        L.or_central_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32,
+                                     ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -282,6 +285,21 @@ class LawMesh(Mesh):
                             int(stretch), _p(bc_kind), _p(bc_vel), _p(b), int(ramp), float(dt),
                             int(state["step"]), int(nsteps), _p(state["u"]), _p(state["v"]),
                             _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
+
+    def central_law(self, state, c, rho, s_c, dt, nsteps, law=LAW_LINEAR, beta=1.0,
+                    stretch=STRETCH_LINEARISED, bc_kind=None, bc_vel=None, b=None, ramp=0):
+        """Central-difference steps (first step velocity Verlet), in place."""
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        lib().or_central_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                             _p(self.V), float(rho), float(c), float(s_c), int(law),
+                             float(beta), int(stretch), _p(bc_kind), _p(bc_vel), _p(b),
+                             int(ramp), float(dt), int(state["step"]), int(nsteps),
+                             _p(state["u"]), _p(state["v"]), _p(state["f"]),
+                             _p(state["alive"]))
         state["step"] += nsteps
         return state
 

@@ -388,6 +388,73 @@ static void or_verlet_core(const or_model *md, double rho, const uint8_t *bc_kin
     }
 }
 
+/* Central-difference scheme (the finite-difference equation of Section      */
+/* "Explicit time integration"): for free nodes                             */
+/*   u^{k+1} = 2 u^k - u^{k-1} + dt^2/rho (f^k + b),                         */
+/* boundary nodes as in the velocity-Verlet steps.  The paper gives no      */
+/* starting rule: the first step is one velocity-Verlet step from (u, v),   */
+/* which is the Taylor start u^1 = u^0 + dt v^0 + dt^2/(2 rho)(f^0 + b).    */
+/* On return u = u^N, f = f^N and, for free nodes, v = v^N =                */
+/* (u^N - u^{N-1})/dt + dt/(2 rho)(f^N + b), the velocity-Verlet velocity.  */
+static void or_central_core(const or_model *md, double rho, const uint8_t *bc_kind,
+                            const double *bc_vel, const double *b, int64_t ramp, double dt,
+                            int64_t step0, int64_t nsteps, double *u, double *v, double *f,
+                            uint8_t *alive) {
+    const int dim = md->dim;
+    const int64_t n = md->n, m = n * dim;
+    if (nsteps <= 0) return;
+    double *up = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
+    for (int64_t q = 0; q < m; ++q) up[q] = u[q];
+    or_verlet_core(md, rho, bc_kind, bc_vel, b, ramp, dt, step0, 1, u, v, f, alive);
+    for (int64_t k = step0 + 1; k < step0 + nsteps; ++k) {
+        double rh = or_ramp((double)k + 0.5, ramp);
+        for (int64_t i = 0; i < n; ++i) {
+            int kind = bc_kind ? bc_kind[i] : OR_BC_FREE;
+            for (int d = 0; d < dim; ++d) {
+                int64_t q = i * dim + d;
+                double un;
+                if (kind == OR_BC_CLAMPED) {
+                    un = 0.0;
+                } else if (kind == OR_BC_VELOCITY) {
+                    un = u[q] + dt * (rh * bc_vel[q]);
+                } else {
+                    double bq = b ? b[q] : 0.0;
+                    un = 2.0 * u[q] - up[q] + dt * dt * (f[q] + bq) / rho;
+                }
+                up[q] = u[q];
+                u[q] = un;
+            }
+        }
+        or_model_force(md, u, alive, f);
+    }
+    double r1 = or_ramp((double)(step0 + nsteps), ramp);
+    for (int64_t i = 0; i < n; ++i) {
+        int kind = bc_kind ? bc_kind[i] : OR_BC_FREE;
+        for (int d = 0; d < dim; ++d) {
+            int64_t q = i * dim + d;
+            if (kind == OR_BC_CLAMPED) {
+                v[q] = 0.0;
+            } else if (kind == OR_BC_VELOCITY) {
+                v[q] = r1 * bc_vel[q];
+            } else if (nsteps > 1) {
+                double bq = b ? b[q] : 0.0;
+                v[q] = (u[q] - up[q]) / dt + (0.5 * dt) * (f[q] + bq) / rho;
+            }
+        }
+    }
+    free(up);
+}
+
+void or_central_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *X, const double *V, double rho, double c, double s_c,
+                    int law, double beta, int stretch, const uint8_t *bc_kind,
+                    const double *bc_vel, const double *b, int64_t ramp, double dt,
+                    int64_t step0, int64_t nsteps, double *u, double *v, double *f,
+                    uint8_t *alive) {
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0};
+    or_central_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
+}
+
 void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
                    const double *X, const double *V, double rho, double c, double s_c,
                    int law, double beta, int stretch,
