@@ -329,6 +329,21 @@ int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *
 int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt);
 
 /*
+ * Advance a simulation by nsteps steps of the central-difference scheme
+ * (the finite-difference equation of Section "Explicit time integration"):
+ *   u^{k+1} = 2 u^k - u^{k-1} + dt^2 (f^k + b)/rho   (free nodes),
+ * boundary data as in pd_verlet_step.  The paper gives no starting rule: the
+ * first step of each call is one velocity-Verlet step from the current
+ * (u, v), the Taylor start u^{k+1} = u^k + dt v^k + dt^2 (f^k + b)/(2 rho).
+ * pd_sim_get then reports v^N = (u^N - u^{N-1})/dt + (dt/2)(f^N + b)/rho.
+ * The scheme equals velocity Verlet in exact arithmetic and differs in
+ * rounding.  Runs on the tile or gather kernel (a simulation on the
+ * streamed kernel hands its state over and takes it back at its next
+ * pd_verlet_step).  Asynchronous; the same dt rule as pd_verlet_step.
+ */
+int pd_central_step(pd_sim sim, int64_t nsteps, double dt);
+
+/*
  * Read the state back (each output may be NULL): u, v device [n][dim],
  * alive device uint8[nnz] (exported order), ke_pe host double[2] =
  * {sum_i rho V_i |v_i|^2 / 2, sum_i V_i U_i}, step host int64.

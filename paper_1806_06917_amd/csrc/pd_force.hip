@@ -840,6 +840,40 @@ static int sim_close(pd_sim sim) {
     return PD_OK;
 }
 
+// Central-difference steps: the first step of the call is a velocity-Verlet
+// step (the scheme's start), the others u^{k+1} = 2 u^k - u^{k-1} + dt^2 a^k
+// with u^{k-1} in the other half of the ping-pong pair.  They run on the
+// tile or gather kernel; a streamed simulation hands its records over first
+// and repacks them before its next streamed step.
+extern "C" int pd_central_step(pd_sim sim, int64_t nsteps, double dt) {
+    if (!sim) return PD_EINVAL;
+    pd_ctx ctx = sim->ctx;
+    PD_TRY(pd_check_ctx(ctx));
+    if (nsteps < 0) return pd_set_error(ctx, PD_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return pd_set_error(ctx, PD_EINVAL, "dt must be > 0");
+    if (sim->v_half && dt != sim->last_dt)
+        return pd_set_error(ctx, PD_EINVAL,
+                            "dt changed mid-trajectory: read the state (pd_sim_get) first");
+    if (nsteps == 0) return PD_OK;
+    PD_TRY(sim_sync_u(sim));
+    NodeArgs a = sim_args(sim);
+    a.dt = dt;
+    const bool mixed = sim->mat.precision == PD_MIXED;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        a.mode = k > 0 ? M_STEP_CD : (sim->v_half ? M_STEP_CONT : M_STEP_FIRST);
+        a.u = sim->u[sim->cur];
+        a.u_out = sim->u[sim->cur ^ 1];
+        a.r_half = ramp_factor((double)sim->step + 0.5, sim->ramp);
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, mixed, sim->block));
+        sim->cur ^= 1;
+        sim->v_half = true;
+        sim->step += 1;
+    }
+    sim->last_dt = dt;
+    if (sim->stream) sim->rec_stale = true;
+    return PD_OK;
+}
+
 extern "C" int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, double *ke_pe,
                           int64_t *step) {
     if (!sim) return PD_EINVAL;

@@ -8,7 +8,10 @@
 
 namespace pdk {
 
-enum Mode { M_FORCE = 0, M_STEP_FIRST = 1, M_STEP_CONT = 2, M_CLOSE = 3, M_ENERGY = 4, M_TANGENT = 5 };
+enum Mode {
+    M_FORCE = 0, M_STEP_FIRST = 1, M_STEP_CONT = 2, M_CLOSE = 3, M_ENERGY = 4, M_TANGENT = 5,
+    M_STEP_CD = 6   // central-difference step: u_out holds u^{k-1} on entry
+};
 
 struct NodeArgs {
     const double *__restrict__ xv;     // [n][4]
@@ -277,7 +280,19 @@ __device__ __forceinline__ void node_update(const NodeArgs &a, uint32_t i, doubl
         return;
     }
     double nx, ny, nz;
-    if (kind == PD_BC_FREE) {
+    if (kind == PD_BC_FREE && a.mode == M_STEP_CD) {
+        // u^{k+1} = 2 u^k - u^{k-1} + dt^2 (f + b)/rho; v keeps the half-step
+        // velocity (u^{k+1} - u^k)/dt, which a closing half-kick completes
+        double bx = 0, by = 0, bz = 0, px, py, pz;
+        if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
+        load_vec<DIM>(a.u_out, i, px, py, pz);
+        nx = (2.0 * uix - px) + a.dt * a.dt * (fx + bx) / a.rho;
+        ny = (2.0 * uiy - py) + a.dt * a.dt * (fy + by) / a.rho;
+        nz = (2.0 * uiz - pz) + a.dt * a.dt * (fz + bz) / a.rho;
+        vx = (nx - uix) / a.dt;
+        vy = (ny - uiy) / a.dt;
+        vz = (nz - uiz) / a.dt;
+    } else if (kind == PD_BC_FREE) {
         double bx = 0, by = 0, bz = 0;
         if (a.b) load_vec<DIM>(a.b, i, bx, by, bz);
         if (a.mode == M_STEP_CONT) {   // second half-kick of the previous step

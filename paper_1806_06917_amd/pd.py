@@ -92,6 +92,7 @@ def _load():
         "pd_sim_create": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, vp, vp, i32, i64,
                                 P(vp)]),
         "pd_verlet_step": (i32, [vp, i64, dbl]),
+        "pd_central_step": (i32, [vp, i64, dbl]),
         "pd_sim_get": (i32, [vp, vp, vp, vp, vp, vp]),
         "pd_sim_set": (i32, [vp, vp, vp, vp, i64]),
         "pd_sim_destroy": (i32, [vp]),
@@ -328,6 +329,10 @@ class Simulation:
 
     def step(self, nsteps, dt):
         self.ctx.check(lib.pd_verlet_step(self.h, int(nsteps), float(dt)), "pd_verlet_step")
+
+    def central_step(self, nsteps, dt):
+        """Central-difference steps (the first one of each call velocity Verlet)."""
+        self.ctx.check(lib.pd_central_step(self.h, int(nsteps), float(dt)), "pd_central_step")
 
     def get(self, u=None, v=None, alive=None, energies=False, allow_nonfinite=False):
         kp = np.zeros(2, np.float64)

@@ -1,0 +1,78 @@
+"""GPU parity of the central-difference scheme (finite-difference equation of
+Section "Explicit time integration") against the FP64 oracle: a free plate,
+a plate under prescribed edge velocities, and a streamed simulation that
+switches between the two integrators."""
+import numpy as np
+import pytest
+
+from conftest import say
+from paper_1806_06917_amd import inputs
+from test_gpu_parity import TOL64, TOLMIX, dev, read_state, relL2
+
+pytestmark = pytest.mark.gpu
+
+
+def sim_of(torch, pd, ctx, nb, w, prec, law="linear", beta=0.0):
+    mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, 0.0, prec, law=law, beta=beta)
+    return pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                         dev(torch, w.v0),
+                         bc_kind=dev(torch, w.bc_kind) if w.bc_kind is not None else None,
+                         bc_vel=dev(torch, w.bc_vel) if w.bc_vel is not None else None,
+                         ramp_steps=w.ramp_steps)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["free", "edges", "np"])
+def test_central_parity(gpu, orc, case, prec):
+    torch, pd, ctx = gpu
+    if case == "edges":
+        w = inputs.notched_plate_2d(N=40, m=3, s_c=0.0, v0=2e-3, steps=0, ramp_steps=10)
+        w.notch = np.zeros((0, 4))
+    else:
+        w = inputs.plate_2d(36, 3, seed=6, steps=0)
+        w.v0 = inputs.random_field(w.n, 2, 131, scale=5e-2)
+    law, beta = ("np", 2e4) if case == "np" else ("linear", 0.0)
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    lw = orc.LAW_NP if law == "np" else orc.LAW_LINEAR
+    st = mesh.start_law(w.u0, w.v0, c, lw, beta)
+    mesh.central_law(st, c, w.rho, 0.0, w.dt, 40, lw, beta, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
+                     ramp=w.ramp_steps)
+    say("central", case, prec)
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    sim = sim_of(torch, pd, ctx, nb, w, prec, law, beta)
+    sim.central_step(40, w.dt)
+    u, v, _, info = read_state(torch, sim, w.n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    assert info["step"] == 40
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
+
+
+def test_switching_integrators_on_a_streamed_simulation(gpu, orc):
+    """Verlet (streamed kernel), then central differences (tile kernel), then
+    Verlet again: the state travels between the kernels intact."""
+    torch, pd, ctx = gpu
+    w = inputs.plate_2d(36, 3, seed=7, steps=0)
+    w.v0 = inputs.random_field(w.n, 2, 133, scale=5e-2)
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    st = mesh.start_law(w.u0, w.v0, c, orc.LAW_LINEAR, 1.0)
+    mesh.verlet_law(st, c, w.rho, 0.0, w.dt, 15, orc.LAW_LINEAR, 1.0)
+    mesh.central_law(st, c, w.rho, 0.0, w.dt, 20, orc.LAW_LINEAR, 1.0)
+    mesh.verlet_law(st, c, w.rho, 0.0, w.dt, 15, orc.LAW_LINEAR, 1.0)
+    say("integrator switch")
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    sim = sim_of(torch, pd, ctx, nb, w, "fp64")
+    assert sim.info()["kernel"] == "stream"
+    sim.step(15, w.dt)
+    sim.central_step(20, w.dt)
+    sim.step(15, w.dt)
+    u, v, _, info = read_state(torch, sim, w.n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    assert info["step"] == 50
+    assert relL2(u, st["u"]) <= TOL64
+    assert relL2(v, st["v"]) <= TOL64
