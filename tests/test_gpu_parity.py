@@ -417,6 +417,42 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
 
 
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_notched512_full_size_steps(gpu, orc, prec):
+    """The 512^2 notched plate at full size: notch, collars and damage, with a
+    random initial velocity so that bonds break; 20 steps against the
+    oracle."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["notched512"]()
+    say("notched512 full size", prec)
+    mesh = cached_mesh(orc, "notched512", w)
+    c = orc.micromodulus(2, w.E, w.delta)
+    v0 = inputs.random_field(w.n, 2, 98, scale=2e-2)
+    v0[w.bc_kind == 2] = 0.0
+    alive0 = mesh.notch_cut(w.notch, mesh.all_alive())
+    st = mesh.start(w.u0, v0, c, w.s_c, alive0)
+    band = np.zeros(mesh.nnz, bool)
+    for _ in range(20):
+        band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
+        mesh.verlet(st, c, w.rho, w.s_c, w.dt, 1, w.bc_kind, w.bc_vel, None, w.ramp_steps)
+    band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    w.v0 = v0
+    sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(2, w.E, w.delta), prec)
+    assert sim.info()["kernel"] == "stream"
+    sim.step(20, w.dt)
+    u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    broken = np.count_nonzero(st["alive"] == 0) - np.count_nonzero(alive0 == 0)
+    assert broken > 0
+    assert np.array_equal(a[~band], st["alive"][~band])
+    same = np.array_equal(a, st["alive"])
+    assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
+    assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
+
+
 @pytest.mark.parametrize("wl,prec", [("plate", "fp64"), ("cube", "mixed"), ("cube", "fp64"),
                                      ("notched", "mixed")])
 def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):

@@ -187,3 +187,36 @@ def test_served_too_large(gpu):
     with pytest.raises(pd.PDError):
         srv.info(12345)
     srv.close()
+
+
+def test_served_full_size_requests_equal_alone(gpu):
+    """Requests of the serving workload at full size (the largest of its first
+    twelve plates, up to 512^2 nodes) in the benchmark's configuration
+    (4 lanes, 4 GiB budget, 100-step chunks): each served result equals the
+    request stepped alone, bit for bit.  Steps are cut to 250 per request."""
+    torch, pd, ctx = gpu
+    reqs = sorted(inputs.serving_requests(256)[:12], key=lambda q: -q.N)[:3]
+    ws = []
+    for q in reqs:
+        w = inputs.serving_workload(q)
+        w.steps = 250
+        ws.append(w)
+    srv = pd.Server(ctx, 4 << 30, chunk_steps=100, lanes=4)
+    ids = [_submit(pd, srv, w, "mixed") for w in ws]
+    while srv.pump() != (0, 0):
+        pass
+    got = [srv.result(i, w.n, w.dim) for i, w in zip(ids, ws)]
+    srv.close()
+    ctx.set_lanes(4)
+    try:
+        for w, (gu, gv) in zip(ws, got):
+            say("full-size request alone", w.name)
+            nb, s = _make(torch, pd, ctx, w, "mixed")
+            s.step(w.steps, w.dt)
+            u, v, _, _ = _state(torch, s, w, nb.nnz)
+            s.close()
+            nb.close()
+            assert np.array_equal(gu, u) and np.array_equal(gv, v)
+    finally:
+        ctx.set_lanes(0)
+    assert max(w.n for w in ws) > 200000
