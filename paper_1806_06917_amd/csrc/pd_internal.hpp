@@ -102,7 +102,6 @@ struct pd_sim_s {
     bool tiled = false;          // this simulation runs the tile kernel
     int block = 0;               // its tile-kernel workgroup size (0: gather kernel)
     double cv_uniform = 0.0;     // c V if all volumes are equal, else 0
-    bool bw_newer = false;       // bw holds damage not yet copied to alive
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
     double *lps = nullptr;       // [n][2] {m, theta} (linear peridynamic solid)
     int64_t step = 0;

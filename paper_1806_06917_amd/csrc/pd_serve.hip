@@ -290,12 +290,11 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         const double ta = now_s();
         const int st = admit(s, r);
         s->stats.admit_s += now_s() - ta;
-        s->stats.admitted += 1;
         if (st != PD_OK) {
-            if (st == PD_EDEVICE) return st;
             r->info.state = PD_REQ_FAILED;
             r->info.status = st;
             r->info.t_done = now_s();
+            if (st == PD_EDEVICE) return st;   // the context is unusable from here on
             continue;
         }
         if (s->used + r->info.bytes > s->budget) {
@@ -319,6 +318,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         }
         s->used += r->info.bytes;
         s->peak = std::max(s->peak, s->used);
+        s->stats.admitted += 1;
         r->info.t_admit = now_s();
         r->info.state = PD_REQ_RUNNING;
         s->running.push_back(r);
@@ -369,15 +369,17 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
     const double t_ret = now_s();
     // retire the finished ones
     std::vector<Req *> keep;
+    int dev_err = PD_OK;
     for (Req *r : s->running) {
         if (r->done >= r->nsteps) {
             const int st = retire(s, r);
-            if (st == PD_EDEVICE) return st;
+            if (st == PD_EDEVICE) dev_err = st;
         } else {
             keep.push_back(r);
         }
     }
     s->running.swap(keep);
+    if (dev_err != PD_OK) return dev_err;
     s->stats.retire_s += now_s() - t_ret;
     if (n_running) *n_running = (int)s->running.size();
     if (n_queued) *n_queued = (int)s->queue.size();
