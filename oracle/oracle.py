@@ -93,6 +93,16 @@ def lib():
         L.or_central_law.restype = None
         L.or_central_law.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32,
                                      ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
+        L.or_force_law_pv.restype = None
+        L.or_force_law_pv.argtypes = [i32, i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, i32, dbl, i32,
+                                      dbl, dbl, ptr, ptr, ptr]
+        L.or_lps_pv.restype = None
+        L.or_lps_pv.argtypes = [i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, dbl, dbl, ptr, ptr, ptr,
+                                ptr, ptr]
+        L.or_verlet_pv.restype = None
+        L.or_verlet_pv.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, dbl, i32, dbl, i32,
+                                   dbl, dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr,
+                                   ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -243,19 +253,39 @@ class LawMesh(Mesh):
     linearised or exact stretch (``or_force_law`` and friends)."""
 
     def force_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, s_c=0.0,
-                  alive=None, energy=False):
+                  alive=None, energy=False, pv_h=0.0):
+        """pv_h > 0: partial volumes, the neighbour radius (self.delta) being
+        delta + pv_h/2."""
         u = _f64(u)
         f = np.zeros_like(self.X)
         U = np.zeros(self.n) if energy else None
-        lib().or_force_law(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
-                           _p(self.V), _p(u), float(c), float(s_c), int(law), float(beta),
-                           int(stretch), _p(alive), _p(f), _p(U))
+        lib().or_force_law_pv(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                              _p(self.V), _p(u), float(c), float(s_c), int(law), float(beta),
+                              int(stretch), float(pv_h), self.delta, _p(alive), _p(f), _p(U))
         return (f, U) if energy else f
 
-    def energy_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, alive=None):
+    def energy_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, alive=None,
+                   pv_h=0.0):
         """Total strain energy sum_i V_i U_i."""
-        _, U = self.force_law(u, c, law, beta, stretch, 0.0, alive, energy=True)
+        _, U = self.force_law(u, c, law, beta, stretch, 0.0, alive, energy=True, pv_h=pv_h)
         return lib().or_potential(self.n, _p(self.V), _p(U))
+
+    def verlet_pv(self, state, rho, dt, nsteps, pv_h, lps=False, c=0.0, s_c=0.0, law=LAW_LINEAR,
+                  beta=1.0, stretch=STRETCH_LINEARISED, K=0.0, mu=0.0, bc_kind=None,
+                  bc_vel=None, b=None, ramp=0):
+        """Velocity-Verlet steps with partial volumes, a pairwise law or
+        (lps=True) the peridynamic solid."""
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        lib().or_verlet_pv(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                           _p(self.V), float(rho), int(bool(lps)), float(c), float(s_c), int(law),
+                           float(beta), int(stretch), float(K), float(mu), float(pv_h),
+                           self.delta, _p(bc_kind), _p(bc_vel), _p(b), int(ramp), float(dt),
+                           int(state["step"]), int(nsteps), _p(state["u"]), _p(state["v"]),
+                           _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
 
     def tangent_law(self, w, c, law=LAW_NP, beta=1.0, ulin=None, fixed=None, alive=None):
         w = _f64(w)
@@ -335,17 +365,18 @@ def lps_moduli(E, nu):
 class LpsMesh(Mesh):
     """The linear peridynamic solid of Algorithm 2 (3-d), ``or_lps``."""
 
-    def lps(self, u, K, mu, alive=None):
-        """(m, theta, f, W) at the displacement u."""
+    def lps(self, u, K, mu, alive=None, pv_h=0.0):
+        """(m, theta, f, W) at the displacement u (pv_h > 0: partial volumes)."""
         u = _f64(u)
         m, th, W = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
         f = np.zeros_like(self.X)
-        lib().or_lps(self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V), _p(u),
-                     float(K), float(mu), _p(alive), _p(m), _p(th), _p(f), _p(W))
+        lib().or_lps_pv(self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V), _p(u),
+                        float(K), float(mu), float(pv_h), self.delta, _p(alive), _p(m), _p(th),
+                        _p(f), _p(W))
         return m, th, f, W
 
-    def energy_lps(self, u, K, mu, alive=None):
-        _, _, _, W = self.lps(u, K, mu, alive)
+    def energy_lps(self, u, K, mu, alive=None, pv_h=0.0):
+        _, _, _, W = self.lps(u, K, mu, alive, pv_h)
         return lib().or_potential(self.n, _p(self.V), _p(W))
 
     def start_lps(self, u0, v0, K, mu, alive=None):

@@ -316,12 +316,13 @@ static double or_ramp(double s, int64_t ramp) {
 /* general pairwise law (or_force_law) or of the linear peridynamic solid   */
 /* (or_lps); or_verlet is the linearised law (law 0, stretch 0), for which  */
 /* or_force_law and or_force agree bit for bit.                             */
-void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
-                  const double *X, const double *V, const double *u, double c, double s_c,
-                  int law, double beta, int stretch, uint8_t *alive, double *f, double *U);
-void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
-            const double *V, const double *u, double K, double mu, const uint8_t *alive,
-            double *m, double *theta, double *f, double *W);
+void or_force_law_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     const double *X, const double *V, const double *u, double c, double s_c,
+                     int law, double beta, int stretch, double pv_h, double pv_R,
+                     uint8_t *alive, double *f, double *U);
+void or_lps_pv(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
+               const double *V, const double *u, double K, double mu, double pv_h, double pv_R,
+               const uint8_t *alive, double *m, double *theta, double *f, double *W);
 
 typedef struct {
     int dim, law, stretch;
@@ -331,15 +332,16 @@ typedef struct {
     const double *X, *V;
     double c, s_c, beta, K, mu;
     int lps;
+    double pv_h, pv_R;
 } or_model;
 
 static void or_model_force(const or_model *md, const double *u, uint8_t *alive, double *f) {
     if (md->lps)
-        or_lps(md->n, md->row_ptr, md->col, md->X, md->V, u, md->K, md->mu, alive, NULL, NULL,
-               f, NULL);
+        or_lps_pv(md->n, md->row_ptr, md->col, md->X, md->V, u, md->K, md->mu, md->pv_h,
+                  md->pv_R, alive, NULL, NULL, f, NULL);
     else
-        or_force_law(md->dim, md->n, md->row_ptr, md->col, md->X, md->V, u, md->c, md->s_c,
-                     md->law, md->beta, md->stretch, alive, f, NULL);
+        or_force_law_pv(md->dim, md->n, md->row_ptr, md->col, md->X, md->V, u, md->c, md->s_c,
+                        md->law, md->beta, md->stretch, md->pv_h, md->pv_R, alive, f, NULL);
 }
 
 static void or_verlet_core(const or_model *md, double rho, const uint8_t *bc_kind,
@@ -451,7 +453,7 @@ void or_central_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *c
                     const double *bc_vel, const double *b, int64_t ramp, double dt,
                     int64_t step0, int64_t nsteps, double *u, double *v, double *f,
                     uint8_t *alive) {
-    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0};
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0};
     or_central_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -461,7 +463,7 @@ void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *co
                    const uint8_t *bc_kind, const double *bc_vel, const double *b,
                    int64_t ramp, double dt, int64_t step0, int64_t nsteps,
                    double *u, double *v, double *f, uint8_t *alive) {
-    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0};
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0};
     or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -470,7 +472,20 @@ void or_verlet_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
                    const double *bc_vel, const double *b, int64_t ramp, double dt,
                    int64_t step0, int64_t nsteps, double *u, double *v, double *f,
                    uint8_t *alive) {
-    or_model md = {3, 0, 0, n, row_ptr, col, X, V, 0.0, 0.0, 0.0, K, mu, 1};
+    or_model md = {3, 0, 0, n, row_ptr, col, X, V, 0.0, 0.0, 0.0, K, mu, 1, 0.0, 0.0};
+    or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
+}
+
+/* Velocity-Verlet steps with partial volumes (or_pv) under a pairwise law   */
+/* (lps = 0: c, s_c, law, beta, stretch) or the peridynamic solid (lps = 1:  */
+/* K, mu, dim 3).                                                            */
+void or_verlet_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *X, const double *V, double rho, int lps, double c, double s_c,
+                  int law, double beta, int stretch, double K, double mu, double pv_h,
+                  double pv_R, const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                  int64_t ramp, double dt, int64_t step0, int64_t nsteps, double *u, double *v,
+                  double *f, uint8_t *alive) {
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, K, mu, lps, pv_h, pv_R};
     or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -647,9 +662,28 @@ int or_solve_implicit(int dim, int64_t n, const int64_t *row_ptr, const int32_t 
 /* Damage as in or_force: with alive given and s_c > 0 a live bond with      */
 /* S > s_c breaks before it contributes.                                     */
 /* ------------------------------------------------------------------------ */
+/* Partial volume of a bond (the correction the paper names without a       */
+/* formula; read here as the partial-area rule): with the neighbour list     */
+/* built at radius R = delta + h/2, V_j is scaled by                          */
+/* min(1, max(0, (R - |xi|)/h)) -- 1 inside delta - h/2, falling linearly to  */
+/* 0 at delta + h/2.  h <= 0: no correction (factor exactly 1).               */
+static double or_pv(double len, double R, double h) {
+    if (!(h > 0.0)) return 1.0;
+    double w = (R - len) / h;
+    return w < 0.0 ? 0.0 : (w > 1.0 ? 1.0 : w);
+}
+
 void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
                   const double *X, const double *V, const double *u, double c, double s_c,
                   int law, double beta, int stretch, uint8_t *alive, double *f, double *U) {
+    or_force_law_pv(dim, n, row_ptr, col, X, V, u, c, s_c, law, beta, stretch, 0.0, 0.0, alive,
+                    f, U);
+}
+
+void or_force_law_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                     const double *X, const double *V, const double *u, double c, double s_c,
+                     int law, double beta, int stretch, double pv_h, double pv_R,
+                     uint8_t *alive, double *f, double *U) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double fi[3] = {0.0, 0.0, 0.0};
@@ -685,10 +719,11 @@ void or_force_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col
             }
             double r = len * S * S;
             double phi = law == 1 ? exp(-beta * r) : 1.0;
-            for (int k = 0; k < dim; ++k) fi[k] = fi[k] + c * phi * S * e[k] * V[j];
+            double Vj = V[j] * or_pv(len, pv_R, pv_h);
+            for (int k = 0; k < dim; ++k) fi[k] = fi[k] + c * phi * S * e[k] * Vj;
             if (U) {
                 double psi = law == 1 ? -expm1(-beta * r) / beta : r;
-                Ui = Ui + 0.25 * c * psi * V[j];
+                Ui = Ui + 0.25 * c * psi * Vj;
             }
         }
         for (int k = 0; k < dim; ++k) f[i * dim + k] = fi[k];
@@ -835,6 +870,14 @@ int or_solve_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
 void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
             const double *V, const double *u, double K, double mu, const uint8_t *alive,
             double *m_out, double *theta_out, double *f, double *W) {
+    or_lps_pv(n, row_ptr, col, X, V, u, K, mu, 0.0, 0.0, alive, m_out, theta_out, f, W);
+}
+
+/* or_lps with partial volumes: every V_j (and the V_i of the scatter to j) */
+/* of a bond is scaled by or_pv(|xi|).                                      */
+void or_lps_pv(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
+               const double *V, const double *u, double K, double mu, double pv_h, double pv_R,
+               const uint8_t *alive, double *m_out, double *theta_out, double *f, double *W) {
     double *m = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     double *th = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) {
@@ -847,7 +890,7 @@ void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double 
                 double x = X[j * 3 + k] - X[i * 3 + k];
                 r2 = r2 + x * x;
             }
-            mi = mi + r2 * V[j];
+            mi = mi + r2 * (V[j] * or_pv(sqrt(r2), pv_R, pv_h));
         }
         m[i] = mi;
     }
@@ -865,7 +908,7 @@ void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double 
             }
             double len = sqrt(r2);
             double e = sqrt(y2) - len;
-            s = s + len * e * V[j];
+            s = s + len * e * (V[j] * or_pv(len, pv_R, pv_h));
         }
         th[i] = m[i] > 0.0 ? 3.0 / m[i] * s : 0.0;
     }
@@ -887,10 +930,11 @@ void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double 
                 double e = ylen - len;
                 double ed = e - th[i] * len / 3.0;
                 double t = 3.0 / m[i] * K * th[i] * len + 15.0 * mu / m[i] * ed;
+                double w = or_pv(len, pv_R, pv_h);
                 for (int k = 0; k < 3; ++k) {
                     double Mk = y[k] / ylen;
-                    f[i * 3 + k] = f[i * 3 + k] + t * Mk * V[j];
-                    f[j * 3 + k] = f[j * 3 + k] - t * Mk * V[i];
+                    f[i * 3 + k] = f[i * 3 + k] + t * Mk * (V[j] * w);
+                    f[j * 3 + k] = f[j * 3 + k] - t * Mk * (V[i] * w);
                 }
             }
         }
@@ -910,7 +954,7 @@ void or_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const double 
                 }
                 double len = sqrt(r2);
                 double ed = (sqrt(y2) - len) - th[i] * len / 3.0;
-                s = s + ed * ed * V[j];
+                s = s + ed * ed * (V[j] * or_pv(len, pv_R, pv_h));
             }
             W[i] = m[i] > 0.0 ? 0.5 * K * th[i] * th[i] + 15.0 * mu / (2.0 * m[i]) * s : 0.0;
         }
