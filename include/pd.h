@@ -109,6 +109,12 @@ typedef struct pd_server_s *pd_server;
  *              flags are); energy W_i = (K/2) theta_i^2 +
  *              (15 mu/(2 m_i)) sum (e - theta_i |xi|/3)^2 V_j.  No damage
  *              (s_c must be <= 0), no tangent or implicit solve.
+ *   pv_h       partial volumes (the correction the paper names without a
+ *              formula; read as the partial-area rule): with pv_h = h > 0 and
+ *              the neighbour list built at radius R = delta + h/2, each
+ *              bond's V_j (and in the solid also m, theta and the energy) is
+ *              scaled by min(1, max(0, (R - |xi|)/h)).  0 = off.  Gather
+ *              kernel only; not for the tangent or the implicit solve.
  * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
  * tiled kernels run that law, and the streamed step kernel also the NP law
  * with the linearised stretch and no damage (its other calls then run on the
@@ -130,6 +136,7 @@ typedef struct {
     double beta;
     double bulk;
     double shear;
+    double pv_h;
 } pd_material;
 
 typedef struct {

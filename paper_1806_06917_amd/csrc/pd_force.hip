@@ -50,7 +50,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
         if (tangent && a.bc) fixed_i = a.bc[i] != 0;
         if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
         const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
-        if (a.law == PD_LAW_LINEAR && a.stretch == PD_STRETCH_LINEARISED) {
+        if (a.law == PD_LAW_LINEAR && a.stretch == PD_STRETCH_LINEARISED && !(a.pv_h > 0.0)) {
             for (uint32_t p = rs + lane; p < re; p += L) {
                 // a dead bond adds exact zeros, like the tile kernel's dummy record
                 const uint32_t j = (uint32_t)a.col[p];
@@ -87,11 +87,12 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 const double dj = sj.x > 0.0 ? 15.0 * a.shear / sj.x : 0.0;
                 const double edi = e - si.y * len / 3.0, edj = e - sj.y * len / 3.0;
                 const double t = (ci * len + di * edi) + (cj * len + dj * edj);
-                const double g = live ? t * xj.w * iy : 0.0;
+                const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
+                const double g = live ? t * Vj * iy : 0.0;
                 s64.x = fma(g, dxx + dux, s64.x);
                 s64.y = fma(g, dxy + duy, s64.y);
                 s64.z = fma(g, dxz + duz, s64.z);
-                if (WANT_E) s64.e += live ? edi * edi * xj.w : 0.0;
+                if (WANT_E) s64.e += live ? edi * edi * Vj : 0.0;
             }
         } else {
             // general law; the tangent's linearisation point, if any
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 if (bond_law<DIM, MIXED, WANT_E>(a.law, a.stretch, a.beta, a.damage, a.s_c, tangent,
                                                  xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
                                                  duz, ljx - lix, ljy - liy, ljz - liz, cVj, !live,
-                                                 s64))
+                                                 s64, a.pv_h, a.pv_R))
                     a.alive[p] = 0;
             }
         }
@@ -152,8 +153,9 @@ __global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
             double len, e, iy;
             lps_bond<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
                             ujz - uiz, len, e, iy);
-            m += len * len * xj.w;
-            s += len * e * xj.w;
+            const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
+            m += len * len * Vj;
+            s += len * e * Vj;
         }
     }
 #pragma unroll
@@ -379,6 +381,8 @@ NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
     a.beta = mat->beta;
     a.bulk = mat->bulk;
     a.shear = mat->shear;
+    a.pv_h = mat->pv_h;
+    a.pv_R = nbr->delta;
     return a;
 }
 
@@ -494,7 +498,7 @@ static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const d
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
-    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS)
+    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0)
         return pd_set_error(ctx, PD_EINVAL,
                             "the tangent takes a pairwise law with the linearised stretch only");
     PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
@@ -607,7 +611,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     // the NP law without damage also runs on the streamed kernel (its other
     // calls, and every other general law, on the gather kernel)
     const bool np_stream = mat->law == PD_LAW_NP && mat->stretch == PD_STRETCH_LINEARISED &&
-                           !(mat->s_c > 0.0);
+                           !(mat->s_c > 0.0) && !(mat->pv_h > 0.0);
     const bool general = pd_general_law(mat) && !np_stream;
     if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);

@@ -52,7 +52,15 @@ struct NodeArgs {
     // linear peridynamic solid: moduli and {m, theta} per node ([n][2], sfc)
     double bulk, shear;
     double *__restrict__ lps;
+    // partial volumes: band width h (0 = off) and the neighbour radius R
+    double pv_h, pv_R;
 };
+
+// partial-volume weight of a bond of length len: min(1, max(0, (R - len)/h)),
+// 1 when h = 0
+__device__ __forceinline__ double pv_weight(double len, double R, double h) {
+    return h > 0.0 ? fmin(1.0, fmax(0.0, (R - len) / h)) : 1.0;
+}
 
 // per-lane FP64 running sums of the bond forces (and bond energies)
 struct Acc64 {
@@ -144,10 +152,12 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
                                          double s_c, bool tangent, double dxx, double dxy,
                                          double dxz, double dux, double duy, double duz,
                                          double dlx, double dly, double dlz, double cVj,
-                                         bool dead, Acc64 &s) {
+                                         bool dead, Acc64 &s, double pvh = 0.0,
+                                         double pvR = 0.0) {
     const double r2 = dotf<DIM>(dxx, dxy, dxz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double len = r2 * inv;
+    if (pvh > 0.0) cVj *= pv_weight(len, pvR, pvh);
     const bool np = law == PD_LAW_NP;
     if (tangent) {
         const double el = dotf<DIM>(dlx, dly, dlz, dxx, dxy, dxz);

@@ -163,6 +163,8 @@ extern "C" const char *pd_last_error(pd_ctx ctx) {
 }
 
 int pd_check_law(pd_ctx ctx, const pd_material *m) {
+    if (!(m->pv_h >= 0.0) || !std::isfinite(m->pv_h))
+        return pd_set_error(ctx, PD_EINVAL, "pv_h must be finite and >= 0");
     if (m->law != PD_LAW_LINEAR && m->law != PD_LAW_NP && m->law != PD_LAW_LPS)
         return pd_set_error(ctx, PD_EINVAL, "law must be PD_LAW_LINEAR, PD_LAW_NP or PD_LAW_LPS");
     if (m->law == PD_LAW_LPS) {
