@@ -344,9 +344,8 @@ int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt);
  * (u, v), the Taylor start u^{k+1} = u^k + dt v^k + dt^2 (f^k + b)/(2 rho).
  * pd_sim_get then reports v^N = (u^N - u^{N-1})/dt + (dt/2)(f^N + b)/rho.
  * The scheme equals velocity Verlet in exact arithmetic and differs in
- * rounding.  Runs on the tile or gather kernel (a simulation on the
- * streamed kernel hands its state over and takes it back at its next
- * pd_verlet_step).  Asynchronous; the same dt rule as pd_verlet_step.
+ * rounding.  Runs on the simulation's step kernel (streamed, tile or
+ * gather).  Asynchronous; the same dt rule as pd_verlet_step.
  */
 int pd_central_step(pd_sim sim, int64_t nsteps, double dt);
 

@@ -846,9 +846,8 @@ static int sim_close(pd_sim sim) {
 
 // Central-difference steps: the first step of the call is a velocity-Verlet
 // step (the scheme's start), the others u^{k+1} = 2 u^k - u^{k-1} + dt^2 a^k
-// with u^{k-1} in the other half of the ping-pong pair.  They run on the
-// tile or gather kernel; a streamed simulation hands its records over first
-// and repacks them before its next streamed step.
+// with u^{k-1} in the other half of the ping-pong pair (of records on the
+// streamed kernel, of u arrays on the tile and gather kernels).
 extern "C" int pd_central_step(pd_sim sim, int64_t nsteps, double dt) {
     if (!sim) return PD_EINVAL;
     pd_ctx ctx = sim->ctx;
@@ -859,10 +858,36 @@ extern "C" int pd_central_step(pd_sim sim, int64_t nsteps, double dt) {
         return pd_set_error(ctx, PD_EINVAL,
                             "dt changed mid-trajectory: read the state (pd_sim_get) first");
     if (nsteps == 0) return PD_OK;
+    const bool mixed = sim->mat.precision == PD_MIXED;
+    if (sim->stream) {
+        // on the streamed kernel: the first launch a Verlet step, the others
+        // central differences from the record pair
+        const pd_nbr nbr = sim->nbr;
+        if (sim->rec_stale) {
+            PD_TRY(pd_rec_pack(ctx, nbr->dim, nbr->n, sim->xv, sim->u[sim->cur],
+                               sim->rec[sim->cur]));
+            sim->rec_stale = false;
+        }
+        StreamArgs sa = pd_stream_args(sim, nullptr, 1, nbr->ntiles);
+        sa.one = pd_stream_inst(sim);
+        sa.one.cur0 = sim->cur;
+        sa.one.vhalf0 = sim->v_half ? 1 : 0;
+        sa.one.dt = dt;
+        sa.one.step0 = sim->step;
+        sa.one.limit = nsteps;
+        sa.one.cd = 1;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            sa.step = k;
+            PD_TRY(pd_launch_stream(ctx, ctx->stream, nbr->dim, sa, sim->lanes, mixed,
+                                    sim->mat.law == PD_LAW_NP, sim->s_block, sim->s_grid,
+                                    sim->s_lds));
+        }
+        pd_sim_advanced(sim, nsteps, dt);
+        return PD_OK;
+    }
     PD_TRY(sim_sync_u(sim));
     NodeArgs a = sim_args(sim);
     a.dt = dt;
-    const bool mixed = sim->mat.precision == PD_MIXED;
     for (int64_t k = 0; k < nsteps; ++k) {
         a.mode = k > 0 ? M_STEP_CD : (sim->v_half ? M_STEP_CONT : M_STEP_FIRST);
         a.u = sim->u[sim->cur];
@@ -874,7 +899,6 @@ extern "C" int pd_central_step(pd_sim sim, int64_t nsteps, double dt) {
         sim->step += 1;
     }
     sim->last_dt = dt;
-    if (sim->stream) sim->rec_stale = true;
     return PD_OK;
 }
 

@@ -363,7 +363,8 @@ struct StreamInst {
     uint32_t n, tile_begin;     // nodes; first tile in the batch numbering
     double cv, s_c, rho, dt;
     double beta;                // NP law (launches of the NP kernel only)
-    int damage, cur0, vhalf0, pad;
+    int damage, cur0, vhalf0;
+    int cd;                     // central-difference steps after the chunk's first (Verlet) step
     int64_t ramp, step0, limit;
 };
 

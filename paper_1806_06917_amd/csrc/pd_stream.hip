@@ -90,7 +90,7 @@ __device__ __forceinline__ StreamInst load_inst(const StreamInst *base, uint32_t
     d.damage = p->damage;
     d.cur0 = p->cur0;
     d.vhalf0 = p->vhalf0;
-    d.pad = 0;
+    d.cd = p->cd;
     d.ramp = p->ramp;
     d.step0 = p->step0;
     d.limit = p->limit;
@@ -261,8 +261,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     };
 
     // bond sums of tile k; then L lanes of each node's group update the node
-    // (kick, drift, boundary data), one component per lane, with the same
-    // arithmetic as node_update's explicit-step branch.  A bond that breaks
+    // (kick, drift, boundary data, or the central-difference update), one
+    // component per lane, with the same arithmetic as node_update.  A bond that breaks
     // gets its dead bit in the LDS copy of the words and goes on the list.
     auto sum_and_update = [&](uint32_t k) {
         if (meta[k * META + MT_HN] == 0) return;
@@ -317,7 +317,14 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 const int kind = (int)reinterpret_cast<const uint8_t *>(bcb)[q];
                 const double hdt = 0.5 * dt;
                 double nd;
-                if (kind == PD_BC_FREE) {
+                if (kind == PD_BC_FREE && I.cd && s > 0) {
+                    // central difference: the other record buffer still holds
+                    // u^{k-1} (this lane's component is overwritten below)
+                    const double bd = I.b ? I.b[(size_t)i * US + d] : 0.0;
+                    const double pd = out[(size_t)i * RD + DIM + d];
+                    nd = (2.0 * ud - pd) + dt * dt * (fd + bd) / rho;
+                    vd = (nd - ud) / dt;
+                } else if (kind == PD_BC_FREE) {
                     const double bd = I.b ? I.b[(size_t)i * US + d] : 0.0;
                     if (mode == M_STEP_CONT) vd = vd + hdt * (fd + bd) / rho;
                     vd = vd + hdt * (fd + bd) / rho;

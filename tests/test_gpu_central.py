@@ -76,3 +76,36 @@ def test_switching_integrators_on_a_streamed_simulation(gpu, orc):
     assert info["step"] == 50
     assert relL2(u, st["u"]) <= TOL64
     assert relL2(v, st["v"]) <= TOL64
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_central_streamed_equals_tile_kernel(gpu, prec):
+    """The central-difference update on the streamed kernel and on the LDS
+    tile kernel round alike: trajectories agree bit for bit."""
+    torch, pd, ctx = gpu
+    w = inputs.notched_plate_2d(N=48, m=3, s_c=1e-3, v0=2e-3, steps=0, ramp_steps=10)
+    w.v0 = inputs.random_field(w.n, 2, 135, scale=2e-2)
+    w.v0[w.bc_kind == 2] = 0.0
+    out = []
+    for kind in ("stream", "tile"):
+        say("central on", kind, prec)
+        ctx.set_tuning(kind, 0, 0)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+            mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, w.s_c, prec)
+            s = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                              dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                              bc_vel=dev(torch, w.bc_vel), notch=w.notch,
+                              ramp_steps=w.ramp_steps)
+            assert s.info()["kernel"] == kind
+            s.central_step(25, w.dt)
+            s.step(5, w.dt)
+            s.central_step(20, w.dt)
+            out.append(read_state(torch, s, w.n, 2, nb.nnz)[:3])
+            s.close()
+            nb.close()
+        finally:
+            ctx.set_tuning(0, 0, 0)
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
+    assert np.count_nonzero(out[0][2] == 0) > 0          # the notch (and any breaks)
