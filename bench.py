@@ -466,7 +466,7 @@ def main():
         out["validation"] = {"study": "2-d convergence, h = delta/2, delta/4, delta/8",
                              "runs": runs}
     if not args.no_cpu_baseline:
-        steps = args.cpu_steps or (60 if w.n > 100000 else 200)
+        steps = args.cpu_steps or (180 if w.n > 100000 else 600)
         out["cpu_baseline"] = cpu_baseline(w, steps)
     print(json.dumps(out), flush=True)
 
