@@ -4,6 +4,8 @@
 // drift with boundary data).
 #pragma once
 
+#include <type_traits>
+
 #include "pd_internal.hpp"
 
 namespace pdk {
@@ -217,17 +219,50 @@ __device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, dou
     e = (2.0 * xe + ee) / (y2 * iy + len);
 }
 
-// xor butterfly over the L lanes of a group: every lane ends with the sum
+// A double moved across lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One reduction level over blocks of 2M lanes whose halves are each uniform:
+// every lane adds the value of a lane in the other half.  M = 1, 2 take the
+// xor partner (quad permutations), M = 4, 8 the mirror lane in the 8- or
+// 16-lane row (uniform halves make that the same sum), M = 16 the xor
+// partner through the LDS crossbar.  Both partners add the same two values,
+// so the block ends uniform, bit for bit.
+template <int M>
+__device__ __forceinline__ double level_sum(double x) {
+    if constexpr (M == 1) return x + dpp_f64<0xB1>(x);        // quad_perm [1,0,3,2]
+    else if constexpr (M == 2) return x + dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+    else if constexpr (M == 4) return x + dpp_f64<0x141>(x);  // row_half_mirror
+    else if constexpr (M == 8) return x + dpp_f64<0x140>(x);  // row_mirror
+    else return x + __shfl_xor(x, M, 2 * M);
+}
+
+// Sum over the L lanes of a group (aligned, L a power of two up to 32),
+// pairing neighbours first: every lane ends with the same sum.
 template <int DIM, int L, bool WANT_E>
 __device__ __forceinline__ void group_reduce(Acc64 &s, double &fx, double &fy, double &fz,
                                              double &Ue) {
-#pragma unroll
-    for (int m = L / 2; m > 0; m >>= 1) {
-        s.x += __shfl_xor(s.x, m, L);
-        s.y += __shfl_xor(s.y, m, L);
-        if (DIM == 3) s.z += __shfl_xor(s.z, m, L);
-        if (WANT_E) s.e += __shfl_xor(s.e, m, L);
-    }
+    auto level = [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if constexpr (M < L) {
+            s.x = level_sum<M>(s.x);
+            s.y = level_sum<M>(s.y);
+            if (DIM == 3) s.z = level_sum<M>(s.z);
+            if (WANT_E) s.e = level_sum<M>(s.e);
+        }
+    };
+    level(std::integral_constant<int, 1>{});
+    level(std::integral_constant<int, 2>{});
+    level(std::integral_constant<int, 4>{});
+    level(std::integral_constant<int, 8>{});
+    level(std::integral_constant<int, 16>{});
     fx = s.x; fy = s.y; fz = s.z; Ue = s.e;
 }
 

@@ -325,9 +325,13 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     nd = (2.0 * ud - pd) + dt * dt * (fd + bd) / rho;
                     vd = (nd - ud) / dt;
                 } else if (kind == PD_BC_FREE) {
-                    const double bd = I.b ? I.b[(size_t)i * US + d] : 0.0;
-                    if (mode == M_STEP_CONT) vd = vd + hdt * (fd + bd) / rho;
-                    vd = vd + hdt * (fd + bd) / rho;
+                    // the body-force load is used in its own branch, so no wait
+                    // for it (nor for other loads in flight) lands on the path
+                    // without one; fd + 0.0 == fd since the sums never end in -0.0
+                    double fb = fd;
+                    if (I.b) fb = fd + I.b[(size_t)i * US + d];
+                    if (mode == M_STEP_CONT) vd = vd + hdt * fb / rho;
+                    vd = vd + hdt * fb / rho;
                     nd = ud + dt * vd;
                 } else if (kind == PD_BC_CLAMPED) {
                     vd = 0.0;
