@@ -7,17 +7,15 @@
 // + l + L, ... : the column and flag streams are read contiguously by the
 // group, the neighbour records XV[j], u[j] are gathered (neighbours of
 // consecutive sfc nodes overlap, so these mostly hit L2).  The L partial sums
-// are combined by an xor butterfly, so the order of the per-node sum depends
-// only on L and on the row, never on the rest of the mesh.  Lane 0 then
-// applies the node update selected by `mode`; the kernel boundary is the
-// global synchronisation between the drift of one step and the gather of the
-// next (the displacement is double-buffered).
+// are combined pairwise (neighbouring lanes first, group_reduce), so the
+// order of the per-node sum depends only on L and on the row, never on the
+// rest of the mesh.  Lane 0 then applies the node update selected by `mode`;
+// the kernel boundary is the global synchronisation between the drift of one
+// step and the gather of the next (the displacement is double-buffered).
 //
-// FP64 mode: every bond operation in float64.  Mixed mode: xi and eta are
-// formed in float64 (differences of nearby float64 values keep their
-// accuracy), rounded to float32; strain, damage test and bond force run in
-// float32 and each lane accumulates with Knuth's two-sum, carrying the
-// rounding error in a second float32, through the butterfly as well.
+// FP64 mode: every bond operation in float64.  Mixed mode: the same float64
+// arithmetic except 1/|xi|, which is the hardware reciprocal-square-root
+// estimate (relative error below 2^-22).
 #include <cmath>
 
 #include "pd_kernels.hpp"

@@ -6,7 +6,7 @@
 // (sorted ids come in long contiguous runs, so these loads coalesce), then
 // every bond reads its neighbour from LDS through a 16-bit tile-local index
 // (lcol), which also halves the per-bond index stream.  The per-node
-// summation order is the gather kernel's (same lanes, same butterfly), so
+// summation order is the gather kernel's (same lanes, same reduction), so
 // both kernels give bit-identical results.
 //
 // Build (once per neighbour list and tile size), one workgroup per tile:
