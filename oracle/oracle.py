@@ -103,6 +103,14 @@ def lib():
         L.or_verlet_pv.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, i32, dbl, dbl, i32, dbl, i32,
                                    dbl, dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr,
                                    ptr, ptr]
+        L.or_force_law_j.restype = None
+        L.or_force_law_j.argtypes = [i32, i64, ptr, ptr, ptr, ptr, ptr, dbl, dbl, i32, dbl, i32,
+                                     dbl, dbl, dbl, dbl, dbl, ptr, ptr, ptr]
+        for name in ("or_verlet_j", "or_central_j"):
+            fn = getattr(L, name)
+            fn.restype = None
+            fn.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32, dbl, dbl,
+                           dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -253,22 +261,48 @@ class LawMesh(Mesh):
     linearised or exact stretch (``or_force_law`` and friends)."""
 
     def force_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, s_c=0.0,
-                  alive=None, energy=False, pv_h=0.0):
+                  alive=None, energy=False, pv_h=0.0, j=None):
         """pv_h > 0: partial volumes, the neighbour radius (self.delta) being
-        delta + pv_h/2."""
+        delta + pv_h/2.  j = (c1, c2): the influence function
+        J(r) = c1 r exp(-r^2/c2) of r = |xi|/delta on every bond (None: J = 1)."""
         u = _f64(u)
         f = np.zeros_like(self.X)
         U = np.zeros(self.n) if energy else None
-        lib().or_force_law_pv(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
-                              _p(self.V), _p(u), float(c), float(s_c), int(law), float(beta),
-                              int(stretch), float(pv_h), self.delta, _p(alive), _p(f), _p(U))
+        if j is None:
+            lib().or_force_law_pv(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                                  _p(self.V), _p(u), float(c), float(s_c), int(law),
+                                  float(beta), int(stretch), float(pv_h), self.delta,
+                                  _p(alive), _p(f), _p(U))
+        else:
+            lib().or_force_law_j(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X),
+                                 _p(self.V), _p(u), float(c), float(s_c), int(law), float(beta),
+                                 int(stretch), float(pv_h), self.delta, float(j[0]),
+                                 float(j[1]), self.delta - 0.5 * float(pv_h), _p(alive), _p(f),
+                                 _p(U))
         return (f, U) if energy else f
 
     def energy_law(self, u, c, law=LAW_NP, beta=1.0, stretch=STRETCH_LINEARISED, alive=None,
-                   pv_h=0.0):
+                   pv_h=0.0, j=None):
         """Total strain energy sum_i V_i U_i."""
-        _, U = self.force_law(u, c, law, beta, stretch, 0.0, alive, energy=True, pv_h=pv_h)
+        _, U = self.force_law(u, c, law, beta, stretch, 0.0, alive, energy=True, pv_h=pv_h, j=j)
         return lib().or_potential(self.n, _p(self.V), _p(U))
+
+    def steps_j(self, state, c, rho, s_c, dt, nsteps, j, law=LAW_LINEAR, beta=1.0,
+                stretch=STRETCH_LINEARISED, pv_h=0.0, central=False, bc_kind=None,
+                bc_vel=None, b=None, ramp=0):
+        """Velocity-Verlet (central=False) or central-difference steps of a
+        pairwise law with the influence function j = (c1, c2), in place."""
+        bc_kind = None if bc_kind is None else np.ascontiguousarray(bc_kind, np.uint8)
+        bc_vel = None if bc_vel is None else _f64(bc_vel)
+        b = None if b is None else _f64(b)
+        fn = lib().or_central_j if central else lib().or_verlet_j
+        fn(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(self.V), float(rho),
+           float(c), float(s_c), int(law), float(beta), int(stretch), float(pv_h), self.delta,
+           float(j[0]), float(j[1]), self.delta - 0.5 * float(pv_h), _p(bc_kind), _p(bc_vel),
+           _p(b), int(ramp), float(dt), int(state["step"]), int(nsteps), _p(state["u"]),
+           _p(state["v"]), _p(state["f"]), _p(state["alive"]))
+        state["step"] += nsteps
+        return state
 
     def verlet_pv(self, state, rho, dt, nsteps, pv_h, lps=False, c=0.0, s_c=0.0, law=LAW_LINEAR,
                   beta=1.0, stretch=STRETCH_LINEARISED, K=0.0, mu=0.0, bc_kind=None,

@@ -29,6 +29,8 @@
  *   - a node is not its own neighbour;
  *   - influence function J = 1 on the closed ball and the linearised
  *     potential psi'(r) -> psi'(0) (the "LP" model of the 2-d validation);
+ *     or_force_law_j also takes the 1-d validation's influence function
+ *     J(r) = c1 r exp(-r^2/c2) of r = |xi|/delta as a factor of each bond;
  *   - no partial-volume correction (V_ij = 1);
  *   - damage: a bond breaks, irreversibly and only in tension, at the first
  *     force evaluation where S > s_c (strict), before it contributes.
@@ -320,6 +322,10 @@ void or_force_law_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *
                      const double *X, const double *V, const double *u, double c, double s_c,
                      int law, double beta, int stretch, double pv_h, double pv_R,
                      uint8_t *alive, double *f, double *U);
+void or_force_law_j(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *X, const double *V, const double *u, double c, double s_c,
+                    int law, double beta, int stretch, double pv_h, double pv_R, double j_c1,
+                    double j_c2, double j_delta, uint8_t *alive, double *f, double *U);
 void or_lps_pv(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *X,
                const double *V, const double *u, double K, double mu, double pv_h, double pv_R,
                const uint8_t *alive, double *m, double *theta, double *f, double *W);
@@ -333,6 +339,7 @@ typedef struct {
     double c, s_c, beta, K, mu;
     int lps;
     double pv_h, pv_R;
+    double j_c1, j_c2, j_delta;   /* influence function (j_c2 = 0: J = 1) */
 } or_model;
 
 static void or_model_force(const or_model *md, const double *u, uint8_t *alive, double *f) {
@@ -340,8 +347,9 @@ static void or_model_force(const or_model *md, const double *u, uint8_t *alive, 
         or_lps_pv(md->n, md->row_ptr, md->col, md->X, md->V, u, md->K, md->mu, md->pv_h,
                   md->pv_R, alive, NULL, NULL, f, NULL);
     else
-        or_force_law_pv(md->dim, md->n, md->row_ptr, md->col, md->X, md->V, u, md->c, md->s_c,
-                        md->law, md->beta, md->stretch, md->pv_h, md->pv_R, alive, f, NULL);
+        or_force_law_j(md->dim, md->n, md->row_ptr, md->col, md->X, md->V, u, md->c, md->s_c,
+                       md->law, md->beta, md->stretch, md->pv_h, md->pv_R, md->j_c1, md->j_c2,
+                       md->j_delta, alive, f, NULL);
 }
 
 static void or_verlet_core(const or_model *md, double rho, const uint8_t *bc_kind,
@@ -453,7 +461,8 @@ void or_central_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *c
                     const double *bc_vel, const double *b, int64_t ramp, double dt,
                     int64_t step0, int64_t nsteps, double *u, double *v, double *f,
                     uint8_t *alive) {
-    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0};
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0,
+                   0.0, 0.0, 0.0};
     or_central_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -463,7 +472,8 @@ void or_verlet_law(int dim, int64_t n, const int64_t *row_ptr, const int32_t *co
                    const uint8_t *bc_kind, const double *bc_vel, const double *b,
                    int64_t ramp, double dt, int64_t step0, int64_t nsteps,
                    double *u, double *v, double *f, uint8_t *alive) {
-    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0};
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, 0.0, 0.0,
+                   0.0, 0.0, 0.0};
     or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -472,7 +482,8 @@ void or_verlet_lps(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
                    const double *bc_vel, const double *b, int64_t ramp, double dt,
                    int64_t step0, int64_t nsteps, double *u, double *v, double *f,
                    uint8_t *alive) {
-    or_model md = {3, 0, 0, n, row_ptr, col, X, V, 0.0, 0.0, 0.0, K, mu, 1, 0.0, 0.0};
+    or_model md = {3, 0, 0, n, row_ptr, col, X, V, 0.0, 0.0, 0.0, K, mu, 1, 0.0, 0.0,
+                   0.0, 0.0, 0.0};
     or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
@@ -485,8 +496,34 @@ void or_verlet_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col
                   double pv_R, const uint8_t *bc_kind, const double *bc_vel, const double *b,
                   int64_t ramp, double dt, int64_t step0, int64_t nsteps, double *u, double *v,
                   double *f, uint8_t *alive) {
-    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, K, mu, lps, pv_h, pv_R};
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, K, mu, lps, pv_h, pv_R,
+                   0.0, 0.0, 0.0};
     or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
+}
+
+/* Velocity-Verlet and central-difference steps of a pairwise law with the  */
+/* influence function J (or_force_law_j; j_c2 = 0: J = 1) and, optionally,  */
+/* partial volumes.                                                          */
+void or_verlet_j(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                 const double *X, const double *V, double rho, double c, double s_c, int law,
+                 double beta, int stretch, double pv_h, double pv_R, double j_c1, double j_c2,
+                 double j_delta, const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                 int64_t ramp, double dt, int64_t step0, int64_t nsteps, double *u, double *v,
+                 double *f, uint8_t *alive) {
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, pv_h, pv_R,
+                   j_c1, j_c2, j_delta};
+    or_verlet_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
+}
+
+void or_central_j(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                  const double *X, const double *V, double rho, double c, double s_c, int law,
+                  double beta, int stretch, double pv_h, double pv_R, double j_c1, double j_c2,
+                  double j_delta, const uint8_t *bc_kind, const double *bc_vel, const double *b,
+                  int64_t ramp, double dt, int64_t step0, int64_t nsteps, double *u, double *v,
+                  double *f, uint8_t *alive) {
+    or_model md = {dim, law, stretch, n, row_ptr, col, X, V, c, s_c, beta, 0.0, 0.0, 0, pv_h, pv_R,
+                   j_c1, j_c2, j_delta};
+    or_central_core(&md, rho, bc_kind, bc_vel, b, ramp, dt, step0, nsteps, u, v, f, alive);
 }
 
 void or_verlet(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -684,6 +721,24 @@ void or_force_law_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *
                      const double *X, const double *V, const double *u, double c, double s_c,
                      int law, double beta, int stretch, double pv_h, double pv_R,
                      uint8_t *alive, double *f, double *U) {
+    or_force_law_j(dim, n, row_ptr, col, X, V, u, c, s_c, law, beta, stretch, pv_h, pv_R, 0.0,
+                   0.0, 0.0, alive, f, U);
+}
+
+/* Influence function of the 1-d validation (Section "One dimensional" of   */
+/* the explicit-scheme validation): J(r) = c1 r exp(-r^2 / c2) at           */
+/* r = |xi|/delta, multiplying the bond's force and energy; c2 <= 0: J = 1  */
+/* (the 2-d validation's choice on the ball).                               */
+static double or_influence(double len, double delta, double c1, double c2) {
+    if (!(c2 > 0.0)) return 1.0;
+    double r = len / delta;
+    return c1 * r * exp(-(r * r) / c2);
+}
+
+void or_force_law_j(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *X, const double *V, const double *u, double c, double s_c,
+                    int law, double beta, int stretch, double pv_h, double pv_R, double j_c1,
+                    double j_c2, double j_delta, uint8_t *alive, double *f, double *U) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double fi[3] = {0.0, 0.0, 0.0};
@@ -719,7 +774,7 @@ void or_force_law_pv(int dim, int64_t n, const int64_t *row_ptr, const int32_t *
             }
             double r = len * S * S;
             double phi = law == 1 ? exp(-beta * r) : 1.0;
-            double Vj = V[j] * or_pv(len, pv_R, pv_h);
+            double Vj = V[j] * or_pv(len, pv_R, pv_h) * or_influence(len, j_delta, j_c1, j_c2);
             for (int k = 0; k < dim; ++k) fi[k] = fi[k] + c * phi * S * e[k] * Vj;
             if (U) {
                 double psi = law == 1 ? -expm1(-beta * r) / beta : r;

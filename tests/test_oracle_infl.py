@@ -1,0 +1,117 @@
+"""Pins of the oracle's influence function (the 1-d validation's
+J(r) = c1 r exp(-r^2/c2) of r = |xi|/delta, a factor of each bond's force and
+energy): switched off it changes nothing; on a line of nodes under a
+quadratic displacement the interior force is a one-dimensional sum written
+out here and tends to the continuum integral as h -> 0; the force is minus
+the gradient of the energy with J on; Verlet steps with J conserve energy to
+second order."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_1806_06917_amd import inputs
+
+J = (1.0, 0.4)     # c1, c2 of the 1-d validation
+
+
+def line(N, h, delta, orc):
+    """N + 1 nodes x_k = k h on the x axis (2-d coordinates, y = 0), V = h."""
+    X = np.zeros((N + 1, 2))
+    X[:, 0] = h * np.arange(N + 1)
+    return orc.LawMesh(X, np.full(N + 1, h), delta, method="brute")
+
+
+def test_off_changes_nothing(orc):
+    h = 1.0 / 14
+    X = inputs.grid_coords((14, 14), h, jitter=0.05, seed=171)
+    m = orc.LawMesh(X, np.full(len(X), h * h), 3 * h)
+    u = inputs.random_field(len(X), 2, 172, scale=3e-3)
+    for law, st in ((orc.LAW_LINEAR, orc.STRETCH_LINEARISED), (orc.LAW_NP, orc.STRETCH_EXACT)):
+        f0, U0 = m.force_law(u, 2.0, law, 50.0, st, energy=True)
+        f1, U1 = m.force_law(u, 2.0, law, 50.0, st, energy=True, j=(1.0, 0.0))
+        assert np.array_equal(f0, f1) and np.array_equal(U0, U1)
+
+
+@pytest.mark.parametrize("m", [3, 5])
+def test_line_quadratic_field(orc, m):
+    """u = (x^2, 0): by the symmetry of the neighbours of an interior node,
+    S e_x = 2 x_i sign(s) + |s| sums to f_x = 2 c V sum_k J(k h/delta) k h
+    over k = 1..m, and f_y = 0."""
+    h = 0.01
+    delta = (m + 0.5) * h
+    N = 40
+    mesh = line(N, h, delta, orc)
+    u = np.zeros_like(mesh.X)
+    u[:, 0] = mesh.X[:, 0] ** 2
+    c = 3.0
+    f = mesh.force_law(u, c, orc.LAW_LINEAR, 1.0, j=J)
+    c1, c2 = J
+    ref = 2.0 * c * h * sum(c1 * (k * h / delta) * math.exp(-(k * h / delta) ** 2 / c2) * (k * h)
+                            for k in range(1, m + 1))
+    inner = slice(m + 1, N - m)
+    np.testing.assert_allclose(f[inner, 0], ref, rtol=1e-11)
+    assert np.all(f[:, 1] == 0.0)
+    # J off: the same sum without the factor
+    f0 = mesh.force_law(u, c, orc.LAW_LINEAR, 1.0)
+    np.testing.assert_allclose(f0[inner, 0], 2.0 * c * h * sum(k * h for k in range(1, m + 1)),
+                               rtol=1e-11)
+
+
+def test_line_quadratic_continuum_limit(orc):
+    """As h -> 0 at fixed delta the interior force of u = x^2 tends to
+    2 c delta^2 int_0^1 c1 t^2 exp(-t^2/c2) dt."""
+    c, delta = 3.0, 0.05
+    c1, c2 = J
+    cont = 2.0 * c * delta ** 2 * integrate.quad(lambda t: c1 * t * t * math.exp(-t * t / c2),
+                                                 0.0, 1.0, epsabs=1e-14)[0]
+    errs = []
+    for m in (4, 8, 16, 32):
+        h = delta / m
+        N = 4 * m + 8
+        mesh = line(N, h, delta * (1 + 1e-9), orc)
+        u = np.zeros_like(mesh.X)
+        u[:, 0] = mesh.X[:, 0] ** 2
+        f = mesh.force_law(u, c, orc.LAW_LINEAR, 1.0, j=J)
+        errs.append(abs(f[N // 2, 0] / cont - 1.0))
+    assert errs[-1] < 0.02
+    assert all(b < 0.7 * a for a, b in zip(errs, errs[1:]))
+
+
+@pytest.mark.parametrize("law,stretch", [(0, 0), (1, 0), (1, 1)])
+def test_force_is_minus_energy_gradient(orc, law, stretch):
+    h = 1.0 / 16
+    X = inputs.grid_coords((16, 16), h, jitter=0.05, seed=173)
+    V = h * h * np.random.Generator(np.random.PCG64(174)).uniform(0.8, 1.2, len(X))
+    mesh = orc.LawMesh(X, V, 3 * h)
+    u = inputs.random_field(len(X), 2, 175, scale=3e-3)
+    w = inputs.random_field(len(X), 2, 176, scale=1.0)
+    c, beta, eps = 2.0, 200.0, 1e-7
+    P = lambda x: mesh.energy_law(x, c, law, beta, stretch, j=J)  # noqa: E731
+    dpi = (P(u + eps * w) - P(u - eps * w)) / (2 * eps)
+    f = mesh.force_law(u, c, law, beta, stretch, j=J)
+    rhs = -np.sum(V[:, None] * f * w)
+    assert abs(dpi - rhs) <= 1e-6 * abs(rhs)
+    # and J does change the force
+    assert not np.allclose(f, mesh.force_law(u, c, law, beta, stretch), rtol=1e-3)
+
+
+def test_verlet_with_influence_second_order(orc):
+    h = 1.0 / 12
+    X = inputs.grid_coords((12, 12), h, jitter=0.05, seed=177)
+    mesh = orc.LawMesh(X, np.full(len(X), h * h), 3 * h)
+    v0 = inputs.random_field(len(X), 2, 178, scale=1e-2)
+    c, beta = 2.0, 100.0
+
+    def drift(dt, steps):
+        st = mesh.start_law(np.zeros_like(v0), v0, c, orc.LAW_NP, beta)
+        st["f"] = mesh.force_law(st["u"], c, orc.LAW_NP, beta, j=J)
+        e0 = mesh.kinetic(st["v"], 1.0) + mesh.energy_law(st["u"], c, orc.LAW_NP, beta, j=J)
+        mesh.steps_j(st, c, 1.0, 0.0, dt, steps, J, orc.LAW_NP, beta)
+        e1 = mesh.kinetic(st["v"], 1.0) + mesh.energy_law(st["u"], c, orc.LAW_NP, beta, j=J)
+        return abs(e1 - e0) / e0
+
+    d1, d2 = drift(0.1 * h, 40), drift(0.05 * h, 80)
+    assert d1 < 1e-3
+    assert 2.5 < d1 / d2 < 6.0
