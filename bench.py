@@ -353,6 +353,62 @@ def convergence(torch, pd, law, ic, t_end=2.0, every=0.25, chunk=500):
             "nodes": [w.n for w in ws], "rates": rows}
 
 
+def convergence_1d(torch, pd, law, ic, t_end=2.0, every=0.25, pv=False):
+    """The paper's 1-d convergence study on the GPU: the bar [0,1] with the
+    clamped collars [-delta, 0] and [1, 1+delta], delta = 0.01, influence
+    function J(r) = r exp(-r^2/0.4), psi(r) = 1 - exp(-r) (NP) or its
+    linearisation (LP), force (2/delta^2) J psi'(r) S per unit length, at
+    h = delta/2, delta/4, delta/8, delta/16 (a line of nodes in 2-d, gather
+    kernel, one simulation per mesh); at every checkpoint the rate of the
+    two sets {h1, h2, h3} and {h2, h3, h4}, norms over [0,1] on the coarser
+    line of each pair (finer solution averaged onto it).  pv: partial volumes
+    (neighbours out to delta + h/2, the node at distance delta weighted 1/2)."""
+    from paper_1806_06917_amd import inputs
+    ws = [inputs.convergence_line(m, ic) for m in (2, 4, 8, 16)]
+    delta = ws[0].delta
+    c = 2.0 / delta ** 2                    # (2/delta^2) psi'(0), psi'(0) = C beta = 1
+    ctx = pd.Context(0)
+    made = []
+    for w in ws:
+        pv_h = w.h if pv else 0.0
+        nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta + pv_h / 2)
+        mat = pd.material(2, c, 1.0, 0.0, "fp64", law=law, beta=1.0, j=inputs.INFLUENCE_1D,
+                          pv_h=pv_h)
+        sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                            dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                            bc_vel=dev(torch, w.bc_vel))
+        made.append((nb, sim))
+    dt = ws[0].dt
+    per = int(round(every / dt))
+    rows = []
+    t0 = time.perf_counter()
+    step = 0
+    while step * dt < t_end - 1e-12:
+        for _, s in made:
+            s.step(per, dt)
+        step += per
+        us = []
+        for w, (nb, s) in zip(ws, made):
+            u = torch.zeros((w.n, 2), dtype=torch.float64, device="cuda")
+            s.get(u)
+            us.append(u.cpu().numpy())
+        norms = []
+        for k in range(3):
+            d = us[k] - inputs.coarsen_line(us[k + 1], ws[k].n)
+            inside = ws[k].bc_kind == inputs.BC_FREE
+            norms.append(float(np.sqrt(np.sum(d[inside] ** 2) * ws[k].h)))
+        rows.append({"t": round(step * dt, 6), "diff": norms,
+                     "alpha_set1": float(np.log(norms[0] / norms[1]) / np.log(2.0)),
+                     "alpha_set2": float(np.log(norms[1] / norms[2]) / np.log(2.0))})
+    secs = time.perf_counter() - t0
+    for nb, s in made:
+        s.close()
+        nb.close()
+    ctx.close()
+    return {"law": law, "ic": ic, "steps": step, "dt": dt, "seconds": secs,
+            "nodes": [w.n for w in ws], "rates": rows}
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle, as it stands, on the same workload for a few steps."""
     from oracle import oracle as orc
@@ -397,7 +453,15 @@ def main():
             for ic in (1, 2):
                 progress("convergence study", law, "IC", ic)
                 res.append(convergence(torch, pd, law, ic, args.convergence_t))
-        print(json.dumps({"validation": "2-d convergence study", "runs": res}), flush=True)
+        res1 = []
+        for pv in (False, True):
+            for law in ("linear", "np"):
+                for ic in (1, 2):
+                    progress("1-d convergence study", law, "IC", ic, "pv" if pv else "")
+                    r = convergence_1d(torch, pd, law, ic, args.convergence_t, pv=pv)
+                    res1.append(dict(r, partial_volumes=pv))
+        print(json.dumps({"validation": "convergence studies", "runs_2d": res,
+                          "runs_1d": res1}), flush=True)
         return
 
     w = inputs.CONFIGS[args.config]()
@@ -463,8 +527,20 @@ def main():
             runs.append({"law": law, "ic": ic, "seconds": r["seconds"], "steps": r["steps"],
                          "alpha": [round(x["alpha"], 3) for x in r["rates"]],
                          "t": [x["t"] for x in r["rates"]]})
+        runs1 = []
+        for pv in (False, True):
+            progress("1-d convergence study, linear, IC 1", "partial volumes" if pv else "")
+            r = convergence_1d(torch, pd, "linear", 1, args.convergence_t, pv=pv)
+            runs1.append({"law": "linear", "ic": 1, "partial_volumes": pv,
+                          "seconds": r["seconds"], "steps": r["steps"],
+                          "alpha_set1": [round(x["alpha_set1"], 3) for x in r["rates"]],
+                          "alpha_set2": [round(x["alpha_set2"], 3) for x in r["rates"]],
+                          "t": [x["t"] for x in r["rates"]]})
         out["validation"] = {"study": "2-d convergence, h = delta/2, delta/4, delta/8",
-                             "runs": runs}
+                             "runs": runs,
+                             "study_1d": "1-d convergence, h = delta/2 ... delta/16, sets "
+                                         "{h1,h2,h3} and {h2,h3,h4}",
+                             "runs_1d": runs1}
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (180 if w.n > 100000 else 600)
         out["cpu_baseline"] = cpu_baseline(w, steps)

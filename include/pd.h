@@ -115,6 +115,12 @@ typedef struct pd_server_s *pd_server;
  *              bond's V_j (and in the solid also m, theta and the energy) is
  *              scaled by min(1, max(0, (R - |xi|)/h)).  0 = off.  Gather
  *              kernel only; not for the tangent or the implicit solve.
+ *   j_c1, j_c2 influence function of a pairwise law (the 1-d validation
+ *              of the explicit scheme): with j_c2 > 0 each bond's force and
+ *              energy carry J = j_c1 r exp(-r^2/j_c2) at r = |xi|/delta,
+ *              delta being the neighbour list's radius minus pv_h/2.
+ *              j_c2 = 0: J = 1 (j_c1 unused).  Not for the solid; gather
+ *              kernel only; not for the tangent or the implicit solve.
  * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
  * tiled kernels run that law, and the streamed step kernel also the NP law
  * with the linearised stretch and no damage (its other calls then run on the
@@ -137,6 +143,8 @@ typedef struct {
     double bulk;
     double shear;
     double pv_h;
+    double j_c1;
+    double j_c2;
 } pd_material;
 
 typedef struct {

@@ -48,7 +48,8 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
         if (tangent && a.bc) fixed_i = a.bc[i] != 0;
         if (tangent && fixed_i) { uix = 0; uiy = 0; uiz = 0; }
         const uint32_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
-        if (a.law == PD_LAW_LINEAR && a.stretch == PD_STRETCH_LINEARISED && !(a.pv_h > 0.0)) {
+        if (a.law == PD_LAW_LINEAR && a.stretch == PD_STRETCH_LINEARISED && !(a.pv_h > 0.0) &&
+            !(a.j_c2 > 0.0)) {
             for (uint32_t p = rs + lane; p < re; p += L) {
                 // a dead bond adds exact zeros, like the tile kernel's dummy record
                 const uint32_t j = (uint32_t)a.col[p];
@@ -110,7 +111,8 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 if (bond_law<DIM, MIXED, WANT_E>(a.law, a.stretch, a.beta, a.damage, a.s_c, tangent,
                                                  xj.x - xix, xj.y - xiy, dxz, ujx - uix, ujy - uiy,
                                                  duz, ljx - lix, ljy - liy, ljz - liz, cVj, !live,
-                                                 s64, a.pv_h, a.pv_R))
+                                                 s64, a.pv_h, a.pv_R, a.j_c1, a.j_c2,
+                                                 a.j_idelta))
                     a.alive[p] = 0;
             }
         }
@@ -156,11 +158,8 @@ __global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
             s += len * e * Vj;
         }
     }
-#pragma unroll
-    for (int k = L / 2; k > 0; k >>= 1) {
-        m += __shfl_xor(m, k, L);
-        s += __shfl_xor(s, k, L);
-    }
+    m = lane_sum<L>(m);
+    s = lane_sum<L>(s);
     if (valid && lane == 0)
         reinterpret_cast<double2 *>(a.lps)[i] = make_double2(m, m > 0.0 ? 3.0 / m * s : 0.0);
 }
@@ -363,6 +362,8 @@ int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
         return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
     if (!std::isfinite(mat->c) || !std::isfinite(mat->s_c))
         return pd_set_error(ctx, PD_EINVAL, "c and s_c must be finite");
+    if (mat->j_c2 > 0.0 && !(nbr->delta - 0.5 * mat->pv_h > 0.0))
+        return pd_set_error(ctx, PD_EINVAL, "the influence function needs radius - pv_h/2 > 0");
     return pd_check_law(ctx, mat);
 }
 
@@ -381,6 +382,9 @@ NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
     a.shear = mat->shear;
     a.pv_h = mat->pv_h;
     a.pv_R = nbr->delta;
+    a.j_c1 = mat->j_c1;
+    a.j_c2 = mat->j_c2;
+    a.j_idelta = mat->j_c2 > 0.0 ? 1.0 / (nbr->delta - 0.5 * mat->pv_h) : 0.0;
     return a;
 }
 
@@ -496,7 +500,8 @@ static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const d
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
-    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0)
+    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0 ||
+        mat->j_c2 > 0.0)
         return pd_set_error(ctx, PD_EINVAL,
                             "the tangent takes a pairwise law with the linearised stretch only");
     PD_TRY(pd_check_dev_ptr(ctx, X, "X"));
@@ -609,7 +614,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     // the NP law without damage also runs on the streamed kernel (its other
     // calls, and every other general law, on the gather kernel)
     const bool np_stream = mat->law == PD_LAW_NP && mat->stretch == PD_STRETCH_LINEARISED &&
-                           !(mat->s_c > 0.0) && !(mat->pv_h > 0.0);
+                           !(mat->s_c > 0.0) && !(mat->pv_h > 0.0) && !(mat->j_c2 > 0.0);
     const bool general = pd_general_law(mat) && !np_stream;
     if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);

@@ -222,7 +222,8 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     if (mat->precision != PD_FP64 && mat->precision != PD_MIXED)
         return pd_set_error(ctx, PD_EINVAL, "bad precision");
     PD_TRY(pd_check_law(ctx, mat));
-    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0)
+    if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0 ||
+        mat->j_c2 > 0.0)
         return pd_set_error(ctx, PD_EINVAL,
                             "the implicit solve takes a pairwise law with the linearised stretch");
     if (!(rtol > 0.0) || !(rtol < 1.0)) return pd_set_error(ctx, PD_EINVAL, "rtol must be in (0,1)");

@@ -230,7 +230,8 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block);
 
 // the material's pairwise law is not the linearised law of the tiled kernels
 inline bool pd_general_law(const pd_material *m) {
-    return m->law != PD_LAW_LINEAR || m->stretch != PD_STRETCH_LINEARISED || m->pv_h > 0.0;
+    return m->law != PD_LAW_LINEAR || m->stretch != PD_STRETCH_LINEARISED || m->pv_h > 0.0 ||
+           m->j_c2 > 0.0;
 }
 // law, stretch and beta are valid (pd_runtime.hip)
 int pd_check_law(pd_ctx ctx, const pd_material *m);

@@ -56,6 +56,9 @@ struct NodeArgs {
     double *__restrict__ lps;
     // partial volumes: band width h (0 = off) and the neighbour radius R
     double pv_h, pv_R;
+    // influence function J = j_c1 r exp(-r^2/j_c2), r = |xi| j_idelta
+    // (j_c2 = 0: off)
+    double j_c1, j_c2, j_idelta;
 };
 
 // partial-volume weight of a bond of length len: min(1, max(0, (R - len)/h)),
@@ -155,11 +158,16 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
                                          double dxz, double dux, double duy, double duz,
                                          double dlx, double dly, double dlz, double cVj,
                                          bool dead, Acc64 &s, double pvh = 0.0,
-                                         double pvR = 0.0) {
+                                         double pvR = 0.0, double jc1 = 0.0, double jc2 = 0.0,
+                                         double jid = 0.0) {
     const double r2 = dotf<DIM>(dxx, dxy, dxz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double len = r2 * inv;
     if (pvh > 0.0) cVj *= pv_weight(len, pvR, pvh);
+    if (jc2 > 0.0) {
+        const double r = len * jid;
+        cVj *= jc1 * r * exp(-(r * r) / jc2);
+    }
     const bool np = law == PD_LAW_NP;
     if (tangent) {
         const double el = dotf<DIM>(dlx, dly, dlz, dxx, dxy, dxz);
@@ -242,6 +250,19 @@ __device__ __forceinline__ double level_sum(double x) {
     else if constexpr (M == 4) return x + dpp_f64<0x141>(x);  // row_half_mirror
     else if constexpr (M == 8) return x + dpp_f64<0x140>(x);  // row_mirror
     else return x + __shfl_xor(x, M, 2 * M);
+}
+
+// Sum of one double over the L lanes of a group (aligned, L a power of two up
+// to 64) in the order of group_reduce
+template <int L>
+__device__ __forceinline__ double lane_sum(double x) {
+    if constexpr (L > 1) x = level_sum<1>(x);
+    if constexpr (L > 2) x = level_sum<2>(x);
+    if constexpr (L > 4) x = level_sum<4>(x);
+    if constexpr (L > 8) x = level_sum<8>(x);
+    if constexpr (L > 16) x = level_sum<16>(x);
+    if constexpr (L > 32) x = level_sum<32>(x);
+    return x;
 }
 
 // Sum over the L lanes of a group (aligned, L a power of two up to 32),

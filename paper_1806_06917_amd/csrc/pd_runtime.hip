@@ -165,6 +165,8 @@ extern "C" const char *pd_last_error(pd_ctx ctx) {
 int pd_check_law(pd_ctx ctx, const pd_material *m) {
     if (!(m->pv_h >= 0.0) || !std::isfinite(m->pv_h))
         return pd_set_error(ctx, PD_EINVAL, "pv_h must be finite and >= 0");
+    if (!(m->j_c2 >= 0.0) || !std::isfinite(m->j_c2) || !std::isfinite(m->j_c1))
+        return pd_set_error(ctx, PD_EINVAL, "j_c1 must be finite and j_c2 finite and >= 0");
     if (m->law != PD_LAW_LINEAR && m->law != PD_LAW_NP && m->law != PD_LAW_LPS)
         return pd_set_error(ctx, PD_EINVAL, "law must be PD_LAW_LINEAR, PD_LAW_NP or PD_LAW_LPS");
     if (m->law == PD_LAW_LPS) {
@@ -173,6 +175,8 @@ int pd_check_law(pd_ctx ctx, const pd_material *m) {
             !std::isfinite(m->shear))
             return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS needs bulk > 0 and shear >= 0");
         if (m->s_c > 0.0) return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS takes no damage");
+        if (m->j_c2 > 0.0)
+            return pd_set_error(ctx, PD_EINVAL, "PD_LAW_LPS takes no influence function");
         return PD_OK;
     }
     if (m->stretch != PD_STRETCH_LINEARISED && m->stretch != PD_STRETCH_EXACT)

@@ -206,6 +206,44 @@ def convergence_plate(m, ic, delta=0.1):
         steps=200000, u0=u0, v0=np.zeros((n, 2)), bc_kind=kind, bc_vel=np.zeros((n, 2)))
 
 
+# initial conditions of the 1-d study: Gaussian pulses a exp(-(x - xc)^2/b)
+CONVERGENCE_ICS_1D = {
+    1: {"a": 0.001, "xc": (0.5,), "b": 0.003},
+    2: {"a": 0.001, "xc": (0.25, 0.75), "b": 0.003},
+}
+# the 1-d study's influence function J(r) = c1 r exp(-r^2/c2)
+INFLUENCE_1D = (1.0, 0.4)
+
+
+def convergence_line(m, ic, delta=0.01):
+    """The 1-d convergence study as a line of nodes in 2-d coordinates
+    (y = 0): material domain [0,1] with the nonlocal collar [-delta, 0] and
+    [1, 1+delta] clamped (u = 0), h = delta/m on a cell-centred grid of
+    [-delta, 1+delta] (meshes with m and 2m nest: each coarse cell holds two
+    fine cells), nodal volume h (a length), rho = 1, dt = 1e-5, initial
+    displacement (x component) from CONVERGENCE_ICS_1D[ic] inside (0,1)."""
+    h = delta / m
+    N = int(round((1.0 + 2.0 * delta) / h))
+    x = -delta + h * (np.arange(N) + 0.5)
+    X = np.stack([x, np.zeros(N)], axis=1)
+    inside = (x > 0.0) & (x < 1.0)
+    kind = np.where(inside, BC_FREE, BC_CLAMPED).astype(np.uint8)
+    p = CONVERGENCE_ICS_1D[ic]
+    g = sum(p["a"] * np.exp(-(x - xc) ** 2 / p["b"]) for xc in p["xc"])
+    u0 = np.zeros((N, 2))
+    u0[inside, 0] = g[inside]
+    return Workload(
+        name=f"convergence1d_m{m}_ic{ic}", dim=2, shape=(N,), h=h, X=X,
+        V=np.full(N, h), delta=delta, E=1.0, rho=1.0, s_c=0.0, dt=1e-5,
+        steps=200000, u0=u0, v0=np.zeros((N, 2)), bc_kind=kind, bc_vel=np.zeros((N, 2)))
+
+
+def coarsen_line(u, N):
+    """Average of the two fine cells under each coarse cell (cell-centred
+    lines of N and 2N cells)."""
+    return 0.5 * (u[0::2] + u[1::2]).reshape(N, -1)
+
+
 def coarsen(u, N):
     """Average of the 2 x 2 fine cells under each coarse cell (x fastest
     cell-centred grids of N and 2N per side)."""

@@ -32,7 +32,8 @@ class Material(C.Structure):
     _fields_ = [("dim", C.c_int), ("precision", C.c_int), ("c", C.c_double),
                 ("rho", C.c_double), ("s_c", C.c_double), ("law", C.c_int),
                 ("stretch", C.c_int), ("beta", C.c_double), ("bulk", C.c_double),
-                ("shear", C.c_double), ("pv_h", C.c_double)]
+                ("shear", C.c_double), ("pv_h", C.c_double), ("j_c1", C.c_double),
+                ("j_c2", C.c_double)]
 
 
 class Request(C.Structure):
@@ -219,19 +220,21 @@ PD_STRETCH_LINEARISED, PD_STRETCH_EXACT = 0, 1
 
 
 def material(dim, c, rho=1.0, s_c=0.0, precision="fp64", law="linear", beta=0.0,
-             stretch="linearised", bulk=0.0, shear=0.0, pv_h=0.0):
+             stretch="linearised", bulk=0.0, shear=0.0, pv_h=0.0, j=None):
     """law: "linear" | "np" (psi(r) = C (1 - exp(-beta r))) | "lps" (the
     3-d linear peridynamic solid with moduli bulk, shear; c unused);
     stretch: "linearised" | "exact"; pv_h > 0: partial volumes (neighbours
-    built at delta + pv_h/2)."""
+    built at delta + pv_h/2); j = (c1, c2): influence function
+    J = c1 r exp(-r^2/c2) of r = |xi|/delta on every bond (None: J = 1)."""
     prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
     lw = {"linear": PD_LAW_LINEAR, "np": PD_LAW_NP, "lps": PD_LAW_LPS}[law] \
         if isinstance(law, str) else int(law)
     sk = {"linearised": PD_STRETCH_LINEARISED, "exact": PD_STRETCH_EXACT}[stretch] \
         if isinstance(stretch, str) else int(stretch)
+    j1, j2 = (0.0, 0.0) if j is None else (float(j[0]), float(j[1]))
     return Material(int(dim), prec, float(c), float(rho), float(s_c), lw, sk, float(beta),
-                    float(bulk), float(shear), float(pv_h))
+                    float(bulk), float(shear), float(pv_h), j1, j2)
 
 
 class Neighbors:
