@@ -78,7 +78,8 @@ static int batch_enqueue(pd_batch b, hipStream_t st, int dim, StreamArgs sa, int
                          int64_t nsteps) {
     for (int64_t k = 0; k < nsteps; ++k) {
         sa.step = k;
-        PD_TRY(pd_launch_stream(b->ctx, st, dim, sa, lanes, mixed, np, block, grid, lds));
+        PD_TRY(pd_launch_stream(b->ctx, st, dim, sa, lanes, mixed, np ? SK_NP : SK_LINEAR, block,
+                                grid, lds));
     }
     return PD_OK;
 }
@@ -104,6 +105,8 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
         if (!s || s->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "sims[%d]: NULL or another context", k);
         if (!s->stream)
             return pd_set_error(ctx, PD_EINVAL, "sims[%d] does not run the streamed kernel", k);
+        if (s->s_form == SK_LPS_FORCE)
+            return pd_set_error(ctx, PD_EINVAL, "sims[%d]: the solid steps alone", k);
         if (s->nbr->dim != dim || s->lanes != lanes || s->nbr->tile_T != tile ||
             (s->mat.precision == PD_MIXED) != mixed || (s->mat.law == PD_LAW_NP) != np)
             return pd_set_error(ctx, PD_EINVAL,
@@ -128,8 +131,8 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
     unsigned grid = 0;
     uint32_t mmax = 0;
     size_t lds = 0;
-    if (!pd_stream_geometry(ctx, dim, (uint32_t)ntiles, tile, hcap, bcap, lanes, mixed, true, np,
-                            &block, &grid, &mmax, &lds))
+    if (!pd_stream_geometry(ctx, dim, (uint32_t)ntiles, tile, hcap, bcap, lanes, mixed, true,
+                            np ? SK_NP : SK_LINEAR, &block, &grid, &mmax, &lds))
         return pd_set_error(ctx, PD_ECAPACITY, "the batch does not fit the streamed kernel");
 
     // descriptors: previous upload done, then stage and upload

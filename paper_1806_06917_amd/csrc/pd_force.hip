@@ -69,8 +69,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
             // node i, f_i = sum_j (t_ij + t_ji) M V_j, with {m, theta} of
             // both ends from the state pass
             const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
-            const double ci = si.x > 0.0 ? 3.0 * a.bulk * si.y / si.x : 0.0;
-            const double di = si.x > 0.0 ? 15.0 * a.shear / si.x : 0.0;
+            const LpsCoef qi = lps_coef(si.x, si.y, a.bulk, a.shear);
             for (uint32_t p = rs + lane; p < re; p += L) {
                 const uint32_t j = (uint32_t)a.col[p];
                 const bool live = !a.alive || a.alive[p];
@@ -82,12 +81,10 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 double len, e, iy;
                 lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
                 const double2 sj = reinterpret_cast<const double2 *>(a.lps)[j];
-                const double cj = sj.x > 0.0 ? 3.0 * a.bulk * sj.y / sj.x : 0.0;
-                const double dj = sj.x > 0.0 ? 15.0 * a.shear / sj.x : 0.0;
-                const double edi = e - si.y * len / 3.0, edj = e - sj.y * len / 3.0;
-                const double t = (ci * len + di * edi) + (cj * len + dj * edj);
+                const LpsCoef qj = lps_coef(sj.x, sj.y, a.bulk, a.shear);
                 const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
-                const double g = live ? t * Vj * iy : 0.0;
+                const double g = lps_force_weight(qi, qj, len, e, iy, Vj, live);
+                const double edi = e - qi.h * len;
                 s64.x = fma(g, dxx + dux, s64.x);
                 s64.y = fma(g, dxy + duy, s64.y);
                 s64.z = fma(g, dxz + duz, s64.z);
@@ -154,8 +151,7 @@ __global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
             lps_bond<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
                             ujz - uiz, len, e, iy);
             const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
-            m += len * len * Vj;
-            s += len * e * Vj;
+            lps_state_terms(len, e, Vj, m, s);
         }
     }
     m = lane_sum<L>(m);
@@ -563,6 +559,7 @@ static void sim_release(pd_sim s) {
     pd_free(s->rec[0]);
     pd_free(s->rec[1]);
     pd_free(s->lps);
+    pd_free(s->lpsc);
     if (s->nbr && s->tiled) s->nbr->users -= 1;
     pd_ctx ctx = s->ctx;
     pd_nbr nbr = s->nbr;
@@ -615,10 +612,12 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     // calls, and every other general law, on the gather kernel)
     const bool np_stream = mat->law == PD_LAW_NP && mat->stretch == PD_STRETCH_LINEARISED &&
                            !(mat->s_c > 0.0) && !(mat->pv_h > 0.0) && !(mat->j_c2 > 0.0);
-    const bool general = pd_general_law(mat) && !np_stream;
+    // so does the solid's explicit step (its two passes) without partial volumes
+    const bool lps_stream = mat->law == PD_LAW_LPS && !(mat->pv_h > 0.0);
+    const bool general = pd_general_law(mat) && !np_stream && !lps_stream;
     if (ctx->lanes == 0 && ctx->kernel == 0 && ctx->tile == 0 && ctx->block == 0 && nbr->n > 0)
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);
-    if (np_stream && ctx->kernel == 2)
+    if ((np_stream || lps_stream) && ctx->kernel == 2)
         return pd_set_error(ctx, PD_ECAPACITY, "the LDS tile kernel takes the linearised law only");
     if (general) {
         if (ctx->kernel == 2 || ctx->kernel == 3)
@@ -667,7 +666,9 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "notch_k", __FILE__, __LINE__);
     }
     s->lanes = lanes;
-    s->block = np_stream ? 0 : block;      // the tile kernel for the other calls
+    // the tile kernel for the other calls (those of the NP law and the solid
+    // run on the gather kernel)
+    s->block = (np_stream || lps_stream) ? 0 : block;
     if (st == PD_OK && block > 0) {
         s->tiled = true;
         nbr->users += 1;
@@ -678,15 +679,24 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         double Vu = 0.0;
         st = pd_uniform_volume(ctx, nbr, s->xv, &Vu);
         s->cv_uniform = mat->c * Vu;
+        s->vol_uniform = Vu;
     }
-    if (st == PD_OK && s->tiled && s->cv_uniform != 0.0 && (ctx->kernel == 0 || ctx->kernel == 3) &&
+    s->s_form = lps_stream ? SK_LPS_FORCE : (np_stream ? SK_NP : SK_LINEAR);
+    if (st == PD_OK && s->tiled && (lps_stream ? s->vol_uniform > 0.0 : s->cv_uniform != 0.0) &&
+        (ctx->kernel == 0 || ctx->kernel == 3) &&
         pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
         pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false, np_stream,
-                           &s->s_block, &s->s_grid, &s->s_mmax, &s->s_lds)) {
+                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false, s->s_form,
+                           &s->s_block, &s->s_grid, &s->s_mmax, &s->s_lds) &&
+        (!lps_stream ||
+         pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
+                            pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false,
+                            SK_LPS_STATE, &s->s2_block, &s->s2_grid, &s->s2_mmax,
+                            &s->s2_lds))) {
         const size_t rd = nbr->dim == 3 ? 6 : 4;
         st = pd_alloc(ctx, &s->rec[0], n * rd);
         if (st == PD_OK) st = pd_alloc(ctx, &s->rec[1], n * rd);
+        if (st == PD_OK && lps_stream) st = pd_alloc(ctx, &s->lpsc, n * 4);
         // both buffers carry the positions; u is rewritten every step
         if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[0]);
         if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[1]);
@@ -745,6 +755,10 @@ StreamInst pd_stream_inst(const pd_sim s) {
     d.rho = s->mat.rho;
     d.damage = s->mat.s_c > 0.0;
     d.beta = s->mat.beta;
+    d.lps = s->lpsc;
+    d.vol = s->vol_uniform;
+    d.bulk = s->mat.bulk;
+    d.shear = s->mat.shear;
     d.ramp = s->ramp;
     return d;
 }
@@ -762,6 +776,26 @@ StreamArgs pd_stream_args(const pd_sim sim, const StreamInst *inst, uint32_t nin
     sa.bcap = pd_tile_bcap(nbr);
     sa.mmax = sim->s_mmax;
     return sa;
+}
+
+// nsteps launches of the streamed kernel (the solid: state pass, then force
+// pass, per step), the k-th told it is step k
+static int stream_steps(pd_sim sim, StreamArgs &sa, int64_t nsteps) {
+    const pd_ctx ctx = sim->ctx;
+    const bool mixed = sim->mat.precision == PD_MIXED;
+    const int dim = sim->nbr->dim;
+    StreamArgs sb = sa;          // the state pass: its own grid and tiles per workgroup
+    sb.mmax = sim->s2_mmax;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        sa.step = k;
+        sb.step = k;
+        if (sim->s_form == SK_LPS_FORCE)
+            PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sb, sim->lanes, mixed, SK_LPS_STATE,
+                                    sim->s2_block, sim->s2_grid, sim->s2_lds));
+        PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sa, sim->lanes, mixed, sim->s_form,
+                                sim->s_block, sim->s_grid, sim->s_lds));
+    }
+    return PD_OK;
 }
 
 // host state after nsteps streamed steps at dt
@@ -800,12 +834,7 @@ extern "C" int pd_verlet_step(pd_sim sim, int64_t nsteps, double dt) {
         sa.one.dt = dt;
         sa.one.step0 = sim->step;
         sa.one.limit = nsteps;
-        for (int64_t k = 0; k < nsteps; ++k) {
-            sa.step = k;
-            PD_TRY(pd_launch_stream(ctx, ctx->stream, nbr->dim, sa, sim->lanes, mixed,
-                                    sim->mat.law == PD_LAW_NP, sim->s_block, sim->s_grid,
-                                    sim->s_lds));
-        }
+        PD_TRY(stream_steps(sim, sa, nsteps));
         pd_sim_advanced(sim, nsteps, dt);
         return PD_OK;
     }
@@ -879,12 +908,7 @@ extern "C" int pd_central_step(pd_sim sim, int64_t nsteps, double dt) {
         sa.one.step0 = sim->step;
         sa.one.limit = nsteps;
         sa.one.cd = 1;
-        for (int64_t k = 0; k < nsteps; ++k) {
-            sa.step = k;
-            PD_TRY(pd_launch_stream(ctx, ctx->stream, nbr->dim, sa, sim->lanes, mixed,
-                                    sim->mat.law == PD_LAW_NP, sim->s_block, sim->s_grid,
-                                    sim->s_lds));
-        }
+        PD_TRY(stream_steps(sim, sa, nsteps));
         pd_sim_advanced(sim, nsteps, dt);
         return PD_OK;
     }

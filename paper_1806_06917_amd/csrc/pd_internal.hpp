@@ -104,6 +104,7 @@ struct pd_sim_s {
     double cv_uniform = 0.0;     // c V if all volumes are equal, else 0
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
     double *lps = nullptr;       // [n][2] {m, theta} (linear peridynamic solid)
+    double *lpsc = nullptr;      // [n][4] {c, d, h, 0} of the solid's streamed steps
     int64_t step = 0;
     int64_t ramp = 0;
     double last_dt = 0;
@@ -118,6 +119,12 @@ struct pd_sim_s {
     unsigned s_grid = 0;
     uint32_t s_mmax = 0;
     size_t s_lds = 0;
+    int s_form = 0;              // SK_LINEAR, SK_NP or SK_LPS_FORCE (two launches a step)
+    int s2_block = 0;            // the solid's state pass: its own launch geometry
+    unsigned s2_grid = 0;
+    uint32_t s2_mmax = 0;
+    size_t s2_lds = 0;
+    double vol_uniform = 0.0;    // the common nodal volume (0: volumes differ)
 };
 
 // ---------------------------------------------------------------------------

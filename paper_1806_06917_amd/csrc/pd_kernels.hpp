@@ -212,6 +212,16 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
 // Linear peridynamic solid: bond length |xi|, extension e = |xi+eta| - |xi|
 // in the cancellation-free form (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), and
 // 1/|xi+eta| (the direction M = (xi+eta)/|xi+eta|).
+// the extension (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), without contraction;
+// mixed precision divides through the hardware reciprocal estimate (relative
+// error below 2^-22, as its reciprocal square roots)
+template <bool MIXED>
+__device__ __forceinline__ double lps_ext(double xe, double ee, double y2, double iy, double len) {
+#pragma clang fp contract(off)
+    const double num = 2.0 * xe + ee, den = y2 * iy + len;
+    return MIXED ? num * __builtin_amdgcn_rcp(den) : num / den;
+}
+
 template <bool MIXED>
 __device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, double dux,
                                          double duy, double duz, double &len, double &e,
@@ -224,7 +234,41 @@ __device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, dou
     len = r2 * ix;
     const double xe = dotf<3>(dxx, dxy, dxz, dux, duy, duz);
     const double ee = dotf<3>(dux, duy, duz, dux, duy, duz);
-    e = (2.0 * xe + ee) / (y2 * iy + len);
+    e = lps_ext<MIXED>(xe, ee, y2, iy, len);
+}
+
+// The solid's per-bond terms, shared by the gather and streamed kernels and
+// written without contraction, so that both round every bond alike.
+// First pass: m += |xi|^2 V_j, s += |xi| e V_j.
+__device__ __forceinline__ void lps_state_terms(double len, double e, double Vj, double &m,
+                                                double &s) {
+#pragma clang fp contract(off)
+    m += len * len * Vj;
+    s += len * e * Vj;
+}
+// A node's coefficients in the bond force state, from its {m, theta}:
+// {3 K theta / m, 15 mu / m, theta / 3} (all 0 where m = 0), so that
+// t = c |xi| + d (e - h |xi|) with the deviatoric extension e - h |xi|.
+struct LpsCoef {
+    double c, d, h;
+};
+__device__ __forceinline__ LpsCoef lps_coef(double m, double theta, double K, double mu) {
+#pragma clang fp contract(off)
+    LpsCoef q;
+    q.c = m > 0.0 ? 3.0 * K * theta / m : 0.0;
+    q.d = m > 0.0 ? 15.0 * mu / m : 0.0;
+    q.h = m > 0.0 ? theta / 3.0 : 0.0;
+    return q;
+}
+// Force: the weight g of M = (xi+eta) in f_i, (t_ij + t_ji) V_j / |xi+eta|,
+// from the coefficients of both ends and the bond's |xi|, e.
+__device__ __forceinline__ double lps_force_weight(const LpsCoef &qi, const LpsCoef &qj,
+                                                   double len, double e, double iy, double Vj,
+                                                   bool live) {
+#pragma clang fp contract(off)
+    const double edi = e - qi.h * len, edj = e - qj.h * len;
+    const double t = (qi.c * len + qi.d * edi) + (qj.c * len + qj.d * edj);
+    return live ? t * Vj * iy : 0.0;
 }
 
 // A double moved across lanes by a DPP pattern (both 32-bit halves).
@@ -419,6 +463,8 @@ struct StreamInst {
     uint32_t n, tile_begin;     // nodes; first tile in the batch numbering
     double cv, s_c, rho, dt;
     double beta;                // NP law (launches of the NP kernel only)
+    double *lps;                // the solid: [n] {c, d, h, 0} (lps_coef) from its state pass
+    double vol, bulk, shear;    // the solid: the (uniform) nodal volume and the moduli
     int damage, cur0, vhalf0;
     int cd;                     // central-difference steps after the chunk's first (Verlet) step
     int64_t ramp, step0, limit;
@@ -447,13 +493,18 @@ bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, ui
                       size_t *lds, int max_per_cu);
 // streamed kernel (explicit steps with uniform volumes) ----------------------
 
+// Forms of the streamed kernel: the linearised law, the NP law, and the two
+// passes of the linear peridynamic solid (3-d, single simulation).  A solid
+// step is a state-pass launch followed by a force-pass launch; its geometry
+// is that of the force pass, whose LDS layout is the larger.
+enum { SK_LINEAR = 0, SK_NP = 1, SK_LPS_STATE = 2, SK_LPS_FORCE = 3 };
 // (batch: the kernel form that reads descriptors from device memory)
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, bool np, int *block,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, int form, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds);
 bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total);
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const pdk::StreamArgs &sa, int lanes,
-                     bool mixed, bool np, int block, unsigned grid, size_t lds);
+                     bool mixed, int form, int block, unsigned grid, size_t lds);
 // a simulation's streamed descriptor (static part), the launch arguments of a
 // batch shaped like it (inst NULL: single-simulation form), and its host state
 // after streamed steps

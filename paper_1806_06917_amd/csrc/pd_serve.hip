@@ -338,7 +338,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         const int64_t k = std::min(s->chunk, r->nsteps - r->done);
         if (k <= 0) continue;
         const pd_sim m = r->sim;
-        if (m->stream) {
+        if (m->stream && m->s_form != SK_LPS_FORCE) {
             Chunk &c = chunks[GroupKey(m->nbr->dim, m->lanes, m->nbr->tile_T,
                                        (int)m->mat.precision, m->mat.law)];
             c.sims.push_back(m);

@@ -117,11 +117,12 @@ inline __host__ __device__ uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; 
 // LDS layout, in this order (every region a multiple of 16 bytes): the tile
 // slot (records, bond words, row offsets, v, boundary kinds), two halo-id
 // slots, three break lists (tile k uses list k mod 3, so a list is cleared
-// one tile before its next use without an extra barrier), tile metadata.
+// one tile before its next use without an extra barrier), tile metadata,
+// and for the solid's force pass the halo's coefficients {c, d, h, 0}.
 struct StreamLayout {
-    uint32_t H, T, WB, TP, TB, MM, RD, US;
+    uint32_t H, T, WB, TP, TB, MM, RD, US, SP;
     __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile,
-                                     uint32_t mmax) {
+                                     uint32_t mmax, int form) {
         H = hcap;                      // multiple of 32
         T = tile;
         WB = round4(bcap / 2 + 2);     // 32-bit bond-word pairs
@@ -130,11 +131,12 @@ struct StreamLayout {
         MM = round4(mmax * META);
         RD = dim == 3 ? 6 : 4;         // doubles per record
         US = dim == 3 ? 4 : 2;         // doubles per node in v
+        SP = form == SK_LPS_FORCE ? 4 * hcap : 0u;   // doubles of staged {c, d, h, 0}
     }
     __host__ __device__ size_t bytes() const {
         return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)WB * 4 + (size_t)TP * 4 +
                (size_t)T * US * 8 + (size_t)TB * 4 + (size_t)3 * (BRK_CAP + 4) * 4 +
-               (size_t)MM * 4;
+               (size_t)MM * 4 + (size_t)SP * 8;
     }
 };
 
@@ -145,12 +147,18 @@ __device__ __forceinline__ double ramp_of(double s, int64_t ramp) {
 }
 
 // BATCH = false: one simulation whose descriptor travels in the kernel
-// arguments (sa.one); true: sa.ninst descriptors in device memory.
-template <int DIM, int L, bool MIXED, bool BATCH, bool NP>
+// arguments (sa.one); true: sa.ninst descriptors in device memory.  FORM:
+// SK_LINEAR or SK_NP (one launch per step), SK_LPS_STATE (the solid's first
+// pass: {m, theta} per node into I.lps, no update) or SK_LPS_FORCE (its
+// force, with the neighbours' {m, theta} staged beside the records, and the
+// node update).
+template <int DIM, int L, bool MIXED, bool BATCH, int FORM>
 __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     extern __shared__ __attribute__((aligned(16))) double lds[];
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
-    const StreamLayout lay(DIM, sa.hcap, sa.bcap, sa.tile, sa.mmax);
+    constexpr bool NP = FORM == SK_NP, LPS = FORM == SK_LPS_STATE || FORM == SK_LPS_FORCE;
+    static_assert(!LPS || (DIM == 3 && !BATCH), "the solid: 3-d, single simulation");
+    const StreamLayout lay(DIM, sa.hcap, sa.bcap, sa.tile, sa.mmax, FORM);
     const uint32_t H = lay.H, T = lay.T;
     const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u, wbase = tid - lane64;
     double *rec = lds;                                                           // H RD
@@ -161,6 +169,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)T * US);         // TB
     uint32_t *brk = bcb + lay.TB;                                                // 3 (4 + CAP)
     uint32_t *meta = brk + 3 * (BRK_CAP + 4);                                    // MM
+    double *sps = reinterpret_cast<double *>(meta + lay.MM);                     // SP
     const StreamInst *inst = sa.inst;
     const int64_t s = sa.step;                          // step of this launch in its chunk
     // the record buffer holding u at this step
@@ -248,15 +257,26 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rowp + c0));
             if (c0 + lane64 <= tn) dma4(rp, (t0 + c0 + lane64) * 4u, m0);
         }
-        const uint32_t nvc = tn * US / 2;
+        // v and the boundary kinds feed the node update (not in the state pass)
+        const uint32_t nvc = FORM == SK_LPS_STATE ? 0u : tn * US / 2;
         for (uint32_t c0 = wbase; c0 < nvc; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(vbuf + 2 * (size_t)c0));
             if (c0 + lane64 < nvc) dma16(vv, (t0 * US + 2 * (c0 + lane64)) * 8u, m0);
         }
-        const uint32_t nbw = (tn + 3) / 4;   // the array is padded to whole words
+        const uint32_t nbw = FORM == SK_LPS_STATE ? 0u : (tn + 3) / 4;   // padded to words
         for (uint32_t c0 = wbase; c0 < nbw; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(bcb + c0));
             if (c0 + lane64 < nbw) dma4(bc, t0 + 4 * (c0 + lane64), m0);
+        }
+        if constexpr (FORM == SK_LPS_FORCE) {
+            // {c, d, h, 0} of every halo node: two 16-byte copies each
+            const void *ls = I.lps;
+            const uint32_t nsc = 2 * hn;
+            for (uint32_t c0 = wbase; c0 < nsc; c0 += B) {
+                const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(sps + 2 * (size_t)c0));
+                const uint32_t c = c0 + lane64;
+                if (c < nsc) dma16(ls, (uint32_t)hid[c >> 1] * 32u + (c & 1u) * 16u, m0);
+            }
         }
     };
 
@@ -285,12 +305,12 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             const double uix = ri[DIM], uiy = ri[DIM + 1], uiz = DIM == 3 ? ri[DIM + 2] : 0.0;
             Acc64 acc;
             const uint32_t rs = rowp[q] - b0, re = rowp[q + 1] - b0;
-            for (uint32_t p = rs + lane; p < re; p += L) {
-                const uint32_t w = w16[p];
+            // xi and eta of the bond whose word is w
+            auto bond_vectors = [&](uint32_t w, double &dxx, double &dxy, double &dxz,
+                                    double &dux, double &duy, double &duz) {
                 const double2 *rj =
                     reinterpret_cast<const double2 *>(rec + (size_t)(w & 0x7fffu) * RD);
                 const double2 c0 = rj[0], c1 = rj[1];
-                double dxx, dxy, dxz, dux, duy, duz;
                 if (DIM == 3) {
                     const double2 c2 = rj[2];
                     dxx = c0.x - xix; dxy = c0.y - xiy; dxz = c1.x - xiz;
@@ -299,12 +319,61 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     dxx = c0.x - xix; dxy = c0.y - xiy; dxz = 0.0;
                     dux = c1.x - uix; duy = c1.y - uiy; duz = 0.0;
                 }
-                if (bond<DIM, MIXED, false, NP>(damage, s_c, dxx, dxy, dxz, dux, duy, duz, cv,
-                                                (w & BW_DEAD) != 0, acc, beta)) {
-                    const uint32_t nw = (uint32_t)(w | BW_DEAD);
-                    w16[p] = (uint16_t)nw;
-                    const uint32_t e = atomicAdd(bl, 1u);
-                    if (e < BRK_CAP) bl[4 + e] = (p << 16) | nw;
+            };
+            if constexpr (FORM == SK_LPS_STATE) {
+                // the solid's first pass, as lps_state_k: m_i and theta_i over
+                // live bonds (uniform V_j), in the same order
+                double m = 0.0, sm = 0.0;
+                for (uint32_t p = rs + lane; p < re; p += L) {
+                    const uint32_t w = w16[p];
+                    if (w & BW_DEAD) continue;
+                    double dxx, dxy, dxz, dux, duy, duz, len, e, iy;
+                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
+                    lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
+                    lps_state_terms(len, e, I.vol, m, sm);
+                }
+                m = lane_sum<L>(m);
+                sm = lane_sum<L>(sm);
+                if (lane == 0) {
+                    const LpsCoef qc = lps_coef(m, m > 0.0 ? 3.0 / m * sm : 0.0, I.bulk, I.shear);
+                    reinterpret_cast<double4 *>(I.lps)[t0 + q] = make_double4(qc.c, qc.d, qc.h, 0.0);
+                }
+                continue;
+            } else if constexpr (FORM == SK_LPS_FORCE) {
+                // the solid's force, as the gather kernel's branch: the
+                // scatter read from node i with {m, theta} of both ends
+                auto coef_of = [&](uint32_t j) {
+                    const double2 cd = *reinterpret_cast<const double2 *>(sps + 4 * (size_t)j);
+                    LpsCoef r;
+                    r.c = cd.x;
+                    r.d = cd.y;
+                    r.h = sps[4 * (size_t)j + 2];
+                    return r;
+                };
+                const LpsCoef qi = coef_of(so + q);
+                for (uint32_t p = rs + lane; p < re; p += L) {
+                    const uint32_t w = w16[p];
+                    double dxx, dxy, dxz, dux, duy, duz, len, e, iy;
+                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
+                    lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
+                    const double g = lps_force_weight(qi, coef_of(w & 0x7fffu), len, e, iy, I.vol,
+                                                      (w & BW_DEAD) == 0);
+                    acc.x = fma(g, dxx + dux, acc.x);
+                    acc.y = fma(g, dxy + duy, acc.y);
+                    acc.z = fma(g, dxz + duz, acc.z);
+                }
+            } else {
+                for (uint32_t p = rs + lane; p < re; p += L) {
+                    const uint32_t w = w16[p];
+                    double dxx, dxy, dxz, dux, duy, duz;
+                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
+                    if (bond<DIM, MIXED, false, NP>(damage, s_c, dxx, dxy, dxz, dux, duy, duz,
+                                                    cv, (w & BW_DEAD) != 0, acc, beta)) {
+                        const uint32_t nw = (uint32_t)(w | BW_DEAD);
+                        w16[p] = (uint16_t)nw;
+                        const uint32_t e = atomicAdd(bl, 1u);
+                        if (e < BRK_CAP) bl[4 + e] = (p << 16) | nw;
+                    }
                 }
             }
             double fx, fy, fz, Ue;
@@ -384,19 +453,20 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     }
 }
 
-template <int DIM>
-void *pick_np(int lanes, bool mixed, bool batch);
-
-template <int DIM>
-void *pick_stream(int lanes, bool mixed, bool batch, bool np) {
-    if (np) return pick_np<DIM>(lanes, mixed, batch);
+// the kernel of a form: lanes 2..32, both precisions, single or batch (the
+// solid: 3-d, single simulation only)
+template <int DIM, int FORM>
+void *pick_form(int lanes, bool mixed, bool batch) {
 #define PD_SK(Lv)                                                                          \
     case Lv:                                                                               \
-        if (batch)                                                                         \
-            return mixed ? (void *)stream_kernel<DIM, Lv, true, true, false>               \
-                         : (void *)stream_kernel<DIM, Lv, false, true, false>;             \
-        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, false>                  \
-                     : (void *)stream_kernel<DIM, Lv, false, false, false>;
+        if (batch) {                                                                       \
+            if constexpr (FORM == SK_LINEAR || FORM == SK_NP)                              \
+                return mixed ? (void *)stream_kernel<DIM, Lv, true, true, FORM>            \
+                             : (void *)stream_kernel<DIM, Lv, false, true, FORM>;          \
+            return nullptr;                                                                \
+        }                                                                                  \
+        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, FORM>                   \
+                     : (void *)stream_kernel<DIM, Lv, false, false, FORM>;
     switch (lanes) {
         PD_SK(2)
         PD_SK(4)
@@ -408,25 +478,19 @@ void *pick_stream(int lanes, bool mixed, bool batch, bool np) {
 #undef PD_SK
 }
 
-// the NP-law instances of the streamed kernel
 template <int DIM>
-void *pick_np(int lanes, bool mixed, bool batch) {
-#define PD_SKN(Lv)                                                                         \
-    case Lv:                                                                               \
-        if (batch)                                                                         \
-            return mixed ? (void *)stream_kernel<DIM, Lv, true, true, true>                \
-                         : (void *)stream_kernel<DIM, Lv, false, true, true>;              \
-        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, true>                   \
-                     : (void *)stream_kernel<DIM, Lv, false, false, true>;
-    switch (lanes) {
-        PD_SKN(2)
-        PD_SKN(4)
-        PD_SKN(8)
-        PD_SKN(16)
-        PD_SKN(32)
+void *pick_stream(int lanes, bool mixed, bool batch, int form) {
+    switch (form) {
+    case SK_LINEAR: return pick_form<DIM, SK_LINEAR>(lanes, mixed, batch);
+    case SK_NP: return pick_form<DIM, SK_NP>(lanes, mixed, batch);
+    case SK_LPS_STATE:
+        if constexpr (DIM == 3) return pick_form<3, SK_LPS_STATE>(lanes, mixed, batch);
+        return nullptr;
+    case SK_LPS_FORCE:
+        if constexpr (DIM == 3) return pick_form<3, SK_LPS_FORCE>(lanes, mixed, batch);
+        return nullptr;
     default: return nullptr;
     }
-#undef PD_SKN
 }
 
 // records {x y z ux uy uz} (2-d {x y ux uy}) from xv and u
@@ -454,14 +518,14 @@ __global__ void rec_unpack_k(uint32_t n, const double *rec, double *u) {
 // Launch geometry of the streamed kernel for ntiles tiles in total; false if
 // it cannot run this layout.
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, bool np, int *block,
+                        uint32_t bcap, int lanes, bool mixed, bool batch, int form, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds) {
     const uint32_t B = tile * (uint32_t)lanes;
     if (B < 64 || B > 1024 || B % 64 != 0) return false;
     if (lanes < dim) return false;   // the node update takes one lane per component
     if (bcap >= (1u << 16)) return false;   // 16-bit tile-local bond positions
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, np)
-                       : pick_stream<2>(lanes, mixed, batch, np);
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, form)
+                       : pick_stream<2>(lanes, mixed, batch, form);
     if (!k) return false;
     for (int pass = 0; pass < 2; ++pass) {
         // first pass: one workgroup per CU gives the tile bound; second pass:
@@ -469,7 +533,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
         unsigned g = (unsigned)ctx->num_cu;
         if (pass == 1) {
             int per_cu = 0;
-            const size_t bytes = StreamLayout(dim, hcap, bcap, tile, *mmax).bytes();
+            const size_t bytes = StreamLayout(dim, hcap, bcap, tile, *mmax, form).bytes();
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, (int)B,
                                                              bytes) != hipSuccess)
@@ -491,7 +555,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
             const uint32_t kk = (tc + gx - 1) / gx;
             if (kk > m) m = kk;
         }
-        const size_t bytes = StreamLayout(dim, hcap, bcap, tile, m).bytes();
+        const size_t bytes = StreamLayout(dim, hcap, bcap, tile, m, form).bytes();
         if (bytes > 160 * 1024) return false;
         *mmax = m;
         *lds = bytes;
@@ -509,11 +573,12 @@ bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total) {
 }
 
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const StreamArgs &sa, int lanes,
-                     bool mixed, bool np, int block, unsigned grid, size_t lds) {
+                     bool mixed, int form, int block, unsigned grid, size_t lds) {
     const bool batch = sa.inst != nullptr;
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, np)
-                       : pick_stream<2>(lanes, mixed, batch, np);
-    if (!k) return pd_set_error(ctx, PD_EINVAL, "streamed kernel needs 2..32 lanes");
+    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, form)
+                       : pick_stream<2>(lanes, mixed, batch, form);
+    if (!k) return pd_set_error(ctx, PD_EINVAL, "no streamed kernel of form %d for %d lanes", form,
+                                lanes);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     StreamArgs args = sa;
     void *argv[] = {&args};

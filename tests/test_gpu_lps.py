@@ -111,3 +111,70 @@ def test_lps_argument_errors(gpu):
         pd.apply_tangent(ctx, nb, lps, Xd, Vd, y, torch.zeros_like(y))
     assert e.value.status == pd.PD_EINVAL
     nb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lps_streamed_equals_gather(gpu, orc, prec):
+    """Equal nodal volumes put the solid's explicit steps on the streamed
+    kernel (state pass, then force pass, per step); they agree with the
+    gather kernel bit for bit through Verlet, central-difference and Verlet
+    steps with clamped and prescribed-velocity layers, and with the oracle."""
+    torch, pd, ctx = gpu
+    N = 14
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * 3, h, jitter=0.05, seed=107)
+    n = len(X)
+    V = np.full(n, h ** 3)
+    K, mu = orc.lps_moduli(1.0, 0.3)
+    v0 = inputs.random_field(n, 3, 108, scale=1e-2)
+    kind = np.zeros(n, np.uint8)
+    kind[X[:, 2] < 1.5 * h] = inputs.BC_CLAMPED
+    kind[X[:, 2] > 1.0 - 1.5 * h] = inputs.BC_VELOCITY
+    bvel = np.zeros((n, 3))
+    bvel[kind == inputs.BC_VELOCITY, 2] = 2e-3
+    v0[kind != inputs.BC_FREE] = 0.0
+    dt = 0.02 * h
+    out = []
+    for kern in ("stream", "gather"):
+        say("LPS streamed vs gather", kern, prec)
+        ctx.set_tuning(kern, 0, 0)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, X), 3 * h)
+            mat = pd.material(3, 0.0, 1.0, 0.0, prec, law="lps", bulk=K, shear=mu)
+            sim = pd.Simulation(ctx, nb, mat, dev(torch, X), dev(torch, V), None, dev(torch, v0),
+                                bc_kind=dev(torch, kind), bc_vel=dev(torch, bvel), ramp_steps=10)
+            assert sim.info()["kernel"] == kern
+            sim.step(25, dt)
+            sim.central_step(10, dt)
+            sim.step(5, dt)
+            u, v, _, info = read_state(torch, sim, n, 3, nb.nnz)
+            out.append((u, v, info))
+            sim.close()
+            nb.close()
+        finally:
+            ctx.set_tuning(0, 0, 0)
+    (us, vs, _), (ug, vg, ig) = out
+    assert np.array_equal(us, ug) and np.array_equal(vs, vg)
+    assert ig["step"] == 40
+    # the oracle over the same schedule
+    mesh = orc.LpsMesh(X, V, 3 * h)
+    st = mesh.start_lps(np.zeros_like(v0), v0, K, mu)
+    mesh.verlet_lps(st, K, mu, 1.0, dt, 25, bc_kind=kind, bc_vel=bvel, ramp=10)
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    # (the central-difference part is checked against the gather path above;
+    # the first 25 steps are checked here)
+    ctx.set_tuning("stream", 0, 0)
+    try:
+        nb = pd.Neighbors(ctx, dev(torch, X), 3 * h)
+        sim = pd.Simulation(ctx, nb, pd.material(3, 0.0, 1.0, 0.0, prec, law="lps", bulk=K,
+                                                 shear=mu),
+                            dev(torch, X), dev(torch, V), None, dev(torch, v0),
+                            bc_kind=dev(torch, kind), bc_vel=dev(torch, bvel), ramp_steps=10)
+        sim.step(25, dt)
+        u, v, _, _ = read_state(torch, sim, n, 3, nb.nnz)
+        sim.close()
+        nb.close()
+    finally:
+        ctx.set_tuning(0, 0, 0)
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
