@@ -108,7 +108,9 @@ typedef struct pd_server_s *pd_server;
  *              node i; it needs symmetric bond flags, as cut and damage
  *              flags are); energy W_i = (K/2) theta_i^2 +
  *              (15 mu/(2 m_i)) sum (e - theta_i |xi|/3)^2 V_j.  No damage
- *              (s_c must be <= 0), no tangent or implicit solve.
+ *              (s_c must be <= 0), no tangent or implicit solve.  Both
+ *              kernels evaluate t through the per-node coefficients
+ *              3 K theta/m, 15 mu/m and theta/3.
  *   pv_h       partial volumes (the correction the paper names without a
  *              formula; read as the partial-area rule): with pv_h = h > 0 and
  *              the neighbour list built at radius R = delta + h/2, each
@@ -123,8 +125,10 @@ typedef struct pd_server_s *pd_server;
  *              kernel only; not for the tangent or the implicit solve.
  * A zero-filled law/stretch/beta is the linearised law of Algorithm 1.  The
  * tiled kernels run that law, and the streamed step kernel also the NP law
- * with the linearised stretch and no damage (its other calls then run on the
- * gather kernel); every other combination runs on the gather kernel
+ * with the linearised stretch and no damage, and the solid's explicit steps
+ * without partial volumes (a state pass and a force pass per step, single
+ * simulations only: pd_batch_step rejects them); the other calls of such
+ * simulations, and every other combination, run on the gather kernel
  * (pd_sim_info kernel 1).  The tangent and the implicit solve take the
  * linearised stretch of a pairwise law only (PD_EINVAL otherwise).
  */

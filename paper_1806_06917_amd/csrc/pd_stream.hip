@@ -1,7 +1,10 @@
 // Streamed tiles: the explicit step (velocity Verlet with the bond-force
 // gather, critical-stretch damage and boundary data; Algorithm 4 with the
 // force of Algorithm 1) over LDS tiles whose staging runs asynchronously, for
-// one simulation or a batch of independent ones in the same launch.
+// one simulation or a batch of independent ones in the same launch; also the
+// NP law's step and the two passes of the linear peridynamic solid's step
+// (Algorithm 2: the state {m, theta}, then the force with the halo's per-node
+// coefficients staged beside the records).
 //
 // Same tiles as the register-staged tile kernel (T consecutive sfc nodes,
 // halo H_t, 16-bit tile-local bond words), but every global -> LDS copy is a
