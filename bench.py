@@ -212,14 +212,18 @@ def serve(pd, reqs, budget, chunk, rate=None):
             "max_running": most, "rounds": rounds, "peak_bytes": peak, "server": stats}
 
 
-def law_runs(torch, pd, steps):
-    """The other material laws (gather kernel): NP explicit steps on the
-    notched 512^2 plate, linear-peridynamic-solid steps (two passes per step)
-    on the 1M-node cube, and the NP Newton-Krylov solve of the 400 x 40 bar
-    (beta set so that beta |xi| S^2 reaches 0.1 at the linear solution)."""
+def law_runs(torch, pd, steps, tuned=None):
+    """The other material laws: NP explicit steps on the notched 512^2 plate
+    and linear-peridynamic-solid steps (two passes per step) on the 1M-node
+    cube, both on the streamed kernel, and the NP Newton-Krylov solve of the
+    400 x 40 bar (beta set so that beta |xi| S^2 reaches 0.1 at the linear
+    solution).  tuned: (dim, mean neighbours, precision, tile, lanes) entries
+    of the autotuner to seed this context with."""
     from paper_1806_06917_amd import inputs
     out = {}
     ctx = pd.Context(0)
+    for t in tuned or ():
+        ctx.tune_set(*t)
     w = inputs.CONFIGS["notched512"]()
     progress("NP law, explicit steps,", w.name)
     X = dev(torch, w.X)
@@ -504,7 +508,13 @@ def main():
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
         out["fp64_launch"] = r64["launch"]
     if not args.no_law:
-        out["law"] = law_runs(torch, pd, 200)
+        # the solid's cube steps use the autotuner's shape for this mesh kind
+        seeds = []
+        for prec, rr in ((precision, r), ("fp64", r64 if "fp64_launch" in out else None)):
+            if rr is not None and rr["autotune"]:
+                b = rr["autotune"]["best"]
+                seeds.append((w.dim, rr["nnz"] / w.n, b["tile"], b["lanes"], prec))
+        out["law"] = law_runs(torch, pd, 200, seeds)
     if not args.no_serve:
         from paper_1806_06917_amd import inputs
         budget = int(args.serve_budget_gib * (1 << 30))
