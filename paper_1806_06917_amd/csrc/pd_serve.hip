@@ -49,11 +49,12 @@ double now_s() {
 // device bytes of a simulation and its neighbour list, from the sizes the
 // library allocates (tiles and records included)
 int64_t footprint(int dim, int64_t n, int64_t nnz, int64_t halo_total, int64_t ntiles,
-                  bool bc_vel) {
+                  bool bc_vel, bool lps) {
     const int64_t us = dim == 3 ? 4 : 2, rd = dim == 3 ? 6 : 4;
     const int64_t nbr = 16 * n + 8 + 10 * nnz + 4 * halo_total + 8 * ntiles + 8;
     const int64_t sim = 32 * n + 3 * 8 * us * n + (n + 16) + nnz + 16 * n +
-                        (bc_vel ? 8 * us * n : 0) + 2 * nnz + 4 + 2 * 8 * rd * n;
+                        (bc_vel ? 8 * us * n : 0) + 2 * nnz + 4 + 2 * 8 * rd * n +
+                        (lps ? 48 * n : 0);   // the solid's {m, theta} and coefficients
     return nbr + sim;
 }
 
@@ -69,7 +70,8 @@ int64_t estimate(const Req &r) {
     const double k = vmean > 0 ? ball / vmean : 0.0;
     const int64_t nnz = (int64_t)(k * (double)r.n) + r.n;
     const int64_t tile = r.dim == 3 ? 64 : 128, ratio = r.dim == 3 ? 12 : 5;
-    return footprint(r.dim, r.n, nnz, ratio * r.n, r.n / tile + 1, !r.bc_vel.empty());
+    return footprint(r.dim, r.n, nnz, ratio * r.n, r.n / tile + 1, !r.bc_vel.empty(),
+                     r.mat.law == PD_LAW_LPS);
 }
 
 }  // namespace
@@ -240,7 +242,8 @@ static int admit(pd_server s, Req *r) {
     r->info.bonds = (int64_t)b->nnz;
     r->info.bytes = std::max(r->estimate,
                              footprint(r->dim, r->n, (int64_t)b->nnz, (int64_t)b->halo_total,
-                                       (int64_t)b->ntiles, !r->bc_kind.empty()));
+                                       (int64_t)b->ntiles, !r->bc_vel.empty(),
+                                       r->mat.law == PD_LAW_LPS));
     return PD_OK;
 }
 
