@@ -115,3 +115,23 @@ def test_verlet_with_influence_second_order(orc):
     d1, d2 = drift(0.1 * h, 40), drift(0.05 * h, 80)
     assert d1 < 1e-3
     assert 2.5 < d1 / d2 < 6.0
+
+
+@pytest.mark.parametrize("m", [2, 4, 8])
+def test_line_meshes_nest(m):
+    """The 1-d study's meshes: cell-centred on [-delta, 1+delta], each coarse
+    cell the union of two fine cells (the fine centres straddle the coarse
+    centre), collars of delta/h clamped cells at each end, the pulses inside
+    (0, 1) only, motion along x only; coarsen_line averages the pairs."""
+    a, b = inputs.convergence_line(m, 2), inputs.convergence_line(2 * m, 2)
+    assert b.n == 2 * a.n and a.n == int(round(1.02 * m / 0.01))
+    np.testing.assert_allclose(0.5 * (b.X[0::2, 0] + b.X[1::2, 0]), a.X[:, 0], atol=1e-15)
+    assert np.all(a.X[:, 1] == 0.0) and np.all(a.u0[:, 1] == 0.0)
+    clamped = a.bc_kind == inputs.BC_CLAMPED
+    assert clamped.sum() == 2 * m and np.all(a.u0[clamped] == 0.0)
+    assert np.all((a.X[~clamped, 0] > 0) & (a.X[~clamped, 0] < 1))
+    u = np.arange(2.0 * b.n).reshape(b.n, 2)
+    np.testing.assert_array_equal(inputs.coarsen_line(u, a.n), 0.5 * (u[0::2] + u[1::2]))
+    # IC 2: two pulses of amplitude a at 0.25 and 0.75
+    i1, i2 = np.argmin(abs(b.X[:, 0] - 0.25)), np.argmin(abs(b.X[:, 0] - 0.75))
+    assert abs(b.u0[i1, 0] - 1e-3) < 1e-5 and abs(b.u0[i2, 0] - 1e-3) < 1e-5
