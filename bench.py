@@ -50,10 +50,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, precision):
+def recorded_traffic(workload, precision, launch=None):
     """HBM bytes per launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
     scaled by a plain copy kernel) -- only if the kernel sources are unchanged
-    since the counters were taken."""
+    since the counters were taken and (launch given) the counters were taken
+    at the same tile size and lane count."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     text = open(TRAFFIC_SUMMARY).read()
@@ -64,6 +65,9 @@ def recorded_traffic(workload, precision):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     if rec.get("workload") != workload or rec.get("precision") != precision:
+        return None
+    if launch is not None and (rec.get("tile"), rec.get("lanes")) != (launch.get("tile"),
+                                                                       launch.get("lanes")):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -495,7 +499,7 @@ def main():
                    "precision": precision, "dt": w.dt, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(w.name, precision),
+                     "traffic": recorded_traffic(w.name, precision, r["launch"]),
                      "algorithmic_bytes_per_launch": B,
                      "kernel_source_hash": kernel_source_hash()},
         "neighbor_build_s": r["t_nbr_s"],

@@ -223,7 +223,7 @@ int pd_ctx_set_tuning(pd_ctx ctx, int kernel, int tile, int block);
  * pd_autotune builds the neighbour list of (X, V, delta) -- device arrays as
  * in pd_build_neighbors -- and, for each candidate tile size x lanes per node
  * (T * lanes in [256, 1024]: 32x8, 32x16, 64x4, 64x8, 64x16, 128x2, 128x4,
- * 128x8, 256x2, 256x4), creates a simulation at rest with damage on, runs 2
+ * 128x8, 192x4, 240x4, 256x2, 256x4), creates a simulation at rest with damage on, runs 2
  * warm-up steps and times `steps` explicit steps (pd_verlet_step) with HIP
  * events on the context's stream.  The fastest is cached in the context
  * under (dim, mean-neighbour-count bucket, precision), the buckets split

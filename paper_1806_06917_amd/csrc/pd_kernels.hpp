@@ -1,7 +1,9 @@
-// Device code shared by the node kernels: bond law (Algorithm 1, linearised,
-// J = 1), damage test, per-node butterfly reduction and the node update
-// (force output, tangent output, energies, velocity-Verlet half-kicks and
-// drift with boundary data).
+// Device code shared by the node kernels: the bond laws (Algorithm 1,
+// linearised or general: the NP potential, the exact stretch, partial
+// volumes and the influence function; the linear peridynamic solid's bond
+// terms of Algorithm 2), the damage test, the per-node lane reduction and
+// the node update (force output, tangent output, energies, velocity-Verlet
+// half-kicks and drift with boundary data, central differences).
 #pragma once
 
 #include <type_traits>

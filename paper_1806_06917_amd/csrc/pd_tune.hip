@@ -14,9 +14,10 @@
 namespace {
 
 // tile sizes x lanes per node with T * lanes in [256, 1024] threads: the
-// shapes the tile kernels are built for (one lane group per tile node)
-constexpr int CAND[][2] = {{32, 8},  {32, 16}, {64, 4},  {64, 8},  {64, 16},
-                           {128, 2}, {128, 4}, {128, 8}, {256, 2}, {256, 4}};
+// shapes the tile kernels are built for (one lane group per tile node); the
+// large 4-lane tiles (192, 240) cut the per-node work per bond of 3-d meshes
+constexpr int CAND[][2] = {{32, 8},  {32, 16}, {64, 4},  {64, 8},  {64, 16}, {128, 2},
+                           {128, 4}, {128, 8}, {192, 4}, {240, 4}, {256, 2}, {256, 4}};
 constexpr int NCAND = (int)(sizeof(CAND) / sizeof(CAND[0]));
 
 struct Events {

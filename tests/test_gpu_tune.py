@@ -11,8 +11,8 @@ from test_gpu_parity import TOL64, TOLMIX, dev, read_state, relL2, sim_from_work
 
 pytestmark = pytest.mark.gpu
 
-CANDIDATES = [(32, 8), (32, 16), (64, 4), (64, 8), (64, 16),
-              (128, 2), (128, 4), (128, 8), (256, 2), (256, 4)]
+CANDIDATES = [(32, 8), (32, 16), (64, 4), (64, 8), (64, 16), (128, 2),
+              (128, 4), (128, 8), (192, 4), (240, 4), (256, 2), (256, 4)]
 
 
 def moving_plate(N, m):
