@@ -263,13 +263,9 @@ int pd_launch_gather(pd_ctx ctx, int dim, const NodeArgs &a, int lanes, bool mix
     return dim == 3 ? launch_d<3>(ctx, a, lanes, mixed) : launch_d<2>(ctx, a, lanes, mixed);
 }
 
-static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int block) {
-    int rpt;
-    unsigned grid;
-    uint32_t mmax;
-    size_t lds;
-    return pd_tile_geometry(nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                            pd_tile_bcap(nbr), block, ctx->num_cu, &rpt, &grid, &mmax, &lds, 0);
+static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, int block) {
+    return pd_tile_resident(nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
+                            pd_tile_bcap(nbr), lanes, block, ctx->num_cu);
 }
 
 // threads per tile workgroup for the tiles nbr holds now: the tuning value,
@@ -280,7 +276,7 @@ static int tile_block(pd_ctx ctx, const pd_nbr nbr, int lanes) {
     if (ctx->block) return ctx->block;
     int block = (int)nbr->tile_T * lanes;
     block = block < 256 ? 256 : (block > 1024 ? 1024 : block);
-    while (block < 1024 && !tile_fits(ctx, nbr, block)) block *= 2;
+    while (block < 1024 && !tile_fits(ctx, nbr, lanes, block)) block *= 2;
     return block;
 }
 
@@ -299,7 +295,7 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
     }
     if (nbr->lcol && nbr->users > 0) {
         const int B = tile_block(ctx, nbr, lanes);
-        if (tile_fits(ctx, nbr, B)) *block = B;
+        if (tile_fits(ctx, nbr, lanes, B)) *block = B;
         else if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit");
         return PD_OK;
     }
@@ -320,7 +316,7 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
             }
         }
         const int B = tile_block(ctx, nbr, lanes);
-        if (tile_fits(ctx, nbr, B)) {
+        if (tile_fits(ctx, nbr, lanes, B)) {
             *block = B;
             return PD_OK;
         }

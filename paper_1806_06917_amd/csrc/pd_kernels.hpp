@@ -488,6 +488,9 @@ int pd_launch_tile(pd_ctx ctx, int dim, const pdk::NodeArgs &a, int lanes, bool 
                    int block);
 // LDS bytes of one tile-kernel workgroup
 size_t tile_lds_bytes(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile, uint32_t mmax);
+// the tile layout fits and every form of the tile kernel can be resident
+bool pd_tile_resident(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
+                      int lanes, int block, int num_cu);
 // launch geometry of the persistent tile kernel; false if the layout does not fit
 // (max_per_cu > 0 caps the workgroups per CU)
 bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,

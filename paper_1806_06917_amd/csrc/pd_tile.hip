@@ -480,6 +480,33 @@ bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, ui
     return false;
 }
 
+// the layout fits and every form of the kernel a simulation may launch on it
+// (both precisions, with and without energies) can be resident at `block`
+// threads: some forms need more registers than others
+bool pd_tile_resident(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, uint32_t bcap,
+                      int lanes, int block, int num_cu) {
+    int rpt = 0;
+    unsigned grid = 0;
+    uint32_t mmax = 0;
+    size_t lds = 0;
+    if (!pd_tile_geometry(dim, ntiles, tile, hcap, bcap, block, num_cu, &rpt, &grid, &mmax, &lds,
+                          0))
+        return false;
+    for (int mixed = 0; mixed < 2; ++mixed)
+        for (int e = 0; e < 2; ++e) {
+            void *k = dim == 3 ? pick_lanes<3>(lanes, mixed != 0, e != 0, rpt)
+                               : pick_lanes<2>(lanes, mixed != 0, e != 0, rpt);
+            if (!k) return false;
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k, block, lds) !=
+                    hipSuccess ||
+                occ < 1)
+                return false;
+        }
+    return true;
+}
+
 int pd_launch_tile(pd_ctx ctx, int dim, const NodeArgs &a0, int lanes, bool mixed, int block) {
     NodeArgs a = a0;
     int rpt = 0;
