@@ -268,6 +268,17 @@ static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, int block) {
                             pd_tile_bcap(nbr), lanes, block, ctx->num_cu);
 }
 
+// the streamed kernel of this form can run on the tiles nbr holds now
+static bool stream_form_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, bool mixed, int form) {
+    int b = 0;
+    unsigned g = 0;
+    uint32_t m = 0;
+    size_t l = 0;
+    return nbr->lcol && pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
+           pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
+                              pd_tile_bcap(nbr), lanes, mixed, false, form, &b, &g, &m, &l);
+}
+
 // threads per tile workgroup for the tiles nbr holds now: the tuning value,
 // else one lane group per tile node (measured best on the 1M-node cube and
 // the 512^2 plate), doubled while the halo or the bond words of the largest
@@ -604,6 +615,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
     const pd_tune_entry *te = nullptr;
+    bool layout_only = false;
     // the NP law without damage also runs on the streamed kernel (its other
     // calls, and every other general law, on the gather kernel)
     const bool np_stream = mat->law == PD_LAW_NP && mat->stretch == PD_STRETCH_LINEARISED &&
@@ -624,10 +636,29 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         const int st = pd_plan_kernel(ctx, nbr, lanes, &block);
         ctx->tile = 0;
         PD_TRY(st);
-        if (block == 0) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+        layout_only = block == 0 && nbr->lcol && nbr->tile_T == (uint32_t)te->tile;
+        // the tuned shape (timed on the linearised law) must also fit this
+        // material's streamed form (the solid stages more per halo node);
+        // else the automatic choice
+        if ((block > 0 || layout_only) && !stream_form_fits(ctx, nbr, lanes,
+                                                            mat->precision == PD_MIXED,
+                                                            lps_stream ? SK_LPS_FORCE
+                                                                       : (np_stream ? SK_NP
+                                                                                    : SK_LINEAR))) {
+            block = 0;
+            layout_only = false;
+            lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+        }
+        if (block == 0 && !layout_only) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
     } else {
         PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+        layout_only = block == 0 && ctx->tile != 0 && nbr->lcol &&
+                      nbr->tile_T == (uint32_t)ctx->tile;
     }
+    // tiles built at the requested size whose tile kernel cannot be resident
+    // there still serve the streamed steps; the simulation's other calls then
+    // run on the gather kernel (layout_only, dropped again if it cannot stream)
+    if (general || !(ctx->kernel == 0 || ctx->kernel == 3)) layout_only = false;
     pd_sim s = new (std::nothrow) pd_sim_s();
     if (!s) return PD_ENOMEM;
     s->ctx = ctx;
@@ -665,7 +696,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     // the tile kernel for the other calls (those of the NP law and the solid
     // run on the gather kernel)
     s->block = (np_stream || lps_stream) ? 0 : block;
-    if (st == PD_OK && block > 0) {
+    if (st == PD_OK && (block > 0 || layout_only)) {
         s->tiled = true;
         nbr->users += 1;
         st = pd_alloc(ctx, &s->bw, nbr->nnz + 2);
@@ -698,6 +729,14 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[1]);
         s->stream = true;
         s->rec_stale = false;
+    }
+    if (st == PD_OK && block == 0 && s->tiled && !s->stream) {
+        // tiles without a resident tile kernel and no streamed steps: all
+        // calls on the gather kernel, with the flags (not bond words)
+        nbr->users -= 1;
+        pd_free(s->bw);
+        s->bw = nullptr;
+        s->tiled = false;
     }
     if (st == PD_OK && ctx->kernel == 3 && !s->stream)
         st = pd_set_error(ctx, PD_ECAPACITY, "the streamed kernel cannot run this simulation");
@@ -858,6 +897,20 @@ static int sim_sync_u(pd_sim sim) {
 }
 
 // completes the last step: force at u^N with the damage test, second half-kick
+// A force evaluation of a simulation outside its steps: on the tile kernel,
+// or, for tiles without a resident tile kernel (sim->block == 0), on the
+// gather kernel, which reads and writes the bond flags: the bond words' dead
+// bits go to the flags first and come back after
+static int sim_launch(pd_sim sim, const NodeArgs &a, bool mixed) {
+    const pd_ctx ctx = sim->ctx;
+    if (sim->tiled && sim->block == 0) {
+        PD_TRY(pd_bw_to_alive(ctx, sim->nbr, sim->bw, sim->alive));
+        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, mixed, 0));
+        return pd_bw_compose(ctx, sim->nbr, sim->alive, sim->bw);
+    }
+    return launch_node(ctx, sim->nbr, a, sim->lanes, mixed, sim->block);
+}
+
 static int sim_close(pd_sim sim) {
     PD_TRY(sim_sync_u(sim));
     if (!sim->v_half) return PD_OK;
@@ -866,8 +919,7 @@ static int sim_close(pd_sim sim) {
     a.mode = M_CLOSE;
     a.u = sim->u[sim->cur];
     a.r_full = ramp_factor((double)sim->step, sim->ramp);
-    PD_TRY(launch_node(sim->ctx, sim->nbr, a, sim->lanes, sim->mat.precision == PD_MIXED,
-                       sim->block));
+    PD_TRY(sim_launch(sim, a, sim->mat.precision == PD_MIXED));
     sim->v_half = false;
     return PD_OK;
 }
@@ -947,7 +999,7 @@ extern "C" int pd_sim_get(pd_sim sim, double *u, double *v, uint8_t *alive, doub
         a.damage = 0;
         a.u = sim->u[sim->cur];
         a.e_out = sim->scratch;
-        PD_TRY(launch_node(ctx, sim->nbr, a, sim->lanes, false, sim->block));
+        PD_TRY(sim_launch(sim, a, false));
         PD_TRY(pd_sum(ctx, sim->scratch, sim->nbr->n, 2, ke_pe));
     }
     if (step) *step = sim->step;
