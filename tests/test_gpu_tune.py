@@ -104,3 +104,42 @@ def test_autotune_cache_and_use(gpu):
             ctx.tune_set(2, k, 48, 3, "mixed")
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_tiles_stream_with_gather_side_calls(gpu, prec):
+    """240-node tiles with 4 lanes on a 3-d cube under tension with damage:
+    the steps stream (whether or not the LDS tile kernel can be resident at
+    that shape, in which case the closing half-kick and the energy read-back
+    run on the gather kernel with the bond flags synchronised), and the
+    trajectory, the breaks and the energies equal the gather kernel's bit for
+    bit through a read-back in the middle of the run."""
+    torch, pd, ctx = gpu
+    w = inputs.cube_3d(N=26, s_c=2e-4, v0=2e-2, steps=0, ramp_steps=5)
+    out = []
+    for kern, tile, lanes in (("stream", 240, 4), ("gather", 0, 4)):
+        say("large tiles", kern, prec)
+        ctx.set_lanes(lanes)
+        ctx.set_tuning(kern, tile, 0)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+            s = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(3, w.E, w.delta), prec)
+            info = s.info()
+            assert info["kernel"] == kern
+            if kern == "stream":
+                assert (info["tile"], info["lanes"]) == (240, 4)
+            s.step(20, w.dt)
+            mid = s.get(energies=True)
+            s.step(20, w.dt)
+            u, v, alive, end = read_state(torch, s, w.n, 3, nb.nnz)
+            out.append((u, v, alive, mid["ke"], mid["pe"], end["ke"], end["pe"]))
+            s.close()
+            nb.close()
+        finally:
+            ctx.set_lanes(0)
+            ctx.set_tuning(0, 0, 0)
+    a, b = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+    assert a[3:] == b[3:]
+    assert np.count_nonzero(a[2] == 0) > 0          # bonds did break
