@@ -316,7 +316,7 @@ int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block) {
         if (forced) return pd_set_error(ctx, PD_ECAPACITY, "tile layout does not fit in LDS");
         return PD_OK;
     }
-    uint32_t T = ctx->tile ? (uint32_t)ctx->tile : (nbr->dim == 3 ? 64u : 128u);
+    uint32_t T = ctx->tile ? (uint32_t)ctx->tile : 128u;
     for (; T >= 16; T >>= 1) {
         if (!(nbr->lcol && nbr->tile_T == T)) {
             const int st = pd_nbr_build_tiles(ctx, nbr, T);

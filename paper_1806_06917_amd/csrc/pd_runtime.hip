@@ -57,8 +57,8 @@ int pd_check_dev_ptr(pd_ctx ctx, const void *p, const char *name) {
 int pd_auto_lanes(pd_ctx ctx, uint64_t nnz, uint32_t n) {
     if (ctx && ctx->lanes > 0) return ctx->lanes;
     // about 16 bonds per lane: enough work per lane to amortise the lane
-    // reduction, and with 64-node (3-d) or 128-node (2-d) tiles 512-thread
-    // workgroups, two of which share a CU
+    // reduction; with the automatic 128-node tiles that gives 1024-thread
+    // (3-d, delta = 3h) or 512-thread (2-d, delta = 4h) workgroups
     const double k = n ? (double)nnz / (double)n : 0.0;
     int L = 1;
     while (L < 32 && L * 16 < k) L *= 2;
