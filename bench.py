@@ -164,10 +164,11 @@ def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)
     return res
 
 
-def serve(pd, reqs, budget, chunk, rate=None):
+def serve(pd, reqs, budget, chunk, rate=None, tile=0):
     """Runs the requests through pd_server_* with arrivals at their Poisson
     times (rate given) or all at once; returns completion-latency statistics
-    and the aggregate bond-evaluation rate."""
+    and the aggregate bond-evaluation rate.  tile: nodes per tile of the
+    requests' simulations (0: automatic)."""
     from paper_1806_06917_amd import inputs
     progress("serving", len(reqs), "requests", "burst" if rate is None else f"rate {rate:.1f}/s")
     loads = []
@@ -175,6 +176,7 @@ def serve(pd, reqs, budget, chunk, rate=None):
         w = inputs.serving_workload(q)
         loads.append((w, pd.micromodulus(w.dim, w.E, w.delta)))
     ctx = pd.Context(0)
+    ctx.set_tuning("auto", tile, 0)
     srv = pd.Server(ctx, budget, chunk_steps=chunk, lanes=4)
     t0 = pd.Server.clock()
     ids, k, most, rounds = [], 0, 0, 0

@@ -69,7 +69,7 @@ int64_t estimate(const Req &r) {
                                    : pi * r.delta * r.delta;
     const double k = vmean > 0 ? ball / vmean : 0.0;
     const int64_t nnz = (int64_t)(k * (double)r.n) + r.n;
-    const int64_t tile = r.dim == 3 ? 64 : 128, ratio = r.dim == 3 ? 12 : 5;
+    const int64_t tile = 128, ratio = r.dim == 3 ? 12 : 5;
     return footprint(r.dim, r.n, nnz, ratio * r.n, r.n / tile + 1, !r.bc_vel.empty(),
                      r.mat.law == PD_LAW_LPS);
 }
