@@ -11,6 +11,10 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# PyTorch first: its HIP runtime is then the one the library binds to, the
+# same one that owns the tensors and streams handed over (on hosts whose
+# driver the system ROCm runtime does not match, only that one sees the GPU)
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpd_hip.so")
