@@ -206,7 +206,8 @@ int pd_ctx_set_lanes(pd_ctx ctx, int lanes);
  *           touch into LDS once per launch), 3 streamed tiles for the
  *           explicit steps (the same tiles, staged by asynchronous
  *           global-to-LDS copies that overlap the bond sums; needs equal
- *           nodal volumes, other calls of such a simulation use kind 2);
+ *           nodal volumes, other calls of such a simulation use kind 2, or
+ *           kind 1 where the tile kernel cannot be resident at that shape);
  *           automatic uses streamed tiles for the steps where they apply,
  *           LDS tiles elsewhere whenever the largest halo fits in LDS.
  *   tile    nodes per tile, a multiple of 16 in [16, 4096]; 0 automatic.
