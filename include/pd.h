@@ -269,6 +269,10 @@ int pd_tune_clear(pd_ctx ctx);
  * Errors: PD_EINVAL for dim not in {2,3}, n <= 0, bad delta, non-finite X or
  * two coincident nodes; PD_ECAPACITY for more than 2^32 - 1 bonds, n >= 2^31
  * or a bounding box needing more than 2^27 bins of edge delta.
+ * A mesh in which no two nodes lie within delta builds (nnz = 0), but the
+ * calls that compute on it (pd_internal_force, pd_apply_tangent[_at],
+ * pd_solve_implicit, pd_sim_create) reject it with PD_EINVAL: it has no
+ * force, tangent or bond to evaluate.
  * Synchronises the stream.
  */
 int pd_build_neighbors(pd_ctx ctx, int dim, int64_t n, const double *X, double delta,

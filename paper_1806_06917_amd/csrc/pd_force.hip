@@ -419,6 +419,8 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
                                  double *U) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
+    if (nbr->nnz == 0)
+        return pd_set_error(ctx, PD_EINVAL, "the mesh has no bonds (no two nodes within delta)");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
@@ -500,6 +502,8 @@ static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const d
                          const uint8_t *fixed, const double *w, double *y) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
+    if (nbr->nnz == 0)
+        return pd_set_error(ctx, PD_EINVAL, "the mesh has no bonds (no two nodes within delta)");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
@@ -583,6 +587,8 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     *out = nullptr;
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
+    if (nbr->nnz == 0)
+        return pd_set_error(ctx, PD_EINVAL, "the mesh has no bonds (no two nodes within delta)");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));

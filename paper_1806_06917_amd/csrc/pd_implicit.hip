@@ -216,6 +216,8 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
                                  pd_solve_info *info) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
+    if (nbr->nnz == 0)
+        return pd_set_error(ctx, PD_EINVAL, "the mesh has no bonds (no two nodes within delta)");
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     if (!mat || mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "bad material");

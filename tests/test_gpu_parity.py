@@ -386,8 +386,9 @@ def test_implicit_noconv_reports(gpu):
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_cube100_full_size_steps(gpu, orc, prec):
-    """The 1M-node jittered cube in the benchmark's launch configuration:
-    random initial velocity, 3 steps, compared with the oracle."""
+    """The 1M-node jittered cube in the benchmark's launch configuration (the
+    streamed kernel at the autotuner's tile size and lanes): random initial
+    velocity, 3 steps, compared with the oracle."""
     torch, pd, ctx = gpu
     w = inputs.CONFIGS["cube100"]()
     say("cube100 full size", prec)
@@ -405,10 +406,20 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     w.v0 = v0
-    sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(3, w.E, w.delta), prec)
-    assert sim.info()["kernel"] == "stream"        # the benchmark's launch configuration
-    sim.step(3, w.dt)
-    u, v, a, info = read_state(torch, sim, w.n, 3, nb.nnz)
+    # the benchmark's launch configuration: the autotuner's shape for this mesh
+    best, _ = ctx.autotune(dev(torch, w.X), dev(torch, w.V), w.delta, prec, steps=20)
+    say("cube100 tuned shape", best["tile"], best["lanes"])
+    try:
+        sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(3, w.E, w.delta), prec)
+        shape = sim.info()
+        assert shape["kernel"] == "stream"
+        assert (shape["tile"], shape["lanes"]) == (best["tile"], best["lanes"])
+        sim.step(3, w.dt)
+        u, v, a, info = read_state(torch, sim, w.n, 3, nb.nnz)
+        sim.close()
+    finally:
+        ctx.tune_clear()
+        nb.close()
     tol = TOL64 if prec == "fp64" else TOLMIX
     assert 0 < np.count_nonzero(st["alive"] == 0) < mesh.nnz
     assert np.array_equal(a[~band], st["alive"][~band])
