@@ -653,9 +653,14 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
                                                                                     : SK_LINEAR))) {
             block = 0;
             layout_only = false;
-            lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
         }
-        if (block == 0 && !layout_only) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+        // the tuned shape does not apply (it does not fit, or the tiles are
+        // held at another size): the automatic lanes as well as tile size,
+        // since the tuned lane count was timed with the tuned tiles
+        if (block == 0 && !layout_only) {
+            lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+            PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+        }
     } else {
         PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
         layout_only = block == 0 && ctx->tile != 0 && nbr->lcol &&

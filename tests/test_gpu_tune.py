@@ -143,3 +143,40 @@ def test_large_tiles_stream_with_gather_side_calls(gpu, prec):
     assert np.array_equal(a[2], b[2])
     assert a[3:] == b[3:]
     assert np.count_nonzero(a[2] == 0) > 0          # bonds did break
+
+
+def test_tuned_shape_applies_whole_or_not_at_all(gpu):
+    """A tuned (tile size, lanes) pair is taken as a whole: a simulation that
+    cannot use the tuned tile size (the solid's streamed layout does not fit
+    240-node tiles, or the mesh's tiles are held at another size) runs at
+    the automatic shape, the one a context without tuning picks, and never
+    with the tuned lanes on other tiles.  Mixed then FP64, on one mesh."""
+    torch, pd, _ = gpu
+    N = 22
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * 3, h, jitter=0.05, seed=201)
+    n = len(X)
+    V = np.full(n, h ** 3)
+    plain, tuned = pd.Context(0), pd.Context(0)
+    ref = {}
+    try:
+        for c in (plain, tuned):
+            nb = pd.Neighbors(c, dev(torch, X), 3 * h)
+            if c is tuned:
+                for prec in ("mixed", "fp64"):
+                    c.tune_set(3, nb.nnz / n, 240, 4, prec)
+            for prec in ("mixed", "fp64"):
+                say("solid under a tuned shape", "tuned" if c is tuned else "plain", prec)
+                sim = pd.Simulation(c, nb, pd.material(3, 0.0, 1.0, 0.0, prec, law="lps",
+                                                       bulk=1.0, shear=0.5),
+                                    dev(torch, X), dev(torch, V), None, None)
+                info = sim.info()
+                sim.close()
+                if c is plain:
+                    ref[prec] = info
+                elif (info["tile"], info["lanes"]) != (240, 4):
+                    assert info == ref[prec], (prec, info, ref[prec])
+            nb.close()
+    finally:
+        tuned.close()
+        plain.close()
