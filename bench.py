@@ -20,7 +20,10 @@ evaluations per second go into the line's "serving" object.
 Prints one JSON line.  `roofline` prices the step kernel against HBM with the
 algorithmic byte model B = nnz * 5 + n * (93 | 133) bytes (2-d | 3-d):
 per bond a 4-byte column index and a 1-byte flag, per node the row offset,
-X, V, u, v, the boundary kind read once and u', v' written once.
+X, V, u, v, the boundary kind read once and u', v' written once.  The other
+laws' step figures carry a `roofline` of the whole step by the same model
+(the solid: two passes, plus 32 B of coefficients per node written by the
+first and read by the second).
 """
 import argparse
 import hashlib
@@ -75,6 +78,22 @@ def recorded_traffic(workload, precision, launch=None):
 def algorithmic_bytes(n, nnz, dim):
     per_node = 4 + 3 * dim * 8 + 8 + 1 + 2 * dim * 8
     return nnz * 5 + n * per_node
+
+
+def lps_algorithmic_bytes(n, nnz, dim):
+    """The solid's step is two passes over the bonds: the state pass reads the
+    bonds, row offsets, X and u and writes 32 B of coefficients per node; the
+    force pass is the linear law's step plus those coefficients read once."""
+    state = nnz * 5 + n * (4 + 2 * dim * 8 + 32)
+    return state + algorithmic_bytes(n, nnz, dim) + n * 32
+
+
+def step_roofline(bytes_per_step, ms):
+    """Algorithmic bytes of one step over its measured time, priced against
+    HBM (the whole step: both passes where there are two)."""
+    gbs = bytes_per_step / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes_per_step": bytes_per_step}
 
 
 def parse():
@@ -252,7 +271,9 @@ def law_runs(torch, pd, steps, tuned=None):
         ms = e0.elapsed_time(e1) / steps
         out[f"np_step_{prec}"] = {"workload": w.name, "ms_per_step": ms,
                                   "bond_evals_per_s": nb.nnz / (ms * 1e-3),
-                                  "launch": sim.info(), "beta": 1e3}
+                                  "launch": sim.info(), "beta": 1e3,
+                                  "roofline": step_roofline(
+                                      algorithmic_bytes(w.n, nb.nnz, w.dim), ms)}
         sim.close()
     nb.close()
     wc = inputs.CONFIGS["cube100"]()
@@ -276,7 +297,9 @@ def law_runs(torch, pd, steps, tuned=None):
         ms = e0.elapsed_time(e1) / (steps // 4)
         out[f"lps_step_{prec}"] = {"workload": wc.name, "ms_per_step": ms,
                                    "bond_evals_per_s": nb.nnz / (ms * 1e-3),
-                                   "launch": sim.info(), "nu": 0.25}
+                                   "launch": sim.info(), "nu": 0.25,
+                                   "roofline": step_roofline(
+                                       lps_algorithmic_bytes(wc.n, nb.nnz, wc.dim), ms)}
         sim.close()
     nb.close()
     wb = inputs.CONFIGS["bar400x40"]()
