@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-validation", action="store_true",
+                    help="skip the 2-d and 1-d convergence studies")
     ap.add_argument("--no-law", action="store_true",
                     help="skip the NP-law measurements (explicit steps, Newton-Krylov)")
     ap.add_argument("--convergence", action="store_true",
@@ -558,7 +560,7 @@ def main():
             "burst": burst, "poisson": dict(poisson, rate_per_s=rate, load=args.serve_load),
             "p50_s": poisson["p50_s"], "p99_s": poisson["p99_s"],
             "bond_evals_per_s": poisson["bond_evals_per_s"]}
-    if not args.no_law:
+    if not args.no_law and not args.no_validation:
         runs = []
         for law, ic in (("linear", 1), ("np", 2)):
             progress("convergence study", law, "IC", ic)
