@@ -111,6 +111,10 @@ def lib():
             fn.restype = None
             fn.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32, dbl, dbl,
                            dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
+        L.or_band_update.restype = None
+        L.or_band_update.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, ptr]
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [i32]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = []
         _lib = L
@@ -202,6 +206,26 @@ class Mesh:
                         _p(state["u"]), _p(state["v"]), _p(state["f"]), _p(state["alive"]))
         state["step"] += nsteps
         return state
+
+    def band_update(self, band, u, s_c, tol=1e-6):
+        """band |= (|S/s_c - 1| <= tol) per bond at displacement u (in place)."""
+        u = _f64(u)
+        lib().or_band_update(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(u),
+                             float(s_c), float(tol), _p(band))
+        return band
+
+    def verlet_banded(self, state, c, rho, s_c, dt, nsteps, bc_kind=None, bc_vel=None, b=None,
+                      ramp=0, band=None, tol=1e-6):
+        """Verlet steps one at a time, collecting in ``band`` (uint8 per bond)
+        every bond whose strain came within tol of s_c at a force evaluation
+        of these steps (the state on entry included)."""
+        if band is None:
+            band = np.zeros(max(self.nnz, 1), np.uint8)[: self.nnz]
+        self.band_update(band, state["u"], s_c, tol)
+        for _ in range(nsteps):
+            self.verlet(state, c, rho, s_c, dt, 1, bc_kind, bc_vel, b, ramp)
+            self.band_update(band, state["u"], s_c, tol)
+        return band
 
     def start(self, u0, v0, c, s_c=0.0, alive=None):
         """Initial state: f^0 = force(u^0), with the damage test at u^0."""
@@ -435,3 +459,8 @@ class LpsMesh(Mesh):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_threads(k):
+    """Threads of the oracle's OpenMP loops (results are the same for any)."""
+    lib().or_set_threads(int(k))

@@ -1020,6 +1020,42 @@ void or_lps_pv(int64_t n, const int64_t *row_ptr, const int32_t *col, const doub
     free(th);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Test bookkeeping for the damage comparison: band[p] |= 1 where bond p's   */
+/* linearised strain S = (eta . xi)/|xi|^2 (Algorithm 1) lies within a       */
+/* relative distance tol of the critical stretch, |S/s_c - 1| <= tol.  Bonds  */
+/* in this band may break on one side and not on the other when the two     */
+/* sides round S differently; every other flag must agree.                   */
+/* ------------------------------------------------------------------------ */
+void or_band_update(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                    const double *X, const double *u, double s_c, double tol, uint8_t *band) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            int64_t j = col[p];
+            double r2 = 0.0, ex = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                double x = X[j * dim + k] - X[i * dim + k];
+                double e = u[j * dim + k] - u[i * dim + k];
+                r2 = r2 + x * x;
+                ex = ex + e * x;
+            }
+            double S = ex / r2;
+            if (fabs(S / s_c - 1.0) <= tol) band[p] = 1;
+        }
+    }
+}
+
+/* threads of the OpenMP loops (timing only: results do not depend on it) */
+void or_set_threads(int k) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 int or_num_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

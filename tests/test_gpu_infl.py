@@ -86,6 +86,39 @@ def test_line_steps_parity(gpu, orc, law, prec):
     assert np.all(u[w.bc_kind == inputs.BC_CLAMPED] == 0.0)
 
 
+@pytest.mark.parametrize("law", ["linear", "np"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_line_central_steps_parity(gpu, orc, law, prec):
+    """300 central-difference steps (pd_central_step) of the 1-d study's line
+    with J (h = delta/4, IC 2, clamped collars) against the oracle's
+    central-difference steps with J."""
+    torch, pd, ctx = gpu
+    w = inputs.convergence_line(4, 2)
+    c = 2.0 / w.delta ** 2
+    lw = orc.LAW_NP if law == "np" else orc.LAW_LINEAR
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    st = mesh.start_law(w.u0, w.v0, c, lw, 1.0)
+    st["f"] = mesh.force_law(st["u"], c, lw, 1.0, j=J)
+    steps = 300
+    mesh.steps_j(st, c, 1.0, 0.0, w.dt, steps, J, lw, 1.0, central=True, bc_kind=w.bc_kind,
+                 bc_vel=w.bc_vel)
+    say("line central steps", law, prec)
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    sim = pd.Simulation(ctx, nb, pd.material(2, c, 1.0, 0.0, prec, law=law, beta=1.0, j=J),
+                        dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0), dev(torch, w.v0),
+                        bc_kind=dev(torch, w.bc_kind), bc_vel=dev(torch, w.bc_vel))
+    sim.central_step(steps, w.dt)
+    u, v, _, info = read_state(torch, sim, w.n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    assert info["step"] == steps
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
+    assert np.all(u[:, 1] == 0.0)
+    assert np.all(u[w.bc_kind == inputs.BC_CLAMPED] == 0.0)
+
+
 def quadrature_rates(pv):
     """Rates of the two mesh sets predicted by the bond sum's quadrature of
     the horizon integral: for smooth u the line's operator is 2 u'' R(m),

@@ -260,3 +260,45 @@ def test_np_stream_equals_gather_within_tolerance_and_batches(gpu, orc, prec):
     for got in (alone[0], gat):
         assert relL2(got[0], st["u"]) <= tol
         assert relL2(got[1], st["v"]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_np_streamed_full_size_steps(gpu, orc, prec):
+    """The NP law's explicit steps on the benchmark's mesh (the 512^2 notched
+    plate, beta = 1e3, no damage) on the streamed kernel at the benchmark's
+    launch shape, where every persistent workgroup walks several tiles (the
+    next tile's copies are issued during the current one's sums): 3 steps
+    from a random velocity against the oracle's NP steps (notch and collars
+    included)."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["notched512"]()
+    v0 = inputs.random_field(w.n, 2, 97, scale=2e-2)
+    v0[w.bc_kind == inputs.BC_VELOCITY] = 0.0
+    beta, steps = 1e3, 3
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    alive0 = mesh.notch_cut(w.notch, mesh.all_alive())
+    st = mesh.start_law(w.u0, v0, c, orc.LAW_NP, beta, alive=alive0)
+    mesh.verlet_law(st, c, w.rho, 0.0, w.dt, steps, orc.LAW_NP, beta, bc_kind=w.bc_kind,
+                    bc_vel=w.bc_vel, ramp=w.ramp_steps)
+    say("NP streamed full size", prec)
+    ctx.tune_clear()
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, 0.0, prec, law="np",
+                      beta=beta)
+    sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                        dev(torch, v0), bc_kind=dev(torch, w.bc_kind),
+                        bc_vel=dev(torch, w.bc_vel), notch=w.notch, ramp_steps=w.ramp_steps)
+    info = sim.info()
+    assert info["kernel"] == "stream"
+    # even at the most workgroups a CU can hold, each walks two tiles or more
+    ntiles = -(-w.n // info["tile"])
+    assert ntiles >= 2 * 256 * (2048 // info["block"])
+    sim.step(steps, w.dt)
+    u, v, a, _ = read_state(torch, sim, w.n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    assert np.array_equal(a, alive0)
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol

@@ -178,3 +178,46 @@ def test_lps_streamed_equals_gather(gpu, orc, prec):
         ctx.set_tuning(0, 0, 0)
     assert relL2(u, st["u"]) <= tol
     assert relL2(v, st["v"]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_lps_streamed_full_size_steps(gpu, orc, prec):
+    """The solid's explicit steps on the benchmark's mesh (the jittered 100^3
+    cube with its collars, nu = 1/4) on the streamed kernel at the
+    benchmark's launch shape (the context holds the linear law's tuned shape
+    for this mesh kind, as in the benchmark), where each persistent
+    workgroup walks many tiles in both passes: 3 steps from a random
+    velocity against the oracle's steps of Algorithm 2."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["cube100"]()
+    v0 = inputs.random_field(w.n, 3, 96, scale=3e-3)
+    v0[w.bc_kind == inputs.BC_VELOCITY] = 0.0
+    K, mu = orc.lps_moduli(w.E, 0.25)
+    steps = 3
+    say("LPS streamed full size: oracle", prec)
+    mesh = orc.LpsMesh(w.X, w.V, w.delta)
+    st = mesh.start_lps(w.u0, v0, K, mu)
+    mesh.verlet_lps(st, K, mu, w.rho, w.dt, steps, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
+                    ramp=w.ramp_steps)
+    say("LPS streamed full size: GPU", prec)
+    ctx.tune_clear()
+    ctx.tune_set(3, mesh.nnz / w.n, 240, 4, prec)
+    try:
+        nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+        mat = pd.material(3, 0.0, w.rho, 0.0, prec, law="lps", bulk=K, shear=mu)
+        sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                            dev(torch, v0), bc_kind=dev(torch, w.bc_kind),
+                            bc_vel=dev(torch, w.bc_vel), ramp_steps=w.ramp_steps)
+        info = sim.info()
+        assert info["kernel"] == "stream"
+        ntiles = -(-w.n // info["tile"])
+        assert ntiles >= 2 * 256 * (2048 // info["block"])
+        sim.step(steps, w.dt)
+        u, v, _, _ = read_state(torch, sim, w.n, 3, nb.nnz)
+        sim.close()
+        nb.close()
+    finally:
+        ctx.tune_clear()
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol

@@ -1,7 +1,11 @@
-"""Batched steps (pd_batch_step) against single-simulation steps: every
-instance of a batch must end bit for bit where pd_verlet_step would have left
-it, whatever else shares the launch, with or without hipGraph replay and in
-chunks of any size."""
+"""Batched steps (pd_batch_step) and served requests (pd_server_*) against
+single-simulation steps and against the FP64 oracle: every instance of a
+batch must end bit for bit where pd_verlet_step would have left it, whatever
+else shares the launch, with or without hipGraph replay and in chunks of any
+size; and each batched or served plate must match the oracle's velocity-Verlet
+steps (Section "Explicit time integration", force of Algorithm 1 with the
+notch, collars and critical-stretch damage) to rel-L2 1e-12 in FP64 and 1e-5
+mixed, with damage flags equal outside the band |S/s_c - 1| <= 1e-6."""
 import numpy as np
 import pytest
 
@@ -9,6 +13,39 @@ from conftest import say
 from paper_1806_06917_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+def _relL2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - b) / (nb if nb > 0 else 1.0)
+
+
+def _oracle(orc, w, steps):
+    """The oracle's trajectory of a notched plate (notch cut, collars, ramp,
+    damage) and the band of bonds whose strain came within 1e-6 of s_c."""
+    mesh = orc.Mesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(w.dim, w.E, w.delta)
+    st = mesh.start(w.u0, w.v0, c, w.s_c, mesh.notch_cut(w.notch, mesh.all_alive()))
+    band = mesh.verlet_banded(st, c, w.rho, w.s_c, w.dt, steps, w.bc_kind, w.bc_vel, None,
+                              w.ramp_steps)
+    return st, band.astype(bool)
+
+
+def _check_oracle(u, v, alive, ref, prec):
+    """u, v (and the flags, when known) of a GPU run against the oracle's."""
+    st, band = ref
+    if alive is not None:
+        assert np.array_equal(alive[~band], st["alive"][~band])
+        same = np.array_equal(alive, st["alive"])
+    else:
+        same = not (prec == "mixed" and band.any())
+    assert same or prec == "mixed"      # FP64 rounds S alike to ~1e-16: no flip
+    tol = TOL[prec] * (1 if same else 10)
+    assert _relL2(u, st["u"]) <= tol
+    assert _relL2(v, st["v"]) <= tol
 
 
 def _dev(torch, a):
@@ -41,12 +78,13 @@ def _state(torch, s, w, nnz):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_batch_equals_alone(gpu, prec):
+def test_batch_equals_alone(gpu, orc, prec):
     torch, pd, ctx = gpu
     ctx.set_lanes(4)                  # one lane count for the whole batch
     try:
         ws = _plates()
         steps = [60, 47, 60]
+        refs = [_oracle(orc, w, k) for w, k in zip(ws, steps)]
         say("batch: alone", prec)
         alone = []
         for w, k in zip(ws, steps):
@@ -67,17 +105,25 @@ def test_batch_equals_alone(gpu, prec):
                 b.step(sims, take, [w.dt for w in ws], c, graph=graph)
                 left = [r - t for r, t in zip(left, take)]
             b.close()
-            for (nb, s), w, ref in zip(made, ws, alone):
+            for (nb, s), w, ref, oref in zip(made, ws, alone, refs):
                 got = _state(torch, s, w, nb.nnz)
                 assert got[3] == ref[3]
                 for x, y in zip(got[:3], ref[:3]):
                     assert np.array_equal(x, y)
+                _check_oracle(got[0], got[1], got[2], oref, prec)
                 s.close()
                 nb.close()
-        # the runs broke bonds, so the damage path is part of the comparison
-        assert any((r[2] == 0).sum() > 0 for r in alone)
+        # the runs broke bonds beyond the notch, so the damage path is part of
+        # the comparison
+        assert any((r[0]["alive"] == 0).sum() > (_notch_only(orc, w) == 0).sum()
+                   for r, w in zip(refs, ws))
     finally:
         ctx.set_lanes(0)
+
+
+def _notch_only(orc, w):
+    mesh = orc.Mesh(w.X, w.V, w.delta)
+    return mesh.notch_cut(w.notch, mesh.all_alive())
 
 
 def test_batch_rejects_mismatch(gpu):
@@ -123,15 +169,16 @@ def _serve(pd, ctx, ws, prec, budget, chunk):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_served_equals_alone(gpu, prec):
+def test_served_equals_alone(gpu, orc, prec):
     """Requests served together under a memory budget end where each would
-    have ended alone; the budget is never exceeded and admission follows
-    arrival order."""
+    have ended alone and where the oracle ends; the budget is never exceeded
+    and admission follows arrival order."""
     torch, pd, ctx = gpu
     ws = _plates() + [inputs.notched_plate_2d(N=48, m=3, s_c=1e-3, v0=2e-3, steps=0,
                                               ramp_steps=5)]
     for w, k in zip(ws, [60, 47, 60, 33]):
         w.steps = k
+    refs = [_oracle(orc, w, w.steps) for w in ws]
     ctx.set_lanes(4)
     try:
         alone = []
@@ -148,10 +195,11 @@ def test_served_equals_alone(gpu, prec):
     assert most == len(ws) and used == 0
     sizes = [f["bytes"] for f in infos]
     assert all(b > 0 for b in sizes) and peak == sum(sizes)
-    for f, r, a in zip(infos, res, alone):
+    for f, r, a, oref in zip(infos, res, alone, refs):
         assert f["state"] == pd.PD_REQ_DONE and f["status"] == pd.PD_OK
         assert f["t_submit"] <= f["t_admit"] <= f["t_done"]
         assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
+        _check_oracle(r[0], r[1], None, oref, prec)
     # a budget that holds the largest request plus a little: queueing
     budget = max(sizes) + min(sizes) // 2
     say("serve: budget", budget, prec)
@@ -159,9 +207,10 @@ def test_served_equals_alone(gpu, prec):
     assert peak2 <= budget and used2 == 0 and most2 < len(ws)
     admits = [f["t_admit"] for f in infos2]
     assert admits == sorted(admits)
-    for f, r, a in zip(infos2, res2, alone):
+    for f, r, a, oref in zip(infos2, res2, alone, refs):
         assert f["state"] == pd.PD_REQ_DONE
         assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
+        _check_oracle(r[0], r[1], None, oref, prec)
 
 
 def test_served_too_large(gpu):
@@ -189,11 +238,13 @@ def test_served_too_large(gpu):
     srv.close()
 
 
-def test_served_full_size_requests_equal_alone(gpu):
+def test_served_full_size_requests_equal_alone(gpu, orc):
     """Requests of the serving workload at full size (the largest of its first
     twelve plates, up to 512^2 nodes) in the benchmark's configuration
-    (4 lanes, 4 GiB budget, 100-step chunks): each served result equals the
-    request stepped alone, bit for bit.  Steps are cut to 250 per request."""
+    (4 lanes, 4 GiB budget, 100-step chunks, mixed precision): each served
+    result equals the request stepped alone, bit for bit, and matches the
+    oracle's steps of the same plate (notch, ramped collars, damage).  Steps
+    are cut to 250 per request."""
     torch, pd, ctx = gpu
     reqs = sorted(inputs.serving_requests(256)[:12], key=lambda q: -q.N)[:3]
     ws = []
@@ -220,3 +271,6 @@ def test_served_full_size_requests_equal_alone(gpu):
     finally:
         ctx.set_lanes(0)
     assert max(w.n for w in ws) > 200000
+    for w, (gu, gv) in zip(ws, got):
+        say("full-size request against the oracle", w.name)
+        _check_oracle(gu, gv, None, _oracle(orc, w, w.steps), "mixed")

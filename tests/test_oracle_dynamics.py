@@ -173,3 +173,24 @@ def test_thread_count_does_not_change_results(orc):
         env = dict(os.environ, OMP_NUM_THREADS=t)
         outs.append(subprocess.check_output([sys.executable, "-c", code], env=env))
     assert outs[0] == outs[1]
+
+
+def test_set_threads_in_process(orc):
+    """The oracle's thread count set in-process (the CPU baseline times one
+    thread and all cores) changes nothing in the results."""
+    from paper_1806_06917_amd import inputs
+    w = inputs.cube_3d(12, 3, steps=4)
+    m = orc.Mesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(3, 1.0, w.delta)
+    before = orc.num_threads()
+    outs = []
+    try:
+        for t in (1, 3):
+            orc.set_threads(t)
+            assert orc.num_threads() == t
+            st = m.start(w.u0, inputs.random_field(m.n, 3, 5), c, 1e-4)
+            m.verlet(st, c, 1.0, 1e-4, w.dt, 4, w.bc_kind, w.bc_vel, None, 2)
+            outs.append((st["u"].copy(), st["alive"].copy()))
+    finally:
+        orc.set_threads(before)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

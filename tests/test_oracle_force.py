@@ -170,3 +170,27 @@ def test_micromodulus_in_paper_form(orc):
     assert np.isclose(orc.micromodulus(2, E, d), 4 * (9 * E / 4) / (d * np.pi * d ** 2), rtol=1e-14)
     assert np.isclose(orc.micromodulus(3, E, d), 4 * (4 * E) / (d * 4 / 3 * np.pi * d ** 3),
                       rtol=1e-14)
+
+
+def test_band_update_matches_definition(orc):
+    """The damage-comparison band: |S/s_c - 1| <= tol with S = (eta.xi)/|xi|^2
+    written out per bond in numpy; the band only grows."""
+    h = 1.0 / 20
+    X = inputs.grid_coords((20, 20), h, jitter=0.05, seed=41)
+    mesh = orc.Mesh(X, np.full(len(X), h * h), 3 * h)
+    u = inputs.random_field(len(X), 2, 42, scale=2e-2 * h)
+    i = np.repeat(np.arange(mesh.n), np.diff(mesh.row_ptr))
+    xi = X[mesh.col] - X[i]
+    S = np.sum((u[mesh.col] - u[i]) * xi, 1) / np.sum(xi * xi, 1)
+    s_c = float(np.sort(S)[int(0.9 * len(S))])     # the strain of a bond (and its pair)
+    for tol in (1e-6, 1e-2):
+        band = np.zeros(mesh.nnz, np.uint8)
+        mesh.band_update(band, u, s_c, tol)
+        want = np.abs(S / s_c - 1) <= tol
+        # the two sides may round S differently only right at the band's edge
+        edge = np.abs(np.abs(S / s_c - 1) - tol) <= 1e-12
+        assert np.array_equal(band.astype(bool)[~edge], want[~edge])
+        assert want.sum() >= 2
+    before = band.copy()
+    mesh.band_update(band, np.zeros_like(u), s_c, 1e-6)     # S = 0: nothing added
+    assert np.array_equal(band, before)

@@ -135,3 +135,74 @@ def test_line_meshes_nest(m):
     # IC 2: two pulses of amplitude a at 0.25 and 0.75
     i1, i2 = np.argmin(abs(b.X[:, 0] - 0.25)), np.argmin(abs(b.X[:, 0] - 0.75))
     assert abs(b.u0[i1, 0] - 1e-3) < 1e-5 and abs(b.u0[i2, 0] - 1e-3) < 1e-5
+
+
+@pytest.mark.parametrize("rho,dt", [(1.0, 0.05), (2.5, 0.11)])
+def test_central_with_influence_oscillator(orc, rho, dt):
+    """Central-difference steps with J on a two-node bond: J multiplies the
+    bond's stiffness by J(L/delta), so the discrete solution is
+    A cos(n theta) with cos theta = 1 - omega^2 dt^2/2,
+    omega^2 = c J(L/delta) (V1 + V2)/(rho L); the returned velocity is the
+    velocity-Verlet one of the same steps."""
+    L, c, A = 0.5, 3.0, 1e-3
+    X = np.array([[0.0, 0.0], [L, 0.0]])
+    m = orc.LawMesh(X, np.array([0.2, 0.3]), 1.1 * L, method="brute")
+    delta = m.delta
+    c1, c2 = J
+    t = L / delta
+    jv = c1 * t * math.exp(-t * t / c2)
+    u0 = np.array([[-A / 2, 0.0], [A / 2, 0.0]])
+    omega2 = c * jv * (m.V[0] + m.V[1]) / (rho * L)
+    theta = math.acos(1 - omega2 * dt * dt / 2)
+    for nsteps in (1, 2, 37, 200):
+        st = m.start_law(u0, np.zeros((2, 2)), c, orc.LAW_LINEAR, 1.0)
+        st["f"] = m.force_law(st["u"], c, orc.LAW_LINEAR, 1.0, j=J)
+        m.steps_j(st, c, rho, 0.0, dt, nsteps, J, central=True)
+        w = st["u"][1, 0] - st["u"][0, 0]
+        assert abs(w - A * math.cos(nsteps * theta)) <= 1e-12 * A
+        sv = m.start_law(u0, np.zeros((2, 2)), c, orc.LAW_LINEAR, 1.0)
+        sv["f"] = m.force_law(sv["u"], c, orc.LAW_LINEAR, 1.0, j=J)
+        m.steps_j(sv, c, rho, 0.0, dt, nsteps, J)
+        np.testing.assert_allclose(st["v"], sv["v"], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("law", [0, 1])
+def test_central_with_influence_equals_verlet(orc, law):
+    """On the 1-d study's line (h = delta/4, IC 2, clamped collars) the
+    central-difference and velocity-Verlet steps with J share one
+    recurrence, so they agree to rounding, but not bit for bit."""
+    w = inputs.convergence_line(4, 2)
+    c = 2.0 / w.delta ** 2
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    runs = []
+    for central in (False, True):
+        st = mesh.start_law(w.u0, w.v0, c, law, 1.0)
+        st["f"] = mesh.force_law(st["u"], c, law, 1.0, j=J)
+        mesh.steps_j(st, c, 1.0, 0.0, w.dt, 400, J, law, 1.0, central=central,
+                     bc_kind=w.bc_kind, bc_vel=w.bc_vel)
+        runs.append(st)
+    a, b = runs
+    assert np.linalg.norm(b["u"] - a["u"]) <= 1e-11 * np.linalg.norm(a["u"])
+    assert np.linalg.norm(b["v"] - a["v"]) <= 1e-9 * np.linalg.norm(a["v"])
+    assert not np.array_equal(b["u"], a["u"])
+    assert np.all(b["u"][w.bc_kind == inputs.BC_CLAMPED] == 0.0)
+    # J is applied: without it the trajectory differs
+    st = mesh.start_law(w.u0, w.v0, c, law, 1.0)
+    mesh.central_law(st, c, 1.0, 0.0, w.dt, 400, law, 1.0, bc_kind=w.bc_kind, bc_vel=w.bc_vel)
+    assert np.linalg.norm(st["u"] - b["u"]) > 1e-3 * np.linalg.norm(b["u"])
+
+
+def test_central_with_influence_prescribed_velocity(orc):
+    """Prescribed-velocity nodes under the central-difference steps with J
+    follow their ramped velocity in closed form (J acts on forces only)."""
+    w = inputs.notched_plate_2d(N=24, m=3, s_c=0.0, v0=2e-3, steps=0, ramp_steps=10)
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    st = mesh.start_law(w.u0, w.v0, c, orc.LAW_LINEAR, 1.0)
+    st["f"] = mesh.force_law(st["u"], c, orc.LAW_LINEAR, 1.0, j=J)
+    mesh.steps_j(st, c, w.rho, 0.0, w.dt, 30, J, central=True, bc_kind=w.bc_kind,
+                 bc_vel=w.bc_vel, ramp=w.ramp_steps)
+    sel = w.bc_kind == 2
+    ramp = sum(min(1.0, (k + 0.5) / 10) for k in range(30))
+    np.testing.assert_allclose(st["u"][sel], w.dt * ramp * w.bc_vel[sel], rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(st["v"][sel], w.bc_vel[sel], rtol=1e-15)
