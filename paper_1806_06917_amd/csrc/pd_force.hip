@@ -399,7 +399,7 @@ int ensure_scratch(pd_ctx ctx, pd_nbr nbr) {
     if (!nbr->s_U) PD_TRY(pd_alloc(ctx, &nbr->s_U, (size_t)nbr->n));
     if (!nbr->s_alive) PD_TRY(pd_alloc(ctx, &nbr->s_alive, nbr->nnz));
     if (!nbr->s_fixed) PD_TRY(pd_alloc(ctx, &nbr->s_fixed, (size_t)nbr->n));
-    if (!nbr->s_bw && nbr->lcol) PD_TRY(pd_alloc(ctx, &nbr->s_bw, nbr->nnz + 2));
+    if (!nbr->s_bw && nbr->lcol) PD_TRY(pd_alloc(ctx, &nbr->s_bw, nbr->nnz + PD_BW_PAD));
     return PD_OK;
 }
 
@@ -642,6 +642,8 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         const int st = pd_plan_kernel(ctx, nbr, lanes, &block);
         ctx->tile = 0;
         PD_TRY(st);
+        // tiles held at another size by a live simulation are not the tuned shape
+        if (block > 0 && nbr->tile_T != (uint32_t)te->tile) block = 0;
         layout_only = block == 0 && nbr->lcol && nbr->tile_T == (uint32_t)te->tile;
         // the tuned shape (timed on the linearised law) must also fit this
         // material's streamed form (the solid stages more per halo node);
@@ -710,7 +712,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     if (st == PD_OK && (block > 0 || layout_only)) {
         s->tiled = true;
         nbr->users += 1;
-        st = pd_alloc(ctx, &s->bw, nbr->nnz + 2);
+        st = pd_alloc(ctx, &s->bw, nbr->nnz + PD_BW_PAD);
         if (st == PD_OK) st = pd_bw_compose(ctx, nbr, s->alive, s->bw);
     }
     if (st == PD_OK) {

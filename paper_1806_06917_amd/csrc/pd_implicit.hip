@@ -270,7 +270,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
     w.block = block;
     if (block > 0) {
-        PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz + 2));
+        PD_TRY(pd_alloc(ctx, &w.bw, nbr->nnz + PD_BW_PAD));
         PD_TRY(pd_bw_compose(ctx, nbr, w.alive, w.bw));
     }
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, w.xv));

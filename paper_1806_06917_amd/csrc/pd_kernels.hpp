@@ -111,8 +111,9 @@ __device__ __forceinline__ double dotf(double ax, double ay, double az, double b
 }
 
 // One bond: xi = X_j - X_i, eta = u_j - u_i, cVj = c V_j; `dead` marks a bond
-// broken earlier; damage on/off and the critical stretch s_c.  Returns true if the bond breaks now (S > s_c); a bond that
-// is dead or breaks now contributes exact zeros.  Otherwise adds
+// broken earlier; damage on/off and the critical stretch s_c.  Returns true if
+// the bond breaks now (S > s_c); a bond that is dead or breaks now contributes
+// nothing.  Otherwise adds
 // c V_j S xi/|xi| (and (c/4) V_j S^2 |xi| if WANT_E) to the lane's sums.
 // Everything runs in float64; mixed precision takes 1/|xi| from the hardware
 // reciprocal-square-root estimate alone (relative error below 2^-22), the
@@ -130,19 +131,24 @@ __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double 
     const double ex = dotf<DIM>(dux, duy, duz, dxx, dxy, dxz);
     const double inv = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     const double S = ex * (inv * inv);
-    const bool brk = damage && S > s_c;
-    const bool off = brk || dead;
-    double g = off ? 0.0 : cVj * S * inv;
-    if (NP) {
-        const double x = -beta * ((r2 * inv) * S * S);
-        g *= MIXED ? (double)__builtin_amdgcn_exp2f((float)(x * 1.4426950408889634)) : exp(x);
+    const bool brk = damage && !dead && S > s_c;
+    // a dead or breaking bond leaves the sums untouched (they are never -0);
+    // the empty volatile statement keeps this a masked block rather than
+    // selects after the sums
+    if (!(brk || dead)) {
+        asm volatile("" ::: "memory");
+        double g = cVj * S * inv;
+        if (NP) {
+            const double x = -beta * ((r2 * inv) * S * S);
+            g *= MIXED ? (double)__builtin_amdgcn_exp2f((float)(x * 1.4426950408889634)) : exp(x);
+        }
+        s.x = fma(g, dxx, s.x);
+        s.y = fma(g, dxy, s.y);
+        if (DIM == 3) s.z = fma(g, dxz, s.z);
+        if (WANT_E && !NP) s.e += 0.25 * cVj * S * S * (r2 * inv);
+        if (WANT_E && NP) s.e += 0.25 * cVj * (-expm1(-beta * ((r2 * inv) * S * S)) / beta);
     }
-    s.x = fma(g, dxx, s.x);
-    s.y = fma(g, dxy, s.y);
-    if (DIM == 3) s.z = fma(g, dxz, s.z);
-    if (WANT_E && !NP) s.e += off ? 0.0 : 0.25 * cVj * S * S * (r2 * inv);
-    if (WANT_E && NP) s.e += off ? 0.0 : 0.25 * cVj * (-expm1(-beta * ((r2 * inv) * S * S)) / beta);
-    return brk && !dead;
+    return brk;
 }
 
 // One bond under the general pairwise law of Algorithm 1 (gather kernel):
@@ -523,6 +529,8 @@ int pd_rec_unpack(pd_ctx ctx, int dim, uint32_t n, const double *rec, double *u)
 inline uint32_t pd_tile_hcap(const pd_nbr nbr) { return (nbr->halo_max + 31u) & ~31u; }
 inline uint32_t pd_tile_bcap(const pd_nbr nbr) { return (nbr->bonds_max + 63u) & ~63u; }
 // bond words of a tiled neighbour list: bw = lcol | 0x8000 where alive == 0
-// (bw arrays hold nnz + 2 entries for the kernel's 32-bit reads)
+// (bw arrays hold nnz + PD_BW_PAD entries, the pad marked dead, for the
+// kernels' 32-bit reads and the streamed kernel's 16-byte copies)
+constexpr uint32_t PD_BW_PAD = 8;
 int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw);
 int pd_bw_to_alive(pd_ctx ctx, const pd_nbr nbr, const uint16_t *bw, uint8_t *alive_sfc);

@@ -128,7 +128,12 @@ struct StreamLayout {
                                      uint32_t mmax, int form) {
         H = hcap;                      // multiple of 32
         T = tile;
-        WB = round4(bcap / 2 + 2);     // 32-bit bond-word pairs
+        // 32-bit bond-word pairs: the tile's words copied in 16-byte pieces
+        // from an 8-word-aligned start, and room for the bond loop's reads up
+        // to 32 words past a row's end (every word there is a valid record
+        // index: the region starts zeroed and later holds earlier tiles'
+        // words or the next tile's)
+        WB = round4(bcap / 2 + 24);
         TP = round4(tile + 1);         // row offsets
         TB = round4(tile / 4 + 1);     // 32-bit words of boundary kinds
         MM = round4(mmax * META);
@@ -163,7 +168,10 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     static_assert(!LPS || (DIM == 3 && !BATCH), "the solid: 3-d, single simulation");
     const StreamLayout lay(DIM, sa.hcap, sa.bcap, sa.tile, sa.mmax, FORM);
     const uint32_t H = lay.H, T = lay.T;
-    const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u, wbase = tid - lane64;
+    const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u;
+    // first thread of this wave, in a scalar register: the copy loops below
+    // then count and address in scalar registers
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane(tid - lane64);
     double *rec = lds;                                                           // H RD
     int32_t *ids = reinterpret_cast<int32_t *>(rec + (size_t)H * RD);            // 2 H
     uint32_t *words = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);         // WB
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         uint32_t *m = meta + (size_t)k * META;
         m[MT_H0] = h0;
         m[MT_HN] = s < I.limit ? I.halo_ptr[t + 1] - h0 : 0u;
-        m[MT_B0] = I.row_ptr[t0] & ~1u;
+        m[MT_B0] = I.row_ptr[t0] & ~7u;   // 16-byte aligned bond-word copies
         m[MT_B1] = I.row_ptr[t0 + tn];
         m[MT_SO] = I.self_off[t];
         m[MT_INST] = lo;
@@ -217,6 +225,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     };
     auto blist = [&](uint32_t k) { return brk + (k % 3u) * (BRK_CAP + 4); };
     if (tid < 3) brk[tid * (BRK_CAP + 4)] = 0;
+    for (uint32_t c = tid; c < lay.WB; c += B) words[c] = 0u;
     __syncthreads();
 
 
@@ -251,10 +260,11 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 dma16(src, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
             }
         }
-        const uint32_t nw = (b1 - b0 + 1) / 2;
+        // bond words in 16-byte pieces (8 words each; the arrays are padded)
+        const uint32_t nw = (b1 - b0 + 7) / 8;
         for (uint32_t c0 = wbase; c0 < nw; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(words + c0));
-            if (c0 + lane64 < nw) dma4(bw, (b0 / 2 + c0 + lane64) * 4u, m0);
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(words + 4 * (size_t)c0));
+            if (c0 + lane64 < nw) dma16(bw, (b0 / 8 + c0 + lane64) * 16u, m0);
         }
         for (uint32_t c0 = wbase; c0 <= tn; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rowp + c0));
@@ -366,17 +376,36 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     acc.z = fma(g, dxz + duz, acc.z);
                 }
             } else {
-                for (uint32_t p = rs + lane; p < re; p += L) {
-                    const uint32_t w = w16[p];
-                    double dxx, dxy, dxz, dux, duy, duz;
-                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
-                    if (bond<DIM, MIXED, false, NP>(damage, s_c, dxx, dxy, dxz, dux, duy, duz,
-                                                    cv, (w & BW_DEAD) != 0, acc, beta)) {
-                        const uint32_t nw = (uint32_t)(w | BW_DEAD);
-                        w16[p] = (uint16_t)nw;
-                        const uint32_t e = atomicAdd(bl, 1u);
-                        if (e < BRK_CAP) bl[4 + e] = (p << 16) | nw;
-                    }
+                // two bonds per pass, p and p + L, summed in that order (the
+                // gather kernel's order); past the row's end the second one is
+                // the first one's record marked dead, which adds nothing
+                // (the loop walks an LDS pointer; a break recovers its word
+                // position behind an opaque copy, so that no induction
+                // variable is kept for the rare case)
+                auto mark = [&](const uint16_t *wq, uint32_t w) {
+                    uint32_t p = (uint32_t)(wq - w16);
+                    asm volatile("" : "+v"(p));
+                    const uint32_t nw = (uint32_t)(w | BW_DEAD);
+                    w16[p] = (uint16_t)nw;
+                    const uint32_t e = atomicAdd(bl, 1u);
+                    if (e < BRK_CAP) bl[4 + e] = (p << 16) | nw;
+                };
+                const uint16_t *we = w16 + re;
+                for (const uint16_t *wq = w16 + rs + lane; wq < we; wq += 2 * L) {
+                    const bool hb = wq + L < we;
+                    const uint32_t wa = wq[0], wb = wq[L];   // wq[L] exists (see the layout)
+                    double ax, ay, az, aux, auy, auz, bx, by, bz, bux, buy, buz;
+                    bond_vectors(wa, ax, ay, az, aux, auy, auz);
+                    bond_vectors(wb, bx, by, bz, bux, buy, buz);
+                    const bool ka = bond<DIM, MIXED, false, NP>(damage, s_c, ax, ay, az, aux, auy,
+                                                                auz, cv, (wa & BW_DEAD) != 0, acc,
+                                                                beta);
+                    const bool kb = bond<DIM, MIXED, false, NP>(damage, s_c, bx, by, bz, bux, buy,
+                                                                buz, cv,
+                                                                !hb || (wb & BW_DEAD) != 0, acc,
+                                                                beta);
+                    if (ka) mark(wq, wa);
+                    if (kb) mark(wq + L, wb);
                 }
             }
             double fx, fy, fz, Ue;

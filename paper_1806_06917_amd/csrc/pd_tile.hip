@@ -398,7 +398,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(NodeArgs a) {
 __global__ void bw_compose_k(uint64_t nnz, const uint16_t *lcol, const uint8_t *alive,
                              uint16_t *bw) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nnz + 2)
+    if (p < nnz + PD_BW_PAD)
         bw[p] = p >= nnz ? BW_DEAD : (uint16_t)(lcol[p] | ((alive && !alive[p]) ? BW_DEAD : 0));
 }
 
@@ -538,7 +538,7 @@ int pd_launch_tile(pd_ctx ctx, int dim, const NodeArgs &a0, int lanes, bool mixe
 }
 
 int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw) {
-    bw_compose_k<<<pd_blocks(nbr->nnz + 2), PD_BLOCK, 0, ctx->stream>>>(nbr->nnz, nbr->lcol,
+    bw_compose_k<<<pd_blocks(nbr->nnz + PD_BW_PAD), PD_BLOCK, 0, ctx->stream>>>(nbr->nnz, nbr->lcol,
                                                                          alive_sfc, bw);
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;

@@ -174,9 +174,35 @@ def test_tuned_shape_applies_whole_or_not_at_all(gpu):
                 sim.close()
                 if c is plain:
                     ref[prec] = info
-                elif (info["tile"], info["lanes"]) != (240, 4):
+                else:
+                    # the solid's streamed layout does not fit 240-node tiles
+                    assert (info["tile"], info["lanes"]) != (240, 4)
                     assert info == ref[prec], (prec, info, ref[prec])
             nb.close()
+        # tiles held at 128 nodes by a live simulation: a linear-law simulation
+        # created under the 240 x 4 entry takes the automatic shape on them,
+        # not the tuned 4 lanes
+        nbp = pd.Neighbors(plain, dev(torch, X), 3 * h)
+        auto = pd.Simulation(plain, nbp, pd.material(3, 1.0, 1.0, 0.0, "mixed"), dev(torch, X),
+                             dev(torch, V), None, None)
+        want = auto.info()
+        auto.close()
+        nbp.close()
+        assert want["tile"] == 128 and want["lanes"] != 4
+        nb = pd.Neighbors(tuned, dev(torch, X), 3 * h)
+        tuned.set_tuning("auto", 128, 0)
+        holder = pd.Simulation(tuned, nb, pd.material(3, 1.0, 1.0, 0.0, "fp64"), dev(torch, X),
+                               dev(torch, V), None, None)
+        tuned.set_tuning(0, 0, 0)
+        assert holder.info()["tile"] == 128
+        say("linear law under a tuned shape on held tiles")
+        sim = pd.Simulation(tuned, nb, pd.material(3, 1.0, 1.0, 0.0, "mixed"), dev(torch, X),
+                            dev(torch, V), None, None)
+        got = sim.info()
+        sim.close()
+        holder.close()
+        nb.close()
+        assert (got["tile"], got["lanes"]) == (want["tile"], want["lanes"]), (got, want)
     finally:
         tuned.close()
         plain.close()
