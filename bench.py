@@ -43,6 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # valid only while these are unchanged
 KERNEL_SOURCES = ["pd_kernels.hpp", "pd_stream.hip", "pd_internal.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_kernel_cube100_traffic.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "stream_kernel_cube100_counters.md")
+FP64_PEAK_TFLOPS = 78.6
 
 
 def kernel_source_hash():
@@ -53,14 +55,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, precision, launch=None):
-    """HBM bytes per launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy kernel) -- only if the kernel sources are unchanged
-    since the counters were taken and (launch given) the counters were taken
-    at the same tile size and lane count."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def recorded_profile(path, workload, precision, launch=None):
+    """The JSON record of a committed rocprofv3 summary -- only if the kernel
+    sources are unchanged since the counters were taken and (launch given)
+    the counters were taken at the same tile size and lane count."""
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_SUMMARY).read()
+    text = open(path).read()
     m = re.search(r"```json\n(.*?)```", text, re.S)
     if not m:
         return None
@@ -72,7 +73,28 @@ def recorded_traffic(workload, precision, launch=None):
     if launch is not None and (rec.get("tile"), rec.get("lanes")) != (launch.get("tile"),
                                                                        launch.get("lanes")):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def recorded_traffic(workload, precision, launch=None):
+    """HBM bytes per launch measured with rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy kernel), under the conditions of recorded_profile."""
+    rec = recorded_profile(TRAFFIC_SUMMARY, workload, precision, launch)
+    return rec.get("hbm_bytes_per_launch") if rec else None
+
+
+def recorded_valu(workload, precision, launch, nnz):
+    """VALU figures of the step kernel from the committed SQ counters (same
+    conditions): busy fraction of the SIMDs, FP64 rate against the vector
+    FP64 peak, and lane-instructions per bond."""
+    rec = recorded_profile(COUNTER_SUMMARY, workload, precision, launch)
+    if not rec:
+        return None
+    return {"valu_busy": rec["valu_busy"], "fp64_tflops": rec["fp64_tflops"],
+            "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+            "fp64_frac": rec["fp64_tflops"] / FP64_PEAK_TFLOPS,
+            "lane_instr_per_bond": rec["valu_lane_instr_per_bond"],
+            "source": os.path.relpath(COUNTER_SUMMARY, ROOT)}
 
 
 def algorithmic_bytes(n, nnz, dim):
@@ -107,6 +129,10 @@ def parse():
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tile"])
     ap.add_argument("--tile", type=int, default=0, help="nodes per tile (0 = automatic)")
     ap.add_argument("--block", type=int, default=0, help="threads per tile workgroup (0 = auto)")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed windows of --steps steps each; the median is reported")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 512^2 / 32^2 plates and the implicit bar")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
@@ -140,7 +166,28 @@ def dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0), tune=True):
+def timed_windows(torch, ctx, work, reps):
+    """Times `work` (a fixed number of steps) reps times with HIP events on the
+    context's stream, each window bracketed by device synchronisation;
+    returns the window times (ms) and the wall time of all of them."""
+    stream = ctx.stream
+    out = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        work()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out, time.perf_counter() - t0
+
+
+def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0), tune=True,
+            reps=5):
     ctx = pd.Context(0)
     if lanes:
         ctx.set_lanes(lanes)
@@ -163,29 +210,18 @@ def run_gpu(torch, pd, w, precision, steps, warmup, lanes, tuning=("auto", 0, 0)
                         bc_kind=dev(torch, w.bc_kind), bc_vel=dev(torch, w.bc_vel),
                         notch=w.notch, ramp_steps=w.ramp_steps)
     sim.step(warmup, w.dt)
-    torch.cuda.synchronize()
-    stream = ctx.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(steps, w.dt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+    windows, wall = timed_windows(torch, ctx, lambda: sim.step(steps, w.dt), reps)
     info = sim.get(energies=True)
-    res = {"ms_total": ms, "wall_s": wall, "nnz": nb.nnz, "t_nbr_s": t_nbr,
-           "ke": info["ke"], "pe": info["pe"], "step": info["step"], "launch": sim.info(),
-           "autotune": tuned}
+    res = {"ms_total": float(np.median(windows)), "windows_ms": windows, "wall_s": wall,
+           "nnz": nb.nnz, "t_nbr_s": t_nbr, "ke": info["ke"], "pe": info["pe"],
+           "step": info["step"], "launch": sim.info(), "autotune": tuned}
     sim.close()
     nb.close()
     ctx.close()
     return res
 
 
-def serve(pd, reqs, budget, chunk, rate=None, tile=0):
+def serve(pd, reqs, budget, chunk, rate=None, tile=0, precision="mixed"):
     """Runs the requests through pd_server_* with arrivals at their Poisson
     times (rate given) or all at once; returns completion-latency statistics
     and the aggregate bond-evaluation rate.  tile: nodes per tile of the
@@ -206,7 +242,7 @@ def serve(pd, reqs, budget, chunk, rate=None, tile=0):
         while k < len(reqs) and (rate is None or reqs[k].arrival <= now):
             w, c = loads[k]
             t_arr = t0 + (reqs[k].arrival if rate is not None else 0.0)
-            ids.append(srv.submit(w.X, w.V, pd.material(w.dim, c, w.rho, w.s_c, "mixed"),
+            ids.append(srv.submit(w.X, w.V, pd.material(w.dim, c, w.rho, w.s_c, precision),
                                   w.delta, w.dt, w.steps, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
                                   notch=w.notch, ramp_steps=w.ramp_steps,
                                   t_arrival=max(t_arr, 1e-9)))
@@ -237,6 +273,53 @@ def serve(pd, reqs, budget, chunk, rate=None, tile=0):
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "queue_p50_s": float(np.percentile(queue, 50)),
             "max_running": most, "rounds": rounds, "peak_bytes": peak, "server": stats}
+
+
+def config_runs(torch, pd, steps, warmup):
+    """The other explicit workloads in the linearised law, timed like the
+    headline one: the 512^2 notched plate (notch, collars, damage) in both
+    precisions and the 32^2 free plate (100 steps per window, FP64)."""
+    from paper_1806_06917_amd import inputs
+    out = {}
+    for name, precs, k in (("notched512", ("mixed", "fp64"), steps), ("plate32", ("fp64",), 100)):
+        w = inputs.CONFIGS[name]()
+        for prec in precs:
+            r = run_gpu(torch, pd, w, prec, k, warmup, 0)
+            ms = r["ms_total"] / k
+            out[f"{name}_{prec}"] = {
+                "workload": w.name, "nodes": w.n, "bonds": r["nnz"], "precision": prec,
+                "steps": k, "ms_per_step": ms,
+                "windows_ms_per_step": [x / k for x in r["windows_ms"]],
+                "bond_evals_per_s": r["nnz"] / (ms * 1e-3), "launch": r["launch"],
+                "roofline": step_roofline(algorithmic_bytes(w.n, r["nnz"], w.dim), ms)}
+    return out
+
+
+def implicit_runs(torch, pd):
+    """Time to solution of the linear quasi-static 400 x 40 bar (relative
+    residual 1e-10) in FP64 and in mixed precision."""
+    from paper_1806_06917_amd import inputs
+    wb = inputs.CONFIGS["bar400x40"]()
+    progress("implicit bar", wb.name)
+    ctx = pd.Context(0)
+    Xb, Vb, bb = dev(torch, wb.X), dev(torch, wb.V), dev(torch, wb.b)
+    fixed = dev(torch, wb.fixed)
+    nb = pd.Neighbors(ctx, Xb, wb.delta)
+    cb = pd.micromodulus(2, wb.E, wb.delta)
+    out = {}
+    for prec in ("fp64", "mixed", "fp64", "mixed"):      # the first pair warms up
+        u = dev(torch, wb.u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pd.solve_implicit(ctx, nb, pd.material(2, cb, precision=prec), Xb, Vb, bb, u,
+                                fixed=fixed, rtol=1e-10)
+        t = time.perf_counter() - t0
+        out[prec] = {"workload": wb.name, "seconds": t, "outer_iterations": res.outer,
+                     "cg_iterations": res.inner, "rel_residual": res.rel_residual,
+                     "bonds": nb.nnz}
+    nb.close()
+    ctx.close()
+    return out
 
 
 def law_runs(torch, pd, steps, tuned=None):
@@ -444,21 +527,48 @@ def convergence_1d(torch, pd, law, ic, t_end=2.0, every=0.25, pv=False):
             "nodes": [w.n for w in ws], "rates": rows}
 
 
-def cpu_baseline(w, steps):
-    """The FP64 oracle, as it stands, on the same workload for a few steps."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, steps, steps_1t):
+    """The FP64 oracle, as it stands, on the same workload: `steps` velocity-
+    Verlet steps on all the host's cores (OpenMP over nodes), then
+    `steps_1t` on one thread."""
     from oracle import oracle as orc
-    progress("oracle on the host,", steps, "steps")
+    progress("oracle on the host,", steps, "steps on all cores,", steps_1t, "on one")
     mesh = orc.Mesh(w.X, w.V, w.delta)
     c = orc.micromodulus(w.dim, w.E, w.delta)
-    st = mesh.start(w.u0, w.v0, c, w.s_c)
-    t0 = time.perf_counter()
-    mesh.verlet(st, c, w.rho, w.s_c, w.dt, steps, w.bc_kind, w.bc_vel, None, w.ramp_steps)
-    dt = time.perf_counter() - t0
-    return {"value": mesh.nnz * steps / dt, "unit": "bond evals/s", "cores": orc.num_threads(),
+    cores = orc.num_threads()
+
+    def run(k):
+        st = mesh.start(w.u0, w.v0, c, w.s_c)
+        t0 = time.perf_counter()
+        mesh.verlet(st, c, w.rho, w.s_c, w.dt, k, w.bc_kind, w.bc_vel, None, w.ramp_steps)
+        return time.perf_counter() - t0
+
+    dt = run(steps)
+    orc.set_threads(1)
+    try:
+        dt1 = run(steps_1t)
+    finally:
+        orc.set_threads(cores)
+    return {"value": mesh.nnz * steps / dt, "unit": "bond evals/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} velocity-Verlet steps of the full workload ({mesh.n} nodes, "
-                      f"{mesh.nnz} bonds), FP64, OpenMP over nodes; {dt:.2f} s",
-            "ms_per_step": 1e3 * dt / steps}
+                      f"{mesh.nnz} bonds), FP64, OpenMP over nodes on {cores} threads, "
+                      f"{dt:.2f} s; then {steps_1t} steps on one thread, {dt1:.2f} s",
+            "ms_per_step": 1e3 * dt / steps,
+            "single_thread": {"value": mesh.nnz * steps_1t / dt1, "unit": "bond evals/s",
+                              "ms_per_step": 1e3 * dt1 / steps_1t, "steps": steps_1t},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def main():
@@ -503,11 +613,12 @@ def main():
     precision = args.precision or ("mixed" if args.config == "cube100" else "fp64")
     tuning = (args.kernel, args.tile, args.block)
     r = run_gpu(torch, pd, w, precision, args.steps, args.warmup, args.lanes, tuning,
-                not args.no_autotune)
-    ms_step = r["ms_total"] / args.steps
+                not args.no_autotune, args.reps)
+    ms_step = r["ms_total"] / args.steps           # median window
     bonds_per_s = r["nnz"] / (ms_step * 1e-3)
     B = algorithmic_bytes(w.n, r["nnz"], w.dim)
     achieved = B / (ms_step * 1e-3) / 1e9
+    traffic = recorded_traffic(w.name, precision, r["launch"])
     out = {
         "metric": "bond evals/sec + ms/explicit step at 1M nodes",
         "value": bonds_per_s,
@@ -526,18 +637,28 @@ def main():
                    "precision": precision, "dt": w.dt, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(w.name, precision, r["launch"]),
+                     "traffic": traffic,
+                     "traffic_gbs": traffic / (ms_step * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": (traffic / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic else None),
+                     "valu": recorded_valu(w.name, precision, r["launch"], r["nnz"]),
                      "algorithmic_bytes_per_launch": B,
                      "kernel_source_hash": kernel_source_hash()},
+        "timing": {"windows": args.reps, "steps_per_window": args.steps,
+                   "windows_ms_per_step": [x / args.steps for x in r["windows_ms"]],
+                   "statistic": "median window"},
         "neighbor_build_s": r["t_nbr_s"],
         "launch": r["launch"],
         "autotune": r["autotune"],
     }
     if not args.no_fp64_compare and precision == "mixed":
         r64 = run_gpu(torch, pd, w, "fp64", args.steps, args.warmup, args.lanes, tuning,
-                      not args.no_autotune)
+                      not args.no_autotune, args.reps)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
         out["fp64_launch"] = r64["launch"]
+    if not args.no_configs:
+        out["configs"] = config_runs(torch, pd, 200, 20)
+        out["implicit"] = implicit_runs(torch, pd)
     if not args.no_law:
         # the solid's cube steps use the autotuner's shape for this mesh kind
         seeds = []
@@ -549,17 +670,24 @@ def main():
     if not args.no_serve:
         from paper_1806_06917_amd import inputs
         budget = int(args.serve_budget_gib * (1 << 30))
-        burst = serve(pd, inputs.serving_requests(args.serve_count), budget, args.serve_chunk)
-        rate = args.serve_load * burst["requests_per_s"]
-        poisson = serve(pd, inputs.serving_requests(args.serve_count, rate=rate), budget,
-                        args.serve_chunk, rate)
-        out["serving"] = {
-            "workload": f"{args.serve_count} notched plates, side U{{64..512}}, delta in "
-                        "{3h,4h}, s_c ~ U[5e-4,2e-3], 1k-5k steps, mixed precision, lanes 4",
-            "budget_bytes": budget, "chunk_steps": args.serve_chunk,
-            "burst": burst, "poisson": dict(poisson, rate_per_s=rate, load=args.serve_load),
-            "p50_s": poisson["p50_s"], "p99_s": poisson["p99_s"],
-            "bond_evals_per_s": poisson["bond_evals_per_s"]}
+        per = {}
+        for prec in ("mixed", "fp64"):
+            burst = serve(pd, inputs.serving_requests(args.serve_count), budget,
+                          args.serve_chunk, precision=prec)
+            rate = args.serve_load * burst["requests_per_s"]
+            poisson = serve(pd, inputs.serving_requests(args.serve_count, rate=rate), budget,
+                            args.serve_chunk, rate, precision=prec)
+            per[prec] = {"burst": burst,
+                         "poisson": dict(poisson, rate_per_s=rate, load=args.serve_load),
+                         "p50_s": poisson["p50_s"], "p99_s": poisson["p99_s"],
+                         "bond_evals_per_s": poisson["bond_evals_per_s"]}
+        out["serving"] = dict(
+            per["mixed"],
+            workload=f"{args.serve_count} notched plates, side U{{64..512}}, delta in "
+                     "{3h,4h}, s_c ~ U[5e-4,2e-3], 1k-5k steps, lanes 4; the top-level "
+                     "figures are the mixed-precision service, `fp64` the same requests "
+                     "served in FP64",
+            budget_bytes=budget, chunk_steps=args.serve_chunk, fp64=per["fp64"])
     if not args.no_law and not args.no_validation:
         runs = []
         for law, ic in (("linear", 1), ("np", 2)):
@@ -584,7 +712,7 @@ def main():
                              "runs_1d": runs1}
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (180 if w.n > 100000 else 600)
-        out["cpu_baseline"] = cpu_baseline(w, steps)
+        out["cpu_baseline"] = cpu_baseline(w, steps, max(1, steps // 18))
     print(json.dumps(out), flush=True)
 
 

@@ -315,6 +315,7 @@ int pd_nbr_destroy(pd_nbr nbr);
 int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
                       const double *V, const double *u, uint8_t *alive, double *f, double *U);
 
+
 /*
  * Create a resident explicit simulation (state kept on the GPU in internal
  * order).  Arrays are copied; the caller may free them afterwards.
@@ -530,8 +531,10 @@ int pd_apply_tangent_at(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const do
  * for PD_LAW_NP a Newton-Krylov iteration, which needs a positive definite
  * tangent: 2 beta r < 1 on the bonds that carry load).
  *   precision PD_FP64: float64 CG solving each Newton system to the target.
- *   PD_MIXED: an inner CG with the estimate-only tangent, each correction to
- *   1e-5 relative, inside float64 iterative refinement.
+ *   PD_MIXED: each correction solved to 1e-5 relative by a CG with float32
+ *   vectors and float32 bond arithmetic in the tangent but float64 dot
+ *   products, inside iterative refinement on float64 residuals (the force
+ *   in float64) until rtol is met.
  *   u      device [n][dim], in: initial guess holding the fixed values,
  *          out: solution (or last iterate)
  *   b      device [n][dim] body force density

@@ -5,17 +5,22 @@
 // constant for the linearised law and c exp(-beta r)(1 - 2 beta r) per bond
 // for the NP law), each Newton system solved by conjugate gradients.
 //
-// CG runs entirely on the device: per iteration one tangent launch and three
-// small vector kernels; the scalars alpha, beta and r.r live in device memory
-// and every reduction is a fixed two-level tree (block partials, then the
-// same ordered sum in every consumer block), so runs are bit-reproducible.
-// A device `done` flag turns the remaining launches of a chunk into no-ops;
-// the host looks at the state once per chunk.
+// CG runs on the device in two launches per iteration.  The first applies
+// the tangent to the new search direction p = r + beta p_old, which it forms
+// on the fly for every node it reads (p is double-buffered, so no block
+// overwrites a direction another block still reads) and stores for its own
+// nodes, and it sums p.q per block.  The second updates x and r with
+// alpha = r.r / p.q and sums r.r per block.  Every block reduces the other
+// launch's block sums in one fixed order, so all blocks derive the same
+// alpha, beta and stopping decision and runs are bit-reproducible; a device
+// state word records r.r and the iteration count, and the host looks at it
+// once per chunk of iterations.
 //
-// Precision: PD_FP64 runs every part in float64.  PD_MIXED applies the
-// tangent with the unrefined reciprocal-square-root estimate inside the CG
-// (float64 vectors and dot products) and wraps it in iterative refinement
-// with full-precision float64 residuals.
+// Precision: PD_FP64 runs every part in float64.  PD_MIXED solves each
+// correction with float32 CG vectors (x, r, p, q) and float32 bond
+// arithmetic in the tangent, with float64 dot products, inside iterative
+// refinement on float64 residuals (the force in float64) until the relative
+// residual reaches the requested tolerance.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -24,18 +29,20 @@
 
 namespace {
 
+using namespace pdk;
+
 struct CgState {
-    double rr[2];   // r.r, double-buffered by iteration parity
+    double rr[2];   // r.r at the start of iteration it, in slot it & 1
     double tol2;    // stop when r.r <= tol2
     int done;
     int iters;
 };
 
-__device__ double reduce_partials(const double *part) {
-    // every block computes the same ordered tree over PD_RED_BLOCKS values
+// ordered tree over nparts block sums (the same in every block)
+__device__ double reduce_partials(const double *part, int nparts) {
     __shared__ double sh[PD_BLOCK];
     double acc = 0.0;
-    for (int k = threadIdx.x; k < PD_RED_BLOCKS; k += PD_BLOCK) acc += part[k];
+    for (int k = threadIdx.x; k < nparts; k += PD_BLOCK) acc += part[k];
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int off = PD_BLOCK / 2; off > 0; off >>= 1) {
@@ -58,9 +65,7 @@ __device__ void block_partial(double acc, double *part) {
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void dot_k(const double *a, const double *b, uint64_t m, double *part,
-                      const CgState *st) {
-    if (st && st->done) return;
+__global__ void dot_k(const double *a, const double *b, uint64_t m, double *part) {
     double acc = 0.0;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
          k += (uint64_t)gridDim.x * blockDim.x)
@@ -68,35 +73,165 @@ __global__ void dot_k(const double *a, const double *b, uint64_t m, double *part
     block_partial(acc, part);
 }
 
-__global__ void cg_update_k(double *x, double *r, const double *p, const double *q, uint64_t m,
-                            const double *part_pq, double *part_rr, CgState *st, int parity) {
-    if (st->done) return;
-    const double pq = reduce_partials(part_pq);
-    const double alpha = st->rr[parity] / pq;
-    double acc = 0.0;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        x[k] = x[k] + alpha * p[k];
-        const double rk = r[k] - alpha * q[k];
-        r[k] = rk;
-        acc += rk * rk;
+// Tangent factor of each bond at the linearisation point u (NP law):
+// k = exp(-beta r)(1 - 2 beta r), r = |xi| S^2, S = (eta.xi)/|xi|^2 -- the
+// factor psi'(r) + 2 r psi''(r) over psi'(0) of the tangent
+template <int DIM>
+__global__ void bond_factor_k(uint32_t n, const uint32_t *row_ptr, const int32_t *col,
+                              const double *xv, const double *u, double beta, double *kb) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int US = DIM == 3 ? 4 : 2;
+    const double xix = xv[4 * (size_t)i], xiy = xv[4 * (size_t)i + 1];
+    const double xiz = DIM == 3 ? xv[4 * (size_t)i + 2] : 0.0;
+    const double uix = u[(size_t)i * US], uiy = u[(size_t)i * US + 1];
+    const double uiz = DIM == 3 ? u[(size_t)i * US + 2] : 0.0;
+    for (uint32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        const uint32_t j = (uint32_t)col[p];
+        const double dx = xv[4 * (size_t)j] - xix, dy = xv[4 * (size_t)j + 1] - xiy;
+        const double dz = DIM == 3 ? xv[4 * (size_t)j + 2] - xiz : 0.0;
+        const double ex = u[(size_t)j * US] - uix, ey = u[(size_t)j * US + 1] - uiy;
+        const double ez = DIM == 3 ? u[(size_t)j * US + 2] - uiz : 0.0;
+        const double r2 = dotf<DIM>(dx, dy, dz, dx, dy, dz);
+        const double S = dotf<DIM>(ex, ey, ez, dx, dy, dz) / r2;
+        const double r = sqrt(r2) * S * S;
+        kb[p] = exp(-beta * r) * (1.0 - 2.0 * beta * r);
     }
-    block_partial(acc, part_rr);
 }
 
-__global__ void cg_direction_k(double *p, const double *r, uint64_t m, const double *part_rr,
-                               CgState *st, int parity) {
+// one CG solve's arrays; vectors in sfc order, [n][US] like u
+template <class T>
+struct CgArgs {
+    uint32_t n;
+    const uint32_t *row_ptr;
+    const int32_t *col;
+    const double *xv;            // {x, y, z, V} / {x, y, V, 0}
+    const uint8_t *alive;        // NULL: all intact
+    const uint8_t *fixed;        // NULL: none
+    const double *kb;            // per-bond tangent factor (NP), NULL: 1
+    double c;
+    T *x, *r, *q;
+    T *p[2];                     // search direction, double-buffered
+    double *part_pq, *part_rr;   // block sums
+    int nparts;
+    CgState *st;
+};
+
+__device__ __forceinline__ double rsq_of(double r2) { return rsqrt_pos(r2); }
+__device__ __forceinline__ float rsq_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
+
+// First launch of iteration `it`: beta from the previous update's r.r (and
+// the stopping test), p = r + beta p_old for every node read, q = H p for
+// the block's nodes (fixed rows identity, p read as 0 at fixed nodes, dead
+// bonds skipped), and the block's sum of p.q.  L lanes per node.
+template <int DIM, int L, class T>
+__global__ __launch_bounds__(PD_BLOCK) void cg_apply_k(CgArgs<T> a, int it) {
+    CgState *st = a.st;
     if (st->done) return;
-    const double rr_new = reduce_partials(part_rr);
-    const double beta = rr_new / st->rr[parity];
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
-         k += (uint64_t)gridDim.x * blockDim.x)
-        p[k] = r[k] + beta * p[k];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->rr[parity ^ 1] = rr_new;
-        st->iters += 1;
-        if (rr_new <= st->tol2) st->done = 1;
+    constexpr int US = DIM == 3 ? 4 : 2;
+    double beta = 0.0;
+    if (it > 0) {
+        const double rr = reduce_partials(a.part_rr, a.nparts);
+        beta = rr / st->rr[(it - 1) & 1];
+        if (rr <= st->tol2) {          // every block takes the same decision
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->rr[it & 1] = rr;
+                st->iters = it;
+                st->done = 1;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->rr[it & 1] = rr;
     }
+    const T tb = (T)beta;
+    const T *__restrict__ pold = a.p[it & 1];
+    T *__restrict__ pnew = a.p[(it + 1) & 1];
+    const T *__restrict__ r = a.r;
+    auto dir = [&](uint32_t j, int d) -> T {
+        return it == 0 ? r[(size_t)j * US + d] : r[(size_t)j * US + d] + tb * pold[(size_t)j * US + d];
+    };
+    const int lane = threadIdx.x & (L - 1);
+    const uint32_t per = (uint32_t)(gridDim.x * PD_BLOCK / L);
+    double pq = 0.0;
+    for (uint32_t i = (blockIdx.x * PD_BLOCK + threadIdx.x) / L; i < a.n; i += per) {
+        const bool fi = a.fixed && a.fixed[i];
+        const T pix = dir(i, 0), piy = dir(i, 1), piz = DIM == 3 ? dir(i, 2) : (T)0;
+        const double xix = a.xv[4 * (size_t)i], xiy = a.xv[4 * (size_t)i + 1];
+        const double xiz = DIM == 3 ? a.xv[4 * (size_t)i + 2] : 0.0;
+        const double Vi = a.xv[4 * (size_t)i + (DIM == 3 ? 3 : 2)];
+        T sx = 0, sy = 0, sz = 0;
+        if (!fi) {
+            for (uint32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += L) {
+                if (a.alive && !a.alive[e]) continue;
+                const uint32_t j = (uint32_t)a.col[e];
+                const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+                const T dx = (T)(xj.x - xix), dy = (T)(xj.y - xiy);
+                const T dz = DIM == 3 ? (T)(xj.z - xiz) : (T)0;
+                T wx = 0, wy = 0, wz = 0;
+                if (!(a.fixed && a.fixed[j])) {
+                    wx = dir(j, 0) - pix;
+                    wy = dir(j, 1) - piy;
+                    if (DIM == 3) wz = dir(j, 2) - piz;
+                } else {
+                    wx = -pix;
+                    wy = -piy;
+                    if (DIM == 3) wz = -piz;
+                }
+                const T r2 = DIM == 3 ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+                const T ew = DIM == 3 ? wx * dx + wy * dy + wz * dz : wx * dx + wy * dy;
+                const T inv = rsq_of(r2);
+                T g = (T)(a.c * (DIM == 3 ? xj.w : xj.z)) * (ew * inv * inv) * inv;
+                if (a.kb) g *= (T)a.kb[e];
+                sx += g * dx;
+                sy += g * dy;
+                if (DIM == 3) sz += g * dz;
+            }
+        }
+        // lane sums (neighbouring lanes first)
+        for (int o = 1; o < L; o <<= 1) {
+            sx += __shfl_xor(sx, o, L);
+            sy += __shfl_xor(sy, o, L);
+            if (DIM == 3) sz += __shfl_xor(sz, o, L);
+        }
+        if (lane == 0) {
+            const T qx = fi ? pix : (T)(-Vi) * sx, qy = fi ? piy : (T)(-Vi) * sy;
+            const T qz = fi ? piz : (T)(-Vi) * sz;
+            a.q[(size_t)i * US] = qx;
+            a.q[(size_t)i * US + 1] = qy;
+            pnew[(size_t)i * US] = pix;
+            pnew[(size_t)i * US + 1] = piy;
+            if (DIM == 3) {
+                a.q[(size_t)i * US + 2] = qz;
+                pnew[(size_t)i * US + 2] = piz;
+            }
+            pq += (double)pix * (double)qx + (double)piy * (double)qy +
+                  (DIM == 3 ? (double)piz * (double)qz : 0.0);
+        }
+    }
+    block_partial(pq, a.part_pq);
+}
+
+// Second launch: alpha = r.r / p.q, x += alpha p, r -= alpha q, block sums
+// of the new r.r.
+template <int DIM, class T>
+__global__ __launch_bounds__(PD_BLOCK) void cg_update_k(CgArgs<T> a, int it) {
+    CgState *st = a.st;
+    if (st->done) return;
+    constexpr int US = DIM == 3 ? 4 : 2;
+    const double pq = reduce_partials(a.part_pq, a.nparts);
+    const T alpha = (T)(st->rr[it & 1] / pq);
+    const T *__restrict__ p = a.p[(it + 1) & 1];
+    double acc = 0.0;
+    const uint64_t m = (uint64_t)a.n * US;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        if (DIM == 3 && (k & 3) == 3) continue;   // padding
+        a.x[k] = a.x[k] + alpha * p[k];
+        const T rk = a.r[k] - alpha * a.q[k];
+        a.r[k] = rk;
+        acc += (double)rk * (double)rk;
+    }
+    block_partial(acc, a.part_rr);
 }
 
 // r_i = V_i (f_i + b_i) on free nodes, 0 on fixed ones; vectors padded to us
@@ -123,39 +258,67 @@ __global__ void rhs_norm_k(uint32_t n, int us, int dim, const double *xv, const 
     out[k] = (c < dim && !(fixed && fixed[i])) ? V * b[k] : 0.0;
 }
 
-__global__ void axpy_k(double *y, const double *x, uint64_t m) {
+// y += (double) x
+template <class T>
+__global__ void add_k(double *y, const T *x, uint64_t m) {
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) y[k] = y[k] + x[k];
+    if (k < m) y[k] = y[k] + (double)x[k];
 }
 
-__global__ void copy_k(double *y, const double *x, uint64_t m) {
+// CG start: x = 0, r = (T) rhs, both directions 0
+template <class T>
+__global__ void cg_init_k(const double *rhs, T *x, T *r, T *p0, T *p1, uint64_t m) {
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) y[k] = x[k];
+    if (k >= m) return;
+    x[k] = 0;
+    r[k] = (T)rhs[k];
+    p0[k] = 0;
+    p1[k] = 0;
 }
 
-__global__ void zero_k(double *y, uint64_t m) {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < m) y[k] = 0.0;
+template <class T>
+__global__ void r_dot_k(const T *r, uint64_t m, double *part) {
+    double acc = 0.0;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (uint64_t)gridDim.x * blockDim.x)
+        acc += (double)r[k] * (double)r[k];
+    block_partial(acc, part);
 }
+
+template <class T>
+struct CgVecs {
+    T *x = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
+    ~CgVecs() { pd_free(x); pd_free(r); pd_free(q); pd_free(p0); pd_free(p1); }
+    int alloc(pd_ctx ctx, uint64_t m) {
+        PD_TRY(pd_alloc(ctx, &x, m));
+        PD_TRY(pd_alloc(ctx, &r, m));
+        PD_TRY(pd_alloc(ctx, &q, m));
+        PD_TRY(pd_alloc(ctx, &p0, m));
+        PD_TRY(pd_alloc(ctx, &p1, m));
+        return PD_OK;
+    }
+};
 
 struct Work {
-    double *xv = nullptr, *u = nullptr, *b = nullptr, *f = nullptr, *r = nullptr, *x = nullptr,
-           *p = nullptr, *q = nullptr, *part_a = nullptr, *part_b = nullptr;
+    double *xv = nullptr, *u = nullptr, *b = nullptr, *f = nullptr, *r = nullptr,
+           *part_a = nullptr, *part_b = nullptr, *kb = nullptr;
     uint8_t *alive = nullptr, *fixed = nullptr;
     uint16_t *bw = nullptr;
     int block = 0;
+    CgVecs<double> v64;
+    CgVecs<float> v32;
     CgState *st = nullptr;
     CgState *st_host = nullptr;
     ~Work() {
-        pd_free(xv); pd_free(u); pd_free(b); pd_free(f); pd_free(r); pd_free(x); pd_free(p);
-        pd_free(q); pd_free(part_a); pd_free(part_b); pd_free(alive); pd_free(fixed); pd_free(bw); pd_free(st);
+        pd_free(xv); pd_free(u); pd_free(b); pd_free(f); pd_free(r); pd_free(part_a);
+        pd_free(part_b); pd_free(kb); pd_free(alive); pd_free(fixed); pd_free(bw); pd_free(st);
         if (st_host) (void)hipHostFree(st_host);
     }
 };
 
 int dot_host(pd_ctx ctx, const double *a, const double *b, uint64_t m, double *part,
              double *out) {
-    dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, ctx->stream>>>(a, b, m, part, nullptr);
+    dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, ctx->stream>>>(a, b, m, part);
     PD_LAUNCH_CHECK(ctx);
     PD_HIP(ctx, hipMemcpyAsync(ctx->red_host, part, sizeof(double) * PD_RED_BLOCKS,
                                hipMemcpyDeviceToHost, ctx->stream));
@@ -166,45 +329,88 @@ int dot_host(pd_ctx ctx, const double *a, const double *b, uint64_t m, double *p
     return PD_OK;
 }
 
-// Solves H x = r (x starts at 0) until ||r_k|| <= tol or `budget` iterations.
-int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, uint64_t m,
-             double tol, int budget, int *iters) {
+template <int DIM, int L, class T>
+void launch_cg_iter(const CgArgs<T> &a, int it, unsigned grid, hipStream_t s) {
+    cg_apply_k<DIM, L, T><<<grid, PD_BLOCK, 0, s>>>(a, it);
+    cg_update_k<DIM, T><<<grid, PD_BLOCK, 0, s>>>(a, it);
+}
+
+template <int DIM, class T>
+int launch_cg_lanes(pd_ctx ctx, const CgArgs<T> &a, int it, unsigned grid, int L) {
+    hipStream_t s = ctx->stream;
+    switch (L) {
+    case 1: launch_cg_iter<DIM, 1, T>(a, it, grid, s); break;
+    case 2: launch_cg_iter<DIM, 2, T>(a, it, grid, s); break;
+    case 4: launch_cg_iter<DIM, 4, T>(a, it, grid, s); break;
+    case 8: launch_cg_iter<DIM, 8, T>(a, it, grid, s); break;
+    case 16: launch_cg_iter<DIM, 16, T>(a, it, grid, s); break;
+    default: launch_cg_iter<DIM, 32, T>(a, it, grid, s); break;
+    }
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
+// Solves H x = rhs (x from 0) until ||r|| <= tol or `budget` iterations, in
+// the vector precision T; x is left in v.x.
+template <class T>
+int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVecs<T> &v,
+             const double *rhs, uint64_t m, double tol, int budget, int *iters) {
     hipStream_t s = ctx->stream;
     const unsigned gm = pd_blocks(m);
-    zero_k<<<gm, PD_BLOCK, 0, s>>>(w.x, m);
-    copy_k<<<gm, PD_BLOCK, 0, s>>>(w.p, w.r, m);
+    cg_init_k<T><<<gm, PD_BLOCK, 0, s>>>(rhs, v.x, v.r, v.p0, v.p1, m);
+    r_dot_k<T><<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(v.r, m, w.part_a);
     PD_LAUNCH_CHECK(ctx);
+    PD_HIP(ctx, hipMemcpyAsync(ctx->red_host, w.part_a, sizeof(double) * PD_RED_BLOCKS,
+                               hipMemcpyDeviceToHost, s));
+    PD_HIP(ctx, hipStreamSynchronize(s));
     double rr = 0.0;
-    PD_TRY(dot_host(ctx, w.r, w.r, m, w.part_a, &rr));
+    for (int k = 0; k < PD_RED_BLOCKS; ++k) rr += ctx->red_host[k];
     w.st_host->rr[0] = rr;
     w.st_host->rr[1] = 0.0;
     w.st_host->tol2 = tol * tol;
     w.st_host->done = rr <= tol * tol;
     w.st_host->iters = 0;
     PD_HIP(ctx, hipMemcpyAsync(w.st, w.st_host, sizeof(CgState), hipMemcpyHostToDevice, s));
+    const int L = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    CgArgs<T> a{};
+    a.n = nbr->n;
+    a.row_ptr = nbr->row_ptr;
+    a.col = nbr->col;
+    a.xv = w.xv;
+    a.alive = w.alive;
+    a.fixed = w.fixed;
+    a.kb = mat->law == PD_LAW_NP ? w.kb : nullptr;
+    a.c = mat->c;
+    a.x = v.x;
+    a.r = v.r;
+    a.q = v.q;
+    a.p[0] = v.p0;
+    a.p[1] = v.p1;
+    a.part_pq = w.part_a;
+    a.part_rr = w.part_b;
+    a.st = w.st;
+    // one grid for both launches: enough blocks for every node's lane group
+    // (at most the partial-sum slots); the update walks the vectors strided
+    uint64_t need = ((uint64_t)nbr->n * L + PD_BLOCK - 1) / PD_BLOCK;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, PD_RED_BLOCKS));
+    a.nparts = (int)grid;
     const int chunk = 32;
     int done = w.st_host->done;
     int it = 0;
     while (!done && it < budget) {
         const int nrun = std::min(chunk, budget - it);
         for (int k = 0; k < nrun; ++k) {
-            const int parity = (it + k) & 1;
-            PD_TRY(pd_tangent_sfc(ctx, nbr, mat, w.xv, w.alive, w.bw, w.block, w.fixed, w.p,
-                                  w.q, &w.st->done, w.u));
-            dot_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.p, w.q, m, w.part_a, w.st);
-            cg_update_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.x, w.r, w.p, w.q, m, w.part_a,
-                                                          w.part_b, w.st, parity);
-            cg_direction_k<<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(w.p, w.r, m, w.part_b, w.st,
-                                                             parity);
-            PD_LAUNCH_CHECK(ctx);
+            const int st = nbr->dim == 3 ? launch_cg_lanes<3, T>(ctx, a, it + k, grid, L)
+                                         : launch_cg_lanes<2, T>(ctx, a, it + k, grid, L);
+            if (st != PD_OK) return st;
         }
         it += nrun;
         PD_HIP(ctx, hipMemcpyAsync(w.st_host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         PD_HIP(ctx, hipStreamSynchronize(s));
         done = w.st_host->done;
-        it = w.st_host->iters;
+        if (done) it = w.st_host->iters;
     }
-    *iters = w.st_host->iters;
+    *iters = it;
     return PD_OK;
 }
 
@@ -246,9 +452,9 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_alloc(ctx, &w.b, m));
     PD_TRY(pd_alloc(ctx, &w.f, m));
     PD_TRY(pd_alloc(ctx, &w.r, m));
-    PD_TRY(pd_alloc(ctx, &w.x, m));
-    PD_TRY(pd_alloc(ctx, &w.p, m));
-    PD_TRY(pd_alloc(ctx, &w.q, m));
+    const bool mixed = mat->precision == PD_MIXED;
+    if (mixed) PD_TRY(w.v32.alloc(ctx, m));
+    else PD_TRY(w.v64.alloc(ctx, m));
     PD_TRY(pd_alloc(ctx, &w.part_a, PD_RED_BLOCKS));
     PD_TRY(pd_alloc(ctx, &w.part_b, PD_RED_BLOCKS));
     PD_TRY(pd_alloc(ctx, &w.st, 1));
@@ -266,6 +472,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     }
     int block = 0;
     const bool np = mat->law == PD_LAW_NP;
+    if (np) PD_TRY(pd_alloc(ctx, &w.kb, nbr->nnz));
     if (!pd_general_law(mat))
         PD_TRY(pd_plan_kernel(ctx, nbr, pd_auto_lanes(ctx, nbr->nnz, nbr->n), &block));
     w.block = block;
@@ -285,8 +492,6 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(dot_host(ctx, w.r, w.r, m, w.part_a, &bn2));
     const double bnorm = bn2 > 0.0 ? std::sqrt(bn2) : 1.0;
 
-    pd_material inner = *mat;
-    const bool mixed = mat->precision == PD_MIXED;
     // Newton steps: one suffices for the linearised law (a few more for
     // iterative refinement); NP converges quadratically near the solution
     const int max_outer = np ? 60 : (mixed ? 30 : 4);
@@ -314,11 +519,26 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         // looser of the two, keeps Newton's convergence fast)
         double target = mixed ? 1e-5 * std::sqrt(rr) : 0.5 * rtol * bnorm;
         if (np) target = std::max(target, 1e-6 * std::sqrt(rr));
+        if (np) {
+            // the tangent's bond factors at this Newton iterate
+            if (dim == 3)
+                bond_factor_k<3><<<pd_blocks(n), PD_BLOCK, 0, ctx->stream>>>(
+                    n, nbr->row_ptr, nbr->col, w.xv, w.u, mat->beta, w.kb);
+            else
+                bond_factor_k<2><<<pd_blocks(n), PD_BLOCK, 0, ctx->stream>>>(
+                    n, nbr->row_ptr, nbr->col, w.xv, w.u, mat->beta, w.kb);
+            PD_LAUNCH_CHECK(ctx);
+        }
         int k = 0;
-        PD_TRY(cg_solve(ctx, nbr, &inner, w, m, target, maxit - inner_total, &k));
-        inner_total += k;
-        axpy_k<<<gm, PD_BLOCK, 0, ctx->stream>>>(w.u, w.x, m);
+        if (mixed) {
+            PD_TRY(cg_solve(ctx, nbr, mat, w, w.v32, w.r, m, target, maxit - inner_total, &k));
+            add_k<float><<<gm, PD_BLOCK, 0, ctx->stream>>>(w.u, w.v32.x, m);
+        } else {
+            PD_TRY(cg_solve(ctx, nbr, mat, w, w.v64, w.r, m, target, maxit - inner_total, &k));
+            add_k<double><<<gm, PD_BLOCK, 0, ctx->stream>>>(w.u, w.v64.x, m);
+        }
         PD_LAUNCH_CHECK(ctx);
+        inner_total += k;
         ++outer;
     }
     PD_TRY(pd_scatter_vec(ctx, nbr, w.u, u));

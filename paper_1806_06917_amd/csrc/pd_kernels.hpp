@@ -530,7 +530,8 @@ inline uint32_t pd_tile_hcap(const pd_nbr nbr) { return (nbr->halo_max + 31u) & 
 inline uint32_t pd_tile_bcap(const pd_nbr nbr) { return (nbr->bonds_max + 63u) & ~63u; }
 // bond words of a tiled neighbour list: bw = lcol | 0x8000 where alive == 0
 // (bw arrays hold nnz + PD_BW_PAD entries, the pad marked dead, for the
-// kernels' 32-bit reads and the streamed kernel's 16-byte copies)
-constexpr uint32_t PD_BW_PAD = 8;
+// kernels' 32-bit reads, the streamed kernel's 16-byte copies and its bond
+// loop's reads up to 6 L - 1 words past a row's end)
+constexpr uint32_t PD_BW_PAD = 256;
 int pd_bw_compose(pd_ctx ctx, const pd_nbr nbr, const uint8_t *alive_sfc, uint16_t *bw);
 int pd_bw_to_alive(pd_ctx ctx, const pd_nbr nbr, const uint16_t *bw, uint8_t *alive_sfc);

@@ -117,13 +117,22 @@ constexpr uint32_t BRK_CAP = 256;    // broken bonds listed per tile (more: the 
 
 inline __host__ __device__ uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
 
+// the forms whose bond loop reads the bond words from global memory (the
+// linearised and NP laws: one read per bond and step, breaks stored at once);
+// the solid's passes stage them in LDS
+__host__ __device__ constexpr bool words_global(int form) {
+    return form == SK_LINEAR || form == SK_NP;
+}
+
 // LDS layout, in this order (every region a multiple of 16 bytes): the tile
 // slot (records, bond words, row offsets, v, boundary kinds), two halo-id
 // slots, three break lists (tile k uses list k mod 3, so a list is cleared
 // one tile before its next use without an extra barrier), tile metadata,
-// and for the solid's force pass the halo's coefficients {c, d, h, 0}.
+// and for the solid's force pass the halo's coefficients {c, d, h, 0}.  The
+// forms that read bond words from global memory have no words region and no
+// break lists.
 struct StreamLayout {
-    uint32_t H, T, WB, TP, TB, MM, RD, US, SP;
+    uint32_t H, T, WB, TP, TB, BL, MM, RD, US, SP;
     __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile,
                                      uint32_t mmax, int form) {
         H = hcap;                      // multiple of 32
@@ -133,7 +142,8 @@ struct StreamLayout {
         // to 32 words past a row's end (every word there is a valid record
         // index: the region starts zeroed and later holds earlier tiles'
         // words or the next tile's)
-        WB = round4(bcap / 2 + 24);
+        WB = words_global(form) ? 0u : round4(bcap / 2 + 24);
+        BL = words_global(form) ? 0u : 3 * (BRK_CAP + 4);
         TP = round4(tile + 1);         // row offsets
         TB = round4(tile / 4 + 1);     // 32-bit words of boundary kinds
         MM = round4(mmax * META);
@@ -143,8 +153,8 @@ struct StreamLayout {
     }
     __host__ __device__ size_t bytes() const {
         return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)WB * 4 + (size_t)TP * 4 +
-               (size_t)T * US * 8 + (size_t)TB * 4 + (size_t)3 * (BRK_CAP + 4) * 4 +
-               (size_t)MM * 4 + (size_t)SP * 8;
+               (size_t)T * US * 8 + (size_t)TB * 4 + (size_t)BL * 4 + (size_t)MM * 4 +
+               (size_t)SP * 8;
     }
 };
 
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     double *vbuf = reinterpret_cast<double *>(rowp + lay.TP);                    // T US
     uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)T * US);         // TB
     uint32_t *brk = bcb + lay.TB;                                                // 3 (4 + CAP)
-    uint32_t *meta = brk + 3 * (BRK_CAP + 4);                                    // MM
+    uint32_t *meta = brk + lay.BL;                                               // MM
     double *sps = reinterpret_cast<double *>(meta + lay.MM);                     // SP
     const StreamInst *inst = sa.inst;
     const int64_t s = sa.step;                          // step of this launch in its chunk
@@ -223,8 +233,9 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         if (!BATCH) return sa.one;
         return load_inst(inst, (uint32_t)__builtin_amdgcn_readfirstlane(meta[k * META + MT_INST]));
     };
+    constexpr bool GW = words_global(FORM);
     auto blist = [&](uint32_t k) { return brk + (k % 3u) * (BRK_CAP + 4); };
-    if (tid < 3) brk[tid * (BRK_CAP + 4)] = 0;
+    if (!GW && tid < 3) brk[tid * (BRK_CAP + 4)] = 0;
     for (uint32_t c = tid; c < lay.WB; c += B) words[c] = 0u;
     __syncthreads();
 
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             }
         }
         // bond words in 16-byte pieces (8 words each; the arrays are padded)
-        const uint32_t nw = (b1 - b0 + 7) / 8;
+        const uint32_t nw = GW ? 0u : (b1 - b0 + 7) / 8;
         for (uint32_t c0 = wbase; c0 < nw; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(words + 4 * (size_t)c0));
             if (c0 + lane64 < nw) dma16(bw, (b0 / 8 + c0 + lane64) * 16u, m0);
@@ -321,8 +332,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             // xi and eta of the bond whose word is w
             auto bond_vectors = [&](uint32_t w, double &dxx, double &dxy, double &dxz,
                                     double &dux, double &duy, double &duz) {
-                const double2 *rj =
-                    reinterpret_cast<const double2 *>(rec + (size_t)(w & 0x7fffu) * RD);
+                const double2 *rj = reinterpret_cast<const double2 *>(
+                    rec + (size_t)__builtin_amdgcn_ubfe(w, 0, 15) * RD);
                 const double2 c0 = rj[0], c1 = rj[1];
                 if (DIM == 3) {
                     const double2 c2 = rj[2];
@@ -378,22 +389,20 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             } else {
                 // two bonds per pass, p and p + L, summed in that order (the
                 // gather kernel's order); past the row's end the second one is
-                // the first one's record marked dead, which adds nothing
-                // (the loop walks an LDS pointer; a break recovers its word
-                // position behind an opaque copy, so that no induction
-                // variable is kept for the rare case)
-                auto mark = [&](const uint16_t *wq, uint32_t w) {
-                    uint32_t p = (uint32_t)(wq - w16);
-                    asm volatile("" : "+v"(p));
-                    const uint32_t nw = (uint32_t)(w | BW_DEAD);
-                    w16[p] = (uint16_t)nw;
-                    const uint32_t e = atomicAdd(bl, 1u);
-                    if (e < BRK_CAP) bl[4 + e] = (p << 16) | nw;
-                };
-                const uint16_t *we = w16 + re;
-                for (const uint16_t *wq = w16 + rs + lane; wq < we; wq += 2 * L) {
+                // marked dead and adds nothing.  The words come from global
+                // memory (reads past a row's end stay inside the padded array
+                // and give valid record indices: the next rows' words, the
+                // next tile's, or the dead pad); a break is stored at once.
+                const uint16_t *gw = I.bw + b0;
+                const uint16_t *we = gw + re;
+                const uint16_t *wq = gw + rs + lane;
+                // the words of a pass are loaded two passes ahead, into the
+                // register pair that pass will use (no rotation between them)
+                auto pass = [&](uint32_t &ra, uint32_t &rb) {
                     const bool hb = wq + L < we;
-                    const uint32_t wa = wq[0], wb = wq[L];   // wq[L] exists (see the layout)
+                    const uint32_t wa = ra, wb = rb;
+                    ra = wq[4 * L];
+                    rb = wq[5 * L];
                     double ax, ay, az, aux, auy, auz, bx, by, bz, bux, buy, buz;
                     bond_vectors(wa, ax, ay, az, aux, auy, auz);
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
@@ -404,8 +413,15 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                                                                 buz, cv,
                                                                 !hb || (wb & BW_DEAD) != 0, acc,
                                                                 beta);
-                    if (ka) mark(wq, wa);
-                    if (kb) mark(wq + L, wb);
+                    if (ka) *const_cast<uint16_t *>(wq) = (uint16_t)(wa | BW_DEAD);
+                    if (kb) *const_cast<uint16_t *>(wq + L) = (uint16_t)(wb | BW_DEAD);
+                    wq += 2 * L;
+                };
+                uint32_t a0 = wq[0], b0w = wq[L], a1 = wq[2 * L], b1w = wq[3 * L];
+                while (wq < we) {
+                    pass(a0, b0w);
+                    if (!(wq < we)) break;
+                    pass(a1, b1w);
                 }
             }
             double fx, fy, fz, Ue;
@@ -474,10 +490,10 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     for (uint32_t k = 0; k < K; ++k) {
         dma_wait();
         lds_barrier();                       // tile k and the ids of tile k+1 are in LDS
-        if (tid == 0) blist(k + 1)[0] = 0;   // last read for tile k-2
+        if (!GW && tid == 0) blist(k + 1)[0] = 0;   // last read for tile k-2
         sum_and_update(k);
         lds_barrier();                       // the slot is free once the sums are done
-        const uint32_t nbk = blist(k)[0];
+        const uint32_t nbk = GW ? 0u : blist(k)[0];
         if (nbk) write_back(k, nbk);
         if (nbk > BRK_CAP) lds_barrier();    // the words were read from the slot
         if (k + 1 < K) issue_tile(k + 1);
