@@ -315,6 +315,25 @@ int pd_nbr_destroy(pd_nbr nbr);
 int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
                       const double *V, const double *u, uint8_t *alive, double *f, double *U);
 
+/*
+ * pd_internal_force for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, results and errors, always on the
+ * gather kernel, with its internal-order working copies (X, V, u, f, U, the
+ * solid's per-node state, the bond flags) in a fixed device array of
+ * PD_NOALLOC_MAX_BYTES bytes that the library holds on every device it runs
+ * on until the process ends.  It calls no allocator.  A mesh whose working
+ * copies exceed the array returns PD_ECAPACITY before any launch (the size
+ * is about 8 (5 + 2 s) n + nnz bytes with s = 2 in 2-d and 4 in 3-d, plus
+ * 16 n for the solid).
+ * Every call on one device shares the array: calls that overlap on a device
+ * (other streams, other contexts, other threads) race and must be ordered
+ * by the caller.  Asynchronous on the context's stream.
+ */
+#define PD_NOALLOC_MAX_BYTES (64ll << 20)
+int pd_internal_force_noalloc(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                              const double *V, const double *u, uint8_t *alive, double *f,
+                              double *U);
 
 /*
  * Create a resident explicit simulation (state kept on the GPU in internal

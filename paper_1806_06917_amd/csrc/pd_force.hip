@@ -414,9 +414,9 @@ double ramp_factor(double s, int64_t ramp) {
 // ---------------------------------------------------------------------------
 // stateless force evaluation
 // ---------------------------------------------------------------------------
-extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
-                                 const double *V, const double *u, uint8_t *alive, double *f,
-                                 double *U) {
+int pd_check_force_args(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                        const double *V, const double *u, const uint8_t *alive, const double *f,
+                        const double *U) {
     if (!nbr) return pd_set_error(ctx, PD_EINVAL, "nbr must not be NULL");
     if (nbr->closing) return pd_set_error(ctx, PD_EINVAL, "nbr has been destroyed");
     if (nbr->nnz == 0)
@@ -430,6 +430,67 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_check_dev_ptr(ctx, f, "f"));
     if (alive) PD_TRY(pd_check_dev_ptr(ctx, alive, "alive"));
     if (U) PD_TRY(pd_check_dev_ptr(ctx, U, "U"));
+    return PD_OK;
+}
+
+size_t pd_force_bufs_bytes(const pd_nbr nbr, const pd_material *mat) {
+    const size_t n = nbr->n, us = nbr->dim == 3 ? 4 : 2;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t bytes = up(n * 4 * 8) + 2 * up(n * us * 8) + up(n * 8) + up(nbr->nnz);
+    if (mat->law == PD_LAW_LPS) bytes += up(n * 2 * 8);
+    return bytes;
+}
+
+pd_force_bufs pd_force_bufs_carve(const pd_nbr nbr, const pd_material *mat, void *base) {
+    const size_t n = nbr->n, us = nbr->dim == 3 ? 4 : 2;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    unsigned char *q = static_cast<unsigned char *>(base);
+    pd_force_bufs b{};
+    b.xv = reinterpret_cast<double *>(q);
+    q += up(n * 4 * 8);
+    b.u = reinterpret_cast<double *>(q);
+    q += up(n * us * 8);
+    b.f = reinterpret_cast<double *>(q);
+    q += up(n * us * 8);
+    b.U = reinterpret_cast<double *>(q);
+    q += up(n * 8);
+    b.alive = q;
+    q += up(nbr->nnz);
+    b.lps = mat->law == PD_LAW_LPS ? reinterpret_cast<double *>(q) : nullptr;
+    return b;
+}
+
+// The force evaluation of pd_internal_force on the gather kernel, with the
+// internal-order copies in the caller's buffers (allocates nothing; arguments
+// already checked)
+int pd_force_gather(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                    const double *V, const double *u, uint8_t *alive, double *f, double *U,
+                    const pd_force_bufs &b) {
+    const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    PD_TRY(pd_gather_xv(ctx, nbr, X, V, b.xv));
+    PD_TRY(pd_gather_vec(ctx, nbr, u, b.u, false));
+    if (alive) PD_TRY(pd_alive_in(ctx, nbr, alive, b.alive));
+    NodeArgs a = base_args(nbr, mat);
+    a.xv = b.xv;
+    a.u = b.u;
+    a.alive = alive ? b.alive : nullptr;
+    a.bw = nullptr;
+    a.damage = alive && mat->s_c > 0.0;
+    a.f_out = b.f;
+    a.e_out = U ? b.U : nullptr;
+    a.mode = M_FORCE;
+    a.lps = b.lps;
+    PD_TRY(launch_node(ctx, nbr, a, lanes, mat->precision == PD_MIXED, 0));
+    PD_TRY(pd_scatter_vec(ctx, nbr, b.f, f));
+    if (U) PD_TRY(pd_scatter_scalar(ctx, nbr, b.U, U));
+    if (alive && a.damage) PD_TRY(pd_alive_out(ctx, nbr, b.alive, alive));
+    return PD_OK;
+}
+
+extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                                 const double *V, const double *u, uint8_t *alive, double *f,
+                                 double *U) {
+    PD_TRY(pd_check_force_args(ctx, nbr, mat, X, V, u, alive, f, U));
     const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
     if (!pd_general_law(mat)) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));

@@ -231,6 +231,26 @@ int pd_tangent_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const d
                    const double *w, double *y, const int *done, const double *u_lin = nullptr);
 int pd_force_sfc(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, const double *xv,
                  const uint8_t *alive_sfc, uint16_t *bw, int block, const double *u, double *f);
+// pd_internal_force in pieces (pd_force.hip): argument checks; the
+// internal-order buffers of one evaluation on the gather kernel (their size
+// for a mesh and law, and their layout in one block of device memory); the
+// evaluation itself with the caller's buffers (it allocates nothing)
+struct pd_force_bufs {
+    double *xv, *u, *f, *U, *lps;
+    uint8_t *alive;
+};
+int pd_check_force_args(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                        const double *V, const double *u, const uint8_t *alive, const double *f,
+                        const double *U);
+size_t pd_force_bufs_bytes(const pd_nbr nbr, const pd_material *mat);
+pd_force_bufs pd_force_bufs_carve(const pd_nbr nbr, const pd_material *mat, void *base);
+int pd_force_gather(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
+                    const double *V, const double *u, uint8_t *alive, double *f, double *U,
+                    const pd_force_bufs &b);
+// the allocation-free entry point's device scratch: looked up once per device
+// (pd_noalloc.hip; called by pd_ctx_create with the device current)
+int pd_noalloc_setup(pd_ctx ctx);
+
 // kernel choice for a call site under the context's tuning; *block > 0 means
 // the tile kernel with that workgroup size, 0 the gather kernel
 int pd_plan_kernel(pd_ctx ctx, pd_nbr nbr, int lanes, int *block);

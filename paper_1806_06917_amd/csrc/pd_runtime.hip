@@ -121,6 +121,7 @@ extern "C" int pd_ctx_create(int device, void *hip_stream, pd_ctx *out) {
         st = PD_ENOMEM;
     if (st == PD_OK && hipHostMalloc((void **)&c->flag_host, sizeof(int)) != hipSuccess)
         st = PD_ENOMEM;
+    if (st == PD_OK) st = pd_noalloc_setup(c);   // with the device current
     if (st != PD_OK) {
         (void)hipGetLastError();
         pd_ctx_destroy(c);

@@ -94,6 +94,7 @@ def _load():
         "pd_nbr_permutation": (i32, [vp, vp]),
         "pd_nbr_destroy": (i32, [vp]),
         "pd_internal_force": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
+        "pd_internal_force_noalloc": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp]),
         "pd_sim_create": (i32, [vp, vp, P(Material), vp, vp, vp, vp, vp, vp, vp, vp, i32, i64,
                                 P(vp)]),
         "pd_verlet_step": (i32, [vp, i64, dbl]),
@@ -284,6 +285,17 @@ class Neighbors:
 def internal_force(ctx, nbr, mat, X, V, u, f, alive=None, U=None):
     ctx.check(lib.pd_internal_force(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V), _ptr(u),
                                     _ptr(alive), _ptr(f), _ptr(U)), "pd_internal_force")
+
+
+def internal_force_noalloc(ctx, nbr, mat, X, V, u, f, alive=None, U=None):
+    """pd_internal_force with the library's fixed device scratch array (no
+    allocation; meshes above PD_NOALLOC_MAX_BYTES of working copies fail)."""
+    ctx.check(lib.pd_internal_force_noalloc(ctx.h, nbr.h, C.byref(mat), _ptr(X), _ptr(V),
+                                            _ptr(u), _ptr(alive), _ptr(f), _ptr(U)),
+              "pd_internal_force_noalloc")
+
+
+NOALLOC_MAX_BYTES = 64 << 20
 
 
 def apply_tangent(ctx, nbr, mat, X, V, w, y, alive=None, fixed=None):

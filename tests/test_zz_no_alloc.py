@@ -1,0 +1,70 @@
+"""The allocation-free force entry point (pd_internal_force_noalloc, for
+callers that cannot allocate) against pd_internal_force: bit-identical
+forces, energies and damage flags on two calls in a row, the second on a
+smaller mesh (the shared scratch array keeps the first call's contents),
+then a mesh too large for the fixed array is rejected before any launch."""
+import numpy as np
+import pytest
+
+from conftest import say
+from paper_1806_06917_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def case(N, dim, seed, scale):
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * dim, h, jitter=0.05, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    V = h ** dim * rng.uniform(0.9, 1.1, len(X))
+    u = inputs.random_field(len(X), dim, seed + 2, scale=scale * h)
+    return X, V, u, 3 * h
+
+
+def run(torch, pd, ctx, X, V, u, delta, dim, prec, s_c, noalloc):
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    mat = pd.material(dim, pd.micromodulus(dim, 1.0, delta), 1.0, s_c, prec)
+    n = len(X)
+    f = torch.full((n, dim), np.nan, dtype=torch.float64, device="cuda")
+    U = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    al = torch.ones(nb.nnz, dtype=torch.uint8, device="cuda")
+    fn = pd.internal_force_noalloc if noalloc else pd.internal_force
+    fn(ctx, nb, mat, dev(torch, X), dev(torch, V), dev(torch, u), f, alive=al, U=U)
+    torch.cuda.synchronize()
+    out = (f.cpu().numpy(), U.cpu().numpy(), al.cpu().numpy())
+    nb.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_noalloc_equals_internal_force(gpu, prec):
+    torch, pd, ctx = gpu
+    # two calls in a row, the second smaller; damage on (some bonds break)
+    for N, dim, seed in ((48, 2, 301), (20, 3, 305), (17, 2, 309)):
+        X, V, u, delta = case(N, dim, seed, 0.05)
+        say("noalloc", prec, N, dim)
+        ref = run(torch, pd, ctx, X, V, u, delta, dim, prec, 0.02, False)
+        got = run(torch, pd, ctx, X, V, u, delta, dim, prec, 0.02, True)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b)
+        assert np.all(np.isfinite(got[0]))
+        assert 0 < np.count_nonzero(ref[2] == 0) < len(ref[2])
+
+
+def test_noalloc_rejects_too_large(gpu):
+    torch, pd, ctx = gpu
+    # 8 (4 + 2*4 + 1) n + nnz bytes for a 3-d mesh: 100^3 nodes need ~207 MB
+    w = inputs.cube_3d(100, 3, steps=0)
+    say("noalloc too large")
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    mat = pd.material(3, pd.micromodulus(3, 1.0, w.delta), 1.0, 0.0, "fp64")
+    f = torch.zeros((w.n, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(pd.PDError) as e:
+        pd.internal_force_noalloc(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V),
+                                  dev(torch, w.u0), f)
+    assert e.value.status == pd.PD_ECAPACITY
+    nb.close()
