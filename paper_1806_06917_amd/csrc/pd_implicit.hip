@@ -371,7 +371,12 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVe
     w.st_host->done = rr <= tol * tol;
     w.st_host->iters = 0;
     PD_HIP(ctx, hipMemcpyAsync(w.st, w.st_host, sizeof(CgState), hipMemcpyHostToDevice, s));
-    const int L = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
+    // about four bonds per lane: the tangent launch of a small system is
+    // latency-bound (each bond a chain of dependent loads), so it takes many
+    // short lanes
+    const double k = nbr->n ? (double)nbr->nnz / (double)nbr->n : 0.0;
+    int L = 1;
+    while (L < 32 && L * 4 < k) L *= 2;
     CgArgs<T> a{};
     a.n = nbr->n;
     a.row_ptr = nbr->row_ptr;
@@ -514,10 +519,11 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
         }
         if (outer >= max_outer || inner_total >= maxit) break;
         // inner target: FP64 solves straight to the requested accuracy (with a
-        // small margin); mixed solves each correction to 1e-5 relative
+        // small margin); mixed solves each correction to 1e-4 relative (a
+        // float32 CG stalls near 1e-5: deeper inner targets cost iterations)
         // (NP: the Newton system to 1e-6 relative or the final target, the
         // looser of the two, keeps Newton's convergence fast)
-        double target = mixed ? 1e-5 * std::sqrt(rr) : 0.5 * rtol * bnorm;
+        double target = mixed ? 1e-4 * std::sqrt(rr) : 0.5 * rtol * bnorm;
         if (np) target = std::max(target, 1e-6 * std::sqrt(rr));
         if (np) {
             // the tangent's bond factors at this Newton iterate
