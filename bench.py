@@ -5,8 +5,10 @@ gather + critical-stretch damage test + half-kicks + drift + boundary data
 (pd_verlet_step).  Default workload: the jittered 100^3 cube (1M nodes,
 delta = 3h, damage on, velocity-driven uniaxial tension) in mixed precision.  Inputs are synthetic and
 resident in HBM before the timed region; the neighbour build is one-off and
-reported separately.  Both precisions compute in float64; "mixed" takes 1/|xi|
-from the hardware reciprocal-square-root estimate without refinement.
+reported separately.  "fp64" and "mixed" compute the bond terms in float64;
+"mixed" takes 1/|xi| from the hardware reciprocal-square-root estimate without
+refinement; "fp32" (timed beside them) computes the bond terms in float32 after
+float64 differences, with compensated float32 sums per node.
 
 Then (unless --no-law) the other material laws: NP explicit steps on the
 notched 512^2 plate, linear-peridynamic-solid steps on the cube, and the NP
@@ -124,7 +126,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="cube100", choices=["cube100", "notched512", "plate32"])
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp32"])
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tile"])
     ap.add_argument("--tile", type=int, default=0, help="nodes per tile (0 = automatic)")
@@ -277,11 +279,12 @@ def serve(pd, reqs, budget, chunk, rate=None, tile=0, precision="mixed"):
 
 def config_runs(torch, pd, steps, warmup):
     """The other explicit workloads in the linearised law, timed like the
-    headline one: the 512^2 notched plate (notch, collars, damage) in both
-    precisions and the 32^2 free plate (100 steps per window, FP64)."""
+    headline one: the 512^2 notched plate (notch, collars, damage) in each
+    precision and the 32^2 free plate (100 steps per window, FP64)."""
     from paper_1806_06917_amd import inputs
     out = {}
-    for name, precs, k in (("notched512", ("mixed", "fp64"), steps), ("plate32", ("fp64",), 100)):
+    for name, precs, k in (("notched512", ("mixed", "fp64", "fp32"), steps),
+                           ("plate32", ("fp64",), 100)):
         w = inputs.CONFIGS[name]()
         for prec in precs:
             r = run_gpu(torch, pd, w, prec, k, warmup, 0)
@@ -656,6 +659,10 @@ def main():
                       not args.no_autotune, args.reps)
         out["fp64_ms_per_step"] = r64["ms_total"] / args.steps
         out["fp64_launch"] = r64["launch"]
+        r32 = run_gpu(torch, pd, w, "fp32", args.steps, args.warmup, args.lanes, tuning,
+                      not args.no_autotune, args.reps)
+        out["fp32_ms_per_step"] = r32["ms_total"] / args.steps
+        out["fp32_launch"] = r32["launch"]
     if not args.no_configs:
         out["configs"] = config_runs(torch, pd, 200, 20)
         out["implicit"] = implicit_runs(torch, pd)

@@ -60,7 +60,7 @@ enum {
     PD_ECAPACITY = -6    /* problem exceeds a documented size limit */
 };
 
-enum { PD_FP64 = 0, PD_MIXED = 1 };
+enum { PD_FP64 = 0, PD_MIXED = 1, PD_FP32 = 2 };
 
 enum { PD_BC_FREE = 0, PD_BC_CLAMPED = 1, PD_BC_VELOCITY = 2 };
 
@@ -80,6 +80,16 @@ typedef struct pd_server_s *pd_server;
  *              refinement (relative error below 2^-22).  Positions,
  *              velocities, sums and the time integration are float64 in
  *              both modes.
+ *              PD_FP32 (PD_LAW_LINEAR with the linearised stretch only;
+ *              other laws return PD_EINVAL): the differences xi and eta are
+ *              taken in float64 and rounded to float32; |xi|^-1 (hardware
+ *              float32 estimate), S, the damage test against s_c rounded to
+ *              float32, and the bond force are float32; each node's sum is
+ *              a compensated float32 pair (TwoSum) converted to float64 at
+ *              the end.  Positions, velocities and the time integration
+ *              stay float64.  Force relative error about 1e-6 of the
+ *              largest bond force.  pd_apply_tangent rejects it;
+ *              pd_solve_implicit treats it as PD_MIXED.
  *   c          micromodulus c = 4 psi'(0)/(delta |B_delta(0)|) (Algorithm 1);
  *              see pd_micromodulus.
  *   rho        mass density (velocity-Verlet equations), > 0
@@ -550,7 +560,7 @@ int pd_apply_tangent_at(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const do
  * for PD_LAW_NP a Newton-Krylov iteration, which needs a positive definite
  * tangent: 2 beta r < 1 on the bonds that carry load).
  *   precision PD_FP64: float64 CG solving each Newton system to the target.
- *   PD_MIXED: each correction solved to 1e-4 relative by a CG with float32
+ *   PD_MIXED (and PD_FP32): each correction solved to 1e-4 relative by a CG with float32
  *   vectors and float32 bond arithmetic in the tangent but float64 dot
  *   products, inside iterative refinement on float64 residuals (the force
  *   in float64) until rtol is met.

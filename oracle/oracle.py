@@ -112,7 +112,7 @@ def lib():
             fn.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, i32, dbl, i32, dbl, dbl,
                            dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_band_update.restype = None
-        L.or_band_update.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, ptr]
+        L.or_band_update.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, ptr]
         L.or_set_threads.restype = None
         L.or_set_threads.argtypes = [i32]
         L.or_num_threads.restype = i32
@@ -207,24 +207,27 @@ class Mesh:
         state["step"] += nsteps
         return state
 
-    def band_update(self, band, u, s_c, tol=1e-6):
-        """band |= (|S/s_c - 1| <= tol) per bond at displacement u (in place)."""
+    def band_update(self, band, u, s_c, tol=1e-6, tol_eta=0.0):
+        """band |= (|S/s_c - 1| <= tol or |S - s_c| <= tol_eta |eta|/|xi|) per
+        bond at displacement u (in place).  The second term covers arithmetic
+        whose rounding of S scales with |eta|/|xi| rather than with S (float32
+        bond terms)."""
         u = _f64(u)
         lib().or_band_update(self.dim, self.n, _p(self.row_ptr), _p(self.col), _p(self.X), _p(u),
-                             float(s_c), float(tol), _p(band))
+                             float(s_c), float(tol), float(tol_eta), _p(band))
         return band
 
     def verlet_banded(self, state, c, rho, s_c, dt, nsteps, bc_kind=None, bc_vel=None, b=None,
-                      ramp=0, band=None, tol=1e-6):
+                      ramp=0, band=None, tol=1e-6, tol_eta=0.0):
         """Verlet steps one at a time, collecting in ``band`` (uint8 per bond)
         every bond whose strain came within tol of s_c at a force evaluation
         of these steps (the state on entry included)."""
         if band is None:
             band = np.zeros(max(self.nnz, 1), np.uint8)[: self.nnz]
-        self.band_update(band, state["u"], s_c, tol)
+        self.band_update(band, state["u"], s_c, tol, tol_eta)
         for _ in range(nsteps):
             self.verlet(state, c, rho, s_c, dt, 1, bc_kind, bc_vel, b, ramp)
-            self.band_update(band, state["u"], s_c, tol)
+            self.band_update(band, state["u"], s_c, tol, tol_eta)
         return band
 
     def start(self, u0, v0, c, s_c=0.0, alive=None):

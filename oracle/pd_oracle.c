@@ -1028,20 +1028,23 @@ void or_lps_pv(int64_t n, const int64_t *row_ptr, const int32_t *col, const doub
 /* sides round S differently; every other flag must agree.                   */
 /* ------------------------------------------------------------------------ */
 void or_band_update(int dim, int64_t n, const int64_t *row_ptr, const int32_t *col,
-                    const double *X, const double *u, double s_c, double tol, uint8_t *band) {
+                    const double *X, const double *u, double s_c, double tol, double tol_eta,
+                    uint8_t *band) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
             int64_t j = col[p];
-            double r2 = 0.0, ex = 0.0;
+            double r2 = 0.0, ex = 0.0, e2 = 0.0;
             for (int k = 0; k < dim; ++k) {
                 double x = X[j * dim + k] - X[i * dim + k];
                 double e = u[j * dim + k] - u[i * dim + k];
                 r2 = r2 + x * x;
                 ex = ex + e * x;
+                e2 = e2 + e * e;
             }
             double S = ex / r2;
-            if (fabs(S / s_c - 1.0) <= tol) band[p] = 1;
+            if (fabs(S / s_c - 1.0) <= tol || fabs(S - s_c) <= tol_eta * sqrt(e2 / r2))
+                band[p] = 1;
         }
     }
 }

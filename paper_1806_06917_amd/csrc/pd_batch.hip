@@ -24,7 +24,8 @@ struct pd_batch_s {
     hipGraphExec_t exec = nullptr;
     // what the captured graph was built for
     int g_ninst = 0, g_dim = 0, g_lanes = 0, g_block = 0;
-    bool g_mixed = false, g_np = false;
+    int g_prec = -1;
+    bool g_np = false;
     uint32_t g_ntiles = 0, g_tile = 0, g_hcap = 0, g_bcap = 0, g_mmax = 0;
     unsigned g_grid = 0;
     size_t g_lds = 0;
@@ -74,11 +75,11 @@ extern "C" int pd_batch_destroy(pd_batch b) {
 
 // the launches of one chunk: nsteps step kernels, the k-th told it is step k
 static int batch_enqueue(pd_batch b, hipStream_t st, int dim, StreamArgs sa, int lanes,
-                         bool mixed, bool np, int block, unsigned grid, size_t lds,
+                         int prec, bool np, int block, unsigned grid, size_t lds,
                          int64_t nsteps) {
     for (int64_t k = 0; k < nsteps; ++k) {
         sa.step = k;
-        PD_TRY(pd_launch_stream(b->ctx, st, dim, sa, lanes, mixed, np ? SK_NP : SK_LINEAR, block,
+        PD_TRY(pd_launch_stream(b->ctx, st, dim, sa, lanes, prec, np ? SK_NP : SK_LINEAR, block,
                                 grid, lds));
     }
     return PD_OK;
@@ -95,7 +96,7 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
     const pd_sim s0 = sims[0];
     if (!s0) return pd_set_error(ctx, PD_EINVAL, "sims[0] is NULL");
     const int dim = s0->nbr->dim, lanes = s0->lanes;
-    const bool mixed = s0->mat.precision == PD_MIXED;
+    const int prec = s0->mat.precision;
     const bool np = s0->mat.law == PD_LAW_NP;
     const uint32_t tile = s0->nbr->tile_T;
     uint64_t ntiles = 0;
@@ -108,7 +109,7 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
         if (s->s_form == SK_LPS_FORCE)
             return pd_set_error(ctx, PD_EINVAL, "sims[%d]: the solid steps alone", k);
         if (s->nbr->dim != dim || s->lanes != lanes || s->nbr->tile_T != tile ||
-            (s->mat.precision == PD_MIXED) != mixed || (s->mat.law == PD_LAW_NP) != np)
+            s->mat.precision != prec || (s->mat.law == PD_LAW_NP) != np)
             return pd_set_error(ctx, PD_EINVAL,
                                 "sims[%d]: dim, lanes, tile size, precision and law must match",
                                 k);
@@ -131,7 +132,7 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
     unsigned grid = 0;
     uint32_t mmax = 0;
     size_t lds = 0;
-    if (!pd_stream_geometry(ctx, dim, (uint32_t)ntiles, tile, hcap, bcap, lanes, mixed, true,
+    if (!pd_stream_geometry(ctx, dim, (uint32_t)ntiles, tile, hcap, bcap, lanes, prec, true,
                             np ? SK_NP : SK_LINEAR, &block, &grid, &mmax, &lds))
         return pd_set_error(ctx, PD_ECAPACITY, "the batch does not fit the streamed kernel");
 
@@ -182,11 +183,11 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
     sa.bcap = bcap;
     sa.mmax = mmax;
     if (!use_graph) {
-        PD_TRY(batch_enqueue(b, ctx->stream, dim, sa, lanes, mixed, np, block, grid, lds,
+        PD_TRY(batch_enqueue(b, ctx->stream, dim, sa, lanes, prec, np, block, grid, lds,
                              nsteps));
     } else {
         const bool same = b->exec && b->g_ninst == nsims && b->g_dim == dim &&
-                          b->g_lanes == lanes && b->g_block == block && b->g_mixed == mixed &&
+                          b->g_lanes == lanes && b->g_block == block && b->g_prec == prec &&
                           b->g_np == np &&
                           b->g_ntiles == (uint32_t)ntiles && b->g_tile == tile &&
                           b->g_hcap == hcap && b->g_bcap == bcap && b->g_mmax == mmax &&
@@ -195,7 +196,7 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
             batch_free_graph(b);
             hipGraph_t graph = nullptr;
             PD_HIP(ctx, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-            const int st = batch_enqueue(b, b->capture, dim, sa, lanes, mixed, np, block, grid,
+            const int st = batch_enqueue(b, b->capture, dim, sa, lanes, prec, np, block, grid,
                                          lds, nsteps);
             const hipError_t e = hipStreamEndCapture(b->capture, &graph);
             if (st != PD_OK) {
@@ -213,7 +214,7 @@ extern "C" int pd_batch_step(pd_batch b, pd_sim *sims, int nsims, const int64_t 
             b->g_dim = dim;
             b->g_lanes = lanes;
             b->g_block = block;
-            b->g_mixed = mixed;
+            b->g_prec = prec;
             b->g_np = np;
             b->g_ntiles = (uint32_t)ntiles;
             b->g_tile = tile;

@@ -127,6 +127,47 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
     node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, fixed_i, vx, vy, vz, kind);
 }
 
+// The gather kernel in PD_FP32 (linearised law only): float32 bond terms
+// after the float64 differences, compensated float32 lane sums, the same
+// rows, lanes and reduction order, then the float64 node update.
+template <int DIM, int L, bool WANT_E>
+__global__ __launch_bounds__(PD_BLOCK) void node_kernel32(NodeArgs a) {
+    if (a.done && *a.done) return;
+    const uint32_t tile = pd_xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = (tile * PD_BLOCK + threadIdx.x) / L;
+    const int lane = threadIdx.x & (L - 1);
+    const bool valid = i < a.n;
+    double xix = 0, xiy = 0, xiz = 0, Vi = 0, uix = 0, uiy = 0, uiz = 0;
+    AccC acc;
+    if (valid) {
+        const double4 q = reinterpret_cast<const double4 *>(a.xv)[i];
+        xix = q.x; xiy = q.y;
+        if (DIM == 3) { xiz = q.z; Vi = q.w; } else { Vi = q.z; }
+        load_vec<DIM>(a.u, i, uix, uiy, uiz);
+        const float sc = (float)a.s_c;
+        for (uint32_t p = a.row_ptr[i] + lane; p < a.row_ptr[i + 1]; p += L) {
+            const uint32_t j = (uint32_t)a.col[p];
+            const bool live = !a.alive || a.alive[p];
+            const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+            double ujx, ujy, ujz;
+            load_vec<DIM>(a.u, j, ujx, ujy, ujz);
+            const float cVj = (float)(a.cv_uniform != 0.0 ? a.cv_uniform
+                                                           : a.c * (DIM == 3 ? xj.w : xj.z));
+            const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
+            if (bond32<DIM, WANT_E>(a.damage, sc, xj.x - xix, xj.y - xiy, dxz, ujx - uix,
+                                    ujy - uiy, duz, cVj, !live, acc))
+                a.alive[p] = 0;
+        }
+    }
+    double fx, fy, fz, Ue;
+    group_reduce_c<DIM, L, WANT_E>(acc, fx, fy, fz, Ue);
+    if (!valid || lane != 0) return;
+    double vx = 0, vy = 0, vz = 0;
+    if (mode_reads_v(a.mode)) load_vec<DIM>(a.v, i, vx, vy, vz);
+    const int kind = a.bc ? a.bc[i] : PD_BC_FREE;
+    node_update<DIM>(a, i, fx, fy, fz, Ue, Vi, uix, uiy, uiz, false, vx, vy, vz, kind);
+}
+
 // Linear peridynamic solid, first pass (Algorithm 2, weighted volume and
 // dilatation): per node m_i = sum |xi|^2 V_j and theta_i = (3/m_i) sum |xi| e V_j
 // over live bonds, stored as {m, theta} in a.lps.
@@ -232,7 +273,10 @@ int launch_t(pd_ctx ctx, const NodeArgs &a, bool mixed) {
     const unsigned grid = pd_blocks((uint64_t)a.n * L);
     if (grid == 0) return PD_OK;
     const bool e = mode_wants_energy(a);
-    if (mixed) {
+    if (a.fp32) {
+        if (e) node_kernel32<DIM, L, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+        else node_kernel32<DIM, L, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
+    } else if (mixed) {
         if (e) node_kernel<DIM, L, true, true><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
         else node_kernel<DIM, L, true, false><<<grid, PD_BLOCK, 0, ctx->stream>>>(a);
     } else {
@@ -269,14 +313,14 @@ static bool tile_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, int block) {
 }
 
 // the streamed kernel of this form can run on the tiles nbr holds now
-static bool stream_form_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, bool mixed, int form) {
+static bool stream_form_fits(pd_ctx ctx, const pd_nbr nbr, int lanes, int prec, int form) {
     int b = 0;
     unsigned g = 0;
     uint32_t m = 0;
     size_t l = 0;
     return nbr->lcol && pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
            pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                              pd_tile_bcap(nbr), lanes, mixed, false, form, &b, &g, &m, &l);
+                              pd_tile_bcap(nbr), lanes, prec, false, form, &b, &g, &m, &l);
 }
 
 // threads per tile workgroup for the tiles nbr holds now: the tuning value,
@@ -342,7 +386,7 @@ namespace {
 
 // block > 0 (with a.bw set): tile kernel; otherwise the gather kernel
 int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed, int block) {
-    if (block > 0 && a.bw) {
+    if (block > 0 && a.bw && !a.fp32) {
         a.halo_ptr = nbr->halo_ptr;
         a.halo = nbr->halo;
         a.self_off = nbr->self_off;
@@ -361,8 +405,10 @@ int launch_node(pd_ctx ctx, const pd_nbr nbr, NodeArgs a, int lanes, bool mixed,
 int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
     if (!mat) return pd_set_error(ctx, PD_EINVAL, "material must not be NULL");
     if (mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "material dim != neighbour dim");
-    if (mat->precision != PD_FP64 && mat->precision != PD_MIXED)
-        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
+    if (mat->precision != PD_FP64 && mat->precision != PD_MIXED && mat->precision != PD_FP32)
+        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64, PD_MIXED or PD_FP32");
+    if (mat->precision == PD_FP32 && pd_general_law(mat))
+        return pd_set_error(ctx, PD_EINVAL, "PD_FP32 takes the linearised law only");
     if (!std::isfinite(mat->c) || !std::isfinite(mat->s_c))
         return pd_set_error(ctx, PD_EINVAL, "c and s_c must be finite");
     if (mat->j_c2 > 0.0 && !(nbr->delta - 0.5 * mat->pv_h > 0.0))
@@ -372,6 +418,7 @@ int check_material(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat) {
 
 NodeArgs base_args(const pd_nbr nbr, const pd_material *mat) {
     NodeArgs a{};
+    a.fp32 = mat->precision == PD_FP32;
     a.row_ptr = nbr->row_ptr;
     a.col = nbr->col;
     a.n = nbr->n;
@@ -493,7 +540,8 @@ extern "C" int pd_internal_force(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_check_force_args(ctx, nbr, mat, X, V, u, alive, f, U));
     const int lanes = pd_auto_lanes(ctx, nbr->nnz, nbr->n);
     int block = 0;
-    if (!pd_general_law(mat)) PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
+    if (!pd_general_law(mat) && mat->precision != PD_FP32)
+        PD_TRY(pd_plan_kernel(ctx, nbr, lanes, &block));
     PD_TRY(ensure_scratch(ctx, nbr));
     const bool tiled = block > 0;
     PD_TRY(pd_gather_xv(ctx, nbr, X, V, nbr->s_xv));
@@ -568,6 +616,8 @@ static int apply_tangent(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const d
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     PD_TRY(check_material(ctx, nbr, mat));
+    if (mat->precision == PD_FP32)
+        return pd_set_error(ctx, PD_EINVAL, "the tangent takes PD_FP64 or PD_MIXED");
     if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0 ||
         mat->j_c2 > 0.0)
         return pd_set_error(ctx, PD_EINVAL,
@@ -694,6 +744,8 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         te = pd_tune_find(ctx, nbr->dim, (double)nbr->nnz / (double)nbr->n, mat->precision);
     if ((np_stream || lps_stream) && ctx->kernel == 2)
         return pd_set_error(ctx, PD_ECAPACITY, "the LDS tile kernel takes the linearised law only");
+    if (mat->precision == PD_FP32 && ctx->kernel == 2)
+        return pd_set_error(ctx, PD_ECAPACITY, "the LDS tile kernel has no PD_FP32 form");
     if (general) {
         if (ctx->kernel == 2 || ctx->kernel == 3)
             return pd_set_error(ctx, PD_ECAPACITY, "the tiled kernels take the linearised law only");
@@ -709,8 +761,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         // the tuned shape (timed on the linearised law) must also fit this
         // material's streamed form (the solid stages more per halo node);
         // else the automatic choice
-        if ((block > 0 || layout_only) && !stream_form_fits(ctx, nbr, lanes,
-                                                            mat->precision == PD_MIXED,
+        if ((block > 0 || layout_only) && !stream_form_fits(ctx, nbr, lanes, mat->precision,
                                                             lps_stream ? SK_LPS_FORCE
                                                                        : (np_stream ? SK_NP
                                                                                     : SK_LINEAR))) {
@@ -769,7 +820,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     s->lanes = lanes;
     // the tile kernel for the other calls (those of the NP law and the solid
     // run on the gather kernel)
-    s->block = (np_stream || lps_stream) ? 0 : block;
+    s->block = (np_stream || lps_stream || mat->precision == PD_FP32) ? 0 : block;
     if (st == PD_OK && (block > 0 || layout_only)) {
         s->tiled = true;
         nbr->users += 1;
@@ -787,11 +838,11 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         (ctx->kernel == 0 || ctx->kernel == 3) &&
         pd_stream_fits(nbr->dim, nbr->n, nbr->nnz, nbr->halo_total) &&
         pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                           pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false, s->s_form,
+                           pd_tile_bcap(nbr), lanes, mat->precision, false, s->s_form,
                            &s->s_block, &s->s_grid, &s->s_mmax, &s->s_lds) &&
         (!lps_stream ||
          pd_stream_geometry(ctx, nbr->dim, nbr->ntiles, nbr->tile_T, pd_tile_hcap(nbr),
-                            pd_tile_bcap(nbr), lanes, mat->precision == PD_MIXED, false,
+                            pd_tile_bcap(nbr), lanes, mat->precision, false,
                             SK_LPS_STATE, &s->s2_block, &s->s2_grid, &s->s2_mmax,
                             &s->s2_lds))) {
         const size_t rd = nbr->dim == 3 ? 6 : 4;
@@ -891,7 +942,7 @@ StreamArgs pd_stream_args(const pd_sim sim, const StreamInst *inst, uint32_t nin
 // pass, per step), the k-th told it is step k
 static int stream_steps(pd_sim sim, StreamArgs &sa, int64_t nsteps) {
     const pd_ctx ctx = sim->ctx;
-    const bool mixed = sim->mat.precision == PD_MIXED;
+    const int prec = sim->mat.precision;
     const int dim = sim->nbr->dim;
     StreamArgs sb = sa;          // the state pass: its own grid and tiles per workgroup
     sb.mmax = sim->s2_mmax;
@@ -899,9 +950,9 @@ static int stream_steps(pd_sim sim, StreamArgs &sa, int64_t nsteps) {
         sa.step = k;
         sb.step = k;
         if (sim->s_form == SK_LPS_FORCE)
-            PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sb, sim->lanes, mixed, SK_LPS_STATE,
+            PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sb, sim->lanes, prec, SK_LPS_STATE,
                                     sim->s2_block, sim->s2_grid, sim->s2_lds));
-        PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sa, sim->lanes, mixed, sim->s_form,
+        PD_TRY(pd_launch_stream(ctx, ctx->stream, dim, sa, sim->lanes, prec, sim->s_form,
                                 sim->s_block, sim->s_grid, sim->s_lds));
     }
     return PD_OK;

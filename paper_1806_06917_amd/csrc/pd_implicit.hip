@@ -432,7 +432,7 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_check_ctx(ctx));
     if (nbr->ctx != ctx) return pd_set_error(ctx, PD_EINVAL, "nbr belongs to another context");
     if (!mat || mat->dim != nbr->dim) return pd_set_error(ctx, PD_EINVAL, "bad material");
-    if (mat->precision != PD_FP64 && mat->precision != PD_MIXED)
+    if (mat->precision != PD_FP64 && mat->precision != PD_MIXED && mat->precision != PD_FP32)
         return pd_set_error(ctx, PD_EINVAL, "bad precision");
     PD_TRY(pd_check_law(ctx, mat));
     if (mat->stretch != PD_STRETCH_LINEARISED || mat->law == PD_LAW_LPS || mat->pv_h > 0.0 ||
@@ -457,7 +457,8 @@ extern "C" int pd_solve_implicit(pd_ctx ctx, pd_nbr nbr, const pd_material *mat,
     PD_TRY(pd_alloc(ctx, &w.b, m));
     PD_TRY(pd_alloc(ctx, &w.f, m));
     PD_TRY(pd_alloc(ctx, &w.r, m));
-    const bool mixed = mat->precision == PD_MIXED;
+    // PD_FP32 solves like PD_MIXED: float32 corrections, float64 residuals
+    const bool mixed = mat->precision != PD_FP64;
     if (mixed) PD_TRY(w.v32.alloc(ctx, m));
     else PD_TRY(w.v64.alloc(ctx, m));
     PD_TRY(pd_alloc(ctx, &w.part_a, PD_RED_BLOCKS));

@@ -35,6 +35,7 @@ struct NodeArgs {
     double *__restrict__ f_out;        // [n][US] force (M_FORCE) or y (M_TANGENT)
     double *__restrict__ e_out;        // M_FORCE: U_i; M_ENERGY: {KE_i, V_i U_i} pairs
     int *__restrict__ flag;            // non-finite report
+    int fp32;                          // PD_FP32: float32 bond terms, compensated sums
     const int *__restrict__ done;      // if set and *done != 0 the launch is a no-op
     const double *__restrict__ rec;    // streamed kernel: records {X, u} per node
     double *__restrict__ rec_out;      // streamed kernel: u^{k+1} goes into these records
@@ -149,6 +150,109 @@ __device__ __forceinline__ bool bond(int damage, double s_c, double dxx, double 
         if (WANT_E && NP) s.e += 0.25 * cVj * (-expm1(-beta * ((r2 * inv) * S * S)) / beta);
     }
     return brk;
+}
+
+// ---------------------------------------------------------------------------
+// PD_FP32: the bond terms of the linearised law in float32 after the float64
+// differences, with compensated float32 per-node sums
+// ---------------------------------------------------------------------------
+// running sums as unevaluated pairs hi + lo (TwoSum keeps every addition's
+// rounding error in lo)
+struct AccC {
+    float hx = 0, lx = 0, hy = 0, ly = 0, hz = 0, lz = 0, he = 0, le = 0;
+};
+
+// h + v as the pair (s, e) with s = fl(h + v) and s + e = h + v exactly
+// (Knuth's TwoSum); the error goes into l
+__device__ __forceinline__ void two_sum_into(float &h, float &l, float v) {
+#pragma clang fp contract(off)
+    const float s = h + v;
+    const float bp = s - h;
+    const float e = (h - (s - bp)) + (v - bp);
+    h = s;
+    l = l + e;
+}
+
+// One bond as in `bond`, in float32: xi and eta arrive as float64
+// differences and are rounded to float32; |xi|^-1 is the hardware float32
+// reciprocal square root; S, the damage test (against s_c rounded to
+// float32) and the bond force are float32; the force components (and the
+// energy) are added to the compensated sums.
+template <int DIM, bool WANT_E>
+__device__ __forceinline__ bool bond32(int damage, float s_c, double dxx, double dxy, double dxz,
+                                       double dux, double duy, double duz, float cVj, bool dead,
+                                       AccC &s) {
+#pragma clang fp contract(off)
+    const float x = (float)dxx, y = (float)dxy, z = DIM == 3 ? (float)dxz : 0.0f;
+    const float ex = (float)dux, ey = (float)duy, ez = DIM == 3 ? (float)duz : 0.0f;
+    const float r2 = DIM == 3 ? (x * x + y * y) + z * z : x * x + y * y;
+    const float et = DIM == 3 ? (ex * x + ey * y) + ez * z : ex * x + ey * y;
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    const float S = et * (inv * inv);
+    const bool brk = damage && !dead && S > s_c;
+    if (!(brk || dead)) {
+        asm volatile("" ::: "memory");
+        const float g = cVj * S * inv;
+        two_sum_into(s.hx, s.lx, g * x);
+        two_sum_into(s.hy, s.ly, g * y);
+        if (DIM == 3) two_sum_into(s.hz, s.lz, g * z);
+        if (WANT_E) two_sum_into(s.he, s.le, 0.25f * cVj * S * S * (r2 * inv));
+    }
+    return brk;
+}
+
+// A float moved across lanes by a DPP pattern
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL,
+                                                              0xF, 0xF, false));
+}
+
+// one reduction level of a compensated pair over blocks of 2M lanes whose
+// halves are uniform (the partners of level_sum); both partners compute the
+// same pair (TwoSum's error is exact, so operand order does not matter)
+template <int M>
+__device__ __forceinline__ void level_sum_c(float &h, float &l) {
+    float hp, lp;
+    if constexpr (M == 1) { hp = dpp_f32<0xB1>(h); lp = dpp_f32<0xB1>(l); }
+    else if constexpr (M == 2) { hp = dpp_f32<0x4E>(h); lp = dpp_f32<0x4E>(l); }
+    else if constexpr (M == 4) { hp = dpp_f32<0x141>(h); lp = dpp_f32<0x141>(l); }
+    else if constexpr (M == 8) { hp = dpp_f32<0x140>(h); lp = dpp_f32<0x140>(l); }
+    else { hp = __shfl_xor(h, M, 2 * M); lp = __shfl_xor(l, M, 2 * M); }
+    {
+#pragma clang fp contract(off)
+        const float sum = h + hp;
+        const float bp = sum - h;
+        const float e = (h - (sum - bp)) + (hp - bp);
+        h = sum;
+        l = (l + lp) + e;
+    }
+}
+
+// group reduction of the compensated sums (the order of group_reduce), then
+// each pair hi + lo in float64
+template <int DIM, int L, bool WANT_E>
+__device__ __forceinline__ void group_reduce_c(AccC &s, double &fx, double &fy, double &fz,
+                                               double &Ue) {
+    auto level = [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if constexpr (M < L) {
+            level_sum_c<M>(s.hx, s.lx);
+            level_sum_c<M>(s.hy, s.ly);
+            if (DIM == 3) level_sum_c<M>(s.hz, s.lz);
+            if (WANT_E) level_sum_c<M>(s.he, s.le);
+        }
+    };
+    level(std::integral_constant<int, 1>{});
+    level(std::integral_constant<int, 2>{});
+    level(std::integral_constant<int, 4>{});
+    level(std::integral_constant<int, 8>{});
+    level(std::integral_constant<int, 16>{});
+    level(std::integral_constant<int, 32>{});
+    fx = (double)s.hx + (double)s.lx;
+    fy = (double)s.hy + (double)s.ly;
+    fz = DIM == 3 ? (double)s.hz + (double)s.lz : 0.0;
+    Ue = WANT_E ? (double)s.he + (double)s.le : 0.0;
 }
 
 // One bond under the general pairwise law of Algorithm 1 (gather kernel):
@@ -317,7 +421,7 @@ __device__ __forceinline__ double lane_sum(double x) {
     return x;
 }
 
-// Sum over the L lanes of a group (aligned, L a power of two up to 32),
+// Sum over the L lanes of a group (aligned, L a power of two up to 64),
 // pairing neighbours first: every lane ends with the same sum.
 template <int DIM, int L, bool WANT_E>
 __device__ __forceinline__ void group_reduce(Acc64 &s, double &fx, double &fy, double &fz,
@@ -336,6 +440,7 @@ __device__ __forceinline__ void group_reduce(Acc64 &s, double &fx, double &fy, d
     level(std::integral_constant<int, 4>{});
     level(std::integral_constant<int, 8>{});
     level(std::integral_constant<int, 16>{});
+    level(std::integral_constant<int, 32>{});
     fx = s.x; fy = s.y; fz = s.z; Ue = s.e;
 }
 
@@ -511,11 +616,11 @@ bool pd_tile_geometry(int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap, ui
 enum { SK_LINEAR = 0, SK_NP = 1, SK_LPS_STATE = 2, SK_LPS_FORCE = 3 };
 // (batch: the kernel form that reads descriptors from device memory)
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, int form, int *block,
+                        uint32_t bcap, int lanes, int prec, bool batch, int form, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds);
 bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total);
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const pdk::StreamArgs &sa, int lanes,
-                     bool mixed, int form, int block, unsigned grid, size_t lds);
+                     int prec, int form, int block, unsigned grid, size_t lds);
 // a simulation's streamed descriptor (static part), the launch arguments of a
 // batch shaped like it (inst NULL: single-simulation form), and its host state
 // after streamed steps

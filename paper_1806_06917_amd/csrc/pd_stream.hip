@@ -170,8 +170,12 @@ __device__ __forceinline__ double ramp_of(double s, int64_t ramp) {
 // pass: {m, theta} per node into I.lps, no update) or SK_LPS_FORCE (its
 // force, with the neighbours' {m, theta} staged beside the records, and the
 // node update).
-template <int DIM, int L, bool MIXED, bool BATCH, int FORM>
+template <int DIM, int L, int PREC, bool BATCH, int FORM>
 __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
+    // PREC: PD_FP64, PD_MIXED, or PD_FP32 (float32 bond terms, compensated
+    // float32 sums; linearised law only)
+    constexpr bool MIXED = PREC == PD_MIXED, F32 = PREC == PD_FP32;
+    static_assert(!F32 || FORM == SK_LINEAR, "PD_FP32: the linearised law only");
     extern __shared__ __attribute__((aligned(16))) double lds[];
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
     constexpr bool NP = FORM == SK_NP, LPS = FORM == SK_LPS_STATE || FORM == SK_LPS_FORCE;
@@ -318,6 +322,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         const int mode = (s > 0 || I.vhalf0) ? M_STEP_CONT : M_STEP_FIRST;
         const double r_half = ramp_of((double)(I.step0 + s) + 0.5, I.ramp);
         const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho, beta = I.beta;
+        const float cv32 = (float)cv, s_c32 = (float)s_c;
         const int damage = I.damage;
         uint16_t *w16 = reinterpret_cast<uint16_t *>(words);
         uint32_t *bl = blist(k);
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             const double *ri = rec + (size_t)(so + q) * RD;
             const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
             const double uix = ri[DIM], uiy = ri[DIM + 1], uiz = DIM == 3 ? ri[DIM + 2] : 0.0;
-            Acc64 acc;
+            std::conditional_t<F32, AccC, Acc64> acc;
             const uint32_t rs = rowp[q] - b0, re = rowp[q + 1] - b0;
             // xi and eta of the bond whose word is w
             auto bond_vectors = [&](uint32_t w, double &dxx, double &dxy, double &dxz,
@@ -406,13 +411,19 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     double ax, ay, az, aux, auy, auz, bx, by, bz, bux, buy, buz;
                     bond_vectors(wa, ax, ay, az, aux, auy, auz);
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
-                    const bool ka = bond<DIM, MIXED, false, NP>(damage, s_c, ax, ay, az, aux, auy,
-                                                                auz, cv, (wa & BW_DEAD) != 0, acc,
-                                                                beta);
-                    const bool kb = bond<DIM, MIXED, false, NP>(damage, s_c, bx, by, bz, bux, buy,
-                                                                buz, cv,
-                                                                !hb || (wb & BW_DEAD) != 0, acc,
-                                                                beta);
+                    bool ka, kb;
+                    if constexpr (F32) {
+                        ka = bond32<DIM, false>(damage, s_c32, ax, ay, az, aux, auy, auz, cv32,
+                                                (wa & BW_DEAD) != 0, acc);
+                        kb = bond32<DIM, false>(damage, s_c32, bx, by, bz, bux, buy, buz, cv32,
+                                                !hb || (wb & BW_DEAD) != 0, acc);
+                    } else {
+                        ka = bond<DIM, MIXED, false, NP>(damage, s_c, ax, ay, az, aux, auy, auz,
+                                                         cv, (wa & BW_DEAD) != 0, acc, beta);
+                        kb = bond<DIM, MIXED, false, NP>(damage, s_c, bx, by, bz, bux, buy, buz,
+                                                         cv, !hb || (wb & BW_DEAD) != 0, acc,
+                                                         beta);
+                    }
                     if (ka) *const_cast<uint16_t *>(wq) = (uint16_t)(wa | BW_DEAD);
                     if (kb) *const_cast<uint16_t *>(wq + L) = (uint16_t)(wb | BW_DEAD);
                     wq += 2 * L;
@@ -425,7 +436,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 }
             }
             double fx, fy, fz, Ue;
-            group_reduce<DIM, L, false>(acc, fx, fy, fz, Ue);
+            if constexpr (F32) group_reduce_c<DIM, L, false>(acc, fx, fy, fz, Ue);
+            else group_reduce<DIM, L, false>(acc, fx, fy, fz, Ue);
             if (lane < (int)DIM) {
                 const uint32_t d = (uint32_t)lane, i = t0 + q;
                 const double fd = d == 0 ? fx : (d == 1 ? fy : fz);
@@ -501,41 +513,51 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     }
 }
 
-// the kernel of a form: lanes 2..32, both precisions, single or batch (the
-// solid: 3-d, single simulation only)
+template <int DIM, int L, int FORM>
+void *pick_lp(int prec, bool batch) {
+    if (batch) {
+        if constexpr (FORM == SK_LINEAR) {
+            if (prec == PD_FP32) return (void *)stream_kernel<DIM, L, PD_FP32, true, FORM>;
+        }
+        if constexpr (FORM == SK_LINEAR || FORM == SK_NP)
+            return prec == PD_MIXED ? (void *)stream_kernel<DIM, L, PD_MIXED, true, FORM>
+                                    : (prec == PD_FP64
+                                           ? (void *)stream_kernel<DIM, L, PD_FP64, true, FORM>
+                                           : nullptr);
+        return nullptr;
+    }
+    if constexpr (FORM == SK_LINEAR) {
+        if (prec == PD_FP32) return (void *)stream_kernel<DIM, L, PD_FP32, false, FORM>;
+    }
+    return prec == PD_MIXED ? (void *)stream_kernel<DIM, L, PD_MIXED, false, FORM>
+                            : (prec == PD_FP64 ? (void *)stream_kernel<DIM, L, PD_FP64, false, FORM>
+                                               : nullptr);
+}
+
+// the kernel of a form: lanes 2..32, each precision, single or batch (the
+// solid: 3-d, single simulation only; PD_FP32: the linearised law)
 template <int DIM, int FORM>
-void *pick_form(int lanes, bool mixed, bool batch) {
-#define PD_SK(Lv)                                                                          \
-    case Lv:                                                                               \
-        if (batch) {                                                                       \
-            if constexpr (FORM == SK_LINEAR || FORM == SK_NP)                              \
-                return mixed ? (void *)stream_kernel<DIM, Lv, true, true, FORM>            \
-                             : (void *)stream_kernel<DIM, Lv, false, true, FORM>;          \
-            return nullptr;                                                                \
-        }                                                                                  \
-        return mixed ? (void *)stream_kernel<DIM, Lv, true, false, FORM>                   \
-                     : (void *)stream_kernel<DIM, Lv, false, false, FORM>;
+void *pick_form(int lanes, int prec, bool batch) {
     switch (lanes) {
-        PD_SK(2)
-        PD_SK(4)
-        PD_SK(8)
-        PD_SK(16)
-        PD_SK(32)
+    case 2: return pick_lp<DIM, 2, FORM>(prec, batch);
+    case 4: return pick_lp<DIM, 4, FORM>(prec, batch);
+    case 8: return pick_lp<DIM, 8, FORM>(prec, batch);
+    case 16: return pick_lp<DIM, 16, FORM>(prec, batch);
+    case 32: return pick_lp<DIM, 32, FORM>(prec, batch);
     default: return nullptr;
     }
-#undef PD_SK
 }
 
 template <int DIM>
-void *pick_stream(int lanes, bool mixed, bool batch, int form) {
+void *pick_stream(int lanes, int prec, bool batch, int form) {
     switch (form) {
-    case SK_LINEAR: return pick_form<DIM, SK_LINEAR>(lanes, mixed, batch);
-    case SK_NP: return pick_form<DIM, SK_NP>(lanes, mixed, batch);
+    case SK_LINEAR: return pick_form<DIM, SK_LINEAR>(lanes, prec, batch);
+    case SK_NP: return pick_form<DIM, SK_NP>(lanes, prec, batch);
     case SK_LPS_STATE:
-        if constexpr (DIM == 3) return pick_form<3, SK_LPS_STATE>(lanes, mixed, batch);
+        if constexpr (DIM == 3) return pick_form<3, SK_LPS_STATE>(lanes, prec, batch);
         return nullptr;
     case SK_LPS_FORCE:
-        if constexpr (DIM == 3) return pick_form<3, SK_LPS_FORCE>(lanes, mixed, batch);
+        if constexpr (DIM == 3) return pick_form<3, SK_LPS_FORCE>(lanes, prec, batch);
         return nullptr;
     default: return nullptr;
     }
@@ -566,14 +588,14 @@ __global__ void rec_unpack_k(uint32_t n, const double *rec, double *u) {
 // Launch geometry of the streamed kernel for ntiles tiles in total; false if
 // it cannot run this layout.
 bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uint32_t hcap,
-                        uint32_t bcap, int lanes, bool mixed, bool batch, int form, int *block,
+                        uint32_t bcap, int lanes, int prec, bool batch, int form, int *block,
                         unsigned *grid, uint32_t *mmax, size_t *lds) {
     const uint32_t B = tile * (uint32_t)lanes;
     if (B < 64 || B > 1024 || B % 64 != 0) return false;
     if (lanes < dim) return false;   // the node update takes one lane per component
     if (bcap >= (1u << 16)) return false;   // 16-bit tile-local bond positions
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, form)
-                       : pick_stream<2>(lanes, mixed, batch, form);
+    void *k = dim == 3 ? pick_stream<3>(lanes, prec, batch, form)
+                       : pick_stream<2>(lanes, prec, batch, form);
     if (!k) return false;
     for (int pass = 0; pass < 2; ++pass) {
         // first pass: one workgroup per CU gives the tile bound; second pass:
@@ -621,10 +643,10 @@ bool pd_stream_fits(int dim, uint32_t n, uint64_t nnz, uint64_t halo_total) {
 }
 
 int pd_launch_stream(pd_ctx ctx, hipStream_t st, int dim, const StreamArgs &sa, int lanes,
-                     bool mixed, int form, int block, unsigned grid, size_t lds) {
+                     int prec, int form, int block, unsigned grid, size_t lds) {
     const bool batch = sa.inst != nullptr;
-    void *k = dim == 3 ? pick_stream<3>(lanes, mixed, batch, form)
-                       : pick_stream<2>(lanes, mixed, batch, form);
+    void *k = dim == 3 ? pick_stream<3>(lanes, prec, batch, form)
+                       : pick_stream<2>(lanes, prec, batch, form);
     if (!k) return pd_set_error(ctx, PD_EINVAL, "no streamed kernel of form %d for %d lanes", form,
                                 lanes);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -96,8 +96,8 @@ extern "C" int pd_autotune(pd_ctx ctx, int dim, int64_t n, const double *X, cons
                            int table_cap, int *ntable, pd_tune_result *best) {
     PD_TRY(pd_check_ctx(ctx));
     if (ntable) *ntable = 0;
-    if (precision != PD_FP64 && precision != PD_MIXED)
-        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
+    if (precision != PD_FP64 && precision != PD_MIXED && precision != PD_FP32)
+        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64, PD_MIXED or PD_FP32");
     if (steps < 1 || steps > 100000) return pd_set_error(ctx, PD_EINVAL, "steps must be in [1, 1e5]");
     if (table_cap < 0 || (table_cap > 0 && !table))
         return pd_set_error(ctx, PD_EINVAL, "table must hold table_cap entries");
@@ -186,8 +186,8 @@ extern "C" int pd_tune_set(pd_ctx ctx, int dim, double mean_neighbors, int preci
                            int lanes) {
     if (!ctx) return PD_EINVAL;
     if (dim != 2 && dim != 3) return pd_set_error(ctx, PD_EINVAL, "dim must be 2 or 3");
-    if (precision != PD_FP64 && precision != PD_MIXED)
-        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64 or PD_MIXED");
+    if (precision != PD_FP64 && precision != PD_MIXED && precision != PD_FP32)
+        return pd_set_error(ctx, PD_EINVAL, "precision must be PD_FP64, PD_MIXED or PD_FP32");
     if (!(mean_neighbors > 0) || !std::isfinite(mean_neighbors))
         return pd_set_error(ctx, PD_EINVAL, "mean_neighbors must be > 0");
     if (!valid_choice(tile, lanes))

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libpd_hip.so")
 
 PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV, PD_ENONFINITE, PD_ECAPACITY = (
     0, -1, -2, -3, -4, -5, -6)
-PD_FP64, PD_MIXED = 0, 1
+PD_FP64, PD_MIXED, PD_FP32 = 0, 1, 2
+_PREC = {"fp64": PD_FP64, "mixed": PD_MIXED, "fp32": PD_FP32}
 PD_REQ_QUEUED, PD_REQ_RUNNING, PD_REQ_DONE, PD_REQ_FAILED = 0, 1, 2, 3
 PD_BC_FREE, PD_BC_CLAMPED, PD_BC_VELOCITY = 0, 1, 2
 
@@ -183,7 +184,7 @@ class Context:
         """Times every tile size x lanes candidate on the mesh (X, V, delta) and
         caches the fastest for meshes of its kind (pd_autotune).  Returns
         (best, table) as dicts."""
-        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        prec = _PREC[precision]
         table = (TuneResult * 16)()
         nt = C.c_int()
         best = TuneResult()
@@ -194,14 +195,14 @@ class Context:
         return row(best), [row(table[i]) for i in range(nt.value)]
 
     def tune_lookup(self, dim, mean_neighbors, precision="mixed"):
-        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        prec = _PREC[precision]
         r = TuneResult()
         self.check(lib.pd_tune_lookup(self.h, int(dim), float(mean_neighbors), prec,
                                       C.byref(r)), "pd_tune_lookup")
         return (r.tile, r.lanes) if r.tile else None
 
     def tune_set(self, dim, mean_neighbors, tile, lanes, precision="mixed"):
-        prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision]
+        prec = _PREC[precision]
         self.check(lib.pd_tune_set(self.h, int(dim), float(mean_neighbors), prec, int(tile),
                                    int(lanes)), "pd_tune_set")
 
@@ -231,7 +232,7 @@ def material(dim, c, rho=1.0, s_c=0.0, precision="fp64", law="linear", beta=0.0,
     stretch: "linearised" | "exact"; pv_h > 0: partial volumes (neighbours
     built at delta + pv_h/2); j = (c1, c2): influence function
     J = c1 r exp(-r^2/c2) of r = |xi|/delta on every bond (None: J = 1)."""
-    prec = {"fp64": PD_FP64, "mixed": PD_MIXED}[precision] if isinstance(precision, str) \
+    prec = _PREC[precision] if isinstance(precision, str) \
         else int(precision)
     lw = {"linear": PD_LAW_LINEAR, "np": PD_LAW_NP, "lps": PD_LAW_LPS}[law] \
         if isinstance(law, str) else int(law)

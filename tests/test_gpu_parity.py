@@ -2,8 +2,11 @@
 oracle on the same seeded inputs.
 
 Bars: neighbour lists bit-exact; FP64 forces/displacements rel-L2 <= 1e-12;
-mixed mode rel-L2 <= 1e-5; damage flags equal except for bonds whose stretch
-lies within 1e-6 (relative) of the critical stretch.
+mixed and FP32 modes rel-L2 <= 1e-5; damage flags equal except for bonds whose
+stretch lies within 1e-6 (relative) of the critical stretch, or, in FP32,
+within 2e-6 |eta|/|xi| of it (float32 rounds S on the scale |eta|/|xi|: about
+ten roundings of 2^-24 in the differences, the dot product and the
+reciprocal square root).
 """
 import numpy as np
 import pytest
@@ -15,6 +18,16 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOLMIX = 1e-5
+TOL32 = 1e-5
+TOL_ETA32 = 2e-6
+
+
+def tol_of(prec):
+    return {"fp64": TOL64, "mixed": TOLMIX, "fp32": TOL32}[prec]
+
+
+def eta_band(prec):
+    return TOL_ETA32 if prec == "fp32" else 0.0
 
 
 def relL2(a, b):
@@ -130,6 +143,7 @@ def force_case(seed, dim, N, m, jitter, scale=1e-3, s_c=0.0, dead_frac=0.0):
 @pytest.mark.parametrize("dim,N,m,prec,lanes", [
     (2, 37, 3, "fp64", 0), (2, 64, 4, "fp64", 0), (3, 17, 3, "fp64", 0),
     (2, 37, 3, "mixed", 0), (3, 17, 3, "mixed", 0),
+    (2, 37, 3, "fp32", 0), (3, 17, 3, "fp32", 0), (2, 33, 3, "fp32", 64), (3, 15, 3, "fp32", 2),
     (2, 33, 3, "fp64", 1), (2, 33, 3, "fp64", 64), (3, 15, 3, "fp64", 2), (3, 15, 3, "mixed", 32),
 ])
 def test_force_and_energy_parity(gpu, orc, dim, N, m, prec, lanes):
@@ -153,13 +167,14 @@ def test_force_and_energy_parity(gpu, orc, dim, N, m, prec, lanes):
         torch.cuda.synchronize()
     finally:
         ctx.set_lanes(0)
-    tol = TOL64 if prec == "fp64" else TOLMIX
+    tol = tol_of(prec)
+    say("force parity relL2", relL2(host(f), ref_f), "energy", relL2(host(U), ref_U))
     assert relL2(host(f), ref_f) <= tol
     assert np.abs(host(f) - ref_f).max() <= 10 * tol * np.abs(ref_f).max()
     assert relL2(host(U), ref_U) <= tol
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_damage_parity(gpu, orc, prec):
     torch, pd, ctx = gpu
     X, V, u, delta = force_case(21, 2, 48, 3, 0.05, scale=0.05)
@@ -179,9 +194,10 @@ def test_damage_parity(gpu, orc, prec):
     pd.internal_force(ctx, nb, mat, dev(torch, X), dev(torch, V), dev(torch, u), f, alive=al)
     torch.cuda.synchronize()
     got = host(al)
-    band = np.abs(S / s_c - 1) <= 1e-6
+    band = mesh.band_update(np.zeros(mesh.nnz, np.uint8), u, s_c, 1e-6,
+                            eta_band(prec)).astype(bool)
     assert np.array_equal(got[~band], ref_alive[~band])
-    tol = TOL64 if prec == "fp64" else TOLMIX
+    tol = tol_of(prec)
     if np.array_equal(got, ref_alive):
         assert relL2(host(f), ref_f) <= tol
 
@@ -203,7 +219,7 @@ def read_state(torch, sim, n, dim, nnz):
     return host(u), host(v), host(a), info
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX), ("fp32", TOL32)])
 def test_plate32_trajectory(gpu, orc, prec, tol):
     """The small free plate: 100 steps, energies and the full trajectory."""
     torch, pd, ctx = gpu
@@ -218,6 +234,7 @@ def test_plate32_trajectory(gpu, orc, prec, tol):
     sim.step(w.steps, w.dt)
     u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
     assert info["step"] == w.steps
+    say("plate32 relL2 u", relL2(u, st["u"]), "v", relL2(v, st["v"]))
     assert relL2(u, st["u"]) <= tol
     assert relL2(v, st["v"]) <= tol
     ke = mesh.kinetic(st["v"], w.rho)
@@ -230,7 +247,7 @@ def notched(N=96, m=4, s_c=4e-4, v0=2e-3, ramp=20):
     return inputs.notched_plate_2d(N=N, m=m, s_c=s_c, v0=v0, steps=0, ramp_steps=ramp)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_notched_windowed_parity(gpu, orc, prec):
     """Fracture run: every window of W steps the oracle restarts from the GPU
     state and must match it after W steps (u, v and flags)."""
@@ -238,7 +255,7 @@ def test_notched_windowed_parity(gpu, orc, prec):
     w = notched()
     mesh = orc.Mesh(w.X, w.V, w.delta)
     c = orc.micromodulus(2, w.E, w.delta)
-    tol = TOL64 if prec == "fp64" else TOLMIX
+    tol = tol_of(prec)
     say("notched windowed", prec)
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(2, w.E, w.delta), prec)
@@ -251,21 +268,19 @@ def test_notched_windowed_parity(gpu, orc, prec):
     for k in range(windows):
         st = mesh.start(u, v, c, w.s_c, a)          # force + damage test at u^k
         st["step"] = step
-        band = np.zeros(mesh.nnz, bool)
-        for _ in range(W):                          # one step at a time: track the band
-            band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
-            mesh.verlet(st, c, w.rho, w.s_c, w.dt, 1, w.bc_kind, w.bc_vel, None, w.ramp_steps)
-        band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
+        band = mesh.verlet_banded(st, c, w.rho, w.s_c, w.dt, W, w.bc_kind, w.bc_vel, None,
+                                  w.ramp_steps, tol_eta=eta_band(prec)).astype(bool)
         sim.step(W, w.dt)
         step += W
         u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
         assert info["step"] == step
         assert np.array_equal(a[~band], st["alive"][~band]), f"window {k}"
+        say("window", k, "relL2 u", relL2(u, st["u"]), "v", relL2(v, st["v"]))
         if np.array_equal(a, st["alive"]):
             assert relL2(u, st["u"]) <= tol, f"window {k}"
             assert relL2(v, st["v"]) <= 10 * tol, f"window {k}"
         else:                                       # a bond inside the band went the other way
-            assert prec == "mixed"
+            assert prec != "fp64"
             assert relL2(u, st["u"]) <= 100 * tol, f"window {k}"
         broke = np.count_nonzero(a == 0) - np.count_nonzero(alive0 == 0)
     assert broke > 0, "the load must break bonds beyond the notch"
@@ -384,7 +399,7 @@ def test_implicit_noconv_reports(gpu):
     assert res.status == pd.PD_ENOCONV and res.inner <= 3 and res.rel_residual > 1e-10
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
 def test_cube100_full_size_steps(gpu, orc, prec):
     """The 1M-node jittered cube in the benchmark's launch configuration (the
     streamed kernel at the autotuner's tile size and lanes): random initial
@@ -399,11 +414,8 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     v0 = inputs.random_field(w.n, 3, 99, scale=3e-3)
     v0[w.bc_kind == 2] = 0.0
     st = mesh.start(w.u0, v0, c, w.s_c)
-    band = np.zeros(mesh.nnz, bool)
-    for _ in range(3):
-        band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
-        mesh.verlet(st, c, w.rho, w.s_c, w.dt, 1, w.bc_kind, w.bc_vel, None, w.ramp_steps)
-    band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
+    band = mesh.verlet_banded(st, c, w.rho, w.s_c, w.dt, 3, w.bc_kind, w.bc_vel, None,
+                              w.ramp_steps, tol_eta=eta_band(prec)).astype(bool)
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     w.v0 = v0
     # the benchmark's launch configuration: the autotuner's shape for this mesh
@@ -420,15 +432,17 @@ def test_cube100_full_size_steps(gpu, orc, prec):
     finally:
         ctx.tune_clear()
         nb.close()
-    tol = TOL64 if prec == "fp64" else TOLMIX
+    tol = tol_of(prec)
     assert 0 < np.count_nonzero(st["alive"] == 0) < mesh.nnz
     assert np.array_equal(a[~band], st["alive"][~band])
     same = np.array_equal(a, st["alive"])
+    say("cube100", prec, "same flags", same, "relL2 u", relL2(u, st["u"]), "v",
+        relL2(v, st["v"]))
     assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
     assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
 def test_notched512_full_size_steps(gpu, orc, prec):
     """The 512^2 notched plate at full size: notch, collars and damage, with a
     random initial velocity so that bonds break; 20 steps against the
@@ -442,11 +456,8 @@ def test_notched512_full_size_steps(gpu, orc, prec):
     v0[w.bc_kind == 2] = 0.0
     alive0 = mesh.notch_cut(w.notch, mesh.all_alive())
     st = mesh.start(w.u0, v0, c, w.s_c, alive0)
-    band = np.zeros(mesh.nnz, bool)
-    for _ in range(20):
-        band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
-        mesh.verlet(st, c, w.rho, w.s_c, w.dt, 1, w.bc_kind, w.bc_vel, None, w.ramp_steps)
-    band |= np.abs(bond_strain(mesh, st["u"]) / w.s_c - 1) <= 1e-6
+    band = mesh.verlet_banded(st, c, w.rho, w.s_c, w.dt, 20, w.bc_kind, w.bc_vel, None,
+                              w.ramp_steps, tol_eta=eta_band(prec)).astype(bool)
     nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
     w.v0 = v0
     sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(2, w.E, w.delta), prec)
@@ -455,17 +466,19 @@ def test_notched512_full_size_steps(gpu, orc, prec):
     u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
     sim.close()
     nb.close()
-    tol = TOL64 if prec == "fp64" else TOLMIX
+    tol = tol_of(prec)
     broken = np.count_nonzero(st["alive"] == 0) - np.count_nonzero(alive0 == 0)
     assert broken > 0
     assert np.array_equal(a[~band], st["alive"][~band])
     same = np.array_equal(a, st["alive"])
+    say("notched512", prec, "same flags", same, "relL2 u", relL2(u, st["u"]), "v",
+        relL2(v, st["v"]))
     assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
     assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
 
 
 @pytest.mark.parametrize("wl,prec", [("plate", "fp64"), ("cube", "mixed"), ("cube", "fp64"),
-                                     ("notched", "mixed")])
+                                     ("notched", "mixed"), ("cube", "fp32"), ("notched", "fp32")])
 def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
     """The LDS-tile kernels (register-staged and streamed) and the gather
     kernel sum every node's bonds in the same order, so trajectories agree bit
@@ -481,9 +494,11 @@ def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
         w = notched(N=72)
     c = pd.micromodulus(w.dim, w.E, w.delta)
     results = []
-    for kind, tile, block in [("gather", 0, 0), ("tile", 32, 0), ("tile", 64, 512),
-                              ("tile", 128, 0), ("tile", 0, 0), ("stream", 0, 0),
-                              ("stream", 32, 0)]:
+    shapes = [("gather", 0, 0), ("tile", 32, 0), ("tile", 64, 512), ("tile", 128, 0),
+              ("tile", 0, 0), ("stream", 0, 0), ("stream", 32, 0)]
+    if prec == "fp32":          # no register-staged tile kernel in float32
+        shapes = [x for x in shapes if x[0] != "tile"]
+    for kind, tile, block in shapes:
         say("tile vs gather", wl, prec, kind, tile, block)
         ctx.set_tuning(kind, tile, block)
         try:

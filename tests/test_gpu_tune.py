@@ -24,7 +24,7 @@ def moving_plate(N, m):
     return w
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX)])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", TOLMIX), ("fp32", TOLMIX)])
 def test_every_candidate_matches_oracle(gpu, orc, prec, tol):
     torch, pd, ctx = gpu
     w = moving_plate(64, 3)

@@ -194,3 +194,13 @@ def test_band_update_matches_definition(orc):
     before = band.copy()
     mesh.band_update(band, np.zeros_like(u), s_c, 1e-6)     # S = 0: nothing added
     assert np.array_equal(band, before)
+    # the eta-scaled term: |S - s_c| <= tol_eta |eta|/|xi|
+    r = np.linalg.norm(u[mesh.col] - u[i], axis=1) / np.linalg.norm(xi, axis=1)
+    for tol_eta in (1e-3, 0.2):
+        band = np.zeros(mesh.nnz, np.uint8)
+        mesh.band_update(band, u, s_c, 0.0, tol_eta)
+        d = np.abs(S - s_c) - tol_eta * r
+        want = d <= 0
+        edge = np.abs(d) <= 1e-12 * np.abs(s_c)
+        assert np.array_equal(band.astype(bool)[~edge], want[~edge])
+        assert 2 <= want.sum() < mesh.nnz

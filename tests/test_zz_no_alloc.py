@@ -40,7 +40,7 @@ def run(torch, pd, ctx, X, V, u, delta, dim, prec, s_c, noalloc):
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_noalloc_equals_internal_force(gpu, prec):
     torch, pd, ctx = gpu
     # two calls in a row, the second smaller; damage on (some bonds break)
