@@ -70,6 +70,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
             // both ends from the state pass
             const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
             const LpsCoef qi = lps_coef(si.x, si.y, a.bulk, a.shear);
+            const double hi = si.x > 0.0 ? si.y / 3.0 : 0.0;    // theta_i / 3
             for (uint32_t p = rs + lane; p < re; p += L) {
                 const uint32_t j = (uint32_t)a.col[p];
                 const bool live = !a.alive || a.alive[p];
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 const LpsCoef qj = lps_coef(sj.x, sj.y, a.bulk, a.shear);
                 const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
                 const double g = lps_force_weight(qi, qj, len, e, iy, Vj, live);
-                const double edi = e - qi.h * len;
+                const double edi = e - hi * len;
                 s64.x = fma(g, dxx + dux, s64.x);
                 s64.y = fma(g, dxy + duy, s64.y);
                 s64.z = fma(g, dxz + duz, s64.z);
@@ -848,7 +849,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
         const size_t rd = nbr->dim == 3 ? 6 : 4;
         st = pd_alloc(ctx, &s->rec[0], n * rd);
         if (st == PD_OK) st = pd_alloc(ctx, &s->rec[1], n * rd);
-        if (st == PD_OK && lps_stream) st = pd_alloc(ctx, &s->lpsc, n * 4);
+        if (st == PD_OK && lps_stream) st = pd_alloc(ctx, &s->lpsc, n * 2);
         // both buffers carry the positions; u is rewritten every step
         if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[0]);
         if (st == PD_OK) st = pd_rec_pack(ctx, nbr->dim, nbr->n, s->xv, s->u[0], s->rec[1]);

@@ -359,17 +359,17 @@ __device__ __forceinline__ void lps_state_terms(double len, double e, double Vj,
     s += len * e * Vj;
 }
 // A node's coefficients in the bond force state, from its {m, theta}:
-// {3 K theta / m, 15 mu / m, theta / 3} (all 0 where m = 0), so that
-// t = c |xi| + d (e - h |xi|) with the deviatoric extension e - h |xi|.
+// t_ij = (3 K theta_i / m_i) |xi| + (15 mu / m_i) (e - theta_i |xi| / 3)
+//      = a_i |xi| + d_i e  with  a_i = (3 K - 5 mu) theta_i / m_i,
+// d_i = 15 mu / m_i (both 0 where m_i = 0).
 struct LpsCoef {
-    double c, d, h;
+    double a, d;
 };
 __device__ __forceinline__ LpsCoef lps_coef(double m, double theta, double K, double mu) {
 #pragma clang fp contract(off)
     LpsCoef q;
-    q.c = m > 0.0 ? 3.0 * K * theta / m : 0.0;
+    q.a = m > 0.0 ? (3.0 * K - 5.0 * mu) * theta / m : 0.0;
     q.d = m > 0.0 ? 15.0 * mu / m : 0.0;
-    q.h = m > 0.0 ? theta / 3.0 : 0.0;
     return q;
 }
 // Force: the weight g of M = (xi+eta) in f_i, (t_ij + t_ji) V_j / |xi+eta|,
@@ -378,8 +378,7 @@ __device__ __forceinline__ double lps_force_weight(const LpsCoef &qi, const LpsC
                                                    double len, double e, double iy, double Vj,
                                                    bool live) {
 #pragma clang fp contract(off)
-    const double edi = e - qi.h * len, edj = e - qj.h * len;
-    const double t = (qi.c * len + qi.d * edi) + (qj.c * len + qj.d * edj);
+    const double t = (qi.a + qj.a) * len + (qi.d + qj.d) * e;
     return live ? t * Vj * iy : 0.0;
 }
 
@@ -576,7 +575,7 @@ struct StreamInst {
     uint32_t n, tile_begin;     // nodes; first tile in the batch numbering
     double cv, s_c, rho, dt;
     double beta;                // NP law (launches of the NP kernel only)
-    double *lps;                // the solid: [n] {c, d, h, 0} (lps_coef) from its state pass
+    double *lps;                // the solid: [n] {a, d} (lps_coef) from its state pass
     double vol, bulk, shear;    // the solid: the (uniform) nodal volume and the moduli
     int damage, cur0, vhalf0;
     int cd;                     // central-difference steps after the chunk's first (Verlet) step

@@ -29,8 +29,10 @@
 // ids of tile k+1 are in LDS); sum the bonds, one lane group per node in the
 // gather kernel's summation order (so results are bit-identical to it), and
 // let L lanes of each group update their node (kick, drift, boundary data),
-// one component per lane; barrier; write back the bond words that broke;
-// issue the copies of tile k+1 and of the halo ids of tile k+2.
+// one component per lane; barrier; issue the copies of tile k+1 and of the
+// halo ids of tile k+2.  The bond words are read from global memory in the
+// bond loop (one read per bond and pass; a break is stored at once), so they
+// take no LDS.
 #include <climits>
 
 #include "pd_kernels.hpp"
@@ -113,48 +115,28 @@ __device__ __forceinline__ void lds_barrier() {
 constexpr int META = 8;
 enum { MT_H0, MT_HN, MT_B0, MT_B1, MT_SO, MT_INST, MT_T0, MT_TN };
 constexpr uint16_t BW_DEAD = 0x8000;
-constexpr uint32_t BRK_CAP = 256;    // broken bonds listed per tile (more: the whole tile)
 
 inline __host__ __device__ uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
 
-// the forms whose bond loop reads the bond words from global memory (the
-// linearised and NP laws: one read per bond and step, breaks stored at once);
-// the solid's passes stage them in LDS
-__host__ __device__ constexpr bool words_global(int form) {
-    return form == SK_LINEAR || form == SK_NP;
-}
-
 // LDS layout, in this order (every region a multiple of 16 bytes): the tile
-// slot (records, bond words, row offsets, v, boundary kinds), two halo-id
-// slots, three break lists (tile k uses list k mod 3, so a list is cleared
-// one tile before its next use without an extra barrier), tile metadata,
-// and for the solid's force pass the halo's coefficients {c, d, h, 0}.  The
-// forms that read bond words from global memory have no words region and no
-// break lists.
+// slot (records, row offsets, v, boundary kinds), two halo-id slots, tile
+// metadata, and for the solid's force pass the halo's coefficients {a, d}.
 struct StreamLayout {
-    uint32_t H, T, WB, TP, TB, BL, MM, RD, US, SP;
-    __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t bcap, uint32_t tile,
-                                     uint32_t mmax, int form) {
+    uint32_t H, T, TP, TB, MM, RD, US, SP;
+    __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t tile, uint32_t mmax,
+                                     int form) {
         H = hcap;                      // multiple of 32
         T = tile;
-        // 32-bit bond-word pairs: the tile's words copied in 16-byte pieces
-        // from an 8-word-aligned start, and room for the bond loop's reads up
-        // to 32 words past a row's end (every word there is a valid record
-        // index: the region starts zeroed and later holds earlier tiles'
-        // words or the next tile's)
-        WB = words_global(form) ? 0u : round4(bcap / 2 + 24);
-        BL = words_global(form) ? 0u : 3 * (BRK_CAP + 4);
         TP = round4(tile + 1);         // row offsets
         TB = round4(tile / 4 + 1);     // 32-bit words of boundary kinds
         MM = round4(mmax * META);
         RD = dim == 3 ? 6 : 4;         // doubles per record
         US = dim == 3 ? 4 : 2;         // doubles per node in v
-        SP = form == SK_LPS_FORCE ? 4 * hcap : 0u;   // doubles of staged {c, d, h, 0}
+        SP = form == SK_LPS_FORCE ? 2 * hcap : 0u;   // doubles of staged {a, d}
     }
     __host__ __device__ size_t bytes() const {
-        return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)WB * 4 + (size_t)TP * 4 +
-               (size_t)T * US * 8 + (size_t)TB * 4 + (size_t)BL * 4 + (size_t)MM * 4 +
-               (size_t)SP * 8;
+        return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)TP * 4 + (size_t)T * US * 8 +
+               (size_t)TB * 4 + (size_t)MM * 4 + (size_t)SP * 8;
     }
 };
 
@@ -167,9 +149,9 @@ __device__ __forceinline__ double ramp_of(double s, int64_t ramp) {
 // BATCH = false: one simulation whose descriptor travels in the kernel
 // arguments (sa.one); true: sa.ninst descriptors in device memory.  FORM:
 // SK_LINEAR or SK_NP (one launch per step), SK_LPS_STATE (the solid's first
-// pass: {m, theta} per node into I.lps, no update) or SK_LPS_FORCE (its
-// force, with the neighbours' {m, theta} staged beside the records, and the
-// node update).
+// pass: the coefficients {a, d} per node into I.lps, no update) or
+// SK_LPS_FORCE (its force, with the neighbours' {a, d} staged beside the
+// records, and the node update).
 template <int DIM, int L, int PREC, bool BATCH, int FORM>
 __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     // PREC: PD_FP64, PD_MIXED, or PD_FP32 (float32 bond terms, compensated
@@ -180,7 +162,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
     constexpr bool NP = FORM == SK_NP, LPS = FORM == SK_LPS_STATE || FORM == SK_LPS_FORCE;
     static_assert(!LPS || (DIM == 3 && !BATCH), "the solid: 3-d, single simulation");
-    const StreamLayout lay(DIM, sa.hcap, sa.bcap, sa.tile, sa.mmax, FORM);
+    const StreamLayout lay(DIM, sa.hcap, sa.tile, sa.mmax, FORM);
     const uint32_t H = lay.H, T = lay.T;
     const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u;
     // first thread of this wave, in a scalar register: the copy loops below
@@ -188,12 +170,10 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     const uint32_t wbase = __builtin_amdgcn_readfirstlane(tid - lane64);
     double *rec = lds;                                                           // H RD
     int32_t *ids = reinterpret_cast<int32_t *>(rec + (size_t)H * RD);            // 2 H
-    uint32_t *words = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);         // WB
-    uint32_t *rowp = words + lay.WB;                                             // TP
+    uint32_t *rowp = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);          // TP
     double *vbuf = reinterpret_cast<double *>(rowp + lay.TP);                    // T US
     uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)T * US);         // TB
-    uint32_t *brk = bcb + lay.TB;                                                // 3 (4 + CAP)
-    uint32_t *meta = brk + lay.BL;                                               // MM
+    uint32_t *meta = bcb + lay.TB;                                               // MM
     double *sps = reinterpret_cast<double *>(meta + lay.MM);                     // SP
     const StreamInst *inst = sa.inst;
     const int64_t s = sa.step;                          // step of this launch in its chunk
@@ -226,7 +206,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         m[MT_H0] = h0;
         m[MT_HN] = s < I.limit ? I.halo_ptr[t + 1] - h0 : 0u;
         m[MT_B0] = I.row_ptr[t0] & ~7u;   // 16-byte aligned bond-word copies
-        m[MT_B1] = I.row_ptr[t0 + tn];
+        m[MT_B1] = I.row_ptr[t0 + tn];   // (end of the tile's words)
         m[MT_SO] = I.self_off[t];
         m[MT_INST] = lo;
         m[MT_T0] = t0;
@@ -237,12 +217,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         if (!BATCH) return sa.one;
         return load_inst(inst, (uint32_t)__builtin_amdgcn_readfirstlane(meta[k * META + MT_INST]));
     };
-    constexpr bool GW = words_global(FORM);
-    auto blist = [&](uint32_t k) { return brk + (k % 3u) * (BRK_CAP + 4); };
-    if (!GW && tid < 3) brk[tid * (BRK_CAP + 4)] = 0;
-    for (uint32_t c = tid; c < lay.WB; c += B) words[c] = 0u;
     __syncthreads();
-
 
     // halo ids of tile k -> ids slot k mod 2
     auto issue_ids = [&](uint32_t k) {
@@ -255,16 +230,15 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             if (c0 + lane64 < hn) dma4(halo, (h0 + c0 + lane64) * 4u, m0);
         }
     };
-    // records, bond words, row offsets, v and boundary kinds of tile k (the
-    // ids of tile k are in ids slot k mod 2)
+    // records, row offsets, v and boundary kinds of tile k (the ids of tile k
+    // are in ids slot k mod 2)
     auto issue_tile = [&](uint32_t k) {
         const uint32_t hn = meta[k * META + MT_HN];
         if (hn == 0) return;
         const uint32_t t0 = meta[k * META + MT_T0], tn = meta[k * META + MT_TN];
-        const uint32_t b0 = meta[k * META + MT_B0], b1 = meta[k * META + MT_B1];
         const int32_t *hid = ids + (size_t)(k & 1u) * H;
         const StreamInst I = inst_of(k);
-        const void *src = cur_of(I) ? I.rec[1] : I.rec[0], *bw = I.bw;
+        const void *src = cur_of(I) ? I.rec[1] : I.rec[0];
         const void *rp = I.row_ptr, *vv = I.v, *bc = I.bc;
         const uint32_t nrc = hn * NCH;
         for (uint32_t c0 = wbase; c0 < nrc; c0 += B) {
@@ -274,12 +248,6 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 const uint32_t r = c / NCH, part = c - r * NCH;
                 dma16(src, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
             }
-        }
-        // bond words in 16-byte pieces (8 words each; the arrays are padded)
-        const uint32_t nw = GW ? 0u : (b1 - b0 + 7) / 8;
-        for (uint32_t c0 = wbase; c0 < nw; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(words + 4 * (size_t)c0));
-            if (c0 + lane64 < nw) dma16(bw, (b0 / 8 + c0 + lane64) * 16u, m0);
         }
         for (uint32_t c0 = wbase; c0 <= tn; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rowp + c0));
@@ -297,21 +265,20 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             if (c0 + lane64 < nbw) dma4(bc, t0 + 4 * (c0 + lane64), m0);
         }
         if constexpr (FORM == SK_LPS_FORCE) {
-            // {c, d, h, 0} of every halo node: two 16-byte copies each
+            // {a, d} of every halo node: one 16-byte copy each
             const void *ls = I.lps;
-            const uint32_t nsc = 2 * hn;
-            for (uint32_t c0 = wbase; c0 < nsc; c0 += B) {
+            for (uint32_t c0 = wbase; c0 < hn; c0 += B) {
                 const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(sps + 2 * (size_t)c0));
                 const uint32_t c = c0 + lane64;
-                if (c < nsc) dma16(ls, (uint32_t)hid[c >> 1] * 32u + (c & 1u) * 16u, m0);
+                if (c < hn) dma16(ls, (uint32_t)hid[c] * 16u, m0);
             }
         }
     };
 
     // bond sums of tile k; then L lanes of each node's group update the node
     // (kick, drift, boundary data, or the central-difference update), one
-    // component per lane, with the same arithmetic as node_update.  A bond that breaks
-    // gets its dead bit in the LDS copy of the words and goes on the list.
+    // component per lane, with the same arithmetic as node_update.  A bond that
+    // breaks gets its dead bit in the global bond word at once.
     auto sum_and_update = [&](uint32_t k) {
         if (meta[k * META + MT_HN] == 0) return;
         const StreamInst I = inst_of(k);
@@ -324,8 +291,6 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho, beta = I.beta;
         const float cv32 = (float)cv, s_c32 = (float)s_c;
         const int damage = I.damage;
-        uint16_t *w16 = reinterpret_cast<uint16_t *>(words);
-        uint32_t *bl = blist(k);
         const uint32_t groups = B / L, g = tid / L;
         const int lane = tid & (L - 1);
         for (uint32_t q = g; q < tn; q += groups) {
@@ -349,65 +314,96 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     dux = c1.x - uix; duy = c1.y - uiy; duz = 0.0;
                 }
             };
-            if constexpr (FORM == SK_LPS_STATE) {
-                // the solid's first pass, as lps_state_k: m_i and theta_i over
-                // live bonds (uniform V_j), in the same order
-                double m = 0.0, sm = 0.0;
-                for (uint32_t p = rs + lane; p < re; p += L) {
-                    const uint32_t w = w16[p];
-                    if (w & BW_DEAD) continue;
-                    double dxx, dxy, dxz, dux, duy, duz, len, e, iy;
-                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
-                    lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
-                    lps_state_terms(len, e, I.vol, m, sm);
-                }
-                m = lane_sum<L>(m);
-                sm = lane_sum<L>(sm);
-                if (lane == 0) {
-                    const LpsCoef qc = lps_coef(m, m > 0.0 ? 3.0 / m * sm : 0.0, I.bulk, I.shear);
-                    reinterpret_cast<double4 *>(I.lps)[t0 + q] = make_double4(qc.c, qc.d, qc.h, 0.0);
-                }
-                continue;
-            } else if constexpr (FORM == SK_LPS_FORCE) {
-                // the solid's force, as the gather kernel's branch: the
-                // scatter read from node i with {m, theta} of both ends
-                auto coef_of = [&](uint32_t j) {
-                    const double2 cd = *reinterpret_cast<const double2 *>(sps + 4 * (size_t)j);
-                    LpsCoef r;
-                    r.c = cd.x;
-                    r.d = cd.y;
-                    r.h = sps[4 * (size_t)j + 2];
-                    return r;
-                };
-                const LpsCoef qi = coef_of(so + q);
-                for (uint32_t p = rs + lane; p < re; p += L) {
-                    const uint32_t w = w16[p];
-                    double dxx, dxy, dxz, dux, duy, duz, len, e, iy;
-                    bond_vectors(w, dxx, dxy, dxz, dux, duy, duz);
-                    lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
-                    const double g = lps_force_weight(qi, coef_of(w & 0x7fffu), len, e, iy, I.vol,
-                                                      (w & BW_DEAD) == 0);
-                    acc.x = fma(g, dxx + dux, acc.x);
-                    acc.y = fma(g, dxy + duy, acc.y);
-                    acc.z = fma(g, dxz + duz, acc.z);
-                }
-            } else {
-                // two bonds per pass, p and p + L, summed in that order (the
-                // gather kernel's order); past the row's end the second one is
-                // marked dead and adds nothing.  The words come from global
-                // memory (reads past a row's end stay inside the padded array
-                // and give valid record indices: the next rows' words, the
-                // next tile's, or the dead pad); a break is stored at once.
-                const uint16_t *gw = I.bw + b0;
-                const uint16_t *we = gw + re;
-                const uint16_t *wq = gw + rs + lane;
-                // the words of a pass are loaded two passes ahead, into the
-                // register pair that pass will use (no rotation between them)
+            // the words of this row come from global memory, two bonds per
+            // pass (p and p + L, summed in that order: the gather kernel's
+            // order), loaded two passes ahead into the register pair that pass
+            // will use.  Reads past a row's end stay inside the padded array
+            // and give valid record indices (the next rows' words, the next
+            // tile's, or the dead pad); such a bond is masked off.
+            const uint16_t *gw = I.bw + b0;
+            const uint16_t *we = gw + re;
+            const uint16_t *wq = gw + rs + lane;
+            auto run_pairs = [&](auto &&pair) {
                 auto pass = [&](uint32_t &ra, uint32_t &rb) {
                     const bool hb = wq + L < we;
                     const uint32_t wa = ra, wb = rb;
                     ra = wq[4 * L];
                     rb = wq[5 * L];
+                    pair(wa, wb, hb);
+                    wq += 2 * L;
+                };
+                uint32_t a0 = wq[0], b0w = wq[L], a1 = wq[2 * L], b1w = wq[3 * L];
+                while (wq < we) {
+                    pass(a0, b0w);
+                    if (!(wq < we)) break;
+                    pass(a1, b1w);
+                }
+            };
+            if constexpr (FORM == SK_LPS_STATE) {
+                // the solid's first pass, as lps_state_k: m_i and theta_i over
+                // live bonds (uniform V_j), in the same order
+                double m = 0.0, sm = 0.0;
+                run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
+                    double ax, ay, az, aux, auy, auz, alen, ae, aiy;
+                    double bx, by, bz, bux, buy, buz, blen, be, biy;
+                    bond_vectors(wa, ax, ay, az, aux, auy, auz);
+                    bond_vectors(wb, bx, by, bz, bux, buy, buz);
+                    lps_bond<MIXED>(ax, ay, az, aux, auy, auz, alen, ae, aiy);
+                    lps_bond<MIXED>(bx, by, bz, bux, buy, buz, blen, be, biy);
+                    if (!(wa & BW_DEAD)) {
+                        asm volatile("" ::: "memory");
+                        lps_state_terms(alen, ae, I.vol, m, sm);
+                    }
+                    if (hb && !(wb & BW_DEAD)) {
+                        asm volatile("" ::: "memory");
+                        lps_state_terms(blen, be, I.vol, m, sm);
+                    }
+                });
+                m = lane_sum<L>(m);
+                sm = lane_sum<L>(sm);
+                if (lane == 0) {
+                    const LpsCoef qc = lps_coef(m, m > 0.0 ? 3.0 / m * sm : 0.0, I.bulk, I.shear);
+                    reinterpret_cast<double2 *>(I.lps)[t0 + q] = make_double2(qc.a, qc.d);
+                }
+                continue;
+            } else if constexpr (FORM == SK_LPS_FORCE) {
+                // the solid's force, as the gather kernel's branch: the
+                // scatter read from node i with {a, d} of both ends (a
+                // dead bond adds nothing there either: its weight is 0)
+                auto coef_of = [&](uint32_t j) {
+                    const double2 ad = *reinterpret_cast<const double2 *>(sps + 2 * (size_t)j);
+                    LpsCoef r;
+                    r.a = ad.x;
+                    r.d = ad.y;
+                    return r;
+                };
+                const LpsCoef qi = coef_of(so + q);
+                run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
+                    double ax, ay, az, aux, auy, auz, alen, ae, aiy;
+                    double bx, by, bz, bux, buy, buz, blen, be, biy;
+                    bond_vectors(wa, ax, ay, az, aux, auy, auz);
+                    bond_vectors(wb, bx, by, bz, bux, buy, buz);
+                    lps_bond<MIXED>(ax, ay, az, aux, auy, auz, alen, ae, aiy);
+                    lps_bond<MIXED>(bx, by, bz, bux, buy, buz, blen, be, biy);
+                    const LpsCoef qa = coef_of(wa & 0x7fffu), qb = coef_of(wb & 0x7fffu);
+                    if (!(wa & BW_DEAD)) {
+                        asm volatile("" ::: "memory");
+                        const double g = lps_force_weight(qi, qa, alen, ae, aiy, I.vol, true);
+                        acc.x = fma(g, ax + aux, acc.x);
+                        acc.y = fma(g, ay + auy, acc.y);
+                        acc.z = fma(g, az + auz, acc.z);
+                    }
+                    if (hb && !(wb & BW_DEAD)) {
+                        asm volatile("" ::: "memory");
+                        const double g = lps_force_weight(qi, qb, blen, be, biy, I.vol, true);
+                        acc.x = fma(g, bx + bux, acc.x);
+                        acc.y = fma(g, by + buy, acc.y);
+                        acc.z = fma(g, bz + buz, acc.z);
+                    }
+                });
+            } else {
+                // a break is stored at once
+                run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
                     double ax, ay, az, aux, auy, auz, bx, by, bz, bux, buy, buz;
                     bond_vectors(wa, ax, ay, az, aux, auy, auz);
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
@@ -424,16 +420,10 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                                                          cv, !hb || (wb & BW_DEAD) != 0, acc,
                                                          beta);
                     }
+                    // wq still addresses this pass's first bond
                     if (ka) *const_cast<uint16_t *>(wq) = (uint16_t)(wa | BW_DEAD);
                     if (kb) *const_cast<uint16_t *>(wq + L) = (uint16_t)(wb | BW_DEAD);
-                    wq += 2 * L;
-                };
-                uint32_t a0 = wq[0], b0w = wq[L], a1 = wq[2 * L], b1w = wq[3 * L];
-                while (wq < we) {
-                    pass(a0, b0w);
-                    if (!(wq < we)) break;
-                    pass(a1, b1w);
-                }
+                });
             }
             double fx, fy, fz, Ue;
             if constexpr (F32) group_reduce_c<DIM, L, false>(acc, fx, fy, fz, Ue);
@@ -475,25 +465,6 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         }
     };
 
-    // the bond words of tile k that broke go back to HBM; a tile with more
-    // breaks than the list holds writes back all its words from LDS
-    auto write_back = [&](uint32_t k, uint32_t nbk) {
-        uint16_t *bw = inst_of(k).bw;
-        const uint32_t *bl = blist(k);
-        const uint32_t b0 = meta[k * META + MT_B0];
-        if (nbk <= BRK_CAP) {
-            for (uint32_t e = tid; e < nbk; e += B) {
-                const uint32_t v = bl[4 + e];
-                bw[b0 + (v >> 16)] = (uint16_t)(v & 0xffffu);
-            }
-        } else {
-            const uint32_t tn = meta[k * META + MT_TN];
-            const uint16_t *w16 = reinterpret_cast<const uint16_t *>(words);
-            const uint32_t rs = rowp[0] - b0, re = rowp[tn] - b0;
-            for (uint32_t q = rs + tid; q < re; q += B) bw[b0 + q] = w16[q];
-        }
-    };
-
     issue_ids(0);
     if (K > 1) issue_ids(1);
     dma_wait();
@@ -502,12 +473,8 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     for (uint32_t k = 0; k < K; ++k) {
         dma_wait();
         lds_barrier();                       // tile k and the ids of tile k+1 are in LDS
-        if (!GW && tid == 0) blist(k + 1)[0] = 0;   // last read for tile k-2
         sum_and_update(k);
         lds_barrier();                       // the slot is free once the sums are done
-        const uint32_t nbk = GW ? 0u : blist(k)[0];
-        if (nbk) write_back(k, nbk);
-        if (nbk > BRK_CAP) lds_barrier();    // the words were read from the slot
         if (k + 1 < K) issue_tile(k + 1);
         if (k + 2 < K) issue_ids(k + 2);
     }
@@ -593,7 +560,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
     const uint32_t B = tile * (uint32_t)lanes;
     if (B < 64 || B > 1024 || B % 64 != 0) return false;
     if (lanes < dim) return false;   // the node update takes one lane per component
-    if (bcap >= (1u << 16)) return false;   // 16-bit tile-local bond positions
+    (void)bcap;                      // the bond words stay in global memory
     void *k = dim == 3 ? pick_stream<3>(lanes, prec, batch, form)
                        : pick_stream<2>(lanes, prec, batch, form);
     if (!k) return false;
@@ -603,7 +570,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
         unsigned g = (unsigned)ctx->num_cu;
         if (pass == 1) {
             int per_cu = 0;
-            const size_t bytes = StreamLayout(dim, hcap, bcap, tile, *mmax, form).bytes();
+            const size_t bytes = StreamLayout(dim, hcap, tile, *mmax, form).bytes();
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, (int)B,
                                                              bytes) != hipSuccess)
@@ -625,7 +592,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
             const uint32_t kk = (tc + gx - 1) / gx;
             if (kk > m) m = kk;
         }
-        const size_t bytes = StreamLayout(dim, hcap, bcap, tile, m, form).bytes();
+        const size_t bytes = StreamLayout(dim, hcap, tile, m, form).bytes();
         if (bytes > 160 * 1024) return false;
         *mmax = m;
         *lds = bytes;
