@@ -69,7 +69,7 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
             // node i, f_i = sum_j (t_ij + t_ji) M V_j, with {m, theta} of
             // both ends from the state pass
             const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
-            const LpsCoef qi = lps_coef(si.x, si.y, a.bulk, a.shear);
+            const LpsCoef qi = lps_coef<MIXED>(si.x, si.y, a.bulk, a.shear);
             const double hi = si.x > 0.0 ? si.y / 3.0 : 0.0;    // theta_i / 3
             for (uint32_t p = rs + lane; p < re; p += L) {
                 const uint32_t j = (uint32_t)a.col[p];
@@ -82,8 +82,9 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 double len, e, iy;
                 lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
                 const double2 sj = reinterpret_cast<const double2 *>(a.lps)[j];
-                const LpsCoef qj = lps_coef(sj.x, sj.y, a.bulk, a.shear);
-                const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
+                const LpsCoef qj = lps_coef<MIXED>(sj.x, sj.y, a.bulk, a.shear);
+                const double Vj =
+                    a.vol_uniform > 0.0 ? 1.0 : xj.w * pv_weight(len, a.pv_R, a.pv_h);
                 const double g = lps_force_weight(qi, qj, len, e, iy, Vj, live);
                 const double edi = e - hi * len;
                 s64.x = fma(g, dxx + dux, s64.x);
@@ -118,6 +119,13 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
     double fx, fy, fz, Ue;
     group_reduce<DIM, L, WANT_E>(s64, fx, fy, fz, Ue);
     if (!valid || lane != 0) return;
+    if (DIM == 3 && a.law == PD_LAW_LPS && a.vol_uniform > 0.0) {
+        // the solid's bond terms left the uniform volume out
+        fx = fx * a.vol_uniform;
+        fy = fy * a.vol_uniform;
+        fz = fz * a.vol_uniform;
+        Ue = Ue * a.vol_uniform;
+    }
     if (WANT_E && DIM == 3 && a.law == PD_LAW_LPS) {
         const double2 si = reinterpret_cast<const double2 *>(a.lps)[i];
         Ue = si.x > 0.0 ? 0.5 * a.bulk * si.y * si.y + 7.5 * a.shear / si.x * Ue : 0.0;
@@ -192,12 +200,16 @@ __global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
             double len, e, iy;
             lps_bond<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
                             ujz - uiz, len, e, iy);
-            const double Vj = xj.w * pv_weight(len, a.pv_R, a.pv_h);
+            const double Vj = a.vol_uniform > 0.0 ? 1.0 : xj.w * pv_weight(len, a.pv_R, a.pv_h);
             lps_state_terms(len, e, Vj, m, s);
         }
     }
     m = lane_sum<L>(m);
     s = lane_sum<L>(s);
+    if (a.vol_uniform > 0.0) {      // the uniform volume, applied once per node
+        m = m * a.vol_uniform;
+        s = s * a.vol_uniform;
+    }
     if (valid && lane == 0)
         reinterpret_cast<double2 *>(a.lps)[i] = make_double2(m, m > 0.0 ? 3.0 / m * s : 0.0);
 }
@@ -891,6 +903,7 @@ static NodeArgs sim_args(pd_sim s) {
     a.b = s->b;
     a.flag = s->ctx->flag;
     a.lps = s->lps;
+    a.vol_uniform = s->mat.law == PD_LAW_LPS && !(s->mat.pv_h > 0.0) ? s->vol_uniform : 0.0;
     return a;
 }
 

@@ -104,7 +104,7 @@ struct pd_sim_s {
     double cv_uniform = 0.0;     // c V if all volumes are equal, else 0
     double *scratch = nullptr;   // [n] per-node energies for diagnostics
     double *lps = nullptr;       // [n][2] {m, theta} (linear peridynamic solid)
-    double *lpsc = nullptr;      // [n][2] {a, d} of the solid's streamed steps
+    double *lpsc = nullptr;      // [n][2] {a, d} of the solid's streamed steps (float32 pairs in mixed precision)
     int64_t step = 0;
     int64_t ramp = 0;
     double last_dt = 0;

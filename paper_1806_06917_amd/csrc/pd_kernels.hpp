@@ -54,9 +54,13 @@ struct NodeArgs {
     int law, stretch;
     double beta;
     const double *__restrict__ u_lin;
-    // linear peridynamic solid: moduli and {m, theta} per node ([n][2], sfc)
+    // linear peridynamic solid: moduli and {m, theta} per node ([n][2], sfc);
+    // vol_uniform: V when every node has volume V and there are no partial
+    // volumes (the bond sums then leave V out and each node's sums are scaled
+    // by V once, as in the streamed kernel), else 0
     double bulk, shear;
     double *__restrict__ lps;
+    double vol_uniform;
     // partial volumes: band width h (0 = off) and the neighbour radius R
     double pv_h, pv_R;
     // influence function J = j_c1 r exp(-r^2/j_c2), r = |xi| j_idelta
@@ -322,15 +326,17 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
 }
 
 // Linear peridynamic solid: bond length |xi|, extension e = |xi+eta| - |xi|
-// in the cancellation-free form (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), and
-// 1/|xi+eta| (the direction M = (xi+eta)/|xi+eta|).
-// the extension (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), without contraction;
-// mixed precision divides through the hardware reciprocal estimate (relative
-// error below 2^-22, as its reciprocal square roots)
+// in the cancellation-free form (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), its
+// numerator taken as eta.(xi + (xi+eta)), and 1/|xi+eta| (the direction
+// M = (xi+eta)/|xi+eta|).  Mixed precision takes the reciprocal square roots
+// and the reciprocal of the denominator from the hardware estimates (relative
+// error below 2^-22).
+// e = num / (|xi+eta| + |xi|), |xi+eta| = y2 iy, without contraction (every
+// kernel rounds it alike)
 template <bool MIXED>
-__device__ __forceinline__ double lps_ext(double xe, double ee, double y2, double iy, double len) {
+__device__ __forceinline__ double lps_ext(double num, double y2, double iy, double len) {
 #pragma clang fp contract(off)
-    const double num = 2.0 * xe + ee, den = y2 * iy + len;
+    const double den = y2 * iy + len;
     return MIXED ? num * __builtin_amdgcn_rcp(den) : num / den;
 }
 
@@ -344,9 +350,8 @@ __device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, dou
     const double ix = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
     iy = MIXED ? __builtin_amdgcn_rsq(y2) : rsqrt_pos(y2);
     len = r2 * ix;
-    const double xe = dotf<3>(dxx, dxy, dxz, dux, duy, duz);
-    const double ee = dotf<3>(dux, duy, duz, dux, duy, duz);
-    e = lps_ext<MIXED>(xe, ee, y2, iy, len);
+    const double num = dotf<3>(dux, duy, duz, dxx + yx, dxy + yy, dxz + yz);
+    e = lps_ext<MIXED>(num, y2, iy, len);
 }
 
 // The solid's per-bond terms, shared by the gather and streamed kernels and
@@ -361,15 +366,21 @@ __device__ __forceinline__ void lps_state_terms(double len, double e, double Vj,
 // A node's coefficients in the bond force state, from its {m, theta}:
 // t_ij = (3 K theta_i / m_i) |xi| + (15 mu / m_i) (e - theta_i |xi| / 3)
 //      = a_i |xi| + d_i e  with  a_i = (3 K - 5 mu) theta_i / m_i,
-// d_i = 15 mu / m_i (both 0 where m_i = 0).
+// d_i = 15 mu / m_i (both 0 where m_i = 0); mixed precision rounds both to
+// float32 (the streamed force pass stages them so).
 struct LpsCoef {
     double a, d;
 };
+template <bool MIXED>
 __device__ __forceinline__ LpsCoef lps_coef(double m, double theta, double K, double mu) {
 #pragma clang fp contract(off)
     LpsCoef q;
     q.a = m > 0.0 ? (3.0 * K - 5.0 * mu) * theta / m : 0.0;
     q.d = m > 0.0 ? 15.0 * mu / m : 0.0;
+    if (MIXED) {
+        q.a = (double)(float)q.a;
+        q.d = (double)(float)q.d;
+    }
     return q;
 }
 // Force: the weight g of M = (xi+eta) in f_i, (t_ij + t_ji) V_j / |xi+eta|,

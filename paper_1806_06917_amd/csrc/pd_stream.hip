@@ -118,13 +118,23 @@ constexpr uint16_t BW_DEAD = 0x8000;
 
 inline __host__ __device__ uint32_t round4(uint32_t x) { return (x + 3u) & ~3u; }
 
+// the forms that stage the tile's velocities in LDS for the node update; the
+// solid's force pass reads them from global memory instead (its LDS goes to
+// the halo's coefficients), its state pass has no update
+__host__ __device__ constexpr bool v_staged(int form) {
+    return form == SK_LINEAR || form == SK_NP;
+}
+// bytes of the solid's coefficients {a, d} per node: float32 in mixed
+// precision, float64 otherwise
+__host__ __device__ constexpr uint32_t coef_bytes(int prec) { return prec == PD_MIXED ? 8u : 16u; }
+
 // LDS layout, in this order (every region a multiple of 16 bytes): the tile
 // slot (records, row offsets, v, boundary kinds), two halo-id slots, tile
 // metadata, and for the solid's force pass the halo's coefficients {a, d}.
 struct StreamLayout {
-    uint32_t H, T, TP, TB, MM, RD, US, SP;
+    uint32_t H, T, TP, VS, TB, MM, RD, US, SB;
     __host__ __device__ StreamLayout(int dim, uint32_t hcap, uint32_t tile, uint32_t mmax,
-                                     int form) {
+                                     int form, int prec) {
         H = hcap;                      // multiple of 32
         T = tile;
         TP = round4(tile + 1);         // row offsets
@@ -132,11 +142,12 @@ struct StreamLayout {
         MM = round4(mmax * META);
         RD = dim == 3 ? 6 : 4;         // doubles per record
         US = dim == 3 ? 4 : 2;         // doubles per node in v
-        SP = form == SK_LPS_FORCE ? 2 * hcap : 0u;   // doubles of staged {a, d}
+        VS = v_staged(form) ? tile * US : 0u;                        // doubles of v
+        SB = form == SK_LPS_FORCE ? hcap * coef_bytes(prec) : 0u;    // bytes of {a, d}
     }
     __host__ __device__ size_t bytes() const {
-        return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)TP * 4 + (size_t)T * US * 8 +
-               (size_t)TB * 4 + (size_t)MM * 4 + (size_t)SP * 8;
+        return (size_t)H * RD * 8 + (size_t)2 * H * 4 + (size_t)TP * 4 + (size_t)VS * 8 +
+               (size_t)TB * 4 + (size_t)MM * 4 + (size_t)SB;
     }
 };
 
@@ -162,7 +173,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     constexpr uint32_t RD = DIM == 3 ? 6 : 4, NCH = RD / 2, US = DIM == 3 ? 4 : 2;
     constexpr bool NP = FORM == SK_NP, LPS = FORM == SK_LPS_STATE || FORM == SK_LPS_FORCE;
     static_assert(!LPS || (DIM == 3 && !BATCH), "the solid: 3-d, single simulation");
-    const StreamLayout lay(DIM, sa.hcap, sa.tile, sa.mmax, FORM);
+    const StreamLayout lay(DIM, sa.hcap, sa.tile, sa.mmax, FORM, PREC);
     const uint32_t H = lay.H, T = lay.T;
     const uint32_t B = blockDim.x, tid = threadIdx.x, lane64 = tid & 63u;
     // first thread of this wave, in a scalar register: the copy loops below
@@ -171,10 +182,10 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     double *rec = lds;                                                           // H RD
     int32_t *ids = reinterpret_cast<int32_t *>(rec + (size_t)H * RD);            // 2 H
     uint32_t *rowp = reinterpret_cast<uint32_t *>(ids + (size_t)2 * H);          // TP
-    double *vbuf = reinterpret_cast<double *>(rowp + lay.TP);                    // T US
-    uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + (size_t)T * US);         // TB
+    double *vbuf = reinterpret_cast<double *>(rowp + lay.TP);                    // VS
+    uint32_t *bcb = reinterpret_cast<uint32_t *>(vbuf + lay.VS);                 // TB
     uint32_t *meta = bcb + lay.TB;                                               // MM
-    double *sps = reinterpret_cast<double *>(meta + lay.MM);                     // SP
+    char *sps = reinterpret_cast<char *>(meta + lay.MM);                         // SB
     const StreamInst *inst = sa.inst;
     const int64_t s = sa.step;                          // step of this launch in its chunk
     // the record buffer holding u at this step
@@ -253,8 +264,9 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rowp + c0));
             if (c0 + lane64 <= tn) dma4(rp, (t0 + c0 + lane64) * 4u, m0);
         }
-        // v and the boundary kinds feed the node update (not in the state pass)
-        const uint32_t nvc = FORM == SK_LPS_STATE ? 0u : tn * US / 2;
+        // v (where staged) and the boundary kinds feed the node update (not in
+        // the state pass)
+        const uint32_t nvc = v_staged(FORM) ? tn * US / 2 : 0u;
         for (uint32_t c0 = wbase; c0 < nvc; c0 += B) {
             const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(vbuf + 2 * (size_t)c0));
             if (c0 + lane64 < nvc) dma16(vv, (t0 * US + 2 * (c0 + lane64)) * 8u, m0);
@@ -265,12 +277,22 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             if (c0 + lane64 < nbw) dma4(bc, t0 + 4 * (c0 + lane64), m0);
         }
         if constexpr (FORM == SK_LPS_FORCE) {
-            // {a, d} of every halo node: one 16-byte copy each
+            // {a, d} of every halo node: one 16-byte copy each, or in mixed
+            // precision two 4-byte copies (the float32 pair)
             const void *ls = I.lps;
-            for (uint32_t c0 = wbase; c0 < hn; c0 += B) {
-                const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(sps + 2 * (size_t)c0));
-                const uint32_t c = c0 + lane64;
-                if (c < hn) dma16(ls, (uint32_t)hid[c] * 16u, m0);
+            if constexpr (MIXED) {
+                const uint32_t nsc = 2 * hn;
+                for (uint32_t c0 = wbase; c0 < nsc; c0 += B) {
+                    const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(sps + 4 * (size_t)c0));
+                    const uint32_t c = c0 + lane64;
+                    if (c < nsc) dma4(ls, (uint32_t)hid[c >> 1] * 8u + (c & 1u) * 4u, m0);
+                }
+            } else {
+                for (uint32_t c0 = wbase; c0 < hn; c0 += B) {
+                    const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(sps + 16 * (size_t)c0));
+                    const uint32_t c = c0 + lane64;
+                    if (c < hn) dma16(ls, (uint32_t)hid[c] * 16u, m0);
+                }
             }
         }
     };
@@ -298,6 +320,11 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
             const double uix = ri[DIM], uiy = ri[DIM + 1], uiz = DIM == 3 ? ri[DIM + 2] : 0.0;
             std::conditional_t<F32, AccC, Acc64> acc;
+            // the solid's force pass reads v from global memory, issued here so
+            // that its latency overlaps the bond loop's first word loads
+            double vg = 0.0;
+            if constexpr (FORM == SK_LPS_FORCE)
+                if (lane < (int)DIM) vg = I.v[(size_t)(t0 + q) * US + lane];
             const uint32_t rs = rowp[q] - b0, re = rowp[q + 1] - b0;
             // xi and eta of the bond whose word is w
             auto bond_vectors = [&](uint32_t w, double &dxx, double &dxy, double &dxz,
@@ -352,18 +379,25 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     lps_bond<MIXED>(bx, by, bz, bux, buy, buz, blen, be, biy);
                     if (!(wa & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        lps_state_terms(alen, ae, I.vol, m, sm);
+                        lps_state_terms(alen, ae, 1.0, m, sm);
                     }
                     if (hb && !(wb & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        lps_state_terms(blen, be, I.vol, m, sm);
+                        lps_state_terms(blen, be, 1.0, m, sm);
                     }
                 });
-                m = lane_sum<L>(m);
-                sm = lane_sum<L>(sm);
+                // the uniform volume V is left out of the bond terms and
+                // applied to each node's sums once
+                m = lane_sum<L>(m) * I.vol;
+                sm = lane_sum<L>(sm) * I.vol;
                 if (lane == 0) {
-                    const LpsCoef qc = lps_coef(m, m > 0.0 ? 3.0 / m * sm : 0.0, I.bulk, I.shear);
-                    reinterpret_cast<double2 *>(I.lps)[t0 + q] = make_double2(qc.a, qc.d);
+                    const LpsCoef qc =
+                        lps_coef<MIXED>(m, m > 0.0 ? 3.0 / m * sm : 0.0, I.bulk, I.shear);
+                    if constexpr (MIXED)
+                        reinterpret_cast<float2 *>(I.lps)[t0 + q] =
+                            make_float2((float)qc.a, (float)qc.d);
+                    else
+                        reinterpret_cast<double2 *>(I.lps)[t0 + q] = make_double2(qc.a, qc.d);
                 }
                 continue;
             } else if constexpr (FORM == SK_LPS_FORCE) {
@@ -371,10 +405,16 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 // scatter read from node i with {a, d} of both ends (a
                 // dead bond adds nothing there either: its weight is 0)
                 auto coef_of = [&](uint32_t j) {
-                    const double2 ad = *reinterpret_cast<const double2 *>(sps + 2 * (size_t)j);
                     LpsCoef r;
-                    r.a = ad.x;
-                    r.d = ad.y;
+                    if constexpr (MIXED) {
+                        const float2 ad = *reinterpret_cast<const float2 *>(sps + 8 * (size_t)j);
+                        r.a = ad.x;
+                        r.d = ad.y;
+                    } else {
+                        const double2 ad = *reinterpret_cast<const double2 *>(sps + 16 * (size_t)j);
+                        r.a = ad.x;
+                        r.d = ad.y;
+                    }
                     return r;
                 };
                 const LpsCoef qi = coef_of(so + q);
@@ -388,14 +428,14 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     const LpsCoef qa = coef_of(wa & 0x7fffu), qb = coef_of(wb & 0x7fffu);
                     if (!(wa & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        const double g = lps_force_weight(qi, qa, alen, ae, aiy, I.vol, true);
+                        const double g = lps_force_weight(qi, qa, alen, ae, aiy, 1.0, true);
                         acc.x = fma(g, ax + aux, acc.x);
                         acc.y = fma(g, ay + auy, acc.y);
                         acc.z = fma(g, az + auz, acc.z);
                     }
                     if (hb && !(wb & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        const double g = lps_force_weight(qi, qb, blen, be, biy, I.vol, true);
+                        const double g = lps_force_weight(qi, qb, blen, be, biy, 1.0, true);
                         acc.x = fma(g, bx + bux, acc.x);
                         acc.y = fma(g, by + buy, acc.y);
                         acc.z = fma(g, bz + buz, acc.z);
@@ -428,11 +468,17 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             double fx, fy, fz, Ue;
             if constexpr (F32) group_reduce_c<DIM, L, false>(acc, fx, fy, fz, Ue);
             else group_reduce<DIM, L, false>(acc, fx, fy, fz, Ue);
+            if constexpr (FORM == SK_LPS_FORCE) {
+                // the solid's weights left the uniform volume out
+                fx = fx * I.vol;
+                fy = fy * I.vol;
+                fz = fz * I.vol;
+            }
             if (lane < (int)DIM) {
                 const uint32_t d = (uint32_t)lane, i = t0 + q;
                 const double fd = d == 0 ? fx : (d == 1 ? fy : fz);
                 const double ud = ri[DIM + d];
-                double vd = vbuf[(size_t)q * US + d];
+                double vd = v_staged(FORM) ? vbuf[(size_t)q * US + d] : vg;
                 const int kind = (int)reinterpret_cast<const uint8_t *>(bcb)[q];
                 const double hdt = 0.5 * dt;
                 double nd;
@@ -570,7 +616,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
         unsigned g = (unsigned)ctx->num_cu;
         if (pass == 1) {
             int per_cu = 0;
-            const size_t bytes = StreamLayout(dim, hcap, tile, *mmax, form).bytes();
+            const size_t bytes = StreamLayout(dim, hcap, tile, *mmax, form, prec).bytes();
             (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k, (int)B,
                                                              bytes) != hipSuccess)
@@ -592,7 +638,7 @@ bool pd_stream_geometry(pd_ctx ctx, int dim, uint32_t ntiles, uint32_t tile, uin
             const uint32_t kk = (tc + gx - 1) / gx;
             if (kk > m) m = kk;
         }
-        const size_t bytes = StreamLayout(dim, hcap, tile, m, form).bytes();
+        const size_t bytes = StreamLayout(dim, hcap, tile, m, form, prec).bytes();
         if (bytes > 160 * 1024) return false;
         *mmax = m;
         *lds = bytes;
