@@ -79,18 +79,22 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel(NodeArgs a) {
                 load_vec<DIM>(a.u, j, ujx, ujy, ujz);
                 const double dxx = xj.x - xix, dxy = xj.y - xiy, dxz = xj.z - xiz;
                 const double dux = ujx - uix, duy = ujy - uiy, duz = ujz - uiz;
-                double len, e, iy;
-                lps_bond<MIXED>(dxx, dxy, dxz, dux, duy, duz, len, e, iy);
+                double r2, qb, w;
+                lps_terms<MIXED>(dxx, dxy, dxz, dux, duy, duz, r2, qb, w);
                 const double2 sj = reinterpret_cast<const double2 *>(a.lps)[j];
                 const LpsCoef qj = lps_coef<MIXED>(sj.x, sj.y, a.bulk, a.shear);
+                // |xi| for partial volumes and the energy only
+                const double len = (a.pv_h > 0.0 || WANT_E) ? lps_len<MIXED>(r2) : 0.0;
                 const double Vj =
                     a.vol_uniform > 0.0 ? 1.0 : xj.w * pv_weight(len, a.pv_R, a.pv_h);
-                const double g = lps_force_weight(qi, qj, len, e, iy, Vj, live);
-                const double edi = e - hi * len;
+                const double g = lps_force_weight(qi, qj, r2, qb, w, Vj, live);
                 s64.x = fma(g, dxx + dux, s64.x);
                 s64.y = fma(g, dxy + duy, s64.y);
                 s64.z = fma(g, dxz + duz, s64.z);
-                if (WANT_E) s64.e += live ? edi * edi * Vj : 0.0;
+                if (WANT_E) {
+                    const double edi = w / len - hi * len;    // e - theta_i |xi| / 3
+                    s64.e += live ? edi * edi * Vj : 0.0;
+                }
             }
         } else {
             // general law; the tangent's linearisation point, if any
@@ -197,11 +201,14 @@ __global__ __launch_bounds__(PD_BLOCK) void lps_state_k(NodeArgs a) {
             const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
             double ujx, ujy, ujz;
             load_vec<3>(a.u, j, ujx, ujy, ujz);
-            double len, e, iy;
-            lps_bond<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
-                            ujz - uiz, len, e, iy);
-            const double Vj = a.vol_uniform > 0.0 ? 1.0 : xj.w * pv_weight(len, a.pv_R, a.pv_h);
-            lps_state_terms(len, e, Vj, m, s);
+            double r2, qb, w;
+            lps_terms<MIXED>(xj.x - q.x, xj.y - q.y, xj.z - q.z, ujx - uix, ujy - uiy,
+                             ujz - uiz, r2, qb, w);
+            const double Vj = a.vol_uniform > 0.0
+                                  ? 1.0
+                                  : xj.w * pv_weight(a.pv_h > 0.0 ? lps_len<MIXED>(r2) : 0.0,
+                                                     a.pv_R, a.pv_h);
+            lps_state_terms(r2, w, Vj, m, s);
         }
     }
     m = lane_sum<L>(m);

@@ -325,43 +325,52 @@ __device__ __forceinline__ bool bond_law(int law, int stretch, double beta, int 
     return brk && !dead;
 }
 
-// Linear peridynamic solid: bond length |xi|, extension e = |xi+eta| - |xi|
-// in the cancellation-free form (2 xi.eta + eta.eta)/(|xi+eta| + |xi|), its
-// numerator taken as eta.(xi + (xi+eta)), and 1/|xi+eta| (the direction
-// M = (xi+eta)/|xi+eta|).  Mixed precision takes the reciprocal square roots
-// and the reciprocal of the denominator from the hardware estimates (relative
-// error below 2^-22).
-// e = num / (|xi+eta| + |xi|), |xi+eta| = y2 iy, without contraction (every
-// kernel rounds it alike)
+// Linear peridynamic solid, per bond, written so that it needs one
+// reciprocal square root and one reciprocal (y = xi + eta):
+//   r2 = |xi|^2,
+//   q  = 1 / (|xi| |y|) = rsqrt(r2 |y|^2),
+//   w  = |xi| e with the extension e = |y| - |xi| in the cancellation-free
+//        form (|y|^2 - |xi|^2)/(|y| + |xi|): w = num / (1 + |y|^2 q), where
+//        num = |y|^2 - |xi|^2 = eta.(xi + y) and |y|^2 q = |y|/|xi|.
+// The state pass sums |xi|^2 = r2 and |xi| e = w; the force pass's weight
+// t / |y| = (A |xi| + D e) / |y| is q (A r2 + D w) (|xi|/|y| = r2 q,
+// e/|y| = w q).  Mixed precision takes both from the hardware estimates
+// (relative error below 2^-22); the denominator is formed without
+// contraction (every kernel rounds it alike).
 template <bool MIXED>
-__device__ __forceinline__ double lps_ext(double num, double y2, double iy, double len) {
+__device__ __forceinline__ double lps_w(double num, double y2, double q) {
 #pragma clang fp contract(off)
-    const double den = y2 * iy + len;
+    const double den = y2 * q + 1.0;
     return MIXED ? num * __builtin_amdgcn_rcp(den) : num / den;
 }
 
 template <bool MIXED>
-__device__ __forceinline__ void lps_bond(double dxx, double dxy, double dxz, double dux,
-                                         double duy, double duz, double &len, double &e,
-                                         double &iy) {
-    const double r2 = dotf<3>(dxx, dxy, dxz, dxx, dxy, dxz);
+__device__ __forceinline__ void lps_terms(double dxx, double dxy, double dxz, double dux,
+                                          double duy, double duz, double &r2, double &q,
+                                          double &w) {
+    r2 = dotf<3>(dxx, dxy, dxz, dxx, dxy, dxz);
     const double yx = dxx + dux, yy = dxy + duy, yz = dxz + duz;
     const double y2 = dotf<3>(yx, yy, yz, yx, yy, yz);
-    const double ix = MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2);
-    iy = MIXED ? __builtin_amdgcn_rsq(y2) : rsqrt_pos(y2);
-    len = r2 * ix;
+    const double r2y2 = r2 * y2;
+    q = MIXED ? __builtin_amdgcn_rsq(r2y2) : rsqrt_pos(r2y2);
     const double num = dotf<3>(dux, duy, duz, dxx + yx, dxy + yy, dxz + yz);
-    e = lps_ext<MIXED>(num, y2, iy, len);
+    w = lps_w<MIXED>(num, y2, q);
+}
+
+// |xi| from r2 (partial volumes, the energy)
+template <bool MIXED>
+__device__ __forceinline__ double lps_len(double r2) {
+    return r2 * (MIXED ? __builtin_amdgcn_rsq(r2) : rsqrt_pos(r2));
 }
 
 // The solid's per-bond terms, shared by the gather and streamed kernels and
 // written without contraction, so that both round every bond alike.
 // First pass: m += |xi|^2 V_j, s += |xi| e V_j.
-__device__ __forceinline__ void lps_state_terms(double len, double e, double Vj, double &m,
+__device__ __forceinline__ void lps_state_terms(double r2, double w, double Vj, double &m,
                                                 double &s) {
 #pragma clang fp contract(off)
-    m += len * len * Vj;
-    s += len * e * Vj;
+    m += r2 * Vj;
+    s += w * Vj;
 }
 // A node's coefficients in the bond force state, from its {m, theta}:
 // t_ij = (3 K theta_i / m_i) |xi| + (15 mu / m_i) (e - theta_i |xi| / 3)
@@ -383,14 +392,15 @@ __device__ __forceinline__ LpsCoef lps_coef(double m, double theta, double K, do
     }
     return q;
 }
-// Force: the weight g of M = (xi+eta) in f_i, (t_ij + t_ji) V_j / |xi+eta|,
-// from the coefficients of both ends and the bond's |xi|, e.
+// Force: the weight g of M = (xi+eta) in f_i, (t_ij + t_ji) V_j / |xi+eta|
+// = q ((a_i + a_j) r2 + (d_i + d_j) w) V_j, from the coefficients of both
+// ends and the bond's r2, q, w (lps_terms).
 __device__ __forceinline__ double lps_force_weight(const LpsCoef &qi, const LpsCoef &qj,
-                                                   double len, double e, double iy, double Vj,
+                                                   double r2, double q, double w, double Vj,
                                                    bool live) {
 #pragma clang fp contract(off)
-    const double t = (qi.a + qj.a) * len + (qi.d + qj.d) * e;
-    return live ? t * Vj * iy : 0.0;
+    const double t = (qi.a + qj.a) * r2 + (qi.d + qj.d) * w;
+    return live ? t * q * Vj : 0.0;
 }
 
 // A double moved across lanes by a DPP pattern (both 32-bit halves).

@@ -371,19 +371,19 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 // live bonds (uniform V_j), in the same order
                 double m = 0.0, sm = 0.0;
                 run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
-                    double ax, ay, az, aux, auy, auz, alen, ae, aiy;
-                    double bx, by, bz, bux, buy, buz, blen, be, biy;
+                    double ax, ay, az, aux, auy, auz, ar2, aq, aw;
+                    double bx, by, bz, bux, buy, buz, br2, bq, bw;
                     bond_vectors(wa, ax, ay, az, aux, auy, auz);
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
-                    lps_bond<MIXED>(ax, ay, az, aux, auy, auz, alen, ae, aiy);
-                    lps_bond<MIXED>(bx, by, bz, bux, buy, buz, blen, be, biy);
                     if (!(wa & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        lps_state_terms(alen, ae, 1.0, m, sm);
+                        lps_terms<MIXED>(ax, ay, az, aux, auy, auz, ar2, aq, aw);
+                        lps_state_terms(ar2, aw, 1.0, m, sm);
                     }
                     if (hb && !(wb & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        lps_state_terms(blen, be, 1.0, m, sm);
+                        lps_terms<MIXED>(bx, by, bz, bux, buy, buz, br2, bq, bw);
+                        lps_state_terms(br2, bw, 1.0, m, sm);
                     }
                 });
                 // the uniform volume V is left out of the bond terms and
@@ -419,23 +419,23 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 };
                 const LpsCoef qi = coef_of(so + q);
                 run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
-                    double ax, ay, az, aux, auy, auz, alen, ae, aiy;
-                    double bx, by, bz, bux, buy, buz, blen, be, biy;
+                    double ax, ay, az, aux, auy, auz, ar2, aq, aw;
+                    double bx, by, bz, bux, buy, buz, br2, bq, bw;
                     bond_vectors(wa, ax, ay, az, aux, auy, auz);
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
-                    lps_bond<MIXED>(ax, ay, az, aux, auy, auz, alen, ae, aiy);
-                    lps_bond<MIXED>(bx, by, bz, bux, buy, buz, blen, be, biy);
+                    lps_terms<MIXED>(ax, ay, az, aux, auy, auz, ar2, aq, aw);
+                    lps_terms<MIXED>(bx, by, bz, bux, buy, buz, br2, bq, bw);
                     const LpsCoef qa = coef_of(wa & 0x7fffu), qb = coef_of(wb & 0x7fffu);
                     if (!(wa & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        const double g = lps_force_weight(qi, qa, alen, ae, aiy, 1.0, true);
+                        const double g = lps_force_weight(qi, qa, ar2, aq, aw, 1.0, true);
                         acc.x = fma(g, ax + aux, acc.x);
                         acc.y = fma(g, ay + auy, acc.y);
                         acc.z = fma(g, az + auz, acc.z);
                     }
                     if (hb && !(wb & BW_DEAD)) {
                         asm volatile("" ::: "memory");
-                        const double g = lps_force_weight(qi, qb, blen, be, biy, 1.0, true);
+                        const double g = lps_force_weight(qi, qb, br2, bq, bw, 1.0, true);
                         acc.x = fma(g, bx + bux, acc.x);
                         acc.y = fma(g, by + buy, acc.y);
                         acc.z = fma(g, bz + buz, acc.z);
