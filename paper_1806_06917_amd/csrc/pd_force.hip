@@ -710,6 +710,8 @@ static void sim_release(pd_sim s) {
     pd_ctx_unref(ctx);
 }
 
+static int lps_mass(pd_sim s);
+
 extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const double *X,
                              const double *V, const double *u0, const double *v0,
                              const uint8_t *bc_kind, const double *bc_vel, const double *b,
@@ -885,6 +887,7 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     }
     if (st == PD_OK && ctx->kernel == 3 && !s->stream)
         st = pd_set_error(ctx, PD_ECAPACITY, "the streamed kernel cannot run this simulation");
+    if (st == PD_OK && s->stream && s->s_form == SK_LPS_FORCE) st = lps_mass(s);
     if (st == PD_OK) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "sim_create", __FILE__, __LINE__);
@@ -895,6 +898,18 @@ extern "C" int pd_sim_create(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, con
     }
     *out = s;
     return PD_OK;
+}
+
+static NodeArgs sim_args(pd_sim s);
+
+// The solid's weighted volume m per node, fixed while the bond flags are (the
+// solid takes no damage): the gather kernel's state pass at the current u
+// leaves {m, theta} in s->lps, whose m the streamed state pass reads.  Run
+// whenever the flags are set (creation, pd_sim_set).
+static int lps_mass(pd_sim s) {
+    NodeArgs a = sim_args(s);
+    a.u = s->u[s->cur];
+    return launch_lps_state(s->ctx, a, s->lanes, s->mat.precision == PD_MIXED);
 }
 
 static NodeArgs sim_args(pd_sim s) {
@@ -937,6 +952,7 @@ StreamInst pd_stream_inst(const pd_sim s) {
     d.damage = s->mat.s_c > 0.0;
     d.beta = s->mat.beta;
     d.lps = s->lpsc;
+    d.lpsm = s->lps;
     d.vol = s->vol_uniform;
     d.bulk = s->mat.bulk;
     d.shear = s->mat.shear;
@@ -1173,6 +1189,7 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
     if (alive) {
         PD_TRY(pd_alive_in(ctx, sim->nbr, alive, sim->alive));
         if (sim->tiled) PD_TRY(pd_bw_compose(ctx, sim->nbr, sim->alive, sim->bw));
+        if (sim->stream && sim->s_form == SK_LPS_FORCE) PD_TRY(lps_mass(sim));
     }
     sim->step = step;
     return PD_OK;

@@ -597,6 +597,7 @@ struct StreamInst {
     double cv, s_c, rho, dt;
     double beta;                // NP law (launches of the NP kernel only)
     double *lps;                // the solid: [n] {a, d} (lps_coef) from its state pass
+    const double *lpsm;         // the solid: [n][2] {m, .}: m per node, fixed with the bonds
     double vol, bulk, shear;    // the solid: the (uniform) nodal volume and the moduli
     int damage, cur0, vhalf0;
     int cd;                     // central-difference steps after the chunk's first (Verlet) step

@@ -367,9 +367,12 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                 }
             };
             if constexpr (FORM == SK_LPS_STATE) {
-                // the solid's first pass, as lps_state_k: m_i and theta_i over
-                // live bonds (uniform V_j), in the same order
-                double m = 0.0, sm = 0.0;
+                // the solid's first pass, as lps_state_k: theta_i over live
+                // bonds (uniform V_j), in the same order; m_i is fixed while
+                // the bonds are (the solid takes no damage) and comes from the
+                // gather kernel's state pass, run when the bonds were set
+                const double m = lane == 0 ? I.lpsm[2 * (size_t)(t0 + q)] : 0.0;
+                double sm = 0.0;
                 run_pairs([&](uint32_t wa, uint32_t wb, bool hb) {
                     double ax, ay, az, aux, auy, auz, ar2, aq, aw;
                     double bx, by, bz, bux, buy, buz, br2, bq, bw;
@@ -378,17 +381,16 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     if (!(wa & BW_DEAD)) {
                         asm volatile("" ::: "memory");
                         lps_terms<MIXED>(ax, ay, az, aux, auy, auz, ar2, aq, aw);
-                        lps_state_terms(ar2, aw, 1.0, m, sm);
+                        sm += aw;
                     }
                     if (hb && !(wb & BW_DEAD)) {
                         asm volatile("" ::: "memory");
                         lps_terms<MIXED>(bx, by, bz, bux, buy, buz, br2, bq, bw);
-                        lps_state_terms(br2, bw, 1.0, m, sm);
+                        sm += bw;
                     }
                 });
                 // the uniform volume V is left out of the bond terms and
                 // applied to each node's sums once
-                m = lane_sum<L>(m) * I.vol;
                 sm = lane_sum<L>(sm) * I.vol;
                 if (lane == 0) {
                     const LpsCoef qc =

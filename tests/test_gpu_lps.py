@@ -221,3 +221,52 @@ def test_lps_streamed_full_size_steps(gpu, orc, prec):
     tol = TOL64 if prec == "fp64" else TOLMIX
     assert relL2(u, st["u"]) <= tol
     assert relL2(v, st["v"]) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lps_streamed_flags_set(gpu, orc, prec):
+    """Bond flags set on a running solid (pd_sim_set): the streamed steps take
+    the weighted volumes m of the new flags (m is kept per node while the bonds
+    are fixed), bit for bit as the gather kernel, and match the oracle
+    restarted from the same state with those flags."""
+    torch, pd, ctx = gpu
+    N = 12
+    h = 1.0 / N
+    X = inputs.grid_coords((N,) * 3, h, jitter=0.05, seed=211)
+    n = len(X)
+    V = np.full(n, h ** 3)
+    K, mu = orc.lps_moduli(1.0, 0.3)
+    v0 = inputs.random_field(n, 3, 212, scale=1e-2)
+    dt = 0.02 * h
+    mesh = orc.LpsMesh(X, V, 3 * h)
+    cut = symmetric_dead(mesh, 0.08, 213)
+    out = []
+    for kern in ("stream", "gather"):
+        say("LPS flags set", kern, prec)
+        ctx.set_tuning(kern, 0, 0)
+        try:
+            nb = pd.Neighbors(ctx, dev(torch, X), 3 * h)
+            mat = pd.material(3, 0.0, 1.0, 0.0, prec, law="lps", bulk=K, shear=mu)
+            sim = pd.Simulation(ctx, nb, mat, dev(torch, X), dev(torch, V), None,
+                                dev(torch, v0))
+            assert sim.info()["kernel"] == kern
+            sim.step(10, dt)
+            u10, v10, a10, _ = read_state(torch, sim, n, 3, nb.nnz)
+            assert a10.all()
+            sim.set(u=dev(torch, u10), v=dev(torch, v10), alive=dev(torch, cut), step=10)
+            sim.step(15, dt)
+            u, v, a, info = read_state(torch, sim, n, 3, nb.nnz)
+            assert info["step"] == 25 and np.array_equal(a, cut)
+            out.append((u10, v10, u, v))
+            sim.close()
+            nb.close()
+        finally:
+            ctx.set_tuning(0, 0, 0)
+    for x, y in zip(out[0], out[1]):
+        assert np.array_equal(x, y)
+    u10, v10, u, v = out[0]
+    st = mesh.start_lps(u10, v10, K, mu, alive=cut)
+    mesh.verlet_lps(st, K, mu, 1.0, dt, 15)
+    tol = TOL64 if prec == "fp64" else TOLMIX
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
