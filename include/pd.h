@@ -449,7 +449,9 @@ int pd_batch_destroy(pd_batch b);
  *   referenced after the call returns.
  * pd_server_pump runs one scheduling round and returns when it is done
  *   (synchronises): admits queued requests in arrival order while the head's
- *   device-memory estimate fits the free budget; a request whose built size
+ *   device-memory estimate fits the free budget (while simulations run, this
+ *   happens during their chunk, on a stream of the server's own, and the
+ *   requests admitted then join at the next round); a request whose built size
  *   (known after its neighbour list is built) does not fit after all is freed
  *   and waits at the head with that size, so the charged bytes never exceed
  *   hbm_budget (continuous batching:
@@ -511,6 +513,7 @@ typedef struct {
     int64_t admitted;
     int64_t launches;   /* batched chunks */
     int64_t replays;    /* of them, replays of a captured graph */
+    double admit_overlap_s; /* of admit_s, the part spent while a chunk ran */
 } pd_server_stats;
 
 double pd_server_clock(void);

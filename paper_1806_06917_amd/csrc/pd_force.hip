@@ -1195,6 +1195,21 @@ extern "C" int pd_sim_set(pd_sim sim, const double *u, const double *v, const ui
     return PD_OK;
 }
 
+int pd_sim_rehome(pd_sim s, pd_ctx to) {
+    const pd_ctx from = s->ctx;
+    const pd_nbr nb = s->nbr;
+    if (from == to) return PD_OK;
+    if (from->device != to->device || nb->ctx != from || nb->refs != 1 || nb->users > 1)
+        return pd_set_error(to, PD_EINVAL, "the simulation cannot move to this context");
+    PD_HIP(from, hipStreamSynchronize(from->stream));
+    pd_mem_restream(from->stream, to->stream, from->red, from->flag);
+    s->ctx = to;
+    nb->ctx = to;
+    from->refs -= 2;
+    to->refs += 2;
+    return PD_OK;
+}
+
 extern "C" int pd_sim_info(pd_sim sim, int *kernel, int *tile, int *block, int *lanes) {
     if (!sim) return PD_EINVAL;
     if (kernel) *kernel = sim->stream ? 3 : (sim->tiled && sim->block > 0 ? 2 : 1);

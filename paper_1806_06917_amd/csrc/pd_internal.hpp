@@ -147,23 +147,30 @@ int pd_hip_error(pd_ctx ctx, hipError_t e, const char *what, const char *file, i
 
 #define PD_LAUNCH_CHECK(ctx) PD_HIP(ctx, hipGetLastError())
 
+// Device memory of the library's own buffers, through a per-device cache
+// (pd_runtime.hip): a freed block is kept and handed out again once the work
+// queued on its owner's stream before the free has completed.
+int pd_alloc_bytes(pd_ctx ctx, void **p, size_t bytes);
+void pd_free_bytes(void *p);
+// the live blocks owned by stream `from` (except keep1, keep2) now belong to
+// stream `to`: their frees wait for the work queued there
+void pd_mem_restream(hipStream_t from, hipStream_t to, const void *keep1, const void *keep2);
+// moves an idle simulation and its neighbour list (used by no other
+// simulation) to another context of the same device (pd_force.hip)
+int pd_sim_rehome(pd_sim s, pd_ctx to);
+
 template <class T>
 int pd_alloc(pd_ctx ctx, T **p, size_t count) {
-    *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return pd_set_error(ctx, PD_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
-                            hipGetErrorString(e));
-    }
-    return PD_OK;
+    void *q = nullptr;
+    const int st = pd_alloc_bytes(ctx, &q, count * sizeof(T));
+    *p = (T *)q;
+    return st;
 }
 
 template <class T>
 void pd_free(T *&p) {
-    if (p) (void)hipFree((void *)p);
+    if (p) pd_free_bytes((void *)p);
     p = nullptr;
 }
 

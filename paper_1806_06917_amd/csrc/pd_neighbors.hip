@@ -414,7 +414,9 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     PD_TRY(pd_flag_read(ctx, &flag));
     if (flag & FLAG_COINCIDENT) return pd_set_error(ctx, PD_EINVAL, "two nodes coincide");
     uint64_t nnz = 0;
-    PD_HIP(ctx, hipMemcpy(&nnz, t.scan + n, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    PD_HIP(ctx, hipMemcpyAsync(&nnz, t.scan + n, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (nnz > 0xffffffffull)
         return pd_set_error(ctx, PD_ECAPACITY, "%llu bonds exceed the 2^32-1 limit",
                             (unsigned long long)nnz);

@@ -3,9 +3,152 @@
 // reordering and deterministic reductions.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "pd_internal.hpp"
+
+// ---------------------------------------------------------------------------
+// device memory cache
+// ---------------------------------------------------------------------------
+// hipMalloc and hipFree cost tens of microseconds each and hipFree waits for
+// the whole device, while a serving loop builds and drops simulations (a
+// dozen buffers each) all the time.  So a freed block is kept per device and
+// handed out again.  A block is freed on the stream of the context that
+// allocated it: an event recorded there at the free marks the end of its
+// last use, and the block is handed out again only after that event has
+// completed (the host waits for it if it has not), so no later work on any
+// stream can overlap an earlier user.  Sizes round up to 256 bytes (64 KiB
+// from 1 MiB on); a request takes the smallest cached block of at least its
+// size and at most an eighth more.  At most PD_CACHE_MAX bytes stay cached;
+// when hipMalloc fails the device's cache is released and the call retried.
+namespace {
+
+constexpr size_t PD_CACHE_MAX = size_t(16) << 30;
+
+struct CachedBlock {
+    void *p;
+    hipEvent_t done;   // recorded at the free on the owner's stream
+};
+struct LiveBlock {
+    size_t bytes;
+    int device;
+    hipStream_t stream;
+};
+struct DeviceCache {
+    std::multimap<size_t, CachedBlock> free;
+    size_t bytes = 0;
+    std::vector<hipEvent_t> events;   // idle events for reuse
+};
+
+std::mutex g_mem_mu;
+std::unordered_map<void *, LiveBlock> g_live;
+std::map<int, DeviceCache> g_cache;
+
+size_t round_bytes(size_t b) {
+    const size_t q = b < (size_t(1) << 20) ? 256 : (size_t(64) << 10);
+    return (b + q - 1) / q * q;
+}
+
+// every cached block of a device back to the driver (device current)
+void release_cache(DeviceCache &c) {
+    for (auto &kv : c.free) {
+        (void)hipEventSynchronize(kv.second.done);
+        (void)hipEventDestroy(kv.second.done);
+        (void)hipFree(kv.second.p);
+    }
+    c.free.clear();
+    c.bytes = 0;
+}
+
+}  // namespace
+
+int pd_alloc_bytes(pd_ctx ctx, void **p, size_t bytes) {
+    *p = nullptr;
+    bytes = round_bytes(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    DeviceCache &c = g_cache[dev];
+    auto it = c.free.lower_bound(bytes);
+    if (it != c.free.end() && it->first <= bytes + bytes / 8) {
+        CachedBlock b = it->second;
+        const size_t have = it->first;
+        c.free.erase(it);
+        c.bytes -= have;
+        if (hipEventQuery(b.done) != hipSuccess) (void)hipEventSynchronize(b.done);
+        (void)hipGetLastError();
+        c.events.push_back(b.done);
+        *p = b.p;
+        g_live[b.p] = LiveBlock{have, dev, ctx ? ctx->stream : nullptr};
+        return PD_OK;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess && !c.free.empty()) {
+        (void)hipGetLastError();
+        release_cache(c);
+        e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return pd_set_error(ctx, PD_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes,
+                            hipGetErrorString(e));
+    }
+    g_live[*p] = LiveBlock{bytes, dev, ctx ? ctx->stream : nullptr};
+    return PD_OK;
+}
+
+void pd_mem_restream(hipStream_t from, hipStream_t to, const void *keep1, const void *keep2) {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    for (auto &kv : g_live)
+        if (kv.second.stream == from && kv.first != keep1 && kv.first != keep2)
+            kv.second.stream = to;
+}
+
+void pd_free_bytes(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    const LiveBlock lb = it->second;
+    g_live.erase(it);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != lb.device) (void)hipSetDevice(lb.device);
+    DeviceCache &c = g_cache[lb.device];
+    hipEvent_t ev = nullptr;
+    if (!c.events.empty()) {
+        ev = c.events.back();
+        c.events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+    }
+    if (ev && hipEventRecord(ev, lb.stream) == hipSuccess) {
+        c.free.emplace(lb.bytes, CachedBlock{p, ev});
+        c.bytes += lb.bytes;
+        // over the cap: the largest cached blocks go back to the driver
+        while (c.bytes > PD_CACHE_MAX && !c.free.empty()) {
+            auto last = std::prev(c.free.end());
+            (void)hipEventSynchronize(last->second.done);
+            c.events.push_back(last->second.done);
+            (void)hipFree(last->second.p);
+            c.bytes -= last->first;
+            c.free.erase(last);
+        }
+    } else {
+        // no event (or the owner's stream is gone): give it back at once
+        (void)hipGetLastError();
+        if (ev) c.events.push_back(ev);
+        (void)hipFree(p);
+    }
+    if (cur != lb.device) (void)hipSetDevice(cur);
+}
 
 // ---------------------------------------------------------------------------
 // errors

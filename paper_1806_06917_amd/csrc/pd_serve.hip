@@ -89,6 +89,10 @@ struct Group {
 
 struct pd_server_s {
     pd_ctx ctx = nullptr;
+    // requests admitted while a chunk runs are built on a context of their
+    // own (its own stream, reduction and status buffers), then moved to ctx
+    pd_ctx actx = nullptr;
+    hipStream_t astream = nullptr;
     int64_t budget = 0, used = 0, peak = 0;
     int64_t chunk = 100;
     int lanes = 0;
@@ -118,6 +122,15 @@ extern "C" int pd_server_create(pd_ctx ctx, int64_t hbm_budget, int64_t chunk_st
     s->budget = hbm_budget;
     s->chunk = chunk_steps;
     s->lanes = lanes;
+    // without a second stream admission simply runs between chunks
+    if (hipStreamCreateWithFlags(&s->astream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        s->astream = nullptr;
+    } else if (pd_ctx_create(ctx->device, (void *)s->astream, &s->actx) != PD_OK) {
+        s->actx = nullptr;
+        (void)hipStreamDestroy(s->astream);
+        s->astream = nullptr;
+    }
     *out = s;
     return PD_OK;
 }
@@ -138,6 +151,8 @@ extern "C" int pd_server_destroy(pd_server s) {
     for (Req *r : s->running) release_device(s, r);
     for (auto &kv : s->all) delete kv.second;
     for (auto &kv : s->groups) pd_batch_destroy(kv.second.batch);
+    if (s->actx) pd_ctx_destroy(s->actx);
+    if (s->astream) (void)hipStreamDestroy(s->astream);
     delete s;
     pd_ctx_unref(ctx);
     return PD_OK;
@@ -191,9 +206,11 @@ extern "C" int pd_server_submit(pd_server s, const pd_request *q, int64_t *id) {
     return PD_OK;
 }
 
-// builds the request's neighbour list and simulation on the device
-static int admit(pd_server s, Req *r) {
-    pd_ctx ctx = s->ctx;
+// builds the request's neighbour list and simulation on the device, on
+// context bctx (the server's own or its admission context; the simulation
+// ends up on the server's)
+static int admit(pd_server s, Req *r, pd_ctx bctx) {
+    pd_ctx ctx = bctx;
     const size_t n = (size_t)r->n, nd = n * r->dim;
     double *X = nullptr, *V = nullptr, *u0 = nullptr, *v0 = nullptr, *bv = nullptr;
     uint8_t *bk = nullptr;
@@ -205,7 +222,7 @@ static int admit(pd_server s, Req *r) {
     if (st == PD_OK && !r->bc_kind.empty()) st = pd_alloc(ctx, &bv, nd);
     auto up = [&](void *d, const void *h, size_t bytes) {
         if (st != PD_OK || !d) return;
-        const hipError_t e = hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+        const hipError_t e = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, ctx->stream);
         if (e != hipSuccess) st = pd_hip_error(ctx, e, "request upload", __FILE__, __LINE__);
     };
     up(X, r->X.data(), nd * 8);
@@ -214,6 +231,14 @@ static int admit(pd_server s, Req *r) {
     up(v0, r->v0.data(), nd * 8);
     up(bk, r->bc_kind.data(), n);
     up(bv, r->bc_vel.data(), nd * 8);
+    if (ctx != s->ctx) {
+        // the server context's launch choices and tuning results
+        ctx->kernel = s->ctx->kernel;
+        ctx->tile = s->ctx->tile;
+        ctx->block = s->ctx->block;
+        ctx->lanes = s->ctx->lanes;
+        ctx->tuned = s->ctx->tuned;
+    }
     const int saved = ctx->lanes;
     if (s->lanes) ctx->lanes = s->lanes;
     if (st == PD_OK) st = pd_build_neighbors(ctx, r->dim, r->n, X, r->delta, &r->nbr);
@@ -231,6 +256,8 @@ static int admit(pd_server s, Req *r) {
     pd_free(v0);
     pd_free(bk);
     pd_free(bv);
+    // built on the admission context: the simulation moves to the server's
+    if (st == PD_OK && ctx != s->ctx) st = pd_sim_rehome(r->sim, s->ctx);
     if (st != PD_OK) {
         if (r->sim) pd_sim_destroy(r->sim);
         if (r->nbr) pd_nbr_destroy(r->nbr);
@@ -260,8 +287,12 @@ static int retire(pd_server s, Req *r) {
         if (st == PD_OK) {
             r->u_out.resize(nd);
             r->v_out.resize(nd);
-            hipError_t e = hipMemcpy(r->u_out.data(), u, nd * 8, hipMemcpyDeviceToHost);
-            if (e == hipSuccess) e = hipMemcpy(r->v_out.data(), v, nd * 8, hipMemcpyDeviceToHost);
+            hipError_t e = hipMemcpyAsync(r->u_out.data(), u, nd * 8, hipMemcpyDeviceToHost,
+                                          ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->v_out.data(), v, nd * 8, hipMemcpyDeviceToHost,
+                                   ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) st = pd_hip_error(ctx, e, "result download", __FILE__, __LINE__);
         }
         pd_free(u);
@@ -274,11 +305,9 @@ static int retire(pd_server s, Req *r) {
     return st;
 }
 
-extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
-    if (!s) return PD_EINVAL;
-    pd_ctx ctx = s->ctx;
-    PD_TRY(pd_check_ctx(ctx));
-    // admission in arrival order while the head fits the budget
+// admission in arrival order while the head fits the budget, on context
+// bctx; returns a device error (the context is unusable), else PD_OK
+static int admit_queued(pd_server s, pd_ctx bctx, bool overlapped) {
     while (!s->queue.empty()) {
         Req *r = s->queue.front();
         if (r->estimate > s->budget) {   // can never fit
@@ -291,8 +320,10 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         if (s->used + r->estimate > s->budget) break;
         s->queue.pop_front();
         const double ta = now_s();
-        const int st = admit(s, r);
-        s->stats.admit_s += now_s() - ta;
+        const int st = admit(s, r, bctx);
+        const double dt = now_s() - ta;
+        s->stats.admit_s += dt;
+        if (overlapped) s->stats.admit_overlap_s += dt;
         if (st != PD_OK) {
             r->info.state = PD_REQ_FAILED;
             r->info.status = st;
@@ -326,6 +357,16 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         r->info.state = PD_REQ_RUNNING;
         s->running.push_back(r);
     }
+    return PD_OK;
+}
+
+extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
+    if (!s) return PD_EINVAL;
+    pd_ctx ctx = s->ctx;
+    PD_TRY(pd_check_ctx(ctx));
+    // with nothing running the device is idle: admit first, on the server's
+    // own context, so that the new requests take this round's chunk
+    if (s->running.empty()) PD_TRY(admit_queued(s, ctx, false));
     // one chunk for every running simulation: one batched launch per step
     // for each group that can share the streamed kernel, single launches for
     // the rest
@@ -337,6 +378,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
     };
     std::map<GroupKey, Chunk> chunks;
     const double t_step = now_s();
+    const size_t stepping = s->running.size();
     for (Req *r : s->running) {
         const int64_t k = std::min(s->chunk, r->nsteps - r->done);
         if (k <= 0) continue;
@@ -366,15 +408,24 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
         g.last_sims = c.sims;
         g.last_nsteps = c.nsteps;
     }
-    if (!s->running.empty()) PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    s->stats.step_s += now_s() - t_step;
+    // while the chunk runs, admit on the admission context (the requests
+    // join at the next round); without one, after the chunk
+    double t_adm = 0.0;
+    if (stepping > 0 && s->actx) {
+        const double ta = now_s();
+        PD_TRY(admit_queued(s, s->actx, true));
+        t_adm = now_s() - ta;
+    }
+    if (stepping > 0) PD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    s->stats.step_s += now_s() - t_step - t_adm;
     s->stats.rounds += 1;
     const double t_ret = now_s();
-    // retire the finished ones
+    // retire the finished ones (those admitted during the chunk have not run)
     std::vector<Req *> keep;
     int dev_err = PD_OK;
-    for (Req *r : s->running) {
-        if (r->done >= r->nsteps) {
+    for (size_t k = 0; k < s->running.size(); ++k) {
+        Req *r = s->running[k];
+        if (k < stepping && r->done >= r->nsteps) {
             const int st = retire(s, r);
             if (st == PD_EDEVICE) dev_err = st;
         } else {
@@ -384,6 +435,7 @@ extern "C" int pd_server_pump(pd_server s, int *n_running, int *n_queued) {
     s->running.swap(keep);
     if (dev_err != PD_OK) return dev_err;
     s->stats.retire_s += now_s() - t_ret;
+    if (stepping > 0 && !s->actx) PD_TRY(admit_queued(s, ctx, false));
     if (n_running) *n_running = (int)s->running.size();
     if (n_queued) *n_queued = (int)s->queue.size();
     return PD_OK;

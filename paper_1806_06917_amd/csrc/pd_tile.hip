@@ -583,15 +583,20 @@ int pd_nbr_build_tiles(pd_ctx ctx, pd_nbr nbr, uint32_t T) {
     if (overflow) return cleanup(), PD_ECAPACITY;
     if ((status = pd_scan_u32(ctx, count, scan, ntiles)) != PD_OK) return cleanup(), status;
     uint64_t total = 0;
-    if (hipMemcpy(&total, scan + ntiles, sizeof total, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(&total, scan + ntiles, sizeof total, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
         return cleanup(), pd_set_error(ctx, PD_EDEVICE, "tile scan copy");
     // largest halo
     std::vector<uint32_t> hc(ntiles);
-    if (hipMemcpy(hc.data(), count, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(hc.data(), count, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
         return cleanup(), pd_set_error(ctx, PD_EDEVICE, "tile count copy");
     uint32_t hmax = 0;
     for (uint32_t c : hc) hmax = c > hmax ? c : hmax;
-    if (hipMemcpy(hc.data(), bonds, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(hc.data(), bonds, sizeof(uint32_t) * ntiles, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
         return cleanup(), pd_set_error(ctx, PD_EDEVICE, "tile bond count copy");
     uint32_t bmax = 0;
     for (uint32_t c : hc) bmax = c > bmax ? c : bmax;

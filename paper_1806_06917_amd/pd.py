@@ -64,7 +64,7 @@ class TuneResult(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("admit_s", C.c_double), ("step_s", C.c_double), ("retire_s", C.c_double),
                 ("rounds", C.c_int64), ("admitted", C.c_int64), ("launches", C.c_int64),
-                ("replays", C.c_int64)]
+                ("replays", C.c_int64), ("admit_overlap_s", C.c_double)]
 
 
 class SolveInfo(C.Structure):
