@@ -270,7 +270,11 @@ def serve(pd, reqs, budget, chunk, rate=None, tile=0, precision="mixed"):
     evals = sum(f["bonds"] * q.steps for f, q in zip(infos, reqs)
                 if f["state"] == pd.PD_REQ_DONE)
     span = t_end - t0
+    # host time of admission and retirement that the device did not hide
+    # (admission during a running chunk overlaps it)
+    exposed = stats["admit_s"] - stats["admit_overlap_s"] + stats["retire_s"]
     return {"requests": len(reqs), "completed": len(ok), "makespan_s": span,
+            "admit_retire_exposed_s": exposed, "admit_retire_exposed_frac": exposed / span,
             "bond_evals_per_s": evals / span, "requests_per_s": len(ok) / span,
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "queue_p50_s": float(np.percentile(queue, 50)),
