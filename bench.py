@@ -334,8 +334,10 @@ def law_runs(torch, pd, steps, tuned=None):
     and linear-peridynamic-solid steps (two passes per step) on the 1M-node
     cube, both on the streamed kernel, and the NP Newton-Krylov solve of the
     400 x 40 bar (beta set so that beta |xi| S^2 reaches 0.1 at the linear
-    solution).  tuned: (dim, mean neighbours, precision, tile, lanes) entries
-    of the autotuner to seed this context with."""
+    solution).  The step timings are the median of five windows after 20
+    warm-up steps (the first milliseconds of a run are slower while the
+    device clock ramps up).  tuned: (dim, mean neighbours, precision, tile,
+    lanes) entries of the autotuner to seed this context with."""
     from paper_1806_06917_amd import inputs
     out = {}
     ctx = pd.Context(0)
@@ -352,16 +354,11 @@ def law_runs(torch, pd, steps, tuned=None):
                             dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
                             bc_vel=dev(torch, w.bc_vel), notch=w.notch,
                             ramp_steps=w.ramp_steps)
-        sim.step(10, w.dt)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(ctx.stream)
-        sim.step(steps, w.dt)
-        e1.record(ctx.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+        sim.step(20, w.dt)
+        windows, _ = timed_windows(torch, ctx, lambda: sim.step(steps, w.dt), 5)
+        ms = float(np.median(windows)) / steps
         out[f"np_step_{prec}"] = {"workload": w.name, "ms_per_step": ms,
+                                  "windows_ms_per_step": [x / steps for x in windows],
                                   "bond_evals_per_s": nb.nnz / (ms * 1e-3),
                                   "launch": sim.info(), "beta": 1e3,
                                   "roofline": step_roofline(
@@ -378,16 +375,12 @@ def law_runs(torch, pd, steps, tuned=None):
         sim = pd.Simulation(ctx, nb, mat, Xc, dev(torch, wc.V), dev(torch, wc.u0),
                             dev(torch, wc.v0), bc_kind=dev(torch, wc.bc_kind),
                             bc_vel=dev(torch, wc.bc_vel), ramp_steps=wc.ramp_steps)
-        sim.step(5, wc.dt)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(ctx.stream)
-        sim.step(steps // 4, wc.dt)
-        e1.record(ctx.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / (steps // 4)
+        sim.step(20, wc.dt)
+        k = steps // 4
+        windows, _ = timed_windows(torch, ctx, lambda: sim.step(k, wc.dt), 5)
+        ms = float(np.median(windows)) / k
         out[f"lps_step_{prec}"] = {"workload": wc.name, "ms_per_step": ms,
+                                   "windows_ms_per_step": [x / k for x in windows],
                                    "bond_evals_per_s": nb.nnz / (ms * 1e-3),
                                    "launch": sim.info(), "nu": 0.25,
                                    "roofline": step_roofline(
