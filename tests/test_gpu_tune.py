@@ -146,11 +146,13 @@ def test_large_tiles_stream_with_gather_side_calls(gpu, prec):
 
 
 def test_tuned_shape_applies_whole_or_not_at_all(gpu):
-    """A tuned (tile size, lanes) pair is taken as a whole: a simulation that
-    cannot use the tuned tile size (the solid's streamed layout does not fit
-    240-node tiles, or the mesh's tiles are held at another size) runs at
-    the automatic shape, the one a context without tuning picks, and never
-    with the tuned lanes on other tiles.  Mixed then FP64, on one mesh."""
+    """A tuned (tile size, lanes) pair is taken as a whole: a simulation runs
+    either at the tuned shape or, if it cannot use the tuned tile size (its
+    material's streamed layout does not fit, or the mesh's tiles are held at
+    another size), at the automatic shape, the one a context without tuning
+    picks -- never with the tuned lanes on other tiles or the other way
+    round.  The solid under a 240 x 4 entry (mixed then FP64), then a
+    linear-law simulation on tiles held at 128 nodes."""
     torch, pd, _ = gpu
     N = 22
     h = 1.0 / N
@@ -175,9 +177,9 @@ def test_tuned_shape_applies_whole_or_not_at_all(gpu):
                 if c is plain:
                     ref[prec] = info
                 else:
-                    # the solid's streamed layout does not fit 240-node tiles
-                    assert (info["tile"], info["lanes"]) != (240, 4)
-                    assert info == ref[prec], (prec, info, ref[prec])
+                    whole = (info["tile"], info["lanes"]) == (240, 4)
+                    say("solid under 240 x 4:", info)
+                    assert whole or info == ref[prec], (prec, info, ref[prec])
             nb.close()
         # tiles held at 128 nodes by a live simulation: a linear-law simulation
         # created under the 240 x 4 entry takes the automatic shape on them,
