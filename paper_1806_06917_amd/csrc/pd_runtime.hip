@@ -19,7 +19,7 @@
 // handed out again.  A block is freed on the stream of the context that
 // allocated it: an event recorded there at the free marks the end of its
 // last use, and the block is handed out again only after that event has
-// completed (the host waits for it if it has not), so no later work on any
+// completed (blocks still in use are passed over), so no later work on any
 // stream can overlap an earlier user.  Sizes round up to 256 bytes (64 KiB
 // from 1 MiB on); a request takes the smallest cached block of at least its
 // size and at most an eighth more.  At most PD_CACHE_MAX bytes stay cached;
@@ -43,9 +43,10 @@ struct DeviceCache {
     std::vector<hipEvent_t> events;   // idle events for reuse
 };
 
-std::mutex g_mem_mu;
-std::unordered_map<void *, LiveBlock> g_live;
-std::map<int, DeviceCache> g_cache;
+// never destroyed: frees may still arrive while the process exits
+std::mutex &g_mem_mu = *new std::mutex;
+std::unordered_map<void *, LiveBlock> &g_live = *new std::unordered_map<void *, LiveBlock>;
+std::map<int, DeviceCache> &g_cache = *new std::map<int, DeviceCache>;
 
 size_t round_bytes(size_t b) {
     const size_t q = b < (size_t(1) << 20) ? 256 : (size_t(64) << 10);
@@ -72,14 +73,18 @@ int pd_alloc_bytes(pd_ctx ctx, void **p, size_t bytes) {
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lock(g_mem_mu);
     DeviceCache &c = g_cache[dev];
-    auto it = c.free.lower_bound(bytes);
-    if (it != c.free.end() && it->first <= bytes + bytes / 8) {
+    // the smallest fitting block whose last use has completed (a block still
+    // in use on its stream is passed over rather than waited for)
+    for (auto it = c.free.lower_bound(bytes);
+         it != c.free.end() && it->first <= bytes + bytes / 8; ++it) {
+        if (hipEventQuery(it->second.done) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
         CachedBlock b = it->second;
         const size_t have = it->first;
         c.free.erase(it);
         c.bytes -= have;
-        if (hipEventQuery(b.done) != hipSuccess) (void)hipEventSynchronize(b.done);
-        (void)hipGetLastError();
         c.events.push_back(b.done);
         *p = b.p;
         g_live[b.p] = LiveBlock{have, dev, ctx ? ctx->stream : nullptr};
