@@ -21,10 +21,12 @@ def sim_of(torch, pd, ctx, nb, w, prec, law="linear", beta=0.0):
                          ramp_steps=w.ramp_steps)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 @pytest.mark.parametrize("case", ["free", "edges", "np"])
 def test_central_parity(gpu, orc, case, prec):
     torch, pd, ctx = gpu
+    if case == "np" and prec == "fp32":
+        pytest.skip("PD_FP32 takes the linearised law only (rejected: test_fp32_scope)")
     if case == "edges":
         w = inputs.notched_plate_2d(N=40, m=3, s_c=0.0, v0=2e-3, steps=0, ramp_steps=10)
         w.notch = np.zeros((0, 4))

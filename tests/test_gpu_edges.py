@@ -125,7 +125,7 @@ def two_nodes(dim):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_two_node_bond(gpu, orc, dim, prec):
     """The smallest mesh with a bond: two nodes.  Force and energy density
     against their closed form f_0 = c S e V_1, f_1 = -c S e V_0,
@@ -202,3 +202,39 @@ def test_server_fails_bondless_request_only(gpu):
     assert fb["state"] == pd.PD_REQ_FAILED and fb["status"] == pd.PD_EINVAL
     assert fb["bonds"] == 0
     assert fg["state"] == pd.PD_REQ_DONE and fg["status"] == pd.PD_OK and fg["bonds"] > 0
+
+
+def test_fp32_scope(gpu):
+    """PD_FP32 covers the linearised law: the NP law, the exact stretch and the
+    solid are rejected with PD_EINVAL, as are the tangent in FP32 and the
+    register-staged tile kernel forced for an FP32 simulation (PD_ECAPACITY);
+    the implicit solve accepts it as the mixed solve."""
+    torch, pd, ctx = gpu
+    X, V, delta = two_nodes(2)
+    Xd, Vd = dev(torch, X), dev(torch, V)
+    nb = pd.Neighbors(ctx, Xd, delta)
+    u = torch.zeros((2, 2), dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(u)
+    for kw in ({"law": "np", "beta": 1.0}, {"stretch": "exact"}):
+        with pytest.raises(pd.PDError) as e:
+            pd.internal_force(ctx, nb, pd.material(2, 1.0, 1.0, 0.0, "fp32", **kw), Xd, Vd, u, f)
+        assert e.value.status == pd.PD_EINVAL
+    with pytest.raises(pd.PDError) as e:
+        pd.apply_tangent(ctx, nb, pd.material(2, 1.0, 1.0, 0.0, "fp32"), Xd, Vd, u, f)
+    assert e.value.status == pd.PD_EINVAL
+    ctx.set_tuning("tile", 0, 0)
+    try:
+        with pytest.raises(pd.PDError) as e:
+            pd.Simulation(ctx, nb, pd.material(2, 1.0, 1.0, 0.0, "fp32"), Xd, Vd, None, None)
+        assert e.value.status == pd.PD_ECAPACITY
+    finally:
+        ctx.set_tuning(0, 0, 0)
+    nb.close()
+    X3, V3, d3 = two_nodes(3)
+    nb3 = pd.Neighbors(ctx, dev(torch, X3), d3)
+    with pytest.raises(pd.PDError) as e:
+        pd.Simulation(ctx, nb3, pd.material(3, 0.0, 1.0, 0.0, "fp32", law="lps", bulk=1.0,
+                                            shear=0.5), dev(torch, X3), dev(torch, V3),
+                      None, None)
+    assert e.value.status == pd.PD_EINVAL
+    nb3.close()

@@ -167,8 +167,9 @@ def _serve(pd, ctx, ws, prec, budget, chunk):
     results = [srv.result(i, w.n, w.dim) if f["state"] == pd.PD_REQ_DONE else None
                for i, w, f in zip(ids, ws, infos)]
     used, peak = srv.usage()
+    stats = srv.stats()
     srv.close()
-    return infos, results, most, used, peak
+    return infos, results, most, used, peak, stats
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
@@ -179,7 +180,9 @@ def test_served_equals_alone(gpu, orc, prec):
     torch, pd, ctx = gpu
     ws = _plates() + [inputs.notched_plate_2d(N=48, m=3, s_c=1e-3, v0=2e-3, steps=0,
                                               ramp_steps=5)]
-    for w, k in zip(ws, [60, 47, 60, 33]):
+    # the first request ends a round before the others (steps 20 at chunks of
+    # 20), which frees room while the rest still run
+    for w, k in zip(ws, [20, 47, 60, 33]):
         w.steps = k
     refs = [_oracle(orc, w, w.steps, prec) for w in ws]
     ctx.set_lanes(4)
@@ -194,8 +197,9 @@ def test_served_equals_alone(gpu, orc, prec):
     finally:
         ctx.set_lanes(0)
     say("serve: unlimited", prec)
-    infos, res, most, used, peak = _serve(pd, ctx, ws, prec, 1 << 40, 25)
-    assert most == len(ws) and used == 0
+    infos, res, most, used, peak, _ = _serve(pd, ctx, ws, prec, 1 << 40, 25)
+    # all admitted at once, before any finished
+    assert max(f["t_admit"] for f in infos) <= min(f["t_done"] for f in infos) and used == 0
     sizes = [f["bytes"] for f in infos]
     assert all(b > 0 for b in sizes) and peak == sum(sizes)
     for f, r, a, oref in zip(infos, res, alone, refs):
@@ -206,7 +210,7 @@ def test_served_equals_alone(gpu, orc, prec):
     # a budget that holds the largest request plus a little: queueing
     budget = max(sizes) + min(sizes) // 2
     say("serve: budget", budget, prec)
-    infos2, res2, most2, used2, peak2 = _serve(pd, ctx, ws, prec, budget, 20)
+    infos2, res2, most2, used2, peak2, _ = _serve(pd, ctx, ws, prec, budget, 20)
     assert peak2 <= budget and used2 == 0 and most2 < len(ws)
     admits = [f["t_admit"] for f in infos2]
     assert admits == sorted(admits)
@@ -214,6 +218,17 @@ def test_served_equals_alone(gpu, orc, prec):
         assert f["state"] == pd.PD_REQ_DONE
         assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
         _check_oracle(r[0], r[1], None, oref, prec)
+    # a budget one byte short of all of them: the last waits for the first
+    # to retire while the others still run, so it is built during a chunk
+    # (on the admission context) and moved into the running set
+    budget3 = sum(sizes) - 1
+    say("serve: overlapped admission", budget3, prec)
+    infos3, res3, most3, used3, peak3, st3 = _serve(pd, ctx, ws, prec, budget3, 20)
+    assert peak3 <= budget3 and used3 == 0 and most3 < len(ws)
+    assert st3["admit_overlap_s"] > 0.0 and st3["admitted"] == len(ws)
+    for f, r, a in zip(infos3, res3, alone):
+        assert f["state"] == pd.PD_REQ_DONE
+        assert np.array_equal(r[0], a[0]) and np.array_equal(r[1], a[1])
 
 
 def test_served_too_large(gpu):
