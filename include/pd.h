@@ -40,6 +40,10 @@
  *     pd_nbr_export, pd_sim_get and pd_solve_implicit, which synchronise the
  *     stream.  Handles built on one context must only be used with it.
  *   - A pd_nbr must outlive every pd_sim created from it.
+ *   - Device memory the library frees is kept in a per-device cache (at most
+ *     16 GiB) and handed out again to later allocations of the library once
+ *     the work queued before the free has completed; it goes back to the
+ *     driver when an allocation fails, or at process exit.
  */
 #ifndef PD_H
 #define PD_H
