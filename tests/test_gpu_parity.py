@@ -517,3 +517,38 @@ def test_tile_kernel_bitwise_equals_gather(gpu, wl, prec):
     for r in results[1:]:
         for x, y in zip(results[0], r):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
+def test_unequal_volume_steps(gpu, orc, prec):
+    """Nodal volumes that differ keep a simulation off the streamed kernel
+    (register-staged tiles in FP64 and mixed, the gather kernel in FP32):
+    30 Verlet steps with damage on a jittered plate against the oracle, flags
+    equal outside the comparison band."""
+    torch, pd, ctx = gpu
+    X, V, _, delta = force_case(407, 2, 40, 3, 0.0)
+    n = len(X)
+    mesh = orc.Mesh(X, V, delta)
+    c = orc.micromodulus(2, 1.0, delta)
+    s_c = 4e-3
+    v0 = inputs.random_field(n, 2, 408, scale=5e-3)
+    dt = 0.05 / 40
+    st = mesh.start(np.zeros((n, 2)), v0, c, s_c)
+    band = mesh.verlet_banded(st, c, 1.0, s_c, dt, 30, tol_eta=eta_band(prec)).astype(bool)
+    say("unequal volumes", prec)
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    sim = pd.Simulation(ctx, nb, pd.material(2, pd.micromodulus(2, 1.0, delta), 1.0, s_c, prec),
+                        dev(torch, X), dev(torch, V), None, dev(torch, v0))
+    assert sim.info()["kernel"] != "stream"
+    sim.step(30, dt)
+    u, v, a, info = read_state(torch, sim, n, 2, nb.nnz)
+    sim.close()
+    nb.close()
+    assert info["step"] == 30
+    broken = np.count_nonzero(st["alive"] == 0)
+    assert 0 < broken < mesh.nnz
+    assert np.array_equal(a[~band], st["alive"][~band])
+    same = np.array_equal(a, st["alive"])
+    tol = tol_of(prec)
+    assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
+    assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
