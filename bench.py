@@ -47,6 +47,7 @@ KERNEL_SOURCES = ["pd_kernels.hpp", "pd_stream.hip", "pd_internal.hpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_kernel_cube100_traffic.md")
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "stream_kernel_cube100_counters.md")
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3   # packed; scalar FP32 issues at the FP64 rate
 
 
 def kernel_source_hash():
@@ -92,10 +93,18 @@ def recorded_valu(workload, precision, launch, nnz):
     rec = recorded_profile(COUNTER_SUMMARY, workload, precision, launch)
     if not rec:
         return None
+    k32 = rec.get("fp32_mode_kernel", {})
     return {"valu_busy": rec["valu_busy"], "fp64_tflops": rec["fp64_tflops"],
             "fp64_peak_tflops": FP64_PEAK_TFLOPS,
             "fp64_frac": rec["fp64_tflops"] / FP64_PEAK_TFLOPS,
+            "fp32_tflops": rec.get("fp32_tflops"),
+            "fp32_peak_tflops": FP32_PEAK_TFLOPS,
             "lane_instr_per_bond": rec["valu_lane_instr_per_bond"],
+            "fp32_mode_kernel": {"valu_busy": k32.get("valu_busy"),
+                                 "fp32_tflops": k32.get("fp32_tflops"),
+                                 "fp32_frac": (k32["fp32_tflops"] / FP32_PEAK_TFLOPS
+                                               if k32 else None),
+                                 "lane_instr_per_bond": k32.get("valu_lane_instr_per_bond")},
             "source": os.path.relpath(COUNTER_SUMMARY, ROOT)}
 
 
@@ -527,6 +536,27 @@ def convergence_1d(torch, pd, law, ic, t_end=2.0, every=0.25, pv=False):
             "nodes": [w.n for w in ws], "rates": rows}
 
 
+def copy_probe(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate of this GPU (read + write bytes over the
+    copy's time, median of reps), the attainable-bandwidth context for the
+    8 TB/s peak."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    return 2 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -619,6 +649,7 @@ def main():
     B = algorithmic_bytes(w.n, r["nnz"], w.dim)
     achieved = B / (ms_step * 1e-3) / 1e9
     traffic = recorded_traffic(w.name, precision, r["launch"])
+    copy_gbs = copy_probe(torch)
     out = {
         "metric": "bond evals/sec + ms/explicit step at 1M nodes",
         "value": bonds_per_s,
@@ -642,6 +673,8 @@ def main():
                      "traffic_frac": (traffic / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
                                       if traffic else None),
                      "valu": recorded_valu(w.name, precision, r["launch"], r["nnz"]),
+                     "copy_probe_gbs": copy_gbs,
+                     "frac_of_copy_probe": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": B,
                      "kernel_source_hash": kernel_source_hash()},
         "timing": {"windows": args.reps, "steps_per_window": args.steps,
