@@ -27,12 +27,13 @@
 //
 // Per workgroup tile k: wait for this wave's copies, barrier (tile k and the
 // ids of tile k+1 are in LDS); sum the bonds, one lane group per node in the
-// gather kernel's summation order (so results are bit-identical to it), and
-// let L lanes of each group update their node (kick, drift, boundary data),
-// one component per lane; barrier; issue the copies of tile k+1 and of the
-// halo ids of tile k+2.  The bond words are read from global memory in the
-// bond loop (one read per bond and pass; a break is stored at once), so they
-// take no LDS.
+// gather kernel's summation order (so results are bit-identical to it),
+// keeping what the node update needs from LDS in registers; barrier; issue
+// the copies of tile k+1 and of the halo ids of tile k+2; then let L lanes of
+// each group reduce their sums and update their node (kick, drift, boundary
+// data), one component per lane, while those copies are in flight.  The bond
+// words are read from global memory in the bond loop (one read per bond and
+// pass; a break is stored at once), so they take no LDS.
 #include <climits>
 
 #include "pd_kernels.hpp"
@@ -297,29 +298,34 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         }
     };
 
-    // bond sums of tile k; then L lanes of each node's group update the node
-    // (kick, drift, boundary data, or the central-difference update), one
-    // component per lane, with the same arithmetic as node_update.  A bond that
-    // breaks gets its dead bit in the global bond word at once.
-    auto sum_and_update = [&](uint32_t k) {
-        if (meta[k * META + MT_HN] == 0) return;
+    // A tile's work in two phases around the barrier that frees its record
+    // slot.  sums(k): the bond loops of tile k, the only phase that reads the
+    // staged records, v and boundary kinds; what the node update needs from
+    // LDS stays in registers.  update(k): the L lanes of each node's group
+    // reduce their sums and update the node (kick, drift, boundary data, or
+    // the central-difference update), one component per lane, with the same
+    // arithmetic as node_update, while the copies of tile k + 1 are already in
+    // flight.  The block holds T groups of L lanes: one node per group.  A
+    // bond that breaks gets its dead bit in the global bond word at once.
+    const uint32_t g = tid / L;
+    const int lane = tid & (L - 1);
+    std::conditional_t<F32, AccC, Acc64> acc;
+    double ud_c = 0.0, vd_c = 0.0;   // this lane's component of u_i and v_i
+    int kind_c = 0;
+    auto sums = [&](uint32_t k) {
+        acc = decltype(acc){};
+        const uint32_t tn = meta[k * META + MT_TN], q = g;
+        if (meta[k * META + MT_HN] == 0 || q >= tn) return;
         const StreamInst I = inst_of(k);
-        const uint32_t t0 = meta[k * META + MT_T0], tn = meta[k * META + MT_TN];
+        const uint32_t t0 = meta[k * META + MT_T0];
         const uint32_t b0 = meta[k * META + MT_B0], so = meta[k * META + MT_SO];
-        const uint32_t cur = cur_of(I);
-        double *out = cur ? I.rec[0] : I.rec[1];
-        const int mode = (s > 0 || I.vhalf0) ? M_STEP_CONT : M_STEP_FIRST;
-        const double r_half = ramp_of((double)(I.step0 + s) + 0.5, I.ramp);
-        const double cv = I.cv, s_c = I.s_c, dt = I.dt, rho = I.rho, beta = I.beta;
+        const double cv = I.cv, s_c = I.s_c, beta = I.beta;
         const float cv32 = (float)cv, s_c32 = (float)s_c;
         const int damage = I.damage;
-        const uint32_t groups = B / L, g = tid / L;
-        const int lane = tid & (L - 1);
-        for (uint32_t q = g; q < tn; q += groups) {
+        {
             const double *ri = rec + (size_t)(so + q) * RD;
             const double xix = ri[0], xiy = ri[1], xiz = DIM == 3 ? ri[2] : 0.0;
             const double uix = ri[DIM], uiy = ri[DIM + 1], uiz = DIM == 3 ? ri[DIM + 2] : 0.0;
-            std::conditional_t<F32, AccC, Acc64> acc;
             // the solid's force pass reads v from global memory, issued here so
             // that its latency overlaps the bond loop's first word loads
             double vg = 0.0;
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     else
                         reinterpret_cast<double2 *>(I.lps)[t0 + q] = make_double2(qc.a, qc.d);
                 }
-                continue;
+                return;
             } else if constexpr (FORM == SK_LPS_FORCE) {
                 // the solid's force, as the gather kernel's branch: the
                 // scatter read from node i with {a, d} of both ends (a
@@ -467,6 +473,23 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     if (kb) *const_cast<uint16_t *>(wq + L) = (uint16_t)(wb | BW_DEAD);
                 });
             }
+            if (lane < (int)DIM) {
+                ud_c = lane == 0 ? uix : (lane == 1 ? uiy : uiz);
+                vd_c = v_staged(FORM) ? vbuf[(size_t)q * US + lane] : vg;
+                kind_c = (int)reinterpret_cast<const uint8_t *>(bcb)[q];
+            }
+        }
+    };
+    auto update = [&](uint32_t k) {
+        const uint32_t tn = meta[k * META + MT_TN], q = g;
+        if (FORM == SK_LPS_STATE || meta[k * META + MT_HN] == 0 || q >= tn) return;
+        const StreamInst I = inst_of(k);
+        const uint32_t t0 = meta[k * META + MT_T0];
+        double *out = cur_of(I) ? I.rec[0] : I.rec[1];
+        const int mode = (s > 0 || I.vhalf0) ? M_STEP_CONT : M_STEP_FIRST;
+        const double r_half = ramp_of((double)(I.step0 + s) + 0.5, I.ramp);
+        const double dt = I.dt, rho = I.rho;
+        {
             double fx, fy, fz, Ue;
             if constexpr (F32) group_reduce_c<DIM, L, false>(acc, fx, fy, fz, Ue);
             else group_reduce<DIM, L, false>(acc, fx, fy, fz, Ue);
@@ -479,9 +502,9 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
             if (lane < (int)DIM) {
                 const uint32_t d = (uint32_t)lane, i = t0 + q;
                 const double fd = d == 0 ? fx : (d == 1 ? fy : fz);
-                const double ud = ri[DIM + d];
-                double vd = v_staged(FORM) ? vbuf[(size_t)q * US + d] : vg;
-                const int kind = (int)reinterpret_cast<const uint8_t *>(bcb)[q];
+                const double ud = ud_c;
+                double vd = vd_c;
+                const int kind = kind_c;
                 const double hdt = 0.5 * dt;
                 double nd;
                 if (kind == PD_BC_FREE && I.cd && s > 0) {
@@ -521,10 +544,11 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     for (uint32_t k = 0; k < K; ++k) {
         dma_wait();
         lds_barrier();                       // tile k and the ids of tile k+1 are in LDS
-        sum_and_update(k);
+        sums(k);
         lds_barrier();                       // the slot is free once the sums are done
         if (k + 1 < K) issue_tile(k + 1);
         if (k + 2 < K) issue_ids(k + 2);
+        update(k);
     }
 }
 
