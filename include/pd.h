@@ -88,9 +88,10 @@ typedef struct pd_server_s *pd_server;
  *              other laws return PD_EINVAL): the differences xi and eta are
  *              taken in float64 and rounded to float32; |xi|^-1 (hardware
  *              float32 estimate), S, the damage test against s_c rounded to
- *              float32, and the bond force are float32; each node's sum is
- *              a compensated float32 pair (TwoSum) converted to float64 at
- *              the end.  Positions, velocities and the time integration
+ *              float32, and the bond force are float32; the force terms
+ *              of a lane's bonds are added two at a time in float32 and
+ *              each pair sum goes into a compensated float32 pair
+ *              (TwoSum), converted to float64 at the end.  Positions, velocities and the time integration
  *              stay float64.  Force relative error about 1e-6 of the
  *              largest bond force.  pd_apply_tangent rejects it;
  *              pd_solve_implicit treats it as PD_MIXED.

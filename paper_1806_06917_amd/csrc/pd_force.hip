@@ -158,7 +158,12 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel32(NodeArgs a) {
         if (DIM == 3) { xiz = q.z; Vi = q.w; } else { Vi = q.z; }
         load_vec<DIM>(a.u, i, uix, uiy, uiz);
         const float sc = (float)a.s_c;
-        for (uint32_t p = a.row_ptr[i] + lane; p < a.row_ptr[i + 1]; p += L) {
+        // bond p's float32 terms (all +0 past the row's end)
+        auto terms = [&](uint32_t p, uint32_t pe, float &tx, float &ty, float &tz, float &te) {
+            if (p >= pe) {
+                tx = ty = tz = te = 0.0f;
+                return;
+            }
             const uint32_t j = (uint32_t)a.col[p];
             const bool live = !a.alive || a.alive[p];
             const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
@@ -168,8 +173,16 @@ __global__ __launch_bounds__(PD_BLOCK) void node_kernel32(NodeArgs a) {
                                                            : a.c * (DIM == 3 ? xj.w : xj.z));
             const double dxz = DIM == 3 ? xj.z - xiz : 0.0, duz = DIM == 3 ? ujz - uiz : 0.0;
             if (bond32<DIM, WANT_E>(a.damage, sc, xj.x - xix, xj.y - xiy, dxz, ujx - uix,
-                                    ujy - uiy, duz, cVj, !live, acc))
+                                    ujy - uiy, duz, cVj, !live, tx, ty, tz, te))
                 a.alive[p] = 0;
+        };
+        // the lane's bonds two at a time (p and p + L), as the streamed kernel
+        const uint32_t pe = a.row_ptr[i + 1];
+        for (uint32_t p = a.row_ptr[i] + lane; p < pe; p += 2 * L) {
+            float ax, ay, az, ae, bx, by, bz, be;
+            terms(p, pe, ax, ay, az, ae);
+            terms(p + L, pe, bx, by, bz, be);
+            pair_into<DIM, WANT_E>(acc, ax, ay, az, ae, bx, by, bz, be);
         }
     }
     double fx, fy, fz, Ue;

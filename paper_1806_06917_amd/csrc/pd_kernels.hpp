@@ -178,31 +178,46 @@ __device__ __forceinline__ void two_sum_into(float &h, float &l, float v) {
 }
 
 // One bond as in `bond`, in float32: xi and eta arrive as float64
-// differences and are rounded to float32; |xi|^-1 is the hardware float32
-// reciprocal square root; S, the damage test (against s_c rounded to
-// float32) and the bond force are float32; the force components (and the
-// energy) are added to the compensated sums.
+// differences and are rounded to float32; |xi|^2 and eta.xi are fused
+// float32 sums, |xi|^-1 is the hardware float32 reciprocal square root; S,
+// the damage test (against s_c rounded to float32) and the bond force are
+// float32.  The force terms (and the energy) come back in t, exactly +0 for
+// a dead or breaking bond; the return value says whether the bond breaks.
 template <int DIM, bool WANT_E>
 __device__ __forceinline__ bool bond32(int damage, float s_c, double dxx, double dxy, double dxz,
                                        double dux, double duy, double duz, float cVj, bool dead,
-                                       AccC &s) {
-#pragma clang fp contract(off)
+                                       float &tx, float &ty, float &tz, float &te) {
     const float x = (float)dxx, y = (float)dxy, z = DIM == 3 ? (float)dxz : 0.0f;
     const float ex = (float)dux, ey = (float)duy, ez = DIM == 3 ? (float)duz : 0.0f;
-    const float r2 = DIM == 3 ? (x * x + y * y) + z * z : x * x + y * y;
-    const float et = DIM == 3 ? (ex * x + ey * y) + ez * z : ex * x + ey * y;
+    const float r2 = DIM == 3 ? __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x))
+                              : __builtin_fmaf(y, y, x * x);
+    const float et = DIM == 3 ? __builtin_fmaf(ez, z, __builtin_fmaf(ey, y, ex * x))
+                              : __builtin_fmaf(ey, y, ex * x);
     const float inv = __builtin_amdgcn_rsqf(r2);
     const float S = et * (inv * inv);
     const bool brk = damage && !dead && S > s_c;
-    if (!(brk || dead)) {
-        asm volatile("" ::: "memory");
-        const float g = cVj * S * inv;
-        two_sum_into(s.hx, s.lx, g * x);
-        two_sum_into(s.hy, s.ly, g * y);
-        if (DIM == 3) two_sum_into(s.hz, s.lz, g * z);
-        if (WANT_E) two_sum_into(s.he, s.le, 0.25f * cVj * S * S * (r2 * inv));
-    }
+    const bool live = !(brk || dead);
+    const float g = cVj * S * inv;
+    tx = live ? g * x : 0.0f;
+    ty = live ? g * y : 0.0f;
+    tz = DIM == 3 && live ? g * z : 0.0f;
+    te = WANT_E && live ? 0.25f * cVj * S * S * (r2 * inv) : 0.0f;
     return brk;
+}
+
+// The terms of two consecutive bonds of a lane (a before b; a lane's last
+// bond, if its count is odd, pairs with terms +0) are added in float32 and
+// the pair sum goes into the compensated sums: one TwoSum per pair and
+// component.  The pair sum adds one rounding of the size of the terms' own,
+// so the sums stay free of error growth with the bond count.
+template <int DIM, bool WANT_E>
+__device__ __forceinline__ void pair_into(AccC &s, float ax, float ay, float az, float ae, float bx,
+                                          float by, float bz, float be) {
+#pragma clang fp contract(off)
+    two_sum_into(s.hx, s.lx, ax + bx);
+    two_sum_into(s.hy, s.ly, ay + by);
+    if (DIM == 3) two_sum_into(s.hz, s.lz, az + bz);
+    if (WANT_E) two_sum_into(s.he, s.le, ae + be);
 }
 
 // A float moved across lanes by a DPP pattern

@@ -457,10 +457,12 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
                     bond_vectors(wb, bx, by, bz, bux, buy, buz);
                     bool ka, kb;
                     if constexpr (F32) {
+                        float tax, tay, taz, tae, tbx, tby, tbz, tbe;
                         ka = bond32<DIM, false>(damage, s_c32, ax, ay, az, aux, auy, auz, cv32,
-                                                (wa & BW_DEAD) != 0, acc);
+                                                (wa & BW_DEAD) != 0, tax, tay, taz, tae);
                         kb = bond32<DIM, false>(damage, s_c32, bx, by, bz, bux, buy, buz, cv32,
-                                                !hb || (wb & BW_DEAD) != 0, acc);
+                                                !hb || (wb & BW_DEAD) != 0, tbx, tby, tbz, tbe);
+                        pair_into<DIM, false>(acc, tax, tay, taz, tae, tbx, tby, tbz, tbe);
                     } else {
                         ka = bond<DIM, MIXED, false, NP>(damage, s_c, ax, ay, az, aux, auy, auz,
                                                          cv, (wa & BW_DEAD) != 0, acc, beta);
