@@ -601,6 +601,49 @@ def cpu_baseline(w, steps, steps_1t):
             "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
+def cpu_config_baselines(gpu_configs, gpu_implicit):
+    """The FP64 oracle on the other workloads, on all the host's cores: 100
+    velocity-Verlet steps of the 512^2 notched plate (notch, collars,
+    damage) and of the 32^2 free plate, and the 400 x 40 bar's quasi-static
+    solve to a relative residual of 1e-10; each beside the GPU's time for
+    the same work when that was measured in this run."""
+    from oracle import oracle as orc
+    from paper_1806_06917_amd import inputs
+    out = {}
+    for name, k in (("notched512", 100), ("plate32", 100)):
+        w = inputs.CONFIGS[name]()
+        progress("oracle on the host,", name, k, "steps")
+        mesh = orc.Mesh(w.X, w.V, w.delta)
+        c = orc.micromodulus(w.dim, w.E, w.delta)
+        alive = mesh.notch_cut(w.notch, mesh.all_alive()) if w.notch is not None else None
+        st = mesh.start(w.u0, w.v0, c, w.s_c, alive)
+        t0 = time.perf_counter()
+        mesh.verlet(st, c, w.rho, w.s_c, w.dt, k, w.bc_kind, w.bc_vel, None, w.ramp_steps)
+        ms = 1e3 * (time.perf_counter() - t0) / k
+        rec = {"workload": w.name, "steps": k, "ms_per_step": ms,
+               "bond_evals_per_s": mesh.nnz / (ms * 1e-3)}
+        for prec in ("mixed", "fp64"):
+            g = (gpu_configs or {}).get(f"{name}_{prec}")
+            if g:
+                rec[f"gpu_speedup_{prec}"] = ms / g["ms_per_step"]   # oracle time over GPU time
+        out[name] = rec
+    wb = inputs.CONFIGS["bar400x40"]()
+    progress("oracle on the host, implicit bar", wb.name)
+    mesh = orc.Mesh(wb.X, wb.V, wb.delta)
+    c = orc.micromodulus(2, wb.E, wb.delta)
+    t0 = time.perf_counter()
+    _, info = mesh.solve_implicit(wb.u0, c, wb.b, wb.fixed, rtol=1e-10, inner_rtol=1e-10)
+    sec = time.perf_counter() - t0
+    rec = {"workload": wb.name, "seconds": sec, "cg_iterations": info["inner"],
+           "rel_residual": info["relres"]}
+    for prec in ("fp64", "mixed"):
+        g = (gpu_implicit or {}).get(prec)
+        if g:
+            rec[f"gpu_speedup_{prec}"] = sec / g["seconds"]
+    out["bar400x40"] = rec
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -750,6 +793,9 @@ def main():
     if not args.no_cpu_baseline:
         steps = args.cpu_steps or (180 if w.n > 100000 else 600)
         out["cpu_baseline"] = cpu_baseline(w, steps, max(1, steps // 18))
+        if not args.no_configs:
+            out["cpu_baseline"]["configs"] = cpu_config_baselines(out.get("configs"),
+                                                                  out.get("implicit"))
     print(json.dumps(out), flush=True)
 
 
