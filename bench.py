@@ -293,11 +293,14 @@ def serve(pd, reqs, budget, chunk, rate=None, tile=0, precision="mixed"):
 def config_runs(torch, pd, steps, warmup):
     """The other explicit workloads in the linearised law, timed like the
     headline one: the 512^2 notched plate (notch, collars, damage) in each
-    precision and the 32^2 free plate (100 steps per window, FP64)."""
+    precision, the 32^2 free plate (100 steps per window, FP64) and the
+    paper's benchmark shape, the 443^2 plate with a 20-cell horizon (mixed
+    and FP64, 100 steps per window)."""
     from paper_1806_06917_amd import inputs
     out = {}
     for name, precs, k in (("notched512", ("mixed", "fp64", "fp32"), steps),
-                           ("plate32", ("fp64",), 100)):
+                           ("plate32", ("fp64",), 100),
+                           ("paper443", ("mixed", "fp64"), 100)):
         w = inputs.CONFIGS[name]()
         for prec in precs:
             r = run_gpu(torch, pd, w, prec, k, warmup, 0)
@@ -604,13 +607,14 @@ def cpu_baseline(w, steps, steps_1t):
 def cpu_config_baselines(gpu_configs, gpu_implicit):
     """The FP64 oracle on the other workloads, on all the host's cores: 100
     velocity-Verlet steps of the 512^2 notched plate (notch, collars,
-    damage) and of the 32^2 free plate, and the 400 x 40 bar's quasi-static
+    damage) and of the 32^2 free plate, 5 of the 443^2 plate with a 20-cell
+    horizon, and the 400 x 40 bar's quasi-static
     solve to a relative residual of 1e-10; each beside the GPU's time for
     the same work when that was measured in this run."""
     from oracle import oracle as orc
     from paper_1806_06917_amd import inputs
     out = {}
-    for name, k in (("notched512", 100), ("plate32", 100)):
+    for name, k in (("notched512", 100), ("plate32", 100), ("paper443", 5)):
         w = inputs.CONFIGS[name]()
         progress("oracle on the host,", name, k, "steps")
         mesh = orc.Mesh(w.X, w.V, w.delta)

@@ -302,6 +302,9 @@ def serving_workload(req: "Request") -> Workload:
 
 CONFIGS = {
     "plate32": lambda: plate_2d(32, 3, seed=1, steps=100),
+    # the paper's explicit benchmark shape: 443^2 nodes, horizon of 20 cells
+    # (about 1208 neighbours per node), linearised law, no damage
+    "paper443": lambda: plate_2d(443, 20, seed=2, steps=100),
     "notched512": lambda: notched_plate_2d(512, 4),
     "cube100": lambda: cube_3d(100, 3),
     "bar400x40": lambda: bar_2d(400, 40, 3),

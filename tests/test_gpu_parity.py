@@ -99,7 +99,7 @@ def test_neighbors_bit_exact(gpu, orc, name):
     assert np.array_equal(np.sort(perm), np.arange(X.shape[0]))
 
 
-@pytest.mark.parametrize("wl", ["notched512", "cube100"])
+@pytest.mark.parametrize("wl", ["notched512", "cube100", "paper443"])
 def test_neighbors_full_size(gpu, orc, wl):
     torch, pd, ctx = gpu
     w = inputs.CONFIGS[wl]()
@@ -440,6 +440,42 @@ def test_cube100_full_size_steps(gpu, orc, prec):
         relL2(v, st["v"]))
     assert relL2(u, st["u"]) <= (tol if same else 10 * tol)
     assert relL2(v, st["v"]) <= (tol if same else 10 * tol)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
+def test_paper443_full_size_steps(gpu, orc, prec):
+    """The paper's explicit benchmark shape (443^2 plate, horizon of 20 cells,
+    about 1208 neighbours per node, 2.4e8 bonds) in the launch shape the
+    autotuner picks for it: 5 steps from the workload's initial velocity
+    against the oracle."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["paper443"]()
+    say("paper443 full size", prec)
+    mesh = cached_mesh(orc, "paper443", w)
+    c = orc.micromodulus(2, w.E, w.delta)
+    st = mesh.start(w.u0, w.v0, c)
+    mesh.verlet(st, c, w.rho, 0.0, w.dt, 5)
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    assert nb.nnz == mesh.nnz
+    best, _ = ctx.autotune(dev(torch, w.X), dev(torch, w.V), w.delta, prec, steps=10)
+    say("paper443 tuned shape", best["tile"], best["lanes"])
+    try:
+        sim = sim_from_workload(torch, pd, ctx, nb, w, pd.micromodulus(2, w.E, w.delta), prec,
+                                damage=False)
+        shape = sim.info()
+        assert shape["kernel"] == "stream"
+        assert (shape["tile"], shape["lanes"]) == (best["tile"], best["lanes"])
+        sim.step(5, w.dt)
+        u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
+        sim.close()
+    finally:
+        ctx.tune_clear()
+        nb.close()
+    tol = tol_of(prec)
+    assert info["step"] == 5
+    say("paper443", prec, "relL2 u", relL2(u, st["u"]), "v", relL2(v, st["v"]))
+    assert relL2(u, st["u"]) <= tol
+    assert relL2(v, st["v"]) <= tol
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
