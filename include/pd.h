@@ -568,7 +568,8 @@ int pd_apply_tangent_at(pd_ctx ctx, pd_nbr nbr, const pd_material *mat, const do
  * for PD_LAW_NP a Newton-Krylov iteration, which needs a positive definite
  * tangent: 2 beta r < 1 on the bonds that carry load).
  *   precision PD_FP64: float64 CG solving each Newton system to the target.
- *   PD_MIXED (and PD_FP32): each correction solved to 1e-4 relative by a CG with float32
+ *   PD_MIXED (and PD_FP32): each correction solved to 1e-2 relative (each Newton
+ *   system of PD_LAW_NP to 1e-4) by a CG with float32
  *   vectors and float32 bond arithmetic in the tangent but float64 dot
  *   products, inside iterative refinement on float64 residuals (the force
  *   in float64) until rtol is met.
