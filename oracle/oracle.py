@@ -113,6 +113,10 @@ def lib():
                            dbl, dbl, dbl, ptr, ptr, ptr, i64, dbl, i64, i64, ptr, ptr, ptr, ptr]
         L.or_band_update.restype = None
         L.or_band_update.argtypes = [i32, i64, ptr, ptr, ptr, ptr, dbl, dbl, dbl, ptr]
+        L.or_ccm_bar_1d.restype = None
+        L.or_ccm_bar_1d.argtypes = [dbl, dbl, dbl, ptr]
+        L.or_ccm_plane_stress.restype = None
+        L.or_ccm_plane_stress.argtypes = [i64, ptr, dbl, dbl, dbl, dbl, dbl, ptr]
         L.or_set_threads.restype = None
         L.or_set_threads.argtypes = [i32]
         L.or_num_threads.restype = i32
@@ -131,6 +135,24 @@ def _f64(a):
 
 def threshold(delta):
     return lib().or_threshold(float(delta))
+
+
+def ccm_bar_1d(F, A, E):
+    """(stress, strain, strain-energy density) of a bar under an end force
+    (the classical values of the paper's 1-d implicit validation)."""
+    out = np.zeros(3)
+    lib().or_ccm_bar_1d(float(F), float(A), float(E), _p(out))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def ccm_plane_stress(X, t, E, nu, x0, yc):
+    """Classical plane-stress displacement of a plate under a uniform
+    traction t along x, held at x = x0 and symmetric about y = yc."""
+    X = _f64(X)
+    u = np.zeros_like(X)
+    lib().or_ccm_plane_stress(X.shape[0], _p(X), float(t), float(E), float(nu), float(x0),
+                              float(yc), _p(u))
+    return u
 
 
 def micromodulus(dim, E, delta):

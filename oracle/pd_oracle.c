@@ -683,6 +683,35 @@ int or_solve_implicit(int dim, int64_t n, const int64_t *row_ptr, const int32_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Classical continuum mechanics comparisons of the implicit validation      */
+/* (Section "Validation", implicit).  One dimension: a bar of cross section */
+/* A and Young's modulus E under an end force F carries the uniform stress  */
+/* F/A, the strain F/(A E) and the strain-energy density stress*strain/2.   */
+/* out = {stress, strain, energy density}.                                   */
+/* ------------------------------------------------------------------------ */
+void or_ccm_bar_1d(double F, double A, double E, double *out) {
+    const double stress = F / A;
+    const double strain = stress / E;
+    out[0] = stress;
+    out[1] = strain;
+    out[2] = 0.5 * stress * strain;
+}
+
+/* Two dimensions, plane stress: a plate under a uniform traction t along x, */
+/* held at x = x0 in x and symmetric about y = yc, has the uniform strains   */
+/* eps_xx = t/E, eps_yy = -nu t/E, no shear, hence the displacement          */
+/*   u_x = (t/E)(x - x0),  u_y = -nu (t/E)(y - yc)                           */
+/* at the nodes X (n x 2); u is n x 2.                                       */
+void or_ccm_plane_stress(int64_t n, const double *X, double t, double E, double nu, double x0,
+                         double yc, double *u) {
+    const double e = t / E;
+    for (int64_t i = 0; i < n; ++i) {
+        u[2 * i] = e * (X[2 * i] - x0);
+        u[2 * i + 1] = -nu * e * (X[2 * i + 1] - yc);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* General pairwise law of Algorithm 1 (the NP model of the validation       */
 /* section): with J = 1 on the ball,                                         */
 /*   f_i += 4/(delta |B_delta(0)|) psi'(|xi| S^2) S e V_j                    */

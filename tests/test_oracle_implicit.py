@@ -96,16 +96,40 @@ def test_implicit_solution_dense_and_residual(orc):
     assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
 
 
-def test_ccm_golden_constants():
-    """The classical 1-d bar values printed in the paper's implicit validation."""
+def test_ccm_golden_constants(orc):
+    """The oracle's classical 1-d bar values against those printed in the
+    paper's implicit validation (F = 40 N, A = 1 m^2, E = 4 GPa)."""
     with open(os.path.join(GOLDEN, "ccm_1d_bar.json")) as fh:
         g = json.load(fh)
-    stress = g["F"] / g["A"]
-    strain = stress / g["E"]
-    energy = stress ** 2 / (2 * g["E"])
+    stress, strain, energy = orc.ccm_bar_1d(g["F"], g["A"], g["E"])
     assert np.isclose(stress, g["stress"], rtol=1e-15)
     assert np.isclose(strain, g["strain"], rtol=1e-15)
     assert np.isclose(energy, g["energy_density"], rtol=1e-15)
+
+
+def test_ccm_plane_stress_field(orc):
+    """The oracle's classical plane-stress field satisfies the equations it
+    stands for: strains from central differences of the field on a lattice,
+    stresses by plane-stress Hooke's law, sigma_xx = t and sigma_yy =
+    sigma_xy = 0 everywhere (equilibrium and the traction-free sides), u_x = 0
+    on x = x0 and u_y = 0 on y = yc.  A field with the lateral contraction's
+    sign flipped or nu t/E dropped fails the sigma_yy check."""
+    E, nu, t, x0, yc, d = 2.5, 1.0 / 3.0, 1e-3, 0.3, 0.5, 1e-3
+    X = inputs.grid_coords((9, 7), 0.125)
+    u = orc.ccm_plane_stress(X, t, E, nu, x0, yc)
+    ux = (orc.ccm_plane_stress(X + [d, 0], t, E, nu, x0, yc)
+          - orc.ccm_plane_stress(X - [d, 0], t, E, nu, x0, yc)) / (2 * d)
+    uy = (orc.ccm_plane_stress(X + [0, d], t, E, nu, x0, yc)
+          - orc.ccm_plane_stress(X - [0, d], t, E, nu, x0, yc)) / (2 * d)
+    exx, eyy, gxy = ux[:, 0], uy[:, 1], ux[:, 1] + uy[:, 0]
+    k = E / (1 - nu * nu)
+    sxx, syy, sxy = k * (exx + nu * eyy), k * (eyy + nu * exx), E / (2 * (1 + nu)) * gxy
+    assert np.allclose(sxx, t, rtol=1e-9, atol=0)
+    assert np.allclose(syy, 0.0, atol=1e-12 * t) and np.allclose(sxy, 0.0, atol=1e-12 * t)
+    at_x0 = orc.ccm_plane_stress(np.array([[x0, 0.9]]), t, E, nu, x0, yc)
+    at_yc = orc.ccm_plane_stress(np.array([[0.7, yc]]), t, E, nu, x0, yc)
+    assert at_x0[0, 0] == 0.0 and at_yc[0, 1] == 0.0
+    assert u.shape == X.shape
 
 
 @pytest.mark.slow
@@ -118,8 +142,17 @@ def test_bar_interior_strain_matches_classical(orc):
     c = orc.micromodulus(2, wk.E, wk.delta)
     u, info = mesh.solve_implicit(wk.u0, c, wk.b, wk.fixed, rtol=1e-10)
     assert info["status"] == 0
-    x = wk.X[:, 0]
+    x, y = wk.X[:, 0], wk.X[:, 1]
     H = 1.0
     sel = (x > 3 * wk.h + 2 * H) & (x < x.max() - 2 * H)
-    slope = np.polyfit(x[sel], u[sel, 0], 1)[0]
-    assert abs(slope / (wk.traction / wk.E) - 1) < 0.10
+    # the classical plane-stress field (nu = 1/3 for the 2-d bond-based
+    # model): interior strains of the oracle's solution within 10 % of it
+    ref = orc.ccm_plane_stress(wk.X, wk.traction, wk.E, 1.0 / 3.0, 0.0, 0.5 * H)
+    exx = np.polyfit(x[sel], u[sel, 0], 1)[0]
+    exx_ref = np.polyfit(x[sel], ref[sel, 0], 1)[0]
+    # lateral strain: the y-slope of u_y once its mean trend along x is removed
+    uy = u[sel, 1] - np.polyval(np.polyfit(x[sel], u[sel, 1], 1), x[sel])
+    eyy = np.polyfit(y[sel], uy, 1)[0]
+    eyy_ref = np.polyfit(y[sel], ref[sel, 1], 1)[0]
+    assert abs(exx / exx_ref - 1) < 0.10
+    assert abs(eyy / eyy_ref - 1) < 0.10
