@@ -379,11 +379,18 @@ def test_implicit_bar_full_size(gpu, orc, prec):
     assert rn / bn <= 2e-10
     # ||du||/||u|| <= kappa * 1e-10; kappa(H) of this bar is below 1e4
     assert relL2(got, ref) <= 1e-6
-    # classical solution in the interior (modelling error, not parity)
-    x = w.X[:, 0]
+    # the classical plane-stress field in the interior (modelling error, not
+    # parity): axial strain within 10 %, lateral within 15 % (the lattice's
+    # own Poisson ratio at a 3-cell horizon is about 0.32, and the clamp
+    # restrains the contraction near it)
+    x, y = w.X[:, 0], w.X[:, 1]
     sel = (x > 3 * w.h + 2) & (x < x.max() - 2)
-    slope = np.polyfit(x[sel], got[sel, 0], 1)[0]
-    assert abs(slope / (w.traction / w.E) - 1) < 0.10
+    ccm = orc.ccm_plane_stress(w.X, w.traction, w.E, 1.0 / 3.0, 0.0, 0.5)
+    exx = np.polyfit(x[sel], got[sel, 0], 1)[0]
+    uy = got[sel, 1] - np.polyval(np.polyfit(x[sel], got[sel, 1], 1), x[sel])
+    eyy = np.polyfit(y[sel], uy, 1)[0]
+    assert abs(exx / np.polyfit(x[sel], ccm[sel, 0], 1)[0] - 1) < 0.10
+    assert abs(eyy / np.polyfit(y[sel], ccm[sel, 1], 1)[0] - 1) < 0.15
 
 
 def test_implicit_noconv_reports(gpu):
