@@ -134,7 +134,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="cube100", choices=["cube100", "notched512", "plate32"])
+    ap.add_argument("--config", default="cube100",
+                    choices=["cube100", "notched512", "plate32", "paper443"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed", "fp32"])
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "gather", "tile"])
@@ -143,7 +144,7 @@ def parse():
     ap.add_argument("--reps", type=int, default=5,
                     help="timed windows of --steps steps each; the median is reported")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the 512^2 / 32^2 plates and the implicit bar")
+                    help="skip the 512^2 / 32^2 / 443^2 plates and the implicit bar")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
