@@ -130,3 +130,89 @@ def test_loaded_horizon_precisions(gpu, wl):
         assert abs(int(dead) - int(dead64)) <= 1e-3 * dead64, key
         assert abs(info["ke"] - i64["ke"]) <= 1e-2 * i64["ke"], key
         assert abs(info["pe"] - i64["pe"]) <= 1e-2 * i64["pe"], key
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_loaded_horizon_np_windows(gpu, orc, prec):
+    """The NP law of the validation section in Algorithm 1 (beta = 1e3, no
+    damage) on the 512^2 notched plate for the whole 10k steps under its
+    collar loading, on the streamed kernel: at checkpoints the oracle's NP
+    steps restart from the GPU state and must match it after 20 steps."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["notched512"]()
+    beta, W = 1e3, 20
+    marks = list(range(0, 10000, 2500)) + [9980]
+    mesh = orc.LawMesh(w.X, w.V, w.delta)
+    c = orc.micromodulus(2, w.E, w.delta)
+    alive0 = mesh.notch_cut(w.notch, mesh.all_alive())
+    tol = TOL64 if prec == "fp64" else tol_of(prec)
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    mat = pd.material(2, pd.micromodulus(2, w.E, w.delta), w.rho, 0.0, prec, law="np",
+                      beta=beta)
+    sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                        dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                        bc_vel=dev(torch, w.bc_vel), notch=w.notch, ramp_steps=w.ramp_steps)
+    try:
+        assert sim.info()["kernel"] == "stream"
+        step = 0
+        for m in marks:
+            sim.step(m - step, w.dt)
+            step = m
+            u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
+            assert info["step"] == step and np.array_equal(a, alive0)
+            st = mesh.start_law(u, v, c, orc.LAW_NP, beta, alive=a)
+            st["step"] = step
+            mesh.verlet_law(st, c, w.rho, 0.0, w.dt, W, orc.LAW_NP, beta, bc_kind=w.bc_kind,
+                            bc_vel=w.bc_vel, ramp=w.ramp_steps)
+            sim.step(W, w.dt)
+            step += W
+            u, v, a, info = read_state(torch, sim, w.n, 2, nb.nnz)
+            eu, ev = relL2(u, st["u"]), relL2(v, st["v"])
+            say("NP window at", m, "relL2 u", eu, "v", ev)
+            assert eu <= tol and ev <= 10 * tol, f"window at {m}"
+        assert np.abs(u).max() > 1e-4          # the collars have moved the plate
+    finally:
+        sim.close()
+        nb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_loaded_horizon_solid_windows(gpu, orc, prec):
+    """The linear peridynamic solid of Algorithm 2 (nu = 1/4, no damage) on the
+    1M-node cube for the whole 2k steps under its uniaxial collar loading, on
+    the streamed kernel's two passes: at checkpoints the oracle's solid steps
+    restart from the GPU state and must match it after 2 steps."""
+    torch, pd, ctx = gpu
+    w = inputs.CONFIGS["cube100"]()
+    K, mu = orc.lps_moduli(w.E, 0.25)
+    marks, W = [0, 700, 1400, 1998], 2
+    mesh = orc.LpsMesh(w.X, w.V, w.delta)
+    tol = TOL64 if prec == "fp64" else tol_of(prec)
+    ctx.tune_clear()
+    nb = pd.Neighbors(ctx, dev(torch, w.X), w.delta)
+    mat = pd.material(3, 0.0, w.rho, 0.0, prec, law="lps", bulk=K, shear=mu)
+    sim = pd.Simulation(ctx, nb, mat, dev(torch, w.X), dev(torch, w.V), dev(torch, w.u0),
+                        dev(torch, w.v0), bc_kind=dev(torch, w.bc_kind),
+                        bc_vel=dev(torch, w.bc_vel), ramp_steps=w.ramp_steps)
+    try:
+        assert sim.info()["kernel"] == "stream"
+        step = 0
+        for m in marks:
+            sim.step(m - step, w.dt)
+            step = m
+            u, v, _, info = read_state(torch, sim, w.n, 3, nb.nnz)
+            assert info["step"] == step
+            st = mesh.start_lps(u, v, K, mu)
+            st["step"] = step
+            mesh.verlet_lps(st, K, mu, w.rho, w.dt, W, bc_kind=w.bc_kind, bc_vel=w.bc_vel,
+                            ramp=w.ramp_steps)
+            sim.step(W, w.dt)
+            step += W
+            u, v, _, info = read_state(torch, sim, w.n, 3, nb.nnz)
+            eu, ev = relL2(u, st["u"]), relL2(v, st["v"])
+            say("solid window at", m, "relL2 u", eu, "v", ev)
+            assert eu <= tol and ev <= 10 * tol, f"window at {m}"
+        assert np.abs(u).max() > 1e-4          # the collars have stretched the cube
+    finally:
+        sim.close()
+        nb.close()
