@@ -10,7 +10,7 @@
 //      by (key, original id): a deterministic space-filling-curve order
 //   4. per node: count candidates from the 3^d surrounding bins that pass the
 //      distance predicate, scan to row offsets, fill, sort each row by the
-//      neighbour's original id
+//      neighbour's original id (segments sorted in LDS by a bitonic network)
 // The predicate is evaluated with FP contraction disabled so that it rounds
 // exactly like the plain definition d2 = (dx*dx + dy*dy) + dz*dz.
 #include <algorithm>
@@ -142,12 +142,83 @@ __global__ void bin_scatter_k(uint32_t n, const uint32_t *binm, const uint64_t *
     perm[pos] = (int32_t)o;
 }
 
-// one thread per bin: insertion sort of the bin's nodes by (key, id)
-__global__ void bin_sort_k(uint64_t nbins, const uint64_t *bstart, const uint64_t *key,
-                           int32_t *perm) {
+// Segments (a bin's nodes, a row's neighbours) are sorted one workgroup per
+// segment: the segment is read into LDS, padded to the next power of two
+// with elements above every real one, put in order by a bitonic sorting
+// network and written back.  A segment longer than the LDS capacity is
+// sorted by one thread (insertion sort) in a second kernel that skips every
+// other segment.  The order is a total order on distinct elements (node ids
+// are unique), so both kernels give the same result.
+constexpr int SEG_BLOCK = 256;
+constexpr uint32_t ROW_CAP = 4096;   // int32 ids: 16 KB of LDS
+constexpr uint32_t BIN_CAP = 2048;   // (key, id) pairs: 24 KB of LDS
+constexpr unsigned SEG_GRID = 16384; // workgroups; each strides over segments
+
+__device__ __forceinline__ uint32_t pow2_ceil(uint32_t x) {
+    return x <= 1u ? 1u : 1u << (32 - __builtin_clz(x - 1u));
+}
+
+// the bitonic network over P (a power of two) elements of LDS: stage k
+// merges runs of length k, pass j compares elements j apart; a pair sits in
+// ascending order when its lower index has bit k clear.  gt(i, l) says
+// whether element i belongs after element l; swap(i, l) exchanges them.
+template <class Gt, class Swap>
+__device__ __forceinline__ void bitonic_lds(uint32_t P, Gt gt, Swap swap) {
+    for (uint32_t k = 2; k <= P; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += SEG_BLOCK) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                if (gt(i, i + j) == ((i & k) == 0)) swap(i, i + j);
+            }
+            __syncthreads();
+        }
+}
+
+// each bin's nodes by (key, original id)
+__global__ __launch_bounds__(SEG_BLOCK) void bin_sort_lds_k(uint64_t nbins, const uint64_t *bstart,
+                                                            const uint64_t *key, int32_t *perm) {
+    __shared__ uint64_t sk[BIN_CAP];
+    __shared__ int32_t si[BIN_CAP];
+    for (uint64_t m = blockIdx.x; m < nbins; m += gridDim.x) {
+        const uint64_t a = bstart[m], len = bstart[m + 1] - a;
+        if (len < 2 || len > BIN_CAP) continue;     // the same for the whole workgroup
+        const uint32_t P = pow2_ceil((uint32_t)len);
+        for (uint32_t x = threadIdx.x; x < P; x += SEG_BLOCK) {
+            int32_t id = INT32_MAX;
+            uint64_t kk = UINT64_MAX;
+            if (x < len) {
+                id = perm[a + x];
+                kk = key[id];
+            }
+            sk[x] = kk;
+            si[x] = id;
+        }
+        __syncthreads();
+        bitonic_lds(
+            P,
+            [&](uint32_t i, uint32_t l) {
+                return sk[i] > sk[l] || (sk[i] == sk[l] && si[i] > si[l]);
+            },
+            [&](uint32_t i, uint32_t l) {
+                const uint64_t tk = sk[i];
+                const int32_t ti = si[i];
+                sk[i] = sk[l];
+                si[i] = si[l];
+                sk[l] = tk;
+                si[l] = ti;
+            });
+        for (uint32_t x = threadIdx.x; x < len; x += SEG_BLOCK) perm[a + x] = si[x];
+        __syncthreads();                            // LDS is reused by the next bin
+    }
+}
+
+// the bins too long for LDS: one thread per bin, insertion sort by (key, id)
+__global__ void bin_sort_long_k(uint64_t nbins, const uint64_t *bstart, const uint64_t *key,
+                                int32_t *perm) {
     const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nbins) return;
     const uint64_t a = bstart[m], e = bstart[m + 1];
+    if (e - a <= BIN_CAP) return;
     for (uint64_t p = a + 1; p < e; ++p) {
         const int32_t id = perm[p];
         const uint64_t kk = key[id];
@@ -209,12 +280,36 @@ __global__ void candidates_k(Grid g, double thr, uint32_t n, const double4 *xs,
     if (!FILL) cnt[s] = m;
 }
 
-// one thread per row: insertion sort of the row by sfc id (the candidates
-// arrive bin by bin in curve order, so rows are nearly sorted already)
-__global__ void row_sort_k(uint32_t n, const uint32_t *row_ptr, int32_t *col) {
+// each CSR row ascending (internal rows by curve position, exported rows by
+// original id)
+__global__ __launch_bounds__(SEG_BLOCK) void row_sort_lds_k(uint32_t n, const uint32_t *row_ptr,
+                                                            int32_t *col) {
+    __shared__ int32_t sc[ROW_CAP];
+    for (uint32_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const uint32_t a = row_ptr[r], len = row_ptr[r + 1] - a;
+        if (len < 2 || len > ROW_CAP) continue;     // the same for the whole workgroup
+        const uint32_t P = pow2_ceil(len);
+        for (uint32_t x = threadIdx.x; x < P; x += SEG_BLOCK)
+            sc[x] = x < len ? col[a + x] : INT32_MAX;
+        __syncthreads();
+        bitonic_lds(
+            P, [&](uint32_t i, uint32_t l) { return sc[i] > sc[l]; },
+            [&](uint32_t i, uint32_t l) {
+                const int32_t t = sc[i];
+                sc[i] = sc[l];
+                sc[l] = t;
+            });
+        for (uint32_t x = threadIdx.x; x < len; x += SEG_BLOCK) col[a + x] = sc[x];
+        __syncthreads();                            // LDS is reused by the next row
+    }
+}
+
+// the rows too long for LDS: one thread per row, insertion sort
+__global__ void row_sort_long_k(uint32_t n, const uint32_t *row_ptr, int32_t *col) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint32_t a = row_ptr[s], e = row_ptr[s + 1];
+    if (e - a <= ROW_CAP) return;
     for (uint32_t p = a + 1; p < e; ++p) {
         const int32_t c = col[p];
         uint32_t q = p;
@@ -226,7 +321,14 @@ __global__ void row_sort_k(uint32_t n, const uint32_t *row_ptr, int32_t *col) {
     }
 }
 
-// exported rows (original numbering) filled unsorted, one wave per row ...
+// both row sorts of the build
+void sort_rows(hipStream_t st, uint32_t n, const uint32_t *row_ptr, int32_t *col) {
+    row_sort_lds_k<<<std::min<unsigned>(n, SEG_GRID), SEG_BLOCK, 0, st>>>(n, row_ptr, col);
+    row_sort_long_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, row_ptr, col);
+}
+
+// exported rows (original numbering) filled unsorted, one wave per row, then
+// sorted by original id
 __global__ void excol_fill_k(uint32_t n, const int32_t *perm, const uint32_t *row_ptr,
                              const uint32_t *ex_row_ptr, const int32_t *col, int32_t *ex_col) {
     const uint32_t s = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
@@ -234,22 +336,6 @@ __global__ void excol_fill_k(uint32_t n, const int32_t *perm, const uint32_t *ro
     if (s >= n) return;
     const uint32_t a = row_ptr[s], e = row_ptr[s + 1], x = ex_row_ptr[perm[s]];
     for (uint32_t k = lane; k < e - a; k += 64) ex_col[x + k] = perm[col[a + k]];
-}
-
-// ... then sorted by original id, one thread per row
-__global__ void excol_sort_k(uint32_t n, const uint32_t *ex_row_ptr, int32_t *ex_col) {
-    const uint32_t o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= n) return;
-    const uint32_t a = ex_row_ptr[o], e = ex_row_ptr[o + 1];
-    for (uint32_t p = a + 1; p < e; ++p) {
-        const int32_t c = ex_col[p];
-        uint32_t q = p;
-        while (q > a && ex_col[q - 1] > c) {
-            ex_col[q] = ex_col[q - 1];
-            --q;
-        }
-        ex_col[q] = c;
-    }
 }
 
 // exported position of every internal bond: binary search of the
@@ -397,7 +483,9 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     PD_TRY(pd_alloc(ctx, &b->iperm, n));
     bin_scatter_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, t.binm, t.bstart, t.cursor, b->perm);
     PD_LAUNCH_CHECK(ctx);
-    bin_sort_k<<<pd_blocks(nbins), PD_BLOCK, 0, st>>>(nbins, t.bstart, t.key, b->perm);
+    bin_sort_lds_k<<<(unsigned)std::min<uint64_t>(nbins, SEG_GRID), SEG_BLOCK, 0, st>>>(
+        nbins, t.bstart, t.key, b->perm);
+    bin_sort_long_k<<<pd_blocks(nbins), PD_BLOCK, 0, st>>>(nbins, t.bstart, t.key, b->perm);
     PD_LAUNCH_CHECK(ctx);
     PD_TRY(pd_alloc(ctx, &t.xs, n));
     invert_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->perm, b->iperm, dim, X, t.xs);
@@ -427,7 +515,7 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     candidates_k<true><<<pd_blocks(n), PD_BLOCK, 0, st>>>(g, b->thr, n, t.xs, t.bstart, nullptr,
                                                          b->row_ptr, b->col, ctx->flag);
     PD_LAUNCH_CHECK(ctx);
-    row_sort_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->row_ptr, b->col);
+    sort_rows(st, n, b->row_ptr, b->col);
     PD_LAUNCH_CHECK(ctx);
 
     // exported (original-order) row offsets and the longest row
@@ -446,7 +534,7 @@ int build(pd_ctx ctx, int dim, uint32_t n, const double *X, double delta, pd_nbr
     excol_fill_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, st>>>(n, b->perm, b->row_ptr,
                                                                     b->ex_row_ptr, b->col, t.ex_col);
     PD_LAUNCH_CHECK(ctx);
-    excol_sort_k<<<pd_blocks(n), PD_BLOCK, 0, st>>>(n, b->ex_row_ptr, t.ex_col);
+    sort_rows(st, n, b->ex_row_ptr, t.ex_col);
     PD_LAUNCH_CHECK(ctx);
     ex_pos_k<<<pd_blocks((uint64_t)n * 64), PD_BLOCK, 0, st>>>(n, b->perm, b->row_ptr,
                                                                 b->ex_row_ptr, b->col, t.ex_col,

@@ -257,6 +257,19 @@ def random_cloud(n, dim, seed, box=1.0):
     return rng.uniform(0.0, box, size=(n, dim))
 
 
+def dense_cluster(n_cluster, n_side, seed):
+    """For delta = 1: n_cluster uniform points in a disk of radius 0.49 about
+    the origin (every pair closer than 1, so every row holds n_cluster - 1
+    neighbours and the cluster fills one bin), beside an n_side^2 lattice of
+    spacing 0.1 at x >= 5 (rows of about 300, bins of about 100)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = 0.49 * np.sqrt(rng.uniform(0.0, 1.0, n_cluster))
+    th = 2.0 * np.pi * rng.uniform(0.0, 1.0, n_cluster)
+    cl = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    g = grid_coords((n_side, n_side), 0.1) + np.array([5.0, 0.0])
+    return np.ascontiguousarray(np.concatenate([cl, g]))
+
+
 def random_field(n, dim, seed, scale=1e-3):
     rng = np.random.Generator(np.random.PCG64(seed))
     return scale * rng.standard_normal((n, dim))

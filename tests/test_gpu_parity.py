@@ -79,6 +79,9 @@ MESHES = {
     "cube_h001": lambda: (inputs.grid_coords((13, 11, 9), 0.01), 0.03),
     "cloud2d": lambda: (inputs.random_cloud(3000, 2, 3), 0.04),
     "cloud3d": lambda: (inputs.random_cloud(4000, 3, 4), 0.12),
+    # rows of 4199 and a bin of 4200 nodes (beyond what one workgroup sorts
+    # in LDS) beside rows and bins of a few hundred
+    "cluster_long_segments": lambda: (inputs.dense_cluster(4200, 30, 31), 1.0),
     "two_nodes": lambda: (np.array([[0.0, 0.0], [0.3, 0.4]]), 0.5),
     "isolated": lambda: (np.array([[0.0, 0.0, 0.0], [5.0, 0.0, 0.0], [0.0, 7.0, 1.0]]), 1.0),
 }
@@ -97,6 +100,45 @@ def test_neighbors_bit_exact(gpu, orc, name):
     assert nb.max_row == (np.diff(orp).max() if X.shape[0] else 0)
     perm = nb.permutation()
     assert np.array_equal(np.sort(perm), np.arange(X.shape[0]))
+
+
+def curve_keys(X, delta):
+    """The internal node order's key: the Morton code of the node's bin (bins
+    of edge delta from the bounding box's low corner) followed by the Morton
+    code of its position inside the bin (10 bits per axis at most)."""
+    n, dim = X.shape
+    edge = np.sqrt(delta * delta * (1.0 + 1e-10)) * (1.0 + 1e-12)
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    nc = np.floor((hi - lo) / edge).astype(np.int64) + 1
+    bits = int(np.ceil(np.log2(nc.max()))) if nc.max() > 1 else 0
+    fbits = min((21 if dim == 3 else 31) - bits, 10)
+    t = (X - lo) / edge
+    cc = np.clip(np.floor(t).astype(np.int64), 0, nc - 1)
+    fc = np.clip(np.floor((t - cc) * float(1 << fbits)).astype(np.int64), 0, (1 << fbits) - 1)
+
+    def morton(c, nb):
+        out = np.zeros(n, dtype=np.uint64)
+        for b in range(nb):
+            for k in range(dim):
+                out |= ((c[:, k].astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) \
+                    << np.uint64(dim * b + k)
+        return out
+
+    return (morton(cc, bits) << np.uint64(dim * fbits)) | morton(fc, fbits)
+
+
+@pytest.mark.parametrize("name", ["plate64_m4", "cube_jit20", "cloud2d", "cloud3d",
+                                  "cluster_long_segments"])
+def test_permutation_is_curve_order(gpu, name):
+    """The internal order sorts the nodes by (curve key, original id)."""
+    torch, pd, ctx = gpu
+    X, delta = MESHES[name]()
+    say("curve order", name, X.shape)
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    perm = nb.permutation()
+    nb.close()
+    want = np.lexsort((np.arange(X.shape[0]), curve_keys(X, delta)))
+    assert np.array_equal(perm, want)
 
 
 @pytest.mark.parametrize("wl", ["notched512", "cube100", "paper443"])
