@@ -231,6 +231,15 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
     };
     __syncthreads();
 
+    // 3-d record copies: record (within a 64-record group) and byte offset
+    // of chunk 64 p + lane of the group
+    uint32_t crec[NCH], cpart[NCH];
+#pragma unroll
+    for (uint32_t p = 0; p < NCH; ++p) {
+        const uint32_t x = 64u * p + lane64;
+        crec[p] = x / NCH;
+        cpart[p] = (x - crec[p] * NCH) * 16u;
+    }
     // halo ids of tile k -> ids slot k mod 2
     auto issue_ids = [&](uint32_t k) {
         const StreamInst I = inst_of(k);
@@ -252,13 +261,29 @@ __global__ __launch_bounds__(1024) void stream_kernel(StreamArgs sa) {
         const StreamInst I = inst_of(k);
         const void *src = cur_of(I) ? I.rec[1] : I.rec[0];
         const void *rp = I.row_ptr, *vv = I.v, *bc = I.bc;
-        const uint32_t nrc = hn * NCH;
-        for (uint32_t c0 = wbase; c0 < nrc; c0 += B) {
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rec + 2 * (size_t)c0));
-            const uint32_t c = c0 + lane64;
-            if (c < nrc) {
-                const uint32_t r = c / NCH, part = c - r * NCH;
-                dma16(src, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
+        if constexpr (NCH == 3) {
+            // a wave copies 64 records per round in three copies of 64 lanes:
+            // lane l of copy p moves 16-byte chunk 64 p + l of the group, whose
+            // record and part are fixed per lane (no division per copy)
+            for (uint32_t g0 = wbase; g0 < hn; g0 += B) {
+#pragma unroll
+                for (uint32_t p = 0; p < NCH; ++p) {
+                    if (g0 + 64u * p / NCH >= hn) break;   // no record left for this copy
+                    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+                        lds_addr(rec + 2 * ((size_t)g0 * NCH + 64u * p)));
+                    const uint32_t r = g0 + crec[p];
+                    if (r < hn) dma16(src, (uint32_t)hid[r] * (RD * 8u) + cpart[p], m0);
+                }
+            }
+        } else {
+            const uint32_t nrc = hn * NCH;   // two chunks per record: a shift
+            for (uint32_t c0 = wbase; c0 < nrc; c0 += B) {
+                const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_addr(rec + 2 * (size_t)c0));
+                const uint32_t c = c0 + lane64;
+                if (c < nrc) {
+                    const uint32_t r = c / NCH, part = c - r * NCH;
+                    dma16(src, (uint32_t)hid[r] * (RD * 8u) + part * 16u, m0);
+                }
             }
         }
         for (uint32_t c0 = wbase; c0 <= tn; c0 += B) {
