@@ -5,24 +5,33 @@
 // constant for the linearised law and c exp(-beta r)(1 - 2 beta r) per bond
 // for the NP law), each Newton system solved by conjugate gradients.
 //
-// CG runs on the device in two launches per iteration.  The first applies
-// the tangent to the new search direction p = r + beta p_old, which it forms
-// on the fly for every node it reads (p is double-buffered, so no block
-// overwrites a direction another block still reads) and stores for its own
-// nodes, and it sums p.q per block.  The second updates x and r with
-// alpha = r.r / p.q and sums r.r per block.  Every block reduces the other
-// launch's block sums in one fixed order, so all blocks derive the same
-// alpha, beta and stopping decision and runs are bit-reproducible; a device
-// state word records r.r and the iteration count, and the host looks at it
-// once per chunk of iterations.
+// CG runs on the device in one launch per iteration, in the form of
+// Chronopoulos and Gear (1989), which needs one fused reduction per iteration
+// instead of two: with w = H r kept beside r, gamma = r.r and delta = w.r
+// give beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma /
+// alpha_old), then p = r + beta p, s = w + beta s, x += alpha p,
+// r -= alpha s, and the next w = H r.  The launch forms the new r on the fly
+// for every neighbour it reads (r, w and s are double-buffered, so no block
+// overwrites a value another block still reads), applies the tangent to it,
+// stores its own nodes' vectors and sums gamma and delta per block.  Every
+// block reduces the previous launch's block sums in one fixed order, so all
+// blocks derive the same alpha, beta and stopping decision and runs are
+// bit-reproducible; a device state word records gamma, alpha and the
+// iteration count, and the host looks at it once per chunk of iterations.
+// The float32 corrections of the mixed solve keep the classic form in two
+// launches per iteration (p = r + beta p and q = H p with the sum of p.q,
+// then x, r and the sum of r.r): in float32 the one-launch recurrences let r
+// drift from the true residual, which cost more iterations (2253 against
+// 1204 on the 400 x 40 bar) than the shorter iterations saved.
 //
 // Precision: PD_FP64 runs every part in float64.  PD_MIXED solves each
-// correction with float32 CG vectors (x, r, p, q) and float32 bond
+// correction with float32 CG vectors (x, r, w, p, s) and float32 bond
 // arithmetic in the tangent, with float64 dot products, inside iterative
 // refinement on float64 residuals (the force in float64) until the relative
 // residual reaches the requested tolerance.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "pd_kernels.hpp"
@@ -32,8 +41,9 @@ namespace {
 using namespace pdk;
 
 struct CgState {
-    double rr[2];   // r.r at the start of iteration it, in slot it & 1
-    double tol2;    // stop when r.r <= tol2
+    double rr[2];      // r.r at the start of iteration m, in slot m & 1
+    double alpha[2];   // alpha of iteration m, in slot m & 1
+    double tol2;       // stop when r.r <= tol2
     int done;
     int iters;
 };
@@ -63,6 +73,50 @@ __device__ void block_partial(double acc, double *part) {
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// both sums of a launch: block sums of a and b in one tree
+__device__ void block_partial2(double a, double b, double *part_a, double *part_b) {
+    __shared__ double sa[PD_BLOCK], sb[PD_BLOCK];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = PD_BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sa[threadIdx.x] += sa[threadIdx.x + off];
+            sb[threadIdx.x] += sb[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_a[blockIdx.x] = sa[0];
+        part_b[blockIdx.x] = sb[0];
+    }
+}
+
+// the totals of both block-sum arrays, each by an ordered tree over the nparts
+// block sums (the same in every block)
+__device__ void reduce_partials2(const double *part_a, const double *part_b, int nparts,
+                                 double &ta, double &tb) {
+    __shared__ double sa[PD_BLOCK], sb[PD_BLOCK];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += PD_BLOCK) {
+        a += part_a[k];
+        b += part_b[k];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = PD_BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sa[threadIdx.x] += sa[threadIdx.x + off];
+            sb[threadIdx.x] += sb[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    ta = sa[0];
+    tb = sb[0];
+    __syncthreads();
 }
 
 __global__ void dot_k(const double *a, const double *b, uint64_t m, double *part) {
@@ -110,6 +164,160 @@ struct CgArgs {
     const uint8_t *fixed;        // NULL: none
     const double *kb;            // per-bond tangent factor (NP), NULL: 1
     double c;
+    T *x, *p;                    // own nodes only: updated in place
+    T *r[2], *w[2], *s[2];       // read in slot k & 1, written in slot (k + 1) & 1
+    double *part_g, *part_d;     // block sums of r.r and w.r
+    int nparts;
+    CgState *st;
+};
+
+__device__ __forceinline__ double rsq_of(double r2) { return rsqrt_pos(r2); }
+__device__ __forceinline__ float rsq_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return fmaf(a, b, c); }
+
+// Launch k.  k = 0 starts the solve: alpha = beta = 0, so it only forms
+// w_0 = H r_0 and the sums of r_0.r_0 and w_0.r_0.  Launch k >= 1 is
+// iteration m = k - 1: it reduces gamma_m and delta_m (the stopping test),
+// derives beta_m and alpha_m, updates its own nodes (s_m = w_m + beta s,
+// p_m = r_m + beta p, x += alpha p_m, r_{m+1} = r_m - alpha s_m), applies
+// the tangent to r_{m+1}, forming it for every neighbour read the same way
+// (fixed rows identity, r read as 0 at fixed nodes, dead bonds skipped), and
+// sums r_{m+1}.r_{m+1} and w_{m+1}.r_{m+1} per block.  L lanes per node.
+template <int DIM, int L, class T>
+__global__ __launch_bounds__(PD_BLOCK) void cg_step_k(CgArgs<T> a, int k) {
+    CgState *st = a.st;
+    if (st->done) return;
+    constexpr int US = DIM == 3 ? 4 : 2;
+    double alpha = 0.0, beta = 0.0;
+    if (k > 0) {
+        const int m = k - 1;
+        double g, d;
+        reduce_partials2(a.part_g, a.part_d, a.nparts, g, d);
+        double den = d;
+        if (m > 0) {
+            beta = g / st->rr[(m - 1) & 1];
+            den = d - beta * g / st->alpha[(m - 1) & 1];
+        }
+        // converged, or the curvature p.Hp (= den in exact arithmetic) no
+        // longer positive: every block takes the same decision
+        if (g <= st->tol2 || !(den > 0.0)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                st->rr[m & 1] = g;
+                st->iters = m;
+                st->done = 1;
+            }
+            return;
+        }
+        alpha = g / den;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->rr[m & 1] = g;
+            st->alpha[m & 1] = alpha;
+        }
+    }
+    const T ta = (T)alpha, tb = (T)beta;
+    const T *__restrict__ rc = a.r[k & 1];
+    const T *__restrict__ wc = a.w[k & 1];
+    const T *__restrict__ sc = a.s[k & 1];
+    T *__restrict__ rn = a.r[(k + 1) & 1];
+    T *__restrict__ wn = a.w[(k + 1) & 1];
+    T *__restrict__ sn = a.s[(k + 1) & 1];
+    // s_m and r_{m+1} of node j, component d (the same operations wherever
+    // they are formed)
+    auto s_of = [&](uint32_t j, int d) -> T {
+        return fma_of(tb, sc[(size_t)j * US + d], wc[(size_t)j * US + d]);
+    };
+    auto r_of = [&](uint32_t j, int d, T sj) -> T {
+        return fma_of(-ta, sj, rc[(size_t)j * US + d]);
+    };
+    const int lane = threadIdx.x & (L - 1);
+    const uint32_t per = (uint32_t)(gridDim.x * PD_BLOCK / L);
+    double gp = 0.0, dp = 0.0;
+    for (uint32_t i = (blockIdx.x * PD_BLOCK + threadIdx.x) / L; i < a.n; i += per) {
+        const bool fi = a.fixed && a.fixed[i];
+        const T six = s_of(i, 0), siy = s_of(i, 1), siz = DIM == 3 ? s_of(i, 2) : (T)0;
+        const T rix = r_of(i, 0, six), riy = r_of(i, 1, siy), riz = DIM == 3 ? r_of(i, 2, siz) : (T)0;
+        const double xix = a.xv[4 * (size_t)i], xiy = a.xv[4 * (size_t)i + 1];
+        const double xiz = DIM == 3 ? a.xv[4 * (size_t)i + 2] : 0.0;
+        const double Vi = a.xv[4 * (size_t)i + (DIM == 3 ? 3 : 2)];
+        T hx = 0, hy = 0, hz = 0;
+        if (!fi) {
+            for (uint32_t e = a.row_ptr[i] + lane; e < a.row_ptr[i + 1]; e += L) {
+                if (a.alive && !a.alive[e]) continue;
+                const uint32_t j = (uint32_t)a.col[e];
+                const double4 xj = reinterpret_cast<const double4 *>(a.xv)[j];
+                const T dx = (T)(xj.x - xix), dy = (T)(xj.y - xiy);
+                const T dz = DIM == 3 ? (T)(xj.z - xiz) : (T)0;
+                T vx, vy, vz = 0;
+                if (!(a.fixed && a.fixed[j])) {
+                    vx = r_of(j, 0, s_of(j, 0)) - rix;
+                    vy = r_of(j, 1, s_of(j, 1)) - riy;
+                    if (DIM == 3) vz = r_of(j, 2, s_of(j, 2)) - riz;
+                } else {
+                    vx = -rix;
+                    vy = -riy;
+                    if (DIM == 3) vz = -riz;
+                }
+                const T r2 = DIM == 3 ? dx * dx + dy * dy + dz * dz : dx * dx + dy * dy;
+                const T ev = DIM == 3 ? vx * dx + vy * dy + vz * dz : vx * dx + vy * dy;
+                const T inv = rsq_of(r2);
+                T g = (T)(a.c * (DIM == 3 ? xj.w : xj.z)) * (ev * inv * inv) * inv;
+                if (a.kb) g *= (T)a.kb[e];
+                hx += g * dx;
+                hy += g * dy;
+                if (DIM == 3) hz += g * dz;
+            }
+        }
+        // lane sums (neighbouring lanes first)
+        for (int o = 1; o < L; o <<= 1) {
+            hx += __shfl_xor(hx, o, L);
+            hy += __shfl_xor(hy, o, L);
+            if (DIM == 3) hz += __shfl_xor(hz, o, L);
+        }
+        if (lane == 0) {
+            const size_t b = (size_t)i * US;
+            const T wx = fi ? rix : (T)(-Vi) * hx, wy = fi ? riy : (T)(-Vi) * hy;
+            const T wz = fi ? riz : (T)(-Vi) * hz;
+            const T px = fma_of(tb, a.p[b], rc[b]), py = fma_of(tb, a.p[b + 1], rc[b + 1]);
+            a.p[b] = px;
+            a.p[b + 1] = py;
+            a.x[b] = fma_of(ta, px, a.x[b]);
+            a.x[b + 1] = fma_of(ta, py, a.x[b + 1]);
+            sn[b] = six;
+            sn[b + 1] = siy;
+            rn[b] = rix;
+            rn[b + 1] = riy;
+            wn[b] = wx;
+            wn[b + 1] = wy;
+            if (DIM == 3) {
+                const T pz = fma_of(tb, a.p[b + 2], rc[b + 2]);
+                a.p[b + 2] = pz;
+                a.x[b + 2] = fma_of(ta, pz, a.x[b + 2]);
+                sn[b + 2] = siz;
+                rn[b + 2] = riz;
+                wn[b + 2] = wz;
+            }
+            gp += (double)rix * (double)rix + (double)riy * (double)riy +
+                  (DIM == 3 ? (double)riz * (double)riz : 0.0);
+            dp += (double)wx * (double)rix + (double)wy * (double)riy +
+                  (DIM == 3 ? (double)wz * (double)riz : 0.0);
+        }
+    }
+    block_partial2(gp, dp, a.part_g, a.part_d);
+}
+
+// The two-launch form (the mixed solve's float32 corrections): one solve's
+// arrays, vectors in sfc order, [n][US] like u
+template <class T>
+struct Cg2Args {
+    uint32_t n;
+    const uint32_t *row_ptr;
+    const int32_t *col;
+    const double *xv;            // {x, y, z, V} / {x, y, V, 0}
+    const uint8_t *alive;        // NULL: all intact
+    const uint8_t *fixed;        // NULL: none
+    const double *kb;            // per-bond tangent factor (NP), NULL: 1
+    double c;
     T *x, *r, *q;
     T *p[2];                     // search direction, double-buffered
     double *part_pq, *part_rr;   // block sums
@@ -117,15 +325,13 @@ struct CgArgs {
     CgState *st;
 };
 
-__device__ __forceinline__ double rsq_of(double r2) { return rsqrt_pos(r2); }
-__device__ __forceinline__ float rsq_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
 
 // First launch of iteration `it`: beta from the previous update's r.r (and
 // the stopping test), p = r + beta p_old for every node read, q = H p for
 // the block's nodes (fixed rows identity, p read as 0 at fixed nodes, dead
 // bonds skipped), and the block's sum of p.q.  L lanes per node.
 template <int DIM, int L, class T>
-__global__ __launch_bounds__(PD_BLOCK) void cg_apply_k(CgArgs<T> a, int it) {
+__global__ __launch_bounds__(PD_BLOCK) void cg_apply_k(Cg2Args<T> a, int it) {
     CgState *st = a.st;
     if (st->done) return;
     constexpr int US = DIM == 3 ? 4 : 2;
@@ -214,7 +420,7 @@ __global__ __launch_bounds__(PD_BLOCK) void cg_apply_k(CgArgs<T> a, int it) {
 // Second launch: alpha = r.r / p.q, x += alpha p, r -= alpha q, block sums
 // of the new r.r.
 template <int DIM, class T>
-__global__ __launch_bounds__(PD_BLOCK) void cg_update_k(CgArgs<T> a, int it) {
+__global__ __launch_bounds__(PD_BLOCK) void cg_update_k(Cg2Args<T> a, int it) {
     CgState *st = a.st;
     if (st->done) return;
     constexpr int US = DIM == 3 ? 4 : 2;
@@ -265,15 +471,16 @@ __global__ void add_k(double *y, const T *x, uint64_t m) {
     if (k < m) y[k] = y[k] + (double)x[k];
 }
 
-// CG start: x = 0, r = (T) rhs, both directions 0
+// CG start: x = 0, r = (T) rhs, p = w = s = 0 (the slots launch 0 reads)
 template <class T>
-__global__ void cg_init_k(const double *rhs, T *x, T *r, T *p0, T *p1, uint64_t m) {
+__global__ void cg_init_k(const double *rhs, T *x, T *p, T *r, T *w, T *s, uint64_t m) {
     const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     x[k] = 0;
+    p[k] = 0;
     r[k] = (T)rhs[k];
-    p0[k] = 0;
-    p1[k] = 0;
+    w[k] = 0;
+    s[k] = 0;
 }
 
 template <class T>
@@ -287,14 +494,25 @@ __global__ void r_dot_k(const T *r, uint64_t m, double *part) {
 
 template <class T>
 struct CgVecs {
-    T *x = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
-    ~CgVecs() { pd_free(x); pd_free(r); pd_free(q); pd_free(p0); pd_free(p1); }
+    T *x = nullptr, *p = nullptr, *r[2] = {nullptr, nullptr}, *w[2] = {nullptr, nullptr},
+      *s[2] = {nullptr, nullptr};
+    ~CgVecs() {
+        pd_free(x);
+        pd_free(p);
+        for (int k = 0; k < 2; ++k) {
+            pd_free(r[k]);
+            pd_free(w[k]);
+            pd_free(s[k]);
+        }
+    }
     int alloc(pd_ctx ctx, uint64_t m) {
         PD_TRY(pd_alloc(ctx, &x, m));
-        PD_TRY(pd_alloc(ctx, &r, m));
-        PD_TRY(pd_alloc(ctx, &q, m));
-        PD_TRY(pd_alloc(ctx, &p0, m));
-        PD_TRY(pd_alloc(ctx, &p1, m));
+        PD_TRY(pd_alloc(ctx, &p, m));
+        for (int k = 0; k < 2; ++k) {
+            PD_TRY(pd_alloc(ctx, &r[k], m));
+            PD_TRY(pd_alloc(ctx, &w[k], m));
+            PD_TRY(pd_alloc(ctx, &s[k], m));
+        }
         return PD_OK;
     }
 };
@@ -329,22 +547,37 @@ int dot_host(pd_ctx ctx, const double *a, const double *b, uint64_t m, double *p
     return PD_OK;
 }
 
+template <int DIM, class T>
+int launch_cg_lanes(pd_ctx ctx, const CgArgs<T> &a, int k, unsigned grid, int L) {
+    hipStream_t s = ctx->stream;
+    switch (L) {
+    case 1: cg_step_k<DIM, 1, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    case 2: cg_step_k<DIM, 2, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    case 4: cg_step_k<DIM, 4, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    case 8: cg_step_k<DIM, 8, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    case 16: cg_step_k<DIM, 16, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    default: cg_step_k<DIM, 32, T><<<grid, PD_BLOCK, 0, s>>>(a, k); break;
+    }
+    PD_LAUNCH_CHECK(ctx);
+    return PD_OK;
+}
+
 template <int DIM, int L, class T>
-void launch_cg_iter(const CgArgs<T> &a, int it, unsigned grid, hipStream_t s) {
+void launch_cg2_iter(const Cg2Args<T> &a, int it, unsigned grid, hipStream_t s) {
     cg_apply_k<DIM, L, T><<<grid, PD_BLOCK, 0, s>>>(a, it);
     cg_update_k<DIM, T><<<grid, PD_BLOCK, 0, s>>>(a, it);
 }
 
 template <int DIM, class T>
-int launch_cg_lanes(pd_ctx ctx, const CgArgs<T> &a, int it, unsigned grid, int L) {
+int launch_cg2_lanes(pd_ctx ctx, const Cg2Args<T> &a, int it, unsigned grid, int L) {
     hipStream_t s = ctx->stream;
     switch (L) {
-    case 1: launch_cg_iter<DIM, 1, T>(a, it, grid, s); break;
-    case 2: launch_cg_iter<DIM, 2, T>(a, it, grid, s); break;
-    case 4: launch_cg_iter<DIM, 4, T>(a, it, grid, s); break;
-    case 8: launch_cg_iter<DIM, 8, T>(a, it, grid, s); break;
-    case 16: launch_cg_iter<DIM, 16, T>(a, it, grid, s); break;
-    default: launch_cg_iter<DIM, 32, T>(a, it, grid, s); break;
+    case 1: launch_cg2_iter<DIM, 1, T>(a, it, grid, s); break;
+    case 2: launch_cg2_iter<DIM, 2, T>(a, it, grid, s); break;
+    case 4: launch_cg2_iter<DIM, 4, T>(a, it, grid, s); break;
+    case 8: launch_cg2_iter<DIM, 8, T>(a, it, grid, s); break;
+    case 16: launch_cg2_iter<DIM, 16, T>(a, it, grid, s); break;
+    default: launch_cg2_iter<DIM, 32, T>(a, it, grid, s); break;
     }
     PD_LAUNCH_CHECK(ctx);
     return PD_OK;
@@ -357,8 +590,8 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVe
              const double *rhs, uint64_t m, double tol, int budget, int *iters) {
     hipStream_t s = ctx->stream;
     const unsigned gm = pd_blocks(m);
-    cg_init_k<T><<<gm, PD_BLOCK, 0, s>>>(rhs, v.x, v.r, v.p0, v.p1, m);
-    r_dot_k<T><<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(v.r, m, w.part_a);
+    cg_init_k<T><<<gm, PD_BLOCK, 0, s>>>(rhs, v.x, v.p, v.r[0], v.w[0], v.s[0], m);
+    r_dot_k<T><<<PD_RED_BLOCKS, PD_BLOCK, 0, s>>>(v.r[0], m, w.part_a);
     PD_LAUNCH_CHECK(ctx);
     PD_HIP(ctx, hipMemcpyAsync(ctx->red_host, w.part_a, sizeof(double) * PD_RED_BLOCKS,
                                hipMemcpyDeviceToHost, s));
@@ -367,6 +600,7 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVe
     for (int k = 0; k < PD_RED_BLOCKS; ++k) rr += ctx->red_host[k];
     w.st_host->rr[0] = rr;
     w.st_host->rr[1] = 0.0;
+    w.st_host->alpha[0] = w.st_host->alpha[1] = 0.0;
     w.st_host->tol2 = tol * tol;
     w.st_host->done = rr <= tol * tol;
     w.st_host->iters = 0;
@@ -377,6 +611,51 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVe
     const double k = nbr->n ? (double)nbr->nnz / (double)nbr->n : 0.0;
     int L = 1;
     while (L < 32 && L * 4 < k) L *= 2;
+    // one grid for every launch: enough blocks for every node's lane group
+    // (at most the partial-sum slots)
+    uint64_t need = ((uint64_t)nbr->n * L + PD_BLOCK - 1) / PD_BLOCK;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, PD_RED_BLOCKS));
+    const int chunk = 32;
+    int done = w.st_host->done;
+    if constexpr (std::is_same<T, float>::value) {
+        // float32 corrections: the two-launch form (its float32 recurrences
+        // keep r close to the true residual; the one-launch form's drift apart
+        // and cost more iterations than its shorter launches save)
+        Cg2Args<T> a{};
+        a.n = nbr->n;
+        a.row_ptr = nbr->row_ptr;
+        a.col = nbr->col;
+        a.xv = w.xv;
+        a.alive = w.alive;
+        a.fixed = w.fixed;
+        a.kb = mat->law == PD_LAW_NP ? w.kb : nullptr;
+        a.c = mat->c;
+        a.x = v.x;
+        a.r = v.r[0];
+        a.q = v.w[0];
+        a.p[0] = v.p;        // both direction buffers start at 0
+        a.p[1] = v.s[0];
+        a.part_pq = w.part_a;
+        a.part_rr = w.part_b;
+        a.nparts = (int)grid;
+        a.st = w.st;
+        int it = 0;
+        while (!done && it < budget) {
+            const int nrun = std::min(chunk, budget - it);
+            for (int k = 0; k < nrun; ++k) {
+                const int st = nbr->dim == 3 ? launch_cg2_lanes<3, T>(ctx, a, it + k, grid, L)
+                                             : launch_cg2_lanes<2, T>(ctx, a, it + k, grid, L);
+                if (st != PD_OK) return st;
+            }
+            it += nrun;
+            PD_HIP(ctx, hipMemcpyAsync(w.st_host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            PD_HIP(ctx, hipStreamSynchronize(s));
+            done = w.st_host->done;
+            if (done) it = w.st_host->iters;
+        }
+        *iters = it;
+        return PD_OK;
+    }
     CgArgs<T> a{};
     a.n = nbr->n;
     a.row_ptr = nbr->row_ptr;
@@ -387,35 +666,32 @@ int cg_solve(pd_ctx ctx, const pd_nbr nbr, const pd_material *mat, Work &w, CgVe
     a.kb = mat->law == PD_LAW_NP ? w.kb : nullptr;
     a.c = mat->c;
     a.x = v.x;
-    a.r = v.r;
-    a.q = v.q;
-    a.p[0] = v.p0;
-    a.p[1] = v.p1;
-    a.part_pq = w.part_a;
-    a.part_rr = w.part_b;
-    a.st = w.st;
-    // one grid for both launches: enough blocks for every node's lane group
-    // (at most the partial-sum slots); the update walks the vectors strided
-    uint64_t need = ((uint64_t)nbr->n * L + PD_BLOCK - 1) / PD_BLOCK;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, PD_RED_BLOCKS));
+    a.p = v.p;
+    for (int k = 0; k < 2; ++k) {
+        a.r[k] = v.r[k];
+        a.w[k] = v.w[k];
+        a.s[k] = v.s[k];
+    }
+    a.part_g = w.part_a;
+    a.part_d = w.part_b;
     a.nparts = (int)grid;
-    const int chunk = 32;
-    int done = w.st_host->done;
-    int it = 0;
-    while (!done && it < budget) {
-        const int nrun = std::min(chunk, budget - it);
+    a.st = w.st;
+    // launch 0 forms w_0 = H r_0; launch k >= 1 is iteration k - 1, so
+    // launches 0..budget run at most `budget` iterations
+    int launched = 0;
+    while (!done && launched <= budget) {
+        const int nrun = std::min(chunk, budget + 1 - launched);
         for (int k = 0; k < nrun; ++k) {
-            const int st = nbr->dim == 3 ? launch_cg_lanes<3, T>(ctx, a, it + k, grid, L)
-                                         : launch_cg_lanes<2, T>(ctx, a, it + k, grid, L);
+            const int st = nbr->dim == 3 ? launch_cg_lanes<3, T>(ctx, a, launched + k, grid, L)
+                                         : launch_cg_lanes<2, T>(ctx, a, launched + k, grid, L);
             if (st != PD_OK) return st;
         }
-        it += nrun;
+        launched += nrun;
         PD_HIP(ctx, hipMemcpyAsync(w.st_host, w.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         PD_HIP(ctx, hipStreamSynchronize(s));
         done = w.st_host->done;
-        if (done) it = w.st_host->iters;
     }
-    *iters = it;
+    *iters = done ? w.st_host->iters : budget;
     return PD_OK;
 }
 
