@@ -435,6 +435,61 @@ def test_implicit_bar_full_size(gpu, orc, prec):
     assert abs(eyy / np.polyfit(y[sel], ccm[sel, 1], 1)[0] - 1) < 0.15
 
 
+def damaged_cube_case():
+    """A jittered 16 x 14 x 12 cube (unequal volumes, horizon 3h) with 5 % of
+    its bonds broken in both directions, the layer x < 2h clamped and a
+    smooth body force."""
+    h = 1.0 / 16
+    X = inputs.grid_coords((16, 14, 12), h, jitter=0.1, seed=41)
+    n = X.shape[0]
+    rng = np.random.Generator(np.random.PCG64(42))
+    V = h ** 3 * rng.uniform(0.8, 1.2, n)
+    fixed = (X[:, 0] < 2 * h).astype(np.uint8)
+    b = np.stack([0.1 * np.sin(4 * X[:, 1]), 0.05 * X[:, 2], -0.05 + 0 * X[:, 0]], axis=1)
+    return X, V, 3 * h, fixed, b
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_implicit_damaged_cube(gpu, orc, prec):
+    """3-d implicit solve with broken bonds, unequal volumes and a clamped
+    layer: relative residual 1e-10 (and evaluated by the oracle in FP64),
+    agreement with the oracle's solution, and a second solve equal bit for
+    bit (the CG's block sums are reduced in a fixed order)."""
+    torch, pd, ctx = gpu
+    X, V, delta, fixed, b = damaged_cube_case()
+    n = X.shape[0]
+    mesh = orc.Mesh(X, V, delta)
+    i_all = np.repeat(np.arange(n), np.diff(mesh.row_ptr))
+    j_all = mesh.col.astype(np.int64)
+    lo, hi = np.minimum(i_all, j_all), np.maximum(i_all, j_all)
+    pair = lo * n + hi                      # the same key for both directions
+    keys = np.unique(pair)
+    dead = keys[np.random.Generator(np.random.PCG64(43)).uniform(size=keys.size) < 0.05]
+    alive = (~np.isin(pair, dead)).astype(np.uint8)
+    assert 0.03 < 1 - alive.mean() < 0.07
+    c = orc.micromodulus(3, 1.0, delta)
+    ref, rinfo = mesh.solve_implicit(np.zeros((n, 3)), c, b, fixed, alive, rtol=1e-12)
+    assert rinfo["status"] == 0
+    say("implicit damaged cube", prec, n, mesh.nnz)
+    nb = pd.Neighbors(ctx, dev(torch, X), delta)
+    mat = pd.material(3, pd.micromodulus(3, 1.0, delta), 1.0, 0.0, prec)
+    outs = []
+    for _ in range(2):
+        u = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+        res = pd.solve_implicit(ctx, nb, mat, dev(torch, X), dev(torch, V), dev(torch, b), u,
+                                fixed=dev(torch, fixed), alive=dev(torch, alive), rtol=1e-10)
+        outs.append(host(u))
+        assert res.rel_residual <= 1e-10
+    nb.close()
+    got = outs[0]
+    assert np.array_equal(outs[0], outs[1])
+    _, rn = mesh.residual(got, c, b, fixed, alive)
+    bn = np.linalg.norm((V[:, None] * b)[fixed == 0])
+    assert rn / bn <= 2e-10
+    assert relL2(got, ref) <= 1e-6
+    assert np.all(got[fixed == 1] == 0.0)
+
+
 def test_implicit_noconv_reports(gpu):
     torch, pd, ctx = gpu
     w = bar_case(40, 8)
