@@ -325,7 +325,6 @@ struct Cg2Args {
     CgState *st;
 };
 
-
 // First launch of iteration `it`: beta from the previous update's r.r (and
 // the stopping test), p = r + beta p_old for every node read, q = H p for
 // the block's nodes (fixed rows identity, p read as 0 at fixed nodes, dead
