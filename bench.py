@@ -311,6 +311,7 @@ def config_runs(torch, pd, steps, warmup):
                 "steps": k, "ms_per_step": ms,
                 "windows_ms_per_step": [x / k for x in r["windows_ms"]],
                 "bond_evals_per_s": r["nnz"] / (ms * 1e-3), "launch": r["launch"],
+                "neighbor_build_s": r["t_nbr_s"],
                 "roofline": step_roofline(algorithmic_bytes(w.n, r["nnz"], w.dim), ms)}
     return out
 
